@@ -1,0 +1,321 @@
+"""Python side of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Loads ``liboracle.so`` (plain C, built with gcc from ``oracle.c``) through
+ctypes and drives it one environment at a time.  Only the tests, the smoke
+check and the benchmark's CPU-baseline leg use this module; the product path
+never imports it.  It shares no code with the HIP library: the two meet only
+through the seeded inputs of ``paper_2306_07552_amd.scenegen``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = ["oracle.c", "oracle_mlp.c"]
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-fvisibility=hidden", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc"] + CFLAGS + ["-o", LIB_PATH + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------
+# ctypes records (mirror the structs in oracle.c)
+# --------------------------------------------------------------------------
+_fp = C.POINTER(C.c_float)
+_u32p = C.POINTER(C.c_uint32)
+_i32p = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class ORobot(C.Structure):
+    _fields_ = [("dh", C.c_float * 28), ("qlim", C.c_float * 14), ("q_home", C.c_float * 7),
+                ("mount", C.c_float * 3), ("cam_offset", C.c_float * 3),
+                ("cam_pitch_cs", C.c_float * 2), ("num_spheres", C.c_int32),
+                ("sphere_link", _i32p), ("sphere_pos", _fp), ("sphere_class", _i32p),
+                ("sphere_held_only", _u8p)]
+
+
+class OParams(C.Structure):
+    _fields_ = [("num_classes", C.c_int32), ("class_radius", C.c_float * 8),
+                ("act_lim", C.c_float * 3), ("episode_len", C.c_int32),
+                ("near_m", C.c_float), ("far_m", C.c_float), ("cell_m", C.c_float)]
+
+
+class OEnv(C.Structure):
+    _fields_ = [("grid_x0", C.c_float), ("grid_y0", C.c_float), ("grid_cell", C.c_float),
+                ("nx", C.c_int32), ("ny", C.c_int32),
+                ("grid_offsets", _u32p * 8), ("grid_layers", _fp * 8),
+                ("num_objects", C.c_int32), ("objects", _fp),
+                ("num_starts", C.c_int32), ("starts", _fp), ("held", C.c_int32)]
+
+
+class ORStats(C.Structure):
+    _fields_ = [("tris_in", C.c_int64), ("tris_front", C.c_int64), ("cand_px", C.c_int64),
+                ("frags", C.c_int64), ("clipped", C.c_int64)]
+
+
+def _declare(L):
+    L.o_sincos_n.argtypes = [_fp, _fp, _fp, C.c_int64]
+    L.o_fk.argtypes = [C.POINTER(ORobot), _fp, _fp]
+    L.o_camera.argtypes = [C.POINTER(ORobot), _fp, _fp]
+    L.o_grid_build.argtypes = [_fp, C.c_int, C.c_float, C.c_float, C.c_int, C.c_int, C.c_float,
+                               C.c_float, _u32p, _fp, C.c_int64]
+    L.o_grid_build.restype = C.c_int64
+    L.o_grid_query.argtypes = [C.POINTER(OEnv), C.c_int, C.c_float, C.c_float, C.c_float]
+    L.o_grid_query.restype = C.c_int
+    L.o_obb_query.argtypes = [_fp, C.c_float, C.c_float, C.c_float, C.c_float]
+    L.o_obb_query.restype = C.c_int
+    L.o_robot_step.argtypes = [C.POINTER(ORobot), C.POINTER(OParams), C.POINTER(OEnv), _fp, _i32p,
+                               _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp]
+    L.o_reset_env.argtypes = [C.POINTER(ORobot), C.POINTER(OEnv), _fp, _i32p, C.c_int]
+    L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
+                           _u32p, _u32p, _u8p, C.POINTER(ORStats)]
+
+
+def ptr(a: Optional[np.ndarray], t):
+    if a is None:
+        return C.cast(None, t)
+    assert a.flags["C_CONTIGUOUS"], "arrays passed to the oracle must be contiguous"
+    return a.ctypes.data_as(t)
+
+
+# --------------------------------------------------------------------------
+# small wrappers
+# --------------------------------------------------------------------------
+def sincos(x: np.ndarray):
+    x = np.ascontiguousarray(x, np.float32)
+    s = np.empty_like(x)
+    c = np.empty_like(x)
+    lib().o_sincos_n(ptr(x, _fp), ptr(s, _fp), ptr(c, _fp), x.size)
+    return s, c
+
+
+def make_robot(robot) -> tuple:
+    """ORobot from a ``scenegen.Robot``; returns (struct, keepalive)."""
+    r = ORobot()
+    r.dh[:] = robot.dh.astype(np.float32).ravel().tolist()
+    r.qlim[:] = robot.qlim.astype(np.float32).ravel().tolist()
+    r.q_home[:] = robot.q_home.astype(np.float32).tolist()
+    r.mount[:] = robot.mount.astype(np.float32).tolist()
+    r.cam_offset[:] = robot.cam_offset.astype(np.float32).tolist()
+    r.cam_pitch_cs[:] = robot.cam_pitch_cs.astype(np.float32).tolist()
+    keep = [np.ascontiguousarray(robot.sphere_link, np.int32),
+            np.ascontiguousarray(robot.sphere_pos, np.float32),
+            np.ascontiguousarray(robot.sphere_class, np.int32),
+            np.ascontiguousarray(robot.sphere_held_only, np.uint8)]
+    r.num_spheres = keep[0].shape[0]
+    r.sphere_link = ptr(keep[0], _i32p)
+    r.sphere_pos = ptr(keep[1], _fp)
+    r.sphere_class = ptr(keep[2], _i32p)
+    r.sphere_held_only = ptr(keep[3], _u8p)
+    return r, keep
+
+
+def make_params(radius_classes, act_lim, episode_len, near, far, cell) -> OParams:
+    p = OParams()
+    p.num_classes = len(radius_classes)
+    rc = list(np.asarray(radius_classes, np.float32)) + [0.0] * (8 - len(radius_classes))
+    p.class_radius[:] = [float(v) for v in rc]
+    p.act_lim[:] = [float(v) for v in np.asarray(act_lim, np.float32)]
+    p.episode_len = int(episode_len)
+    p.near_m = float(np.float32(near))
+    p.far_m = float(np.float32(far))
+    p.cell_m = float(np.float32(cell))
+    return p
+
+
+def grid_build(boxes: np.ndarray, x0: float, y0: float, nx: int, ny: int, cell: float,
+               r: float):
+    """Column grid of one radius class (CSR offsets, layers [L][2])."""
+    boxes = np.ascontiguousarray(boxes, np.float32)
+    L = lib()
+    n = L.o_grid_build(ptr(boxes, _fp), boxes.shape[0], float(np.float32(x0)),
+                       float(np.float32(y0)), nx, ny, float(np.float32(cell)),
+                       float(np.float32(r)), C.cast(None, _u32p), C.cast(None, _fp), 0)
+    if n < 0:
+        raise RuntimeError("oracle grid build: too many blocking boxes in one column")
+    offs = np.zeros(nx * ny + 1, np.uint32)
+    lay = np.zeros((max(n, 1), 2), np.float32)
+    n2 = L.o_grid_build(ptr(boxes, _fp), boxes.shape[0], float(np.float32(x0)),
+                        float(np.float32(y0)), nx, ny, float(np.float32(cell)),
+                        float(np.float32(r)), ptr(offs, _u32p), ptr(lay, _fp), n)
+    assert n2 == n
+    return offs, lay[:n]
+
+
+def render(verts, tris, cam, W, H, near, far, want_id=False, want_cover=False):
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.int32)
+    cam = np.ascontiguousarray(cam, np.float32)
+    depth = np.empty((H, W), np.uint32)
+    win = np.empty((H, W), np.uint32) if want_id else None
+    cov = np.empty((H, W), np.uint8) if want_cover else None
+    st = ORStats()
+    lib().o_render(ptr(verts, _fp), ptr(tris, _i32p), tris.shape[0], ptr(cam, _fp), W, H,
+                   float(np.float32(near)), float(np.float32(far)), ptr(depth, _u32p),
+                   ptr(win, _u32p), ptr(cov, _u8p), C.byref(st))
+    stats = dict(tris_in=st.tris_in, tris_front=st.tris_front, cand_px=st.cand_px,
+                 frags=st.frags, clipped=st.clipped)
+    return depth, win, cov, stats
+
+
+# --------------------------------------------------------------------------
+# the whole step over a batch of environments
+# --------------------------------------------------------------------------
+class OracleBatch:
+    """Reference simulator for a subset of a scene set's environments.
+
+    Holds per-env state f32 [n][10] (x, y, yaw, q0..q6) and counters i32 [n][2]
+    (step in episode, episode).  ``step(actions)`` runs the kinematic update,
+    collision, resolution and episode bookkeeping, then renders depth (and the
+    winning triangle, from which flat colour follows)."""
+
+    def __init__(self, robot, scenes, cfg_consts: dict, envs: Optional[Sequence[int]] = None,
+                 color: bool = False):
+        self.robot_src = robot
+        self.robot, self._rkeep = make_robot(robot)
+        self.scenes = scenes
+        self.envs = list(range(scenes.num_envs)) if envs is None else list(envs)
+        cc = cfg_consts
+        self.near, self.far, self.cell = cc["near"], cc["far"], cc["cell"]
+        self.radius_classes = tuple(cc["radius_classes"])
+        self.params = make_params(self.radius_classes, cc["act_lim"], cc["episode_len"],
+                                  self.near, self.far, self.cell)
+        self.color = color
+        n = len(self.envs)
+        self.state = np.zeros((n, 10), np.float32)
+        self.counters = np.zeros((n, 2), np.int32)
+        self.words = (robot.num_spheres + 31) // 32
+        self._env_structs = []
+        self._env_keep = []
+        for e in self.envs:
+            self._build_env(e)
+        for i, e in enumerate(self.envs):
+            st = scenes.starts[e, 0]
+            self.state[i, 0:3] = st
+            self.state[i, 3:10] = robot.q_home
+
+    def _build_env(self, e: int):
+        S = self.scenes
+        boxes = S.env_boxes(e)
+        x0, y0 = (float(v) for v in S.grid_origin[e])
+        nx, ny = (int(v) for v in S.grid_dims[e])
+        env = OEnv()
+        env.grid_x0, env.grid_y0, env.grid_cell = x0, y0, float(np.float32(self.cell))
+        env.nx, env.ny = nx, ny
+        keep = []
+        grids = []
+        for k, r in enumerate(self.radius_classes):
+            offs, lay = grid_build(boxes, x0, y0, nx, ny, self.cell, r)
+            lay = np.ascontiguousarray(lay if lay.size else np.zeros((1, 2), np.float32))
+            keep += [offs, lay]
+            grids.append((offs, lay))
+            env.grid_offsets[k] = ptr(offs, _u32p)
+            env.grid_layers[k] = ptr(lay, _fp)
+        objs = np.ascontiguousarray(S.objects[e], np.float32)
+        starts = np.ascontiguousarray(S.starts[e], np.float32)
+        keep += [objs, starts]
+        env.num_objects = objs.shape[0]
+        env.objects = ptr(objs, _fp)
+        env.num_starts = starts.shape[0]
+        env.starts = ptr(starts, _fp)
+        env.held = int(S.held[e])
+        self._env_structs.append(env)
+        self._env_keep.append((keep, grids))
+
+    def grid(self, i: int, k: int):
+        return self._env_keep[i][1][k]
+
+    def reset(self, mask: Optional[np.ndarray] = None):
+        L = lib()
+        for i in range(len(self.envs)):
+            if mask is None or mask[i]:
+                L.o_reset_env(C.byref(self.robot), C.byref(self._env_structs[i]),
+                              ptr(self.state[i], _fp), ptr(self.counters[i], _i32p), 1)
+
+    def set_state(self, state: np.ndarray, counters: np.ndarray):
+        self.state[...] = state
+        self.counters[...] = counters
+
+    def _step_env(self, i, act, out):
+        L = lib()
+        e = self.envs[i]
+        L.o_robot_step(C.byref(self.robot), C.byref(self.params), C.byref(self._env_structs[i]),
+                       ptr(self.state[i], _fp), ptr(self.counters[i], _i32p), ptr(act, _fp),
+                       ptr(out["contact_static"][i], _u32p), ptr(out["contact_object"][i], _u32p),
+                       ptr(out["accepted"][i:i + 1], _u8p), ptr(out["done"][i:i + 1], _u8p),
+                       ptr(out["frames"][i], _fp), ptr(out["cam"][i], _fp))
+        res = int(self.scenes.res[e])
+        v, t, _rgb = self.scenes.env_mesh(e)
+        depth, win, _cov, stats = render(v, t, out["cam"][i], res, res, self.near, self.far,
+                                         want_id=self.color)
+        out["depth"][i] = depth
+        if self.color:
+            rgb = np.zeros((res, res, 3), np.uint8)
+            hit = win != 0xFFFFFFFF
+            rgb[hit] = _rgb[win[hit]]
+            out["rgb"][i] = rgb
+        out["stats"][i] = stats
+
+    def step(self, actions: np.ndarray, threads: int = 1):
+        n = len(self.envs)
+        actions = np.ascontiguousarray(actions, np.float32)
+        out = dict(contact_static=np.zeros((n, self.words), np.uint32),
+                   contact_object=np.zeros((n, self.words), np.uint32),
+                   accepted=np.zeros(n, np.uint8), done=np.zeros(n, np.uint8),
+                   frames=np.zeros((n, 8, 12), np.float32), cam=np.zeros((n, 12), np.float32),
+                   depth=[None] * n, rgb=[None] * n, stats=[None] * n)
+        if threads <= 1:
+            for i in range(n):
+                self._step_env(i, actions[i], out)
+        else:
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda i: self._step_env(i, actions[i], out), range(n)))
+        out["state"] = self.state.copy()
+        out["counters"] = self.counters.copy()
+        return out
+
+
+def fk(robot, state: np.ndarray) -> np.ndarray:
+    r, _keep = make_robot(robot)
+    state = np.ascontiguousarray(state, np.float32)
+    frames = np.zeros((8, 12), np.float32)
+    lib().o_fk(C.byref(r), ptr(state, _fp), ptr(frames, _fp))
+    return frames
+
+
+def camera(robot, state: np.ndarray) -> np.ndarray:
+    r, _keep = make_robot(robot)
+    state = np.ascontiguousarray(state, np.float32)
+    cam = np.zeros(12, np.float32)
+    lib().o_camera(C.byref(r), ptr(state, _fp), ptr(cam, _fp))
+    return cam
