@@ -1,0 +1,140 @@
+"""Throughput of the batched kinematic step on one MI355X.
+
+Default workload: 1024 environments of procedural apartments with 20k-80k
+triangles each, 128x128 24-bit depth, 65 collision spheres, 8 object boxes
+(the paper-scale plain step).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
+    """The CPU oracle, as is, on a bounded sample of the same workload."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    from paper_2306_07552_amd import scenegen as sg
+    threads = max(1, min(16, os.cpu_count() or 1))
+    envs = list(range(min(sample_envs, scenes.num_envs)))
+    # per-env oracle objects, built in parallel (setup, not timed)
+    with ThreadPoolExecutor(threads) as ex:
+        obs = list(ex.map(lambda e: O.OracleBatch(robot, scenes, consts, envs=[e]), envs))
+    t0 = time.perf_counter()
+    done = 0
+    k = 0
+    with ThreadPoolExecutor(threads) as ex:
+        while time.perf_counter() - t0 < seconds:
+            a = sg.actions(cfg, k)
+            list(ex.map(lambda i: obs[i].step(a[envs[i]:envs[i] + 1]), range(len(envs))))
+            done += len(envs)
+            k += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"{len(envs)} envs of the same workload x {k} steps ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
+                          "environment with no communication, and only the 1-GPU figure is "
+                          "measured", "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_07552_amd import gal, scenegen as sg
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    cfg = sg.CONFIGS[args.config]
+    t = time.perf_counter()
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    log(f"scenes: {scenes.num_envs} envs, {int(scenes.tri_offset[-1])} triangles "
+        f"({time.perf_counter() - t:.1f} s)")
+    t = time.perf_counter()
+    b = gal.Batch(robot, scenes, consts, color=cfg.color)
+    log(f"gal_create_batch: {time.perf_counter() - t:.1f} s, mesh {b.mesh_info()}")
+    N = b.num_envs
+    out = b.alloc_outputs()
+    stream = torch.cuda.current_stream()
+
+    # actions for every step, resident in HBM before timing
+    g = torch.Generator(device="cuda")
+    g.manual_seed(cfg.seed)
+    lim = torch.tensor([cfg.act_lim[0], cfg.act_lim[1]] + [cfg.act_lim[2]] * 7,
+                       dtype=torch.float32, device="cuda")
+    total = args.warmup + args.steps
+    acts = (torch.rand((total, N, 9), generator=g, device="cuda") * 2 - 1) * lim
+
+    for k in range(args.warmup):
+        b.step(acts[k], out)
+    torch.cuda.synchronize()
+
+    b.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.warmup, total):
+        b.step(acts[k], out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    b.profile(False)
+    robot_ms, raster_ms, nsteps = b.profile_read()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    value = N * args.steps / (gpu_ms / 1e3)
+    log(f"timed {args.steps} steps: {gpu_ms:.2f} ms device, {wall * 1e3:.2f} ms wall; "
+        f"robot {robot_ms / nsteps:.4f} ms, raster {raster_ms / nsteps:.4f} ms per step")
+
+    mi = b.mesh_info()
+    raster_bytes = mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4 + 4 * b.depth_pixels
+    raster_s = raster_ms / nsteps / 1e3
+    achieved = raster_bytes / raster_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_raster", "algorithmic_bytes_per_launch": int(raster_bytes),
+                "avg_launch_ms": round(raster_ms / nsteps, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(cfg, robot, scenes, consts)
+
+    res = {"metric": "env-steps/sec @1024 envs, 128x128 depth (plain step)",
+           "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
+           "config": {"workload": cfg.name, "envs": N, "res": int(cfg.res0),
+                      "tris_total": int(scenes.tri_offset[-1]), "spheres": robot.num_spheres,
+                      "objects": cfg.num_objects, "episode_len": cfg.episode_len,
+                      "path": "plain"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

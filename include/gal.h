@@ -1,0 +1,235 @@
+/*
+ * gal.h -- C ABI of the MI355X batched kinematic simulator step.
+ *
+ * One batch object steps every environment at once, the way the paper's
+ * single simulator instance steps physics for a whole batch of environments
+ * and a single renderer produces one stacked image per sensor in GPU memory
+ * that the learner consumes in place (Galactic, Section 3.1 "Batch
+ * Simulation").  The step itself follows Section 3.2 "Approximate Kinematic
+ * Simulation" and Appendix G: action offsets applied directly to the robot
+ * state, forward kinematics of the articulated links, sphere-proxy overlap
+ * tests against a static-scene column grid (one grid per sphere-radius
+ * class) and against the movable objects' oriented boxes, a collision
+ * resolved by disallowing all robot movement for the step, and a head-camera
+ * depth observation (Section 4.1: 90 degree FoV).
+ *
+ * Conventions
+ *  - Every function returns an int status: GAL_OK (0) or a negative GAL_E*
+ *    code; the message of the last failure on the calling thread is returned
+ *    by gal_last_error().  Nothing is thrown across the ABI.
+ *  - "host" pointers are ordinary CPU memory read during the call only;
+ *    "device" pointers are HIP device memory owned by the caller (for
+ *    example torch tensors on cuda:0) and must stay valid until the work
+ *    enqueued on `stream` has finished.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    gal_step / gal_reset only enqueue work on it: they never synchronise
+ *    the device and never copy to the host.
+ *  - Coordinates are metres, Z-up, right-handed; angles are radians.
+ *  - All floating point is IEEE binary32 evaluated in a fixed order with
+ *    round-to-nearest-even, so results are reproducible bit for bit.
+ */
+#ifndef GAL_H
+#define GAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GAL_OK 0
+#define GAL_EINVAL (-1)    /* bad argument or configuration                    */
+#define GAL_ENOMEM (-2)    /* device or host allocation failed                 */
+#define GAL_EDEVICE (-3)   /* a HIP call failed (its text is in gal_last_error) */
+#define GAL_ESTATE (-4)    /* state buffer size / layout mismatch              */
+#define GAL_EOVERFLOW (-5) /* a fixed-capacity structure overflowed at build   */
+
+#define GAL_MAX_CLASSES 8
+#define GAL_MAX_SPHERES 256
+#define GAL_STATE_FLOATS 10 /* x, y, yaw, q0..q6 */
+
+/* flags of gal_config.flags */
+#define GAL_COLOR 0x1u      /* also produce flat-shaded RGB8 per pixel         */
+
+/*
+ * Robot (Section 3.2 / Appendix G): a planar base (x, y, yaw) and a 7-DoF
+ * revolute arm.  Link frame 0 is the base; link frame j+1 = (link frame j,
+ * or for j = 0 the base frame translated by `mount`) * Rz(q_j) Tz(d_j)
+ * Tx(a_j) Rx(alpha_j) (standard Denavit-Hartenberg).  alpha_j is given by its
+ * cosine and sine.  Each link is proxied by spheres whose radius is one of
+ * the configured radius classes; a sphere flagged held-only exists only in
+ * environments whose `held` flag is set (a grasped-object proxy carried on
+ * the end effector).  Host memory, copied at gal_create_batch.
+ */
+typedef struct gal_robot {
+    float dh[7][4];             /* a, d, cos(alpha), sin(alpha)              */
+    float qlim[7][2];           /* joint limits lo, hi                       */
+    float q_home[7];            /* joint angles at episode start             */
+    float mount[3];             /* arm mount in the base frame               */
+    float cam_offset[3];        /* head camera position in the base frame    */
+    float cam_pitch_cs[2];      /* cos, sin of the camera's downward pitch   */
+    int32_t num_spheres;        /* S, 1..GAL_MAX_SPHERES                     */
+    const int32_t *sphere_link; /* [S] link frame 0..7                       */
+    const float *sphere_pos;    /* [S][3] centre in the link frame           */
+    const int32_t *sphere_class;/* [S] radius class index                    */
+    const uint8_t *sphere_held_only; /* [S] or NULL (none held-only)         */
+} gal_robot;
+
+/*
+ * Scenes, one per environment, as concatenated host arrays indexed by
+ * per-env offsets (CSR).  Copied to the device at gal_create_batch.
+ *  - Render mesh: triangles of env-local vertex indices, wound
+ *    counter-clockwise around the outward normal (back faces are culled).
+ *  - Static collision boxes (axis-aligned, min xyz / max xyz) build the
+ *    column grids; the floor z <= 0 is implicit.  Movable objects are not
+ *    part of the grid: they are oriented boxes (yaw only).
+ *  - The column grid of env e covers nx * ny square cells of `cell_m` from
+ *    `grid_origin`; a sphere centre outside it is in contact.
+ */
+typedef struct gal_scene_set {
+    int32_t num_envs;           /* N >= 1                                    */
+    const int64_t *vert_offset; /* [N+1]                                     */
+    const float *verts;         /* [V][3]                                    */
+    const int64_t *tri_offset;  /* [N+1]                                     */
+    const int32_t *tris;        /* [T][3] env-local vertex indices           */
+    const uint8_t *tri_rgb;     /* [T][3] flat colour, or NULL               */
+    const int64_t *box_offset;  /* [N+1]                                     */
+    const float *boxes;         /* [B][6] min x,y,z, max x,y,z               */
+    int32_t num_objects;        /* O per env, 0..64                          */
+    const float *objects;       /* [N][O][8] centre xyz, half extents xyz,
+                                   cos(yaw), sin(yaw)                        */
+    const float *grid_origin;   /* [N][2]                                    */
+    const int32_t *grid_dims;   /* [N][2] nx, ny                             */
+    int32_t num_starts;         /* P >= 1 start poses per env                */
+    const float *starts;        /* [N][P][3] x, y, yaw                       */
+    const uint8_t *held;        /* [N] or NULL (no env holds an object)      */
+    const int32_t *res;         /* [N] square depth resolution per env, or
+                                   NULL for res0 everywhere; 8..256, a
+                                   multiple of 8                             */
+} gal_scene_set;
+
+typedef struct gal_config {
+    int32_t res0;               /* depth resolution when scenes->res is NULL */
+    float near_m, far_m;        /* depth range; the field of view is 90 deg  */
+    float cell_m;               /* column-grid cell size                     */
+    int32_t num_classes;        /* K, 1..GAL_MAX_CLASSES                     */
+    float class_radius[GAL_MAX_CLASSES];
+    float act_lim[3];           /* |forward| m, |yaw| rad, |joint delta| rad */
+    int32_t episode_len;        /* steps per episode; 0 = never auto-reset   */
+    uint32_t flags;             /* GAL_COLOR                                 */
+} gal_config;
+
+/*
+ * Caller-owned device outputs of one step.  Per-env images are packed one
+ * after the other (env e starts at gal_depth_offsets()[e] pixels); depth is
+ * the 24-bit value floor((1/near - 1/z) * (2^24-1) / (1/near - 1/far)) of
+ * the nearest surface's camera-space distance z, 0xFFFFFF where nothing was
+ * hit.  Any pointer except `depth` may be NULL to skip that output.
+ */
+typedef struct gal_outputs {
+    uint32_t *depth;            /* [sum res^2]                               */
+    uint8_t *rgb;               /* [sum res^2][3] (needs GAL_COLOR)          */
+    uint32_t *contact_static;   /* [N][W], W = ceil(S/32): bit s of word s/32
+                                   = sphere s of the candidate pose overlaps
+                                   the static scene (column grid)            */
+    uint32_t *contact_object;   /* [N][W]: ... overlaps a movable object     */
+    uint8_t *accepted;          /* [N] 1 = the move was committed            */
+    float *state;               /* [N][10] state after the step              */
+    float *frames;              /* [N][8][12] link frames (3x4 row-major)    */
+    int32_t *counters;          /* [N][2] step in episode, episode index     */
+    uint8_t *done;              /* [N] 1 = the episode ended at this step    */
+} gal_outputs;
+
+typedef struct gal_batch gal_batch;   /* opaque, owned by the library */
+
+/*
+ * Create a batch: validates the inputs, copies robot and scenes to the
+ * device, builds the column grids (one per env and radius class) and the
+ * clustered render meshes, and sets every env to episode 0 at its first
+ * start pose with the arm at q_home.  Synchronous (returns when done).
+ * Errors: GAL_EINVAL (inconsistent sizes, res not a multiple of 8 or out of
+ * range, S or K out of range, near/far invalid), GAL_ENOMEM, GAL_EDEVICE,
+ * GAL_EOVERFLOW (a grid column blocked by more than 64 boxes).
+ */
+int gal_create_batch(const gal_config *cfg, const gal_robot *robot,
+                     const gal_scene_set *scenes, void *stream, gal_batch **out);
+
+/*
+ * Start a new episode in the envs selected by `env_mask_dev` (device u8[N],
+ * nonzero = reset; NULL = all envs): episode += 1, pose = start pose
+ * (episode mod P), arm at q_home, step counter 0.  Asynchronous on `stream`.
+ */
+int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
+
+/*
+ * One step of every environment (asynchronous on `stream`):
+ *  1. actions_dev f32 [N][9] = forward offset (m), yaw offset (rad), 7 joint
+ *     offsets (rad); NaN components count as 0, then each is clamped to
+ *     +-act_lim.  Candidate: yaw' = yaw + a1 wrapped into [-pi, pi]; x, y move
+ *     a0 along the new heading; q' = clamp(q + a, qlim).
+ *  2. forward kinematics of the candidate; every active sphere is tested
+ *     against its class's column grid and every object box;
+ *  3. any overlap rejects the whole move (state unchanged), otherwise the
+ *     candidate is committed;
+ *  4. the step counter advances; at episode_len the env auto-resets
+ *     (gal_reset semantics) and `done` is set;
+ *  5. frames and the depth (and colour) image are produced for the final
+ *     state.
+ * Errors: GAL_EINVAL (NULL batch/actions/depth, rgb without GAL_COLOR),
+ * GAL_EDEVICE (launch failure).
+ */
+int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream);
+
+/* Number of environments, spheres, contact words, and the packed depth size. */
+int gal_batch_info(const gal_batch *b, int32_t *num_envs, int32_t *num_spheres,
+                   int32_t *contact_words, int64_t *depth_pixels);
+
+/* Host copy of the per-env pixel offsets of the packed depth output, [N+1]. */
+int gal_depth_offsets(const gal_batch *b, int64_t *offsets_host, size_t count);
+
+/*
+ * Checkpoint / restore of the simulation state (synchronises `stream`):
+ * host buffer of N * (10 floats + 2 int32) bytes, laid out as f32 state
+ * [N][10] followed by i32 counters [N][2].  GAL_ESTATE when `bytes` differs.
+ */
+int gal_get_state(gal_batch *b, void *host, size_t bytes, void *stream);
+int gal_set_state(gal_batch *b, const void *host, size_t bytes, void *stream);
+
+/*
+ * Inspection of the column grid built on the device for env `env` and
+ * radius class `cls` (synchronous): the layer count of every column as CSR
+ * offsets (host u32 [nx*ny+1]) and the free layers (host f32 [L][2] = lowest
+ * and highest admissible sphere-centre height; the top one ends at +inf).
+ * Pass layers_host = NULL to query L through *num_layers.
+ */
+int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
+                 size_t offsets_count, float *layers_host, size_t layers_count,
+                 int64_t *num_layers);
+
+/*
+ * Per-kernel timing of gal_step with HIP events recorded on the step's own
+ * stream.  While enabled, every gal_step records an event before, between
+ * and after its kernels (robot step, raster); gal_profile_read waits for the
+ * recorded events, returns the summed milliseconds of each kernel and the
+ * number of timed steps, and clears the record.  Adds no synchronisation to
+ * gal_step itself.
+ */
+int gal_profile_enable(gal_batch *b, int on);
+int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps);
+
+/* Sizes of the device-resident render mesh: 64-triangle clusters, their
+ * (per-cluster unique) vertices, and triangles. */
+int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
+                  int64_t *tris);
+
+void gal_destroy(gal_batch *b);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *gal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAL_H */

@@ -601,7 +601,9 @@ O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, co
         }
         /* Sutherland-Hodgman: planes near, left, right, top, bottom */
         local.clipped += 1;
-        o_cv poly[16], tmp[16];
+        /* a convex triangle clipped by 5 planes has at most 3 + 5 = 8 vertices;
+           should rounding ever emit more, the extra vertices are dropped */
+        o_cv poly[8], tmp[8];
         int n = 3;
         memcpy(poly, v, sizeof(v));
         for (int k = 0; k < 5 && n > 0; ++k) {
@@ -612,10 +614,10 @@ O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, co
                 int cin = plane_value(cur, k, near_m) >= 0.0f;
                 int pin = plane_value(prv, k, near_m) >= 0.0f;
                 if (cin) {
-                    if (!pin) tmp[m++] = intersect(prv, cur, k, near_m);
-                    tmp[m++] = *cur;
+                    if (!pin && m < 8) tmp[m++] = intersect(prv, cur, k, near_m);
+                    if (m < 8) tmp[m++] = *cur;
                 } else if (pin) {
-                    tmp[m++] = intersect(prv, cur, k, near_m);
+                    if (m < 8) tmp[m++] = intersect(prv, cur, k, near_m);
                 }
             }
             n = m;

@@ -1,0 +1,679 @@
+// Host runtime of the C ABI declared in include/gal.h: validation, device
+// buffers, render-cluster construction, column-grid construction (on the
+// device) and the asynchronous step / reset launches.
+#include "gal.h"
+#include "gal_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(GAL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+struct DevAlloc {
+    std::vector<void *> ptrs;
+    ~DevAlloc()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    int alloc(T **out, size_t count)
+    {
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess)
+            return fail(GAL_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        ptrs.push_back(p);
+        *out = static_cast<T *>(p);
+        return GAL_OK;
+    }
+};
+
+// Clusters of one env: <= 64 consecutive triangles using <= 64 unique vertices.
+struct EnvClusters {
+    std::vector<float> cl;        // [C][12] words (see RenderMesh), bases relative to env
+    std::vector<float> verts;     // [Vc][3]
+    std::vector<uint32_t> tris;   // [T]
+    int bad = 0;
+};
+
+void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
+                        EnvClusters &out)
+{
+    std::vector<int64_t> mark(std::max<int64_t>(nverts, 1), -1);
+    std::vector<int32_t> lidx(std::max<int64_t>(nverts, 1), 0);
+    out.tris.reserve(ntris);
+    out.verts.reserve(ntris * 3 / 2 + 64);
+    int64_t cid = 0;
+    int nv = 0, nt = 0;
+    int64_t vstart = 0, tstart = 0;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    auto close = [&]() {
+        if (nt == 0) return;
+        float w[12];
+        uint32_t vb = (uint32_t)vstart, tb = (uint32_t)tstart, cnt = (uint32_t)nv | ((uint32_t)nt << 8);
+        uint32_t first = (uint32_t)tstart, zero = 0;
+        w[0] = lo[0]; w[1] = lo[1]; w[2] = lo[2]; memcpy(&w[3], &vb, 4);
+        w[4] = hi[0]; w[5] = hi[1]; w[6] = hi[2]; memcpy(&w[7], &tb, 4);
+        memcpy(&w[8], &cnt, 4); memcpy(&w[9], &first, 4); memcpy(&w[10], &zero, 4);
+        memcpy(&w[11], &zero, 4);
+        out.cl.insert(out.cl.end(), w, w + 12);
+        ++cid;
+        nv = nt = 0;
+        vstart = (int64_t)out.verts.size() / 3;
+        tstart = (int64_t)out.tris.size();
+        for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    };
+    for (int64_t t = 0; t < ntris; ++t) {
+        int32_t v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+        for (int k = 0; k < 3; ++k)
+            if (v[k] < 0 || v[k] >= nverts) { out.bad = 1; return; }
+        int fresh = 0;
+        for (int k = 0; k < 3; ++k) {
+            bool seen = mark[v[k]] == cid;
+            for (int q = 0; q < k; ++q) seen = seen || v[q] == v[k];
+            fresh += seen ? 0 : 1;
+        }
+        if (nt == gal::kClusterTris || nv + fresh > gal::kClusterVerts) close();
+        uint32_t packed = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (mark[v[k]] != cid) {
+                mark[v[k]] = cid;
+                lidx[v[k]] = nv++;
+                const float *p = verts + 3 * (int64_t)v[k];
+                out.verts.insert(out.verts.end(), p, p + 3);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], p[a]);
+                    hi[a] = std::max(hi[a], p[a]);
+                }
+            }
+            packed |= (uint32_t)lidx[v[k]] << (8 * k);
+        }
+        out.tris.push_back(packed);
+        ++nt;
+    }
+    close();
+}
+
+template <class F>
+void parallel_for(int64_t n, F &&f)
+{
+    unsigned hc = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> th;
+    for (unsigned i = 0; i < hc; ++i)
+        th.emplace_back([&]() {
+            for (;;) {
+                int64_t k = next.fetch_add(1);
+                if (k >= n) break;
+                f(k);
+            }
+        });
+    for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+struct gal_batch {
+    DevAlloc mem;
+    int32_t N = 0, S = 0, K = 0, O = 0, P = 0, words = 0;
+    uint32_t flags = 0;
+    gal::RobotParams rp{};
+    gal::SimBuffers sb{};
+    gal::RenderMesh mesh{};
+    gal::RasterParams rast{};
+    std::vector<int64_t> depth_off_host;   // [N+1]
+    std::vector<int32_t> res_host;
+    std::vector<gal::GridMeta> meta_host;
+    std::vector<uint64_t> off_base_host, layer_base_host;
+    int32_t *d_res = nullptr;
+    uint64_t *d_depth_off = nullptr;
+    uint32_t *d_work = nullptr;
+    int32_t num_work = 0;
+    int64_t n_clusters = 0, n_cverts = 0, n_tris = 0;
+    // per-kernel timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;     // free events
+    std::vector<hipEvent_t> ev_rec;      // recorded triples (start, mid, end)
+    ~gal_batch()
+    {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_rec) (void)hipEventDestroy(e);
+    }
+    hipEvent_t take_event()
+    {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+extern "C" {
+
+const char *gal_last_error(void) { return g_last_error.c_str(); }
+
+int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_scene_set *sc,
+                     void *stream, gal_batch **out)
+{
+    g_last_error.clear();
+    if (!cfg || !robot || !sc || !out) return fail(GAL_EINVAL, "null argument");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    const int N = sc->num_envs;
+    if (N < 1 || N > (1 << 20)) return fail(GAL_EINVAL, "num_envs %d out of range", N);
+    if (cfg->num_classes < 1 || cfg->num_classes > GAL_MAX_CLASSES)
+        return fail(GAL_EINVAL, "num_classes %d out of range", cfg->num_classes);
+    if (robot->num_spheres < 1 || robot->num_spheres > GAL_MAX_SPHERES)
+        return fail(GAL_EINVAL, "num_spheres %d out of range", robot->num_spheres);
+    if (!(cfg->near_m > 0.0f) || !(cfg->far_m > cfg->near_m))
+        return fail(GAL_EINVAL, "need 0 < near < far");
+    if (!(cfg->cell_m > 0.0f)) return fail(GAL_EINVAL, "cell_m must be positive");
+    if (sc->num_objects < 0 || sc->num_objects > gal::kMaxObjects)
+        return fail(GAL_EINVAL, "num_objects %d out of range", sc->num_objects);
+    if (sc->num_starts < 1) return fail(GAL_EINVAL, "need at least one start pose");
+    if (cfg->episode_len < 0) return fail(GAL_EINVAL, "episode_len must be >= 0");
+    if (!sc->vert_offset || !sc->verts || !sc->tri_offset || !sc->tris || !sc->box_offset ||
+        !sc->grid_origin || !sc->grid_dims || !sc->starts || (sc->num_objects > 0 && !sc->objects))
+        return fail(GAL_EINVAL, "missing scene array");
+    if (!robot->sphere_link || !robot->sphere_pos || !robot->sphere_class)
+        return fail(GAL_EINVAL, "missing sphere array");
+    if ((cfg->flags & GAL_COLOR) && !sc->tri_rgb)
+        return fail(GAL_EINVAL, "GAL_COLOR needs tri_rgb");
+    for (int i = 0; i < robot->num_spheres; ++i) {
+        if (robot->sphere_link[i] < 0 || robot->sphere_link[i] > 7)
+            return fail(GAL_EINVAL, "sphere %d: link out of range", i);
+        if (robot->sphere_class[i] < 0 || robot->sphere_class[i] >= cfg->num_classes)
+            return fail(GAL_EINVAL, "sphere %d: class out of range", i);
+    }
+    for (int k = 0; k < cfg->num_classes; ++k)
+        if (!(cfg->class_radius[k] > 0.0f)) return fail(GAL_EINVAL, "class radius must be > 0");
+
+    gal_batch *b = new gal_batch();
+    auto cleanup = [&](int code) {
+        delete b;
+        return code;
+    };
+    b->N = N;
+    b->S = robot->num_spheres;
+    b->K = cfg->num_classes;
+    b->O = sc->num_objects;
+    b->P = sc->num_starts;
+    b->words = (b->S + 31) / 32;
+    b->flags = cfg->flags;
+
+    // ---- per-env resolution, depth offsets
+    b->res_host.resize(N);
+    b->depth_off_host.resize(N + 1);
+    b->depth_off_host[0] = 0;
+    for (int e = 0; e < N; ++e) {
+        int r = sc->res ? sc->res[e] : cfg->res0;
+        if (r < 8 || r > 256 || (r % 8) != 0)
+            return cleanup(fail(GAL_EINVAL, "env %d: resolution %d must be a multiple of 8 in [8, 256]", e, r));
+        if (r > gal::kMaxRegion && (r % gal::kMaxRegion) != 0)
+            return cleanup(fail(GAL_EINVAL, "env %d: resolution %d must be a multiple of %d", e, r, gal::kMaxRegion));
+        b->res_host[e] = r;
+        b->depth_off_host[e + 1] = b->depth_off_host[e] + (int64_t)r * r;
+    }
+    for (int64_t i = 0; i < sc->box_offset[N]; ++i) {
+        const float *B = sc->boxes + 6 * i;
+        for (int k = 0; k < 6; ++k)
+            if (!std::isfinite(B[k])) return cleanup(fail(GAL_EINVAL, "static box %lld: non-finite coordinate", (long long)i));
+        if (!(B[0] <= B[3] && B[1] <= B[4] && B[2] <= B[5]))
+            return cleanup(fail(GAL_EINVAL, "static box %lld: min > max", (long long)i));
+    }
+    for (int e = 0; e < N; ++e) {
+        if (sc->vert_offset[e + 1] < sc->vert_offset[e] || sc->tri_offset[e + 1] < sc->tri_offset[e] ||
+            sc->box_offset[e + 1] < sc->box_offset[e])
+            return cleanup(fail(GAL_EINVAL, "env %d: offsets not monotone", e));
+        if (sc->grid_dims[2 * e] < 1 || sc->grid_dims[2 * e + 1] < 1 ||
+            (int64_t)sc->grid_dims[2 * e] * sc->grid_dims[2 * e + 1] > (1 << 26))
+            return cleanup(fail(GAL_EINVAL, "env %d: grid dims out of range", e));
+    }
+
+    // ---- robot parameters
+    gal::RobotParams &rp = b->rp;
+    memcpy(rp.dh, robot->dh, sizeof(rp.dh));
+    memcpy(rp.qlim, robot->qlim, sizeof(rp.qlim));
+    memcpy(rp.q_home, robot->q_home, sizeof(rp.q_home));
+    memcpy(rp.mount, robot->mount, sizeof(rp.mount));
+    memcpy(rp.cam_offset, robot->cam_offset, sizeof(rp.cam_offset));
+    memcpy(rp.cam_pitch_cs, robot->cam_pitch_cs, sizeof(rp.cam_pitch_cs));
+    for (int k = 0; k < gal::kMaxClasses; ++k)
+        rp.class_radius[k] = k < cfg->num_classes ? cfg->class_radius[k] : 0.0f;
+    memcpy(rp.act_lim, cfg->act_lim, sizeof(rp.act_lim));
+    rp.num_spheres = b->S;
+    rp.num_classes = b->K;
+    rp.num_objects = b->O;
+    rp.num_starts = b->P;
+    rp.episode_len = cfg->episode_len;
+    rp.contact_words = b->words;
+
+    int rc;
+    // ---- spheres, per-env tables
+    std::vector<gal::Sphere> sph(b->S);
+    for (int i = 0; i < b->S; ++i) {
+        sph[i].px = robot->sphere_pos[3 * i];
+        sph[i].py = robot->sphere_pos[3 * i + 1];
+        sph[i].pz = robot->sphere_pos[3 * i + 2];
+        sph[i].link = robot->sphere_link[i];
+        sph[i].cls = robot->sphere_class[i];
+        sph[i].held_only = robot->sphere_held_only ? robot->sphere_held_only[i] : 0;
+    }
+    gal::Sphere *d_sph;
+    float *d_state, *d_cam, *d_starts, *d_obj;
+    int32_t *d_counters;
+    uint8_t *d_held;
+    gal::GridMeta *d_meta;
+    if ((rc = b->mem.alloc(&d_sph, b->S)) || (rc = b->mem.alloc(&d_state, (size_t)N * 10)) ||
+        (rc = b->mem.alloc(&d_cam, (size_t)N * 12)) || (rc = b->mem.alloc(&d_counters, (size_t)N * 2)) ||
+        (rc = b->mem.alloc(&d_starts, (size_t)N * b->P * 3)) ||
+        (rc = b->mem.alloc(&d_obj, (size_t)N * std::max(b->O, 1) * 8)) ||
+        (rc = b->mem.alloc(&d_held, (size_t)N)) || (rc = b->mem.alloc(&d_meta, (size_t)N)))
+        return cleanup(rc);
+    HIP_TRY(hipMemcpy(d_sph, sph.data(), sizeof(gal::Sphere) * b->S, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_starts, sc->starts, sizeof(float) * (size_t)N * b->P * 3, hipMemcpyHostToDevice));
+    if (b->O > 0)
+        HIP_TRY(hipMemcpy(d_obj, sc->objects, sizeof(float) * (size_t)N * b->O * 8, hipMemcpyHostToDevice));
+    {
+        std::vector<uint8_t> held(N, 0);
+        if (sc->held)
+            for (int e = 0; e < N; ++e) held[e] = sc->held[e] ? 1 : 0;
+        HIP_TRY(hipMemcpy(d_held, held.data(), N, hipMemcpyHostToDevice));
+    }
+    b->meta_host.resize(N);
+    int32_t max_cols = 0;
+    for (int e = 0; e < N; ++e) {
+        b->meta_host[e].x0 = sc->grid_origin[2 * e];
+        b->meta_host[e].y0 = sc->grid_origin[2 * e + 1];
+        b->meta_host[e].nx = sc->grid_dims[2 * e];
+        b->meta_host[e].ny = sc->grid_dims[2 * e + 1];
+        max_cols = std::max(max_cols, b->meta_host[e].nx * b->meta_host[e].ny);
+    }
+    HIP_TRY(hipMemcpy(d_meta, b->meta_host.data(), sizeof(gal::GridMeta) * N, hipMemcpyHostToDevice));
+
+    gal::SimBuffers &sb = b->sb;
+    sb.state = d_state;
+    sb.counters = d_counters;
+    sb.camera = d_cam;
+    sb.held = d_held;
+    sb.starts = d_starts;
+    sb.objects = d_obj;
+    sb.spheres = d_sph;
+    sb.grid_meta = d_meta;
+    sb.cell = cfg->cell_m;
+    sb.inv_cell = 1.0f / cfg->cell_m;
+    sb.num_envs = N;
+
+    // ---- column grids: count, scan, fill (on the device)
+    {
+        const int K = b->K;
+        b->off_base_host.resize((size_t)N * K);
+        uint64_t total_cols = 0;
+        for (int e = 0; e < N; ++e)
+            for (int k = 0; k < K; ++k) {
+                b->off_base_host[(size_t)e * K + k] = total_cols;
+                total_cols += (uint64_t)b->meta_host[e].nx * b->meta_host[e].ny + 1;
+            }
+        uint32_t *d_offsets;
+        uint64_t *d_off_base, *d_layer_base, *d_box_off;
+        float *d_boxes;
+        int32_t *d_overflow;
+        const int64_t nbox = sc->box_offset[N];
+        std::vector<uint64_t> box_off(N + 1);
+        for (int e = 0; e <= N; ++e) box_off[e] = (uint64_t)sc->box_offset[e];
+        if ((rc = b->mem.alloc(&d_offsets, total_cols)) || (rc = b->mem.alloc(&d_off_base, (size_t)N * K)) ||
+            (rc = b->mem.alloc(&d_layer_base, (size_t)N * K)) || (rc = b->mem.alloc(&d_box_off, (size_t)N + 1)) ||
+            (rc = b->mem.alloc(&d_boxes, (size_t)std::max<int64_t>(nbox, 1) * 6)) ||
+            (rc = b->mem.alloc(&d_overflow, 1)))
+            return cleanup(rc);
+        HIP_TRY(hipMemcpy(d_off_base, b->off_base_host.data(), sizeof(uint64_t) * N * K, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_box_off, box_off.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        if (nbox > 0)
+            HIP_TRY(hipMemcpy(d_boxes, sc->boxes, sizeof(float) * nbox * 6, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(d_overflow, 0, sizeof(int32_t)));
+        gal::ClassRadii radii{};
+        for (int k = 0; k < K; ++k) radii.r[k] = cfg->class_radius[k];
+        sb.grid_offsets = d_offsets;
+        sb.grid_off_base = d_off_base;
+        HIP_TRY(gal::launch_grid_count(sb, d_boxes, d_box_off, N, K, radii, max_cols, d_offsets,
+                                       d_overflow, s));
+        HIP_TRY(gal::launch_grid_scan(d_off_base, d_meta, N, K, d_offsets, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int32_t ovf = 0;
+        HIP_TRY(hipMemcpy(&ovf, d_overflow, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (ovf)
+            return cleanup(fail(GAL_EOVERFLOW, "a grid column is blocked by more than %d boxes",
+                                gal::kGridIvCap));
+        // totals -> layer bases
+        b->layer_base_host.resize((size_t)N * K);
+        uint64_t total_layers = 0;
+        for (size_t ek = 0; ek < (size_t)N * K; ++ek) {
+            const int e = (int)(ek / K);
+            const uint64_t ncols = (uint64_t)b->meta_host[e].nx * b->meta_host[e].ny;
+            uint32_t tot = 0;
+            HIP_TRY(hipMemcpy(&tot, d_offsets + b->off_base_host[ek] + ncols, sizeof(uint32_t),
+                              hipMemcpyDeviceToHost));
+            b->layer_base_host[ek] = total_layers;
+            total_layers += tot;
+        }
+        float2 *d_layers;
+        if ((rc = b->mem.alloc(&d_layers, (size_t)std::max<uint64_t>(total_layers, 1))))
+            return cleanup(rc);
+        HIP_TRY(hipMemcpy(d_layer_base, b->layer_base_host.data(), sizeof(uint64_t) * N * K,
+                          hipMemcpyHostToDevice));
+        sb.grid_layers = d_layers;
+        sb.grid_layer_base = d_layer_base;
+        HIP_TRY(gal::launch_grid_fill(sb, d_boxes, d_box_off, N, K, radii, max_cols, d_overflow, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+
+    // ---- render clusters (host), then upload
+    {
+        std::vector<EnvClusters> ec(N);
+        parallel_for(N, [&](int64_t e) {
+            const int64_t v0 = sc->vert_offset[e], v1 = sc->vert_offset[e + 1];
+            const int64_t t0 = sc->tri_offset[e], t1 = sc->tri_offset[e + 1];
+            build_env_clusters(sc->verts + 3 * v0, v1 - v0, sc->tris + 3 * t0, t1 - t0, ec[e]);
+        });
+        std::vector<uint64_t> cl_off(N + 1, 0), tri_off(N + 1, 0);
+        uint64_t nv_tot = 0, nt_tot = 0;
+        for (int e = 0; e < N; ++e) {
+            if (ec[e].bad) return cleanup(fail(GAL_EINVAL, "env %d: triangle index out of range", e));
+            cl_off[e + 1] = cl_off[e] + ec[e].cl.size() / 12;
+            tri_off[e + 1] = tri_off[e] + ec[e].tris.size();
+            nv_tot += ec[e].verts.size() / 3;
+            nt_tot += ec[e].tris.size();
+        }
+        if (nv_tot >= (1ull << 32) || nt_tot >= (1ull << 32))
+            return cleanup(fail(GAL_EINVAL, "scene set too large for 32-bit cluster bases"));
+        float4 *d_cl;
+        float *d_cv;
+        uint32_t *d_ct;
+        uint64_t *d_cl_off, *d_tri_off;
+        if ((rc = b->mem.alloc(&d_cl, (size_t)cl_off[N] * 3)) || (rc = b->mem.alloc(&d_cv, nv_tot * 3)) ||
+            (rc = b->mem.alloc(&d_ct, nt_tot)) || (rc = b->mem.alloc(&d_cl_off, (size_t)N + 1)) ||
+            (rc = b->mem.alloc(&d_tri_off, (size_t)N + 1)))
+            return cleanup(rc);
+        // rebase cluster vertex / triangle bases to global indices while copying
+        std::vector<uint64_t> vb(N + 1, 0);
+        for (int e = 0; e < N; ++e) vb[e + 1] = vb[e] + ec[e].verts.size() / 3;
+        std::vector<float> cl_all((size_t)cl_off[N] * 12);
+        std::vector<float> cv_all(nv_tot * 3);
+        std::vector<uint32_t> ct_all(nt_tot);
+        parallel_for(N, [&](int64_t e) {
+            EnvClusters &c = ec[e];
+            const size_t nc = c.cl.size() / 12;
+            for (size_t i = 0; i < nc; ++i) {
+                float *w = &c.cl[i * 12];
+                uint32_t v, t;
+                memcpy(&v, &w[3], 4);
+                memcpy(&t, &w[7], 4);
+                v += (uint32_t)vb[e];
+                t += (uint32_t)tri_off[e];
+                memcpy(&w[3], &v, 4);
+                memcpy(&w[7], &t, 4);
+            }
+            std::copy(c.cl.begin(), c.cl.end(), cl_all.begin() + cl_off[e] * 12);
+            std::copy(c.verts.begin(), c.verts.end(), cv_all.begin() + vb[e] * 3);
+            std::copy(c.tris.begin(), c.tris.end(), ct_all.begin() + tri_off[e]);
+            std::vector<float>().swap(c.cl);
+            std::vector<float>().swap(c.verts);
+            std::vector<uint32_t>().swap(c.tris);
+        });
+        HIP_TRY(hipMemcpy(d_cl, cl_all.data(), sizeof(float) * cl_all.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_cv, cv_all.data(), sizeof(float) * cv_all.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_ct, ct_all.data(), sizeof(uint32_t) * ct_all.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_cl_off, cl_off.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d_tri_off, tri_off.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        b->mesh.clusters = d_cl;
+        b->mesh.env_cluster_off = d_cl_off;
+        b->mesh.cverts = d_cv;
+        b->mesh.ctris = d_ct;
+        b->mesh.env_tri_off = d_tri_off;
+        b->mesh.tri_rgb = nullptr;
+        b->n_clusters = (int64_t)cl_off[N];
+        b->n_cverts = (int64_t)nv_tot;
+        b->n_tris = (int64_t)nt_tot;
+        if (cfg->flags & GAL_COLOR) {
+            uint8_t *d_rgb;
+            if ((rc = b->mem.alloc(&d_rgb, (size_t)std::max<uint64_t>(nt_tot, 1) * 3))) return cleanup(rc);
+            HIP_TRY(hipMemcpy(d_rgb, sc->tri_rgb, nt_tot * 3, hipMemcpyHostToDevice));
+            b->mesh.tri_rgb = d_rgb;
+        }
+    }
+
+    // ---- raster parameters and the (env, region) work list
+    {
+        b->rast.near_m = cfg->near_m;
+        b->rast.invn = 1.0f / cfg->near_m;
+        const float invf = 1.0f / cfg->far_m;
+        b->rast.kd = 16777215.0f / (b->rast.invn - invf);
+        b->rast.region = gal::kMaxRegion;
+        b->rast.small_max = 16;
+        std::vector<uint32_t> work;
+        // regions of one env are 8 items apart so they land on the same XCD
+        for (int e0 = 0; e0 < N; e0 += 8) {
+            int maxreg = 0;
+            for (int e = e0; e < std::min(N, e0 + 8); ++e) {
+                const int R = std::min(b->res_host[e], b->rast.region);
+                maxreg = std::max(maxreg, (b->res_host[e] / R) * (b->res_host[e] / R));
+            }
+            for (int r = 0; r < maxreg; ++r)
+                for (int e = e0; e < std::min(N, e0 + 8); ++e) {
+                    const int R = std::min(b->res_host[e], b->rast.region);
+                    const int nreg = (b->res_host[e] / R) * (b->res_host[e] / R);
+                    if (r < nreg) work.push_back((uint32_t)e | ((uint32_t)r << 20));
+                }
+        }
+        b->num_work = (int32_t)work.size();
+        if ((rc = b->mem.alloc(&b->d_work, work.size())) || (rc = b->mem.alloc(&b->d_res, (size_t)N)) ||
+            (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
+            return cleanup(rc);
+        HIP_TRY(hipMemcpy(b->d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b->d_res, b->res_host.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+        std::vector<uint64_t> doff(N + 1);
+        for (int e = 0; e <= N; ++e) doff[e] = (uint64_t)b->depth_off_host[e];
+        HIP_TRY(hipMemcpy(b->d_depth_off, doff.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+    }
+
+    // ---- initial state: episode 0 at the first start pose (reset from episode -1)
+    {
+        std::vector<int32_t> cnt((size_t)N * 2);
+        for (int e = 0; e < N; ++e) {
+            cnt[2 * e] = 0;
+            cnt[2 * e + 1] = -1;
+        }
+        HIP_TRY(hipMemcpy(d_counters, cnt.data(), sizeof(int32_t) * N * 2, hipMemcpyHostToDevice));
+        HIP_TRY(gal::launch_reset(b->rp, b->sb, nullptr, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    *out = b;
+    return GAL_OK;
+}
+
+int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    HIP_TRY(gal::launch_reset(b->rp, b->sb, env_mask_dev, (hipStream_t)stream));
+    return GAL_OK;
+}
+
+int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream)
+{
+    if (!b || !actions_dev || !out || !out->depth)
+        return fail(GAL_EINVAL, "gal_step needs a batch, actions and a depth output");
+    if (out->rgb && !(b->flags & GAL_COLOR))
+        return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
+    hipStream_t s = (hipStream_t)stream;
+    gal::StepOutputs so;
+    so.contact_static = out->contact_static;
+    so.contact_object = out->contact_object;
+    so.accepted = out->accepted;
+    so.state = out->state;
+    so.frames = out->frames;
+    so.counters = out->counters;
+    so.done = out->done;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (b->profiling) {
+        for (int i = 0; i < 3; ++i)
+            if (!(ev[i] = b->take_event())) return fail(GAL_EDEVICE, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+    HIP_TRY(gal::launch_robot_step(b->rp, b->sb, actions_dev, so, s));
+    if (b->profiling) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
+                               b->num_work, out->depth, s));
+    if (b->profiling) {
+        HIP_TRY(hipEventRecord(ev[2], s));
+        b->ev_rec.insert(b->ev_rec.end(), ev, ev + 3);
+    }
+    return GAL_OK;
+}
+
+int gal_profile_enable(gal_batch *b, int on)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    b->profiling = on != 0;
+    return GAL_OK;
+}
+
+int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    double r0 = 0.0, r1 = 0.0;
+    const size_t n = b->ev_rec.size() / 3;
+    for (size_t i = 0; i < n; ++i) {
+        hipEvent_t *e = &b->ev_rec[3 * i];
+        HIP_TRY(hipEventSynchronize(e[2]));
+        float a = 0.f, c = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, e[0], e[1]));
+        HIP_TRY(hipEventElapsedTime(&c, e[1], e[2]));
+        r0 += a;
+        r1 += c;
+    }
+    b->ev_pool.insert(b->ev_pool.end(), b->ev_rec.begin(), b->ev_rec.end());
+    b->ev_rec.clear();
+    if (robot_ms) *robot_ms = r0;
+    if (raster_ms) *raster_ms = r1;
+    if (steps) *steps = (int64_t)n;
+    return GAL_OK;
+}
+
+int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts, int64_t *tris)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    if (clusters) *clusters = b->n_clusters;
+    if (cluster_verts) *cluster_verts = b->n_cverts;
+    if (tris) *tris = b->n_tris;
+    return GAL_OK;
+}
+
+int gal_batch_info(const gal_batch *b, int32_t *num_envs, int32_t *num_spheres,
+                   int32_t *contact_words, int64_t *depth_pixels)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    if (num_envs) *num_envs = b->N;
+    if (num_spheres) *num_spheres = b->S;
+    if (contact_words) *contact_words = b->words;
+    if (depth_pixels) *depth_pixels = b->depth_off_host[b->N];
+    return GAL_OK;
+}
+
+int gal_depth_offsets(const gal_batch *b, int64_t *offsets_host, size_t count)
+{
+    if (!b || !offsets_host) return fail(GAL_EINVAL, "null argument");
+    if (count != (size_t)b->N + 1) return fail(GAL_EINVAL, "need %d offsets", b->N + 1);
+    memcpy(offsets_host, b->depth_off_host.data(), sizeof(int64_t) * (b->N + 1));
+    return GAL_OK;
+}
+
+int gal_get_state(gal_batch *b, void *host, size_t bytes, void *stream)
+{
+    if (!b || !host) return fail(GAL_EINVAL, "null argument");
+    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t));
+    if (bytes != need) return fail(GAL_ESTATE, "state buffer must be %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    char *h = static_cast<char *>(host);
+    HIP_TRY(hipMemcpy(h, b->sb.state, sizeof(float) * b->N * 10, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(h + sizeof(float) * b->N * 10, b->sb.counters, sizeof(int32_t) * b->N * 2,
+                      hipMemcpyDeviceToHost));
+    return GAL_OK;
+}
+
+int gal_set_state(gal_batch *b, const void *host, size_t bytes, void *stream)
+{
+    if (!b || !host) return fail(GAL_EINVAL, "null argument");
+    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t));
+    if (bytes != need) return fail(GAL_ESTATE, "state buffer must be %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    const char *h = static_cast<const char *>(host);
+    HIP_TRY(hipMemcpy(b->sb.state, h, sizeof(float) * b->N * 10, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->sb.counters, h + sizeof(float) * b->N * 10, sizeof(int32_t) * b->N * 2,
+                      hipMemcpyHostToDevice));
+    return GAL_OK;
+}
+
+int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
+                 size_t offsets_count, float *layers_host, size_t layers_count, int64_t *num_layers)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    if (env < 0 || env >= b->N || cls < 0 || cls >= b->K)
+        return fail(GAL_EINVAL, "env or class out of range");
+    const size_t ek = (size_t)env * b->K + cls;
+    const uint64_t ncols = (uint64_t)b->meta_host[env].nx * b->meta_host[env].ny;
+    uint32_t total = 0;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&total, b->sb.grid_offsets + b->off_base_host[ek] + ncols, sizeof(uint32_t),
+                      hipMemcpyDeviceToHost));
+    if (num_layers) *num_layers = total;
+    if (offsets_host) {
+        if (offsets_count != ncols + 1) return fail(GAL_EINVAL, "need %llu offsets", (unsigned long long)(ncols + 1));
+        HIP_TRY(hipMemcpy(offsets_host, b->sb.grid_offsets + b->off_base_host[ek],
+                          sizeof(uint32_t) * (ncols + 1), hipMemcpyDeviceToHost));
+    }
+    if (layers_host) {
+        if (layers_count != (size_t)total) return fail(GAL_EINVAL, "need %u layers", total);
+        if (total > 0)
+            HIP_TRY(hipMemcpy(layers_host, b->sb.grid_layers + b->layer_base_host[ek],
+                              sizeof(float2) * total, hipMemcpyDeviceToHost));
+    }
+    return GAL_OK;
+}
+
+void gal_destroy(gal_batch *b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal definitions shared by the library's host runtime and its HIP
+// kernels (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gal {
+
+constexpr int kMaxClasses = 8;
+constexpr int kMaxSpheres = 256;
+constexpr int kMaxObjects = 64;
+constexpr int kClusterTris = 64;    // triangles per render cluster (one per lane)
+constexpr int kClusterVerts = 64;   // unique vertices per render cluster
+constexpr int kMaxRegion = 128;     // largest square region rendered by one workgroup
+constexpr int kGridIvCap = 64;      // blocking boxes one grid column may see
+
+// Robot constants, passed by value to the step kernel.
+struct RobotParams {
+    float dh[7][4];
+    float qlim[7][2];
+    float q_home[7];
+    float mount[3];
+    float cam_offset[3];
+    float cam_pitch_cs[2];
+    float class_radius[kMaxClasses];
+    float act_lim[3];
+    int32_t num_spheres;
+    int32_t num_classes;
+    int32_t num_objects;
+    int32_t num_starts;
+    int32_t episode_len;
+    int32_t contact_words;
+};
+
+struct ClassRadii {
+    float r[kMaxClasses];
+};
+
+// One collision sphere (device table [S]).
+struct Sphere {
+    float px, py, pz;
+    int32_t link;
+    int32_t cls;
+    int32_t held_only;
+};
+
+// Per-env grid placement (device table [N]).
+struct GridMeta {
+    float x0, y0;
+    int32_t nx, ny;
+};
+
+// Device pointers of the simulation state and scene tables.
+struct SimBuffers {
+    float *state;              // [N][10]
+    int32_t *counters;         // [N][2]
+    float *camera;             // [N][12] position, right, down, forward
+    const uint8_t *held;       // [N]
+    const float *starts;       // [N][P][3]
+    const float *objects;      // [N][O][8]
+    const Sphere *spheres;     // [S]
+    const GridMeta *grid_meta; // [N]
+    const uint64_t *grid_off_base;   // [N*K] base into grid_offsets
+    const uint64_t *grid_layer_base; // [N*K] base into grid_layers
+    const uint32_t *grid_offsets;    // per (env, class): [nx*ny+1] CSR (relative)
+    const float2 *grid_layers;       // free layers (lo, hi)
+    float cell;
+    float inv_cell;
+    int32_t num_envs;
+};
+
+// Step outputs (device, caller-owned).
+struct StepOutputs {
+    uint32_t *contact_static;
+    uint32_t *contact_object;
+    uint8_t *accepted;
+    float *state;
+    float *frames;
+    int32_t *counters;
+    uint8_t *done;
+};
+
+// Render cluster: up to 64 consecutive triangles of one env and the unique
+// vertices they use.  Three float4 words:
+//   w0 = (aabb lo x, y, z, bits of vertex base)
+//   w1 = (aabb hi x, y, z, bits of triangle base)
+//   w2 = (bits of nverts | ntris << 8, bits of first triangle id, 0, 0)
+struct RenderMesh {
+    const float4 *clusters;          // [C][3]
+    const uint64_t *env_cluster_off; // [N+1]
+    const float *cverts;             // [Vc][3] cluster-local vertex positions
+    const uint32_t *ctris;           // [T] packed local indices i0 | i1<<8 | i2<<16
+    const uint8_t *tri_rgb;          // [T][3] in original order per env, or null
+    const uint64_t *env_tri_off;     // [N+1] for colour lookup
+};
+
+struct RasterParams {
+    float near_m;
+    float invn;       // 1/near
+    float kd;         // (2^24-1) / (1/near - 1/far)
+    int32_t region;   // square region edge rendered by one workgroup (<= 128)
+    int32_t small_max;// bbox pixel count rasterised by a single lane
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
+                             const StepOutputs &out, hipStream_t s);
+hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
+                        hipStream_t s);
+hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
+                         const int32_t *env_res, const uint64_t *env_depth_off,
+                         const uint32_t *work, int32_t num_work, uint32_t *depth,
+                         hipStream_t s);
+hipError_t launch_grid_count(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
+                             int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
+                             int32_t max_cols, uint32_t *counts, int32_t *overflow, hipStream_t s);
+hipError_t launch_grid_scan(const uint64_t *off_base, const GridMeta *meta, int32_t num_envs,
+                            int32_t num_classes, uint32_t *offsets, hipStream_t s);
+hipError_t launch_grid_fill(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
+                            int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
+                            int32_t max_cols, int32_t *overflow, hipStream_t s);
+
+}  // namespace gal

@@ -1,0 +1,299 @@
+// Robot step kernel: action decode, kinematic update, forward kinematics,
+// sphere-proxy collision against the column grid and the object boxes,
+// resolution, episode bookkeeping and the head-camera pose (Galactic,
+// Section 3.2 and Appendix G).  One wave64 per environment: the chain of
+// seven joint frames is evaluated redundantly by every lane (it is a short
+// serial chain), each lane owns spheres lane, lane+64, ..., and the
+// accept/reject decision is a wave ballot.
+#include "gal_internal.h"
+#include "gal_math.h"
+
+namespace gal {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+__device__ __forceinline__ float sanitize(float a, float lim)
+{
+    if (a != a) a = 0.0f;
+    return clampf(a, -lim, lim);
+}
+
+// Frame of link `link` for pose `st` (10 floats).  All eight frames are built
+// in order; the requested ones are kept by predicated copies so no register
+// array is indexed dynamically.
+struct Fk {
+    Frame f[8];
+};
+
+__device__ __forceinline__ void forward_kinematics(const RobotParams &rp, const float *st, Fk &out)
+{
+    float s, c;
+    dsincos(st[2], s, c);
+    Frame F0;
+    F0.m[0] = c;    F0.m[1] = -s;   F0.m[2] = 0.0f;  F0.m[3] = st[0];
+    F0.m[4] = s;    F0.m[5] = c;    F0.m[6] = 0.0f;  F0.m[7] = st[1];
+    F0.m[8] = 0.0f; F0.m[9] = 0.0f; F0.m[10] = 1.0f; F0.m[11] = 0.0f;
+    Frame T;
+    T.m[0] = 1.0f; T.m[1] = 0.0f; T.m[2] = 0.0f;  T.m[3] = rp.mount[0];
+    T.m[4] = 0.0f; T.m[5] = 1.0f; T.m[6] = 0.0f;  T.m[7] = rp.mount[1];
+    T.m[8] = 0.0f; T.m[9] = 0.0f; T.m[10] = 1.0f; T.m[11] = rp.mount[2];
+    out.f[0] = F0;
+    Frame prev = fmul(F0, T);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        float sq, cq;
+        dsincos(st[3 + j], sq, cq);
+        const float a = rp.dh[j][0], d = rp.dh[j][1], ca = rp.dh[j][2], sa = rp.dh[j][3];
+        Frame A;
+        A.m[0] = cq;   A.m[1] = -(sq * ca); A.m[2] = sq * sa;     A.m[3] = a * cq;
+        A.m[4] = sq;   A.m[5] = cq * ca;    A.m[6] = -(cq * sa);  A.m[7] = a * sq;
+        A.m[8] = 0.0f; A.m[9] = sa;         A.m[10] = ca;         A.m[11] = d;
+        prev = fmul(prev, A);
+        out.f[j + 1] = prev;
+    }
+}
+
+__device__ __forceinline__ Frame pick(const Fk &fk, int link)
+{
+    Frame r = fk.f[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j)
+        if (link == j) r = fk.f[j];
+    return r;
+}
+
+__device__ __forceinline__ bool grid_contact(const SimBuffers &sb, const GridMeta &gm,
+                                             uint64_t off_base, uint64_t layer_base,
+                                             float x, float y, float z)
+{
+    float fx = (x - gm.x0) * sb.inv_cell;
+    float fy = (y - gm.y0) * sb.inv_cell;
+    if (!(fx >= 0.0f && fx < (float)gm.nx)) return true;
+    if (!(fy >= 0.0f && fy < (float)gm.ny)) return true;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    uint64_t col = (uint64_t)j * (uint64_t)gm.nx + (uint64_t)i;
+    const uint32_t *off = sb.grid_offsets + off_base + col;
+    uint32_t l0 = off[0], l1 = off[1];
+    const float2 *lay = sb.grid_layers + layer_base;
+    for (uint32_t l = l0; l < l1; ++l) {
+        float2 L = lay[l];
+        if (L.x <= z && z <= L.y) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool obb_contact(const float *o, float x, float y, float z, float r)
+{
+    float dx = x - o[0], dy = y - o[1], dz = z - o[2];
+    float cps = o[6], sps = o[7];
+    float l0 = cps * dx + sps * dy;
+    float l1 = cps * dy - sps * dx;
+    float l2 = dz;
+    float q0 = clampf(l0, -o[3], o[3]);
+    float q1 = clampf(l1, -o[4], o[4]);
+    float q2 = clampf(l2, -o[5], o[5]);
+    float d0 = l0 - q0, d1 = l1 - q1, d2 = l2 - q2;
+    float dd = (d0 * d0 + d1 * d1) + d2 * d2;
+    return dd < r * r;
+}
+
+__device__ __forceinline__ void load_start(const RobotParams &rp, const SimBuffers &sb, int env,
+                                           int episode, float *st)
+{
+    int p = episode % rp.num_starts;
+    const float *s0 = sb.starts + ((size_t)env * rp.num_starts + p) * 3;
+    st[0] = s0[0];
+    st[1] = s0[1];
+    st[2] = s0[2];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) st[3 + j] = rp.q_home[j];
+}
+
+__device__ __forceinline__ void write_camera(const RobotParams &rp, const Frame &F0, float *cam)
+{
+    const float cp = rp.cam_pitch_cs[0], sp = rp.cam_pitch_cs[1];
+    fpoint(F0, rp.cam_offset[0], rp.cam_offset[1], rp.cam_offset[2], cam[0], cam[1], cam[2]);
+    fvec(F0, 0.0f, -1.0f, 0.0f, cam[3], cam[4], cam[5]);
+    fvec(F0, -sp, 0.0f, -cp, cam[6], cam[7], cam[8]);
+    fvec(F0, cp, 0.0f, -sp, cam[9], cam[10], cam[11]);
+}
+
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
+    RobotParams rp, SimBuffers sb, const float *__restrict__ actions, StepOutputs out)
+{
+    const int lane = threadIdx.x & 63;
+    const int env = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (env >= sb.num_envs) return;
+
+    float st[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) st[k] = sb.state[(size_t)env * 10 + k];
+    int t = sb.counters[(size_t)env * 2 + 0];
+    int episode = sb.counters[(size_t)env * 2 + 1];
+    const float *act = actions + (size_t)env * 9;
+
+    // 1. kinematic update: offsets applied directly to the state
+    float cand[10];
+    {
+        float a0 = sanitize(act[0], rp.act_lim[0]);
+        float a1 = sanitize(act[1], rp.act_lim[1]);
+        const float pi_f = 0x1.921fb6p+1f, two_pi_f = 0x1.921fb6p+2f;
+        float yaw = st[2] + a1;
+        if (yaw > pi_f) yaw = yaw - two_pi_f;
+        else if (yaw < -pi_f) yaw = yaw + two_pi_f;
+        float sy, cy;
+        dsincos(yaw, sy, cy);
+        cand[0] = st[0] + a0 * cy;
+        cand[1] = st[1] + a0 * sy;
+        cand[2] = yaw;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            float aj = sanitize(act[2 + j], rp.act_lim[2]);
+            cand[3 + j] = clampf(st[3 + j] + aj, rp.qlim[j][0], rp.qlim[j][1]);
+        }
+    }
+
+    // 2. forward kinematics of the candidate, sphere tests
+    Fk fk;
+    forward_kinematics(rp, cand, fk);
+    const GridMeta gm = sb.grid_meta[env];
+    const bool held = sb.held ? (sb.held[env] != 0) : false;
+    const float *objs = sb.objects + (size_t)env * rp.num_objects * 8;
+    bool any = false;
+    for (int base = 0; base < rp.num_spheres; base += 64) {
+        const int s = base + lane;
+        bool hit_static = false, hit_object = false;
+        if (s < rp.num_spheres) {
+            const Sphere sp = sb.spheres[s];
+            if (!(sp.held_only && !held)) {
+                Frame F = pick(fk, sp.link);
+                float cx, cy, cz;
+                fpoint(F, sp.px, sp.py, sp.pz, cx, cy, cz);
+                const float r = rp.class_radius[sp.cls];
+                const size_t gk = (size_t)env * rp.num_classes + sp.cls;
+                hit_static = grid_contact(sb, gm, sb.grid_off_base[gk], sb.grid_layer_base[gk],
+                                          cx, cy, cz);
+                for (int o = 0; o < rp.num_objects; ++o) {
+                    if (obb_contact(objs + 8 * o, cx, cy, cz, r)) {
+                        hit_object = true;
+                        break;
+                    }
+                }
+            }
+        }
+        const uint64_t ms = __ballot(hit_static);
+        const uint64_t mo = __ballot(hit_object);
+        any = any || (ms | mo) != 0;
+        if (lane == 0) {
+            const int w = base >> 5;
+            if (out.contact_static) {
+                uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
+                if (w < rp.contact_words) cs[w] = (uint32_t)ms;
+                if (w + 1 < rp.contact_words) cs[w + 1] = (uint32_t)(ms >> 32);
+            }
+            if (out.contact_object) {
+                uint32_t *co = out.contact_object + (size_t)env * rp.contact_words;
+                if (w < rp.contact_words) co[w] = (uint32_t)mo;
+                if (w + 1 < rp.contact_words) co[w + 1] = (uint32_t)(mo >> 32);
+            }
+        }
+    }
+
+    // 3. resolve: any overlap rejects the whole move
+    const bool accepted = !any;
+    if (accepted) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) st[k] = cand[k];
+    }
+
+    // 4. episode bookkeeping (auto-reset at the horizon)
+    bool done = false;
+    t += 1;
+    if (rp.episode_len > 0 && t >= rp.episode_len) {
+        episode += 1;
+        load_start(rp, sb, env, episode, st);
+        t = 0;
+        done = true;
+    }
+
+    // 5. frames and camera of the final state
+    if (!accepted || done) forward_kinematics(rp, st, fk);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sb.state[(size_t)env * 10 + k] = st[k];
+        sb.counters[(size_t)env * 2 + 0] = t;
+        sb.counters[(size_t)env * 2 + 1] = episode;
+        float cam[12];
+        write_camera(rp, fk.f[0], cam);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sb.camera[(size_t)env * 12 + k] = cam[k];
+        if (out.state) {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) out.state[(size_t)env * 10 + k] = st[k];
+        }
+        if (out.counters) {
+            out.counters[(size_t)env * 2 + 0] = t;
+            out.counters[(size_t)env * 2 + 1] = episode;
+        }
+        if (out.accepted) out.accepted[env] = accepted ? 1 : 0;
+        if (out.done) out.done[env] = done ? 1 : 0;
+    }
+    if (out.frames && lane < 8) {
+        Frame F = pick(fk, lane);
+        float *dst = out.frames + ((size_t)env * 8 + lane) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+    }
+}
+
+// New episode for the selected envs (mask null = all): episode += 1, start
+// pose of that episode, arm at home, step counter 0; camera refreshed.
+__global__ void k_reset(RobotParams rp, SimBuffers sb, const uint8_t *__restrict__ mask)
+{
+    const int env = blockIdx.x * blockDim.x + threadIdx.x;
+    if (env >= sb.num_envs) return;
+    if (mask && !mask[env]) return;
+    int episode = sb.counters[(size_t)env * 2 + 1] + 1;
+    float st[10];
+    load_start(rp, sb, env, episode, st);
+    for (int k = 0; k < 10; ++k) sb.state[(size_t)env * 10 + k] = st[k];
+    sb.counters[(size_t)env * 2 + 0] = 0;
+    sb.counters[(size_t)env * 2 + 1] = episode;
+    float s, c;
+    dsincos(st[2], s, c);
+    Frame F0;
+    F0.m[0] = c;    F0.m[1] = -s;   F0.m[2] = 0.0f;  F0.m[3] = st[0];
+    F0.m[4] = s;    F0.m[5] = c;    F0.m[6] = 0.0f;  F0.m[7] = st[1];
+    F0.m[8] = 0.0f; F0.m[9] = 0.0f; F0.m[10] = 1.0f; F0.m[11] = 0.0f;
+    float cam[12];
+    write_camera(rp, F0, cam);
+    for (int k = 0; k < 12; ++k) sb.camera[(size_t)env * 12 + k] = cam[k];
+}
+
+}  // namespace
+
+hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
+                             const StepOutputs &out, hipStream_t s)
+{
+    const int blocks = (sb.num_envs + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_robot_step, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, rp, sb,
+                       actions, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
+                        hipStream_t s)
+{
+    const int blocks = (sb.num_envs + 255) / 256;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, rp, sb, mask);
+    return hipGetLastError();
+}
+
+}  // namespace gal

@@ -1,0 +1,269 @@
+"""Python binding of libgal.so (the C ABI in include/gal.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the ABI.  PyTorch provides device memory (tensors) and the
+stream.  If the library has not been built, loading fails loudly; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgal.so")
+
+GAL_OK = 0
+GAL_COLOR = 0x1
+ERRORS = {-1: "GAL_EINVAL", -2: "GAL_ENOMEM", -3: "GAL_EDEVICE", -4: "GAL_ESTATE",
+          -5: "GAL_EOVERFLOW"}
+
+_fp = C.POINTER(C.c_float)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u8p = C.POINTER(C.c_uint8)
+_u32p = C.POINTER(C.c_uint32)
+
+
+class GalRobot(C.Structure):
+    _fields_ = [("dh", C.c_float * 28), ("qlim", C.c_float * 14), ("q_home", C.c_float * 7),
+                ("mount", C.c_float * 3), ("cam_offset", C.c_float * 3),
+                ("cam_pitch_cs", C.c_float * 2), ("num_spheres", C.c_int32),
+                ("sphere_link", _i32p), ("sphere_pos", _fp), ("sphere_class", _i32p),
+                ("sphere_held_only", _u8p)]
+
+
+class GalSceneSet(C.Structure):
+    _fields_ = [("num_envs", C.c_int32), ("vert_offset", _i64p), ("verts", _fp),
+                ("tri_offset", _i64p), ("tris", _i32p), ("tri_rgb", _u8p),
+                ("box_offset", _i64p), ("boxes", _fp), ("num_objects", C.c_int32),
+                ("objects", _fp), ("grid_origin", _fp), ("grid_dims", _i32p),
+                ("num_starts", C.c_int32), ("starts", _fp), ("held", _u8p), ("res", _i32p)]
+
+
+class GalConfig(C.Structure):
+    _fields_ = [("res0", C.c_int32), ("near_m", C.c_float), ("far_m", C.c_float),
+                ("cell_m", C.c_float), ("num_classes", C.c_int32),
+                ("class_radius", C.c_float * 8), ("act_lim", C.c_float * 3),
+                ("episode_len", C.c_int32), ("flags", C.c_uint32)]
+
+
+class GalOutputs(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("rgb", C.c_void_p), ("contact_static", C.c_void_p),
+                ("contact_object", C.c_void_p), ("accepted", C.c_void_p), ("state", C.c_void_p),
+                ("frames", C.c_void_p), ("counters", C.c_void_p), ("done", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libgal.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2306_07552_amd.build` "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.gal_create_batch.argtypes = [C.POINTER(GalConfig), C.POINTER(GalRobot),
+                                       C.POINTER(GalSceneSet), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.gal_reset.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gal_step.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(GalOutputs), C.c_void_p]
+        L.gal_batch_info.argtypes = [C.c_void_p, _i32p, _i32p, _i32p, _i64p]
+        L.gal_depth_offsets.argtypes = [C.c_void_p, _i64p, C.c_size_t]
+        L.gal_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gal_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gal_get_grid.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _u32p, C.c_size_t, _fp,
+                                   C.c_size_t, _i64p]
+        L.gal_profile_enable.argtypes = [C.c_void_p, C.c_int]
+        L.gal_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       _i64p]
+        L.gal_mesh_info.argtypes = [C.c_void_p, _i64p, _i64p, _i64p]
+        L.gal_destroy.argtypes = [C.c_void_p]
+        L.gal_destroy.restype = None
+        L.gal_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class GalError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != GAL_OK:
+        raise GalError(rc, load_library().gal_last_error().decode())
+
+
+def _p(a: Optional[np.ndarray], t):
+    if a is None:
+        return C.cast(None, t)
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(t)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Batch:
+    """A batch of environments stepped together on one GPU."""
+
+    def __init__(self, robot, scenes, consts: dict, color: bool = False, stream=None):
+        L = load_library()
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dt)
+            keep.append(a)
+            return a
+
+        cfg = GalConfig()
+        cfg.res0 = int(consts["res0"])
+        cfg.near_m = float(np.float32(consts["near"]))
+        cfg.far_m = float(np.float32(consts["far"]))
+        cfg.cell_m = float(np.float32(consts["cell"]))
+        rc = list(consts["radius_classes"])
+        cfg.num_classes = len(rc)
+        cfg.class_radius[:] = [float(np.float32(v)) for v in rc] + [0.0] * (8 - len(rc))
+        cfg.act_lim[:] = [float(np.float32(v)) for v in consts["act_lim"]]
+        cfg.episode_len = int(consts["episode_len"])
+        cfg.flags = GAL_COLOR if color else 0
+
+        r = GalRobot()
+        r.dh[:] = [float(v) for v in np.asarray(robot.dh, np.float32).ravel()]
+        r.qlim[:] = [float(v) for v in np.asarray(robot.qlim, np.float32).ravel()]
+        r.q_home[:] = [float(v) for v in np.asarray(robot.q_home, np.float32)]
+        r.mount[:] = [float(v) for v in np.asarray(robot.mount, np.float32)]
+        r.cam_offset[:] = [float(v) for v in np.asarray(robot.cam_offset, np.float32)]
+        r.cam_pitch_cs[:] = [float(v) for v in np.asarray(robot.cam_pitch_cs, np.float32)]
+        r.num_spheres = int(robot.num_spheres)
+        r.sphere_link = _p(arr(robot.sphere_link, np.int32), _i32p)
+        r.sphere_pos = _p(arr(robot.sphere_pos, np.float32), _fp)
+        r.sphere_class = _p(arr(robot.sphere_class, np.int32), _i32p)
+        r.sphere_held_only = _p(arr(robot.sphere_held_only, np.uint8), _u8p)
+
+        s = GalSceneSet()
+        S = scenes
+        s.num_envs = int(S.num_envs)
+        s.vert_offset = _p(arr(S.vert_offset, np.int64), _i64p)
+        s.verts = _p(arr(S.verts, np.float32), _fp)
+        s.tri_offset = _p(arr(S.tri_offset, np.int64), _i64p)
+        s.tris = _p(arr(S.tris, np.int32), _i32p)
+        s.tri_rgb = _p(arr(S.tri_rgb, np.uint8), _u8p)
+        s.box_offset = _p(arr(S.box_offset, np.int64), _i64p)
+        s.boxes = _p(arr(S.boxes, np.float32), _fp)
+        s.num_objects = int(S.num_objects)
+        s.objects = _p(arr(S.objects, np.float32), _fp)
+        s.grid_origin = _p(arr(S.grid_origin, np.float32), _fp)
+        s.grid_dims = _p(arr(S.grid_dims, np.int32), _i32p)
+        s.num_starts = int(S.num_starts)
+        s.starts = _p(arr(S.starts, np.float32), _fp)
+        s.held = _p(arr(S.held, np.uint8), _u8p)
+        s.res = _p(arr(S.res, np.int32), _i32p)
+
+        h = C.c_void_p()
+        _check(L.gal_create_batch(C.byref(cfg), C.byref(r), C.byref(s),
+                                  _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self.color = color
+        n, sp, w, px = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(L.gal_batch_info(h, C.byref(n), C.byref(sp), C.byref(w), C.byref(px)))
+        self.num_envs, self.num_spheres, self.contact_words = n.value, sp.value, w.value
+        self.depth_pixels = px.value
+        off = np.zeros(self.num_envs + 1, np.int64)
+        _check(L.gal_depth_offsets(h, _p(off, _i64p), off.size))
+        self.depth_off = off
+        self.res = np.asarray(S.res, np.int32).copy()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load_library().gal_destroy(h)
+            self._h = None
+
+    def alloc_outputs(self, device="cuda") -> Dict[str, "object"]:
+        import torch
+        N, W = self.num_envs, self.contact_words
+        out = dict(
+            depth=torch.empty(self.depth_pixels, dtype=torch.int32, device=device),
+            contact_static=torch.empty((N, W), dtype=torch.int32, device=device),
+            contact_object=torch.empty((N, W), dtype=torch.int32, device=device),
+            accepted=torch.empty(N, dtype=torch.uint8, device=device),
+            state=torch.empty((N, 10), dtype=torch.float32, device=device),
+            frames=torch.empty((N, 8, 12), dtype=torch.float32, device=device),
+            counters=torch.empty((N, 2), dtype=torch.int32, device=device),
+            done=torch.empty(N, dtype=torch.uint8, device=device),
+        )
+        if self.color:
+            out["rgb"] = torch.empty((self.depth_pixels, 3), dtype=torch.uint8, device=device)
+        return out
+
+    def step(self, actions, out: Dict[str, "object"], stream=None):
+        o = GalOutputs()
+        for k in ("depth", "rgb", "contact_static", "contact_object", "accepted", "state",
+                  "frames", "counters", "done"):
+            setattr(o, k, _ptr(out.get(k)))
+        assert actions.is_contiguous() and actions.dtype.is_floating_point
+        _check(load_library().gal_step(self._h, actions.data_ptr(), C.byref(o),
+                                       _stream_handle(stream)))
+
+    def reset(self, mask=None, stream=None):
+        _check(load_library().gal_reset(self._h, _ptr(mask), _stream_handle(stream)))
+
+    def get_state(self, stream=None):
+        N = self.num_envs
+        buf = np.zeros(N * 12, np.float32)
+        _check(load_library().gal_get_state(self._h, buf.ctypes.data, buf.nbytes,
+                                            _stream_handle(stream)))
+        return buf[:N * 10].reshape(N, 10).copy(), buf[N * 10:].view(np.int32).reshape(N, 2).copy()
+
+    def set_state(self, state: np.ndarray, counters: np.ndarray, stream=None):
+        N = self.num_envs
+        buf = np.concatenate([np.ascontiguousarray(state, np.float32).ravel(),
+                              np.ascontiguousarray(counters, np.int32).ravel().view(np.float32)])
+        assert buf.size == N * 12
+        _check(load_library().gal_set_state(self._h, buf.ctypes.data, buf.nbytes,
+                                            _stream_handle(stream)))
+
+    def get_grid(self, env: int, cls: int, nx: int, ny: int):
+        L = load_library()
+        n = C.c_int64()
+        _check(L.gal_get_grid(self._h, env, cls, C.cast(None, _u32p), 0, C.cast(None, _fp), 0,
+                              C.byref(n)))
+        offs = np.zeros(nx * ny + 1, np.uint32)
+        lay = np.zeros((max(n.value, 1), 2), np.float32)
+        _check(L.gal_get_grid(self._h, env, cls, _p(offs, _u32p), offs.size, _p(lay, _fp),
+                              n.value, C.byref(n)))
+        return offs, lay[:n.value]
+
+    def profile(self, on: bool):
+        _check(load_library().gal_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(robot-step ms, raster ms, steps) summed over the recorded steps."""
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(load_library().gal_profile_read(self._h, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
+
+    def mesh_info(self):
+        c, v, t = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load_library().gal_mesh_info(self._h, C.byref(c), C.byref(v), C.byref(t)))
+        return dict(clusters=c.value, cluster_verts=v.value, tris=t.value)
+
+    def env_depth(self, depth_flat, e: int):
+        r = int(self.res[e])
+        return depth_flat[int(self.depth_off[e]):int(self.depth_off[e + 1])].reshape(r, r)

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.  Depth, contact masks, acceptance, counters and the
+state are compared bit for bit; link frames bit for bit (and so within the
+1e-5 m FK tolerance)."""
+import numpy as np
+import pytest
+
+from paper_2306_07552_amd import scenegen as sg
+from parity_util import compare_step, make_pair, u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def run_trajectory(torch, cfg, steps, envs=None, oracle_envs=None, color=False, act_fn=None):
+    b, ob, scenes, robot = make_pair(cfg, envs, oracle_envs, color=color)
+    out = b.alloc_outputs()
+    N = b.num_envs
+    for k in range(steps):
+        a = sg.actions(cfg, k, num_envs=N) if act_fn is None else act_fn(k, N)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        oout = ob.step(a[ob.envs])
+        compare_step(b, ob, out, oout, label=f"step {k}")
+    return b, ob
+
+
+def test_config0_full_trajectory(torch_cuda):
+    """16 envs x 100 steps, every env, every step."""
+    print("case: config 0, 16 envs x 100 steps", flush=True)
+    run_trajectory(torch_cuda, sg.CONFIGS[0], 100)
+
+
+def test_grid_bitwise_equal(torch_cuda):
+    print("case: column grids, config 0 and 1", flush=True)
+    from oracle import oracle as O
+    for cfgid, envs in ((0, range(4)), (1, [0, 5])):
+        cfg = sg.CONFIGS[cfgid]
+        b, ob, scenes, robot = make_pair(cfg, envs, oracle_envs=[])
+        for e in range(scenes.num_envs):
+            nx, ny = (int(v) for v in scenes.grid_dims[e])
+            for k, r in enumerate(sg.RADIUS_CLASSES):
+                go, gl = b.get_grid(e, k, nx, ny)
+                oo, ol = O.grid_build(scenes.env_boxes(e), *scenes.grid_origin[e], nx, ny,
+                                      sg.CELL, r)
+                assert np.array_equal(go, oo), f"cfg {cfgid} env {e} class {k} offsets"
+                assert np.array_equal(gl.view(np.uint32), ol.view(np.uint32)), \
+                    f"cfg {cfgid} env {e} class {k} layers"
+
+
+def test_config1_subset_with_resets(torch_cuda):
+    """Paper-scale scenes (20k-80k triangles, 128x128, 65 spheres incl. the
+    held proxy), 24 envs, a short episode so auto-resets happen."""
+    print("case: config 1 scenes, 24 envs x 30 steps, episode 12", flush=True)
+    cfg = sg.scaled_config(1, 24, episode_len=12)
+    run_trajectory(torch_cuda, cfg, 30)
+
+
+def test_config1_full_batch_sampled(torch_cuda):
+    """The benchmarked configuration: 1024 envs.  The oracle follows 16 of
+    them for 6 steps; then one-step parity from a restored state."""
+    torch = torch_cuda
+    print("case: config 1, 1024 envs, 16 sampled", flush=True)
+    cfg = sg.CONFIGS[1]
+    sample = sorted(set(np.random.default_rng(0).choice(1024, 16, replace=False).tolist()) | {1023})
+    b, ob, scenes, robot = make_pair(cfg, None, sample)
+    out = b.alloc_outputs()
+    for k in range(6):
+        a = sg.actions(cfg, k)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        compare_step(b, ob, out, ob.step(a[sample]), label=f"step {k}")
+    # one-step parity from an arbitrary restored state
+    st, cnt = b.get_state()
+    rng = np.random.default_rng(5)
+    st[:, 3:] += rng.uniform(-0.5, 0.5, (st.shape[0], 7)).astype(np.float32)
+    st[:, 3:] = np.clip(st[:, 3:], robot.qlim[:, 0], robot.qlim[:, 1])
+    cnt[:, 0] = 499
+    b.set_state(st, cnt)
+    ob.set_state(st[sample], cnt[sample])
+    a = sg.actions(cfg, 77)
+    b.step(torch.from_numpy(a).cuda(), out)
+    torch.cuda.synchronize()
+    compare_step(b, ob, out, ob.step(a[sample]), label="restored")
+    assert out["done"].cpu().numpy().all()
+
+
+def test_state_roundtrip_and_reset_mask(torch_cuda):
+    torch = torch_cuda
+    print("case: state round trip, masked reset", flush=True)
+    cfg = sg.scaled_config(0, 13)     # ragged: not a multiple of the 4 envs per block
+    b, ob, scenes, robot = make_pair(cfg)
+    out = b.alloc_outputs()
+    for k in range(3):
+        a = sg.actions(cfg, k, num_envs=13)
+        b.step(torch.from_numpy(a).cuda(), out)
+        ob.step(a)
+    st, cnt = b.get_state()
+    b.set_state(st, cnt)
+    st2, cnt2 = b.get_state()
+    assert np.array_equal(st.view(np.uint32), st2.view(np.uint32)) and np.array_equal(cnt, cnt2)
+    mask = np.zeros(13, np.uint8)
+    mask[[0, 4, 12]] = 1
+    b.reset(torch.from_numpy(mask).cuda())
+    ob.reset(mask)
+    st3, cnt3 = b.get_state()
+    assert np.array_equal(st3.view(np.uint32), ob.state.view(np.uint32))
+    assert np.array_equal(cnt3, ob.counters)
+    a = sg.actions(cfg, 9, num_envs=13)
+    b.step(torch.from_numpy(a).cuda(), out)
+    torch.cuda.synchronize()
+    compare_step(b, ob, out, ob.step(a), label="after reset")
+
+
+def test_degenerate_actions(torch_cuda):
+    """NaN components count as zero; infinities and huge values clamp."""
+    print("case: NaN / inf actions", flush=True)
+    cfg = sg.scaled_config(0, 8)
+
+    def act(k, N):
+        a = sg.actions(cfg, k, num_envs=N)
+        a[::2, k % 9] = np.nan
+        a[1::3, (k + 4) % 9] = np.inf
+        a[2::3, (k + 2) % 9] = -1e30
+        return a
+    run_trajectory(torch_cuda, cfg, 12, act_fn=act)
+
+
+def test_mixed_resolutions_and_empty_scene(torch_cuda):
+    """Per-env resolutions 64/128/256 in one batch (256 renders as four
+    128x128 regions); one env with no triangles at all."""
+    torch = torch_cuda
+    print("case: mixed resolutions, empty env", flush=True)
+    cfg = sg.scaled_config(2, 9, tri_target=(2000.0, 6000.0))
+    scenes = sg.make_scene_set(cfg)
+    scenes.res[:] = [64, 128, 256, 256, 64, 128, 256, 64, 128]
+    # env 3: drop every triangle
+    t0, t1 = int(scenes.tri_offset[3]), int(scenes.tri_offset[4])
+    scenes.tris = np.concatenate([scenes.tris[:t0], scenes.tris[t1:]])
+    scenes.tri_rgb = np.concatenate([scenes.tri_rgb[:t0], scenes.tri_rgb[t1:]])
+    scenes.tri_offset[4:] -= (t1 - t0)
+    from oracle import oracle as O
+    from paper_2306_07552_amd import gal
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    b = gal.Batch(robot, scenes, consts)
+    ob = O.OracleBatch(robot, scenes, consts)
+    out = b.alloc_outputs()
+    for k in range(4):
+        a = sg.actions(cfg, k, num_envs=9)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        oout = ob.step(a)
+        compare_step(b, ob, out, oout, label=f"step {k}")
+    assert (b.env_depth(u32(out["depth"]), 3) == 0xFFFFFF).all()
+
+
+def test_repeatable(torch_cuda):
+    """The same inputs give the same bits on every run (no order dependence
+    in the LDS z-min)."""
+    torch = torch_cuda
+    print("case: repeatability", flush=True)
+    cfg = sg.scaled_config(1, 8)
+    res = []
+    for _ in range(2):
+        b, _, _, _ = make_pair(cfg, oracle_envs=[])
+        out = b.alloc_outputs()
+        for k in range(3):
+            b.step(torch.from_numpy(sg.actions(cfg, k, num_envs=8)).cuda(), out)
+        torch.cuda.synchronize()
+        res.append(u32(out["depth"]).copy())
+    assert np.array_equal(res[0], res[1])
