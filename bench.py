@@ -53,6 +53,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="JSON dict of raster launch settings (gal_tuning fields)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
@@ -64,6 +69,15 @@ def main():
     from paper_2306_07552_amd import gal, scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_reference:
+        n = args.copy_reference * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": n * 4, "dispatches": 5}), flush=True)
+        return
 
     cfg = sg.CONFIGS[args.config]
     t = time.perf_counter()
@@ -75,6 +89,9 @@ def main():
     t = time.perf_counter()
     b = gal.Batch(robot, scenes, consts, color=cfg.color)
     log(f"gal_create_batch: {time.perf_counter() - t:.1f} s, mesh {b.mesh_info()}")
+    if args.tuning:
+        b.set_tuning(**json.loads(args.tuning))
+    log(f"tuning {b.get_tuning()}")
     N = b.num_envs
     out = b.alloc_outputs()
     stream = torch.cuda.current_stream()
@@ -128,7 +145,7 @@ def main():
            "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
-           "config": {"workload": cfg.name, "envs": N, "res": int(cfg.res0),
+           "config": {"workload": cfg.name, "tuning": b.get_tuning(), "envs": N, "res": int(cfg.res0),
                       "tris_total": int(scenes.tri_offset[-1]), "spheres": robot.num_spheres,
                       "objects": cfg.num_objects, "episode_len": cfg.episode_len,
                       "path": "plain"},

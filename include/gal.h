@@ -181,6 +181,39 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
  */
 int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream);
 
+/*
+ * Launch configuration of the raster kernel.  Every setting produces the same
+ * bits (the outputs are defined independently of how the work is split); the
+ * settings only change speed, and an autotuner picks among them.
+ *  block      threads per workgroup: 256, 512 or 1024
+ *  region     square pixel region owned by one workgroup: 32, 64 or 128 (must
+ *             divide every env resolution above it)
+ *  lane_max   triangles whose clipped pixel bbox has at most this many pixels
+ *             are rasterised by their own lane (0..4096)
+ *  small_max  larger ones up to this many pixels are rasterised together by
+ *             the wave, pixels spread evenly over the lanes (0..65536); the
+ *             rest one at a time by the whole wave, 8x8 tile by tile
+ *  refresh    clusters a wave draws between refreshes of the occlusion
+ *             bounds (1..1024)
+ *  occlusion  1 = skip clusters provably hidden behind conservative z-buffer
+ *             bounds, 0 = frustum culling only
+ *  prologue   clusters drawn before occlusion culling starts (>= 0)
+ */
+typedef struct gal_tuning {
+    int32_t block;
+    int32_t region;
+    int32_t lane_max;
+    int32_t small_max;
+    int32_t refresh;
+    int32_t occlusion;
+    int32_t prologue;
+} gal_tuning;
+
+int gal_get_tuning(const gal_batch *b, gal_tuning *t);
+/* Errors: GAL_EINVAL for values out of range.  Not to be called while a step
+ * on the batch is in flight on another stream. */
+int gal_set_tuning(gal_batch *b, const gal_tuning *t);
+
 /* Number of environments, spheres, contact words, and the packed depth size. */
 int gal_batch_info(const gal_batch *b, int32_t *num_envs, int32_t *num_spheres,
                    int32_t *contact_words, int64_t *depth_pixels);
@@ -217,6 +250,19 @@ int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
  */
 int gal_profile_enable(gal_batch *b, int on);
 int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps);
+
+/*
+ * On-device work counters of the raster kernel, summed over the steps run
+ * while enabled (reading synchronises the device and clears them).
+ * counters_host receives GAL_NUM_COUNTERS values: [0] clusters tested against
+ * the frustum, [1] inside it, [2] of those proven hidden by the occlusion
+ * bounds, [3] clusters drawn, [4] triangles surviving trivial rejection,
+ * [5] of which clipped, [6] front-facing (sub)triangles with pixels in a
+ * region, [7] their bbox pixel count.  Counting costs a few atomics per wave.
+ */
+#define GAL_NUM_COUNTERS 8
+int gal_counters_enable(gal_batch *b, int on);
+int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count);
 
 /* Sizes of the device-resident render mesh: 64-triangle clusters, their
  * (per-cluster unique) vertices, and triangles. */

@@ -20,7 +20,8 @@
  *   5. the episode counter advances (500-step horizon, Section 4.1);
  *   6. a depth image of the head camera (128x128, 90 degree FoV, Section 4.1)
  *      is rasterised: fixed-point vertices, integer edge functions with a
- *      top-left fill rule, 24-bit depth, z-min.
+ *      top-left fill rule, depth interpolated with the barycentric weights
+ *      the edge functions give, 24-bit depth, z-min.
  * The paper leaves every numeric detail open; the readings taken here are the
  * ones listed in the design notes (FP32 with a fixed evaluation order, own
  * sincos, Sutherland-Hodgman clipping with canonical endpoint order, ...).
@@ -514,26 +515,27 @@ static void raster_tri(o_rctx *cx, const o_cv *in, uint32_t id)
         int top_left = (ey < 0) || (ey == 0 && ex > 0);
         bias[k] = top_left ? 0 : 1;
     }
-    float e1 = d[1] - d[0], e2 = d[2] - d[0];
-    float fx1 = (float)(x[1] - x[0]), fy1 = (float)(y[1] - y[0]);
-    float fx2 = (float)(x[2] - x[0]), fy2 = (float)(y[2] - y[0]);
-    float fA = (float)A2;
-    float a = (e1 * fy2 - e2 * fy1) / fA;
-    float b = (e2 * fx1 - e1 * fx2) / fA;
+    /* depth: convex combination of the vertex depths with the barycentric
+       weights E_k / A2 given by the integer edge functions (edge k is opposite
+       vertex k); the weights are non-negative on covered pixels, so the
+       result stays within a few LSB of the vertices' depth range */
+    float invA = 1.0f / (float)A2;
+    float q[3] = {d[0] * invA, d[1] * invA, d[2] * invA};
 
     for (int py = py0; py <= py1; ++py) {
         for (int px = px0; px <= px1; ++px) {
             int32_t Px = 16 * px + 8, Py = 16 * py + 8;
             cx->st->cand_px += 1;
             int inside = 1;
+            int32_t E[3];
             for (int k = 0; k < 3; ++k) {
                 int i = EI[k], j = EJ[k];
-                int32_t E = (x[j] - x[i]) * (Py - y[i]) - (y[j] - y[i]) * (Px - x[i]);
-                if (E < bias[k]) { inside = 0; break; }
+                E[k] = (x[j] - x[i]) * (Py - y[i]) - (y[j] - y[i]) * (Px - x[i]);
+                if (E[k] < bias[k]) inside = 0;
             }
             if (!inside) continue;
             cx->st->frags += 1;
-            float dv = d[0] + (a * (float)(Px - x[0]) + b * (float)(Py - y[0]));
+            float dv = ((float)E[0] * q[0] + (float)E[1] * q[1]) + (float)E[2] * q[2];
             uint32_t D;
             if (!(dv > 0.0f)) D = 0;
             else if (dv >= 16777215.0f) D = 16777215u;

@@ -158,6 +158,9 @@ struct gal_batch {
     uint32_t *d_work = nullptr;
     int32_t num_work = 0;
     int64_t n_clusters = 0, n_cverts = 0, n_tris = 0;
+    unsigned long long *d_stats = nullptr;  // raster work counters (allocated on demand)
+    std::vector<int64_t> cl_count_host;    // clusters per env
+    int32_t work_cap = 0;
     // per-kernel timing
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;     // free events
@@ -180,9 +183,94 @@ struct gal_batch {
     }
 };
 
+namespace {
+
+// (env, region) work items, longest envs first (so the tail of the launch is
+// short), regions of one env 8 items apart (same XCD, shared L2).
+int build_work(gal_batch *b)
+{
+    const int N = b->N;
+    std::vector<int32_t> order(N);
+    for (int e = 0; e < N; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        const double ca = (double)b->cl_count_host[a] + 1e-3 * b->res_host[a] * b->res_host[a];
+        const double cc = (double)b->cl_count_host[c] + 1e-3 * b->res_host[c] * b->res_host[c];
+        return ca > cc;
+    });
+    std::vector<uint32_t> work;
+    for (int g = 0; g < N; g += 8) {
+        int maxreg = 0;
+        for (int k = g; k < std::min(N, g + 8); ++k) {
+            const int r = b->res_host[order[k]];
+            const int R = std::min(r, b->rast.region);
+            maxreg = std::max(maxreg, (r / R) * (r / R));
+        }
+        for (int reg = 0; reg < maxreg; ++reg)
+            for (int k = g; k < std::min(N, g + 8); ++k) {
+                const int e = order[k];
+                const int r = b->res_host[e];
+                const int R = std::min(r, b->rast.region);
+                if (reg < (r / R) * (r / R)) work.push_back((uint32_t)e | ((uint32_t)reg << 20));
+            }
+    }
+    if ((int32_t)work.size() > b->work_cap) {
+        int rc = b->mem.alloc(&b->d_work, work.size());
+        if (rc) return rc;
+        b->work_cap = (int32_t)work.size();
+    }
+    b->num_work = (int32_t)work.size();
+    hipError_t e = hipMemcpy(b->d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(GAL_EDEVICE, "hipMemcpy(work) failed: %s", hipGetErrorString(e));
+    return GAL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *gal_last_error(void) { return g_last_error.c_str(); }
+
+int gal_get_tuning(const gal_batch *b, gal_tuning *t)
+{
+    if (!b || !t) return fail(GAL_EINVAL, "null argument");
+    t->block = b->rast.block;
+    t->region = b->rast.region;
+    t->lane_max = b->rast.lane_max;
+    t->small_max = b->rast.small_max;
+    t->refresh = b->rast.refresh;
+    t->occlusion = b->rast.occlusion;
+    t->prologue = b->rast.prologue;
+    return GAL_OK;
+}
+
+int gal_set_tuning(gal_batch *b, const gal_tuning *t)
+{
+    if (!b || !t) return fail(GAL_EINVAL, "null argument");
+    if (t->block != 256 && t->block != 512 && t->block != 1024)
+        return fail(GAL_EINVAL, "block must be 256, 512 or 1024");
+    if (t->region != 32 && t->region != 64 && t->region != 128)
+        return fail(GAL_EINVAL, "region must be 32, 64 or 128");
+    for (int e = 0; e < b->N; ++e)
+        if (b->res_host[e] > t->region && b->res_host[e] % t->region != 0)
+            return fail(GAL_EINVAL, "region %d does not divide resolution %d", t->region, b->res_host[e]);
+    if (t->small_max < 0 || t->small_max > 65536) return fail(GAL_EINVAL, "small_max out of range");
+    if (t->lane_max < 0 || t->lane_max > 4096) return fail(GAL_EINVAL, "lane_max out of range");
+    if (t->refresh < 1 || t->refresh > 1024) return fail(GAL_EINVAL, "refresh must be in 1..1024");
+    if (t->prologue < 0) return fail(GAL_EINVAL, "prologue must be >= 0");
+    const bool rebuild = t->region != b->rast.region;
+    b->rast.block = t->block;
+    b->rast.region = t->region;
+    b->rast.lane_max = t->lane_max;
+    b->rast.small_max = t->small_max;
+    b->rast.refresh = t->refresh;
+    b->rast.occlusion = t->occlusion ? 1 : 0;
+    b->rast.prologue = t->prologue;
+    if (rebuild) {
+        HIP_TRY(hipDeviceSynchronize());
+        return build_work(b);
+    }
+    return GAL_OK;
+}
 
 int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_scene_set *sc,
                      void *stream, gal_batch **out)
@@ -464,6 +552,8 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         b->mesh.env_tri_off = d_tri_off;
         b->mesh.tri_rgb = nullptr;
         b->n_clusters = (int64_t)cl_off[N];
+        b->cl_count_host.resize(N);
+        for (int e = 0; e < N; ++e) b->cl_count_host[e] = (int64_t)(cl_off[e + 1] - cl_off[e]);
         b->n_cverts = (int64_t)nv_tot;
         b->n_tris = (int64_t)nt_tot;
         if (cfg->flags & GAL_COLOR) {
@@ -481,31 +571,20 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         const float invf = 1.0f / cfg->far_m;
         b->rast.kd = 16777215.0f / (b->rast.invn - invf);
         b->rast.region = gal::kMaxRegion;
-        b->rast.small_max = 16;
-        std::vector<uint32_t> work;
-        // regions of one env are 8 items apart so they land on the same XCD
-        for (int e0 = 0; e0 < N; e0 += 8) {
-            int maxreg = 0;
-            for (int e = e0; e < std::min(N, e0 + 8); ++e) {
-                const int R = std::min(b->res_host[e], b->rast.region);
-                maxreg = std::max(maxreg, (b->res_host[e] / R) * (b->res_host[e] / R));
-            }
-            for (int r = 0; r < maxreg; ++r)
-                for (int e = e0; e < std::min(N, e0 + 8); ++e) {
-                    const int R = std::min(b->res_host[e], b->rast.region);
-                    const int nreg = (b->res_host[e] / R) * (b->res_host[e] / R);
-                    if (r < nreg) work.push_back((uint32_t)e | ((uint32_t)r << 20));
-                }
-        }
-        b->num_work = (int32_t)work.size();
-        if ((rc = b->mem.alloc(&b->d_work, work.size())) || (rc = b->mem.alloc(&b->d_res, (size_t)N)) ||
-            (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
+        b->rast.lane_max = 4;
+        b->rast.small_max = 256;
+        b->rast.block = 512;
+        b->rast.refresh = 4;
+        b->rast.occlusion = 0;
+        b->rast.prologue = 8;
+        b->rast.stats = nullptr;
+        if ((rc = b->mem.alloc(&b->d_res, (size_t)N)) || (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
             return cleanup(rc);
-        HIP_TRY(hipMemcpy(b->d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(b->d_res, b->res_host.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
         std::vector<uint64_t> doff(N + 1);
         for (int e = 0; e <= N; ++e) doff[e] = (uint64_t)b->depth_off_host[e];
         HIP_TRY(hipMemcpy(b->d_depth_off, doff.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        if ((rc = build_work(b))) return cleanup(rc);
     }
 
     // ---- initial state: episode 0 at the first start pose (reset from episode -1)
@@ -588,6 +667,32 @@ int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t 
     if (robot_ms) *robot_ms = r0;
     if (raster_ms) *raster_ms = r1;
     if (steps) *steps = (int64_t)n;
+    return GAL_OK;
+}
+
+int gal_counters_enable(gal_batch *b, int on)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    if (on && !b->d_stats) {
+        int rc = b->mem.alloc(&b->d_stats, GAL_NUM_COUNTERS);
+        if (rc) return rc;
+        HIP_TRY(hipMemset(b->d_stats, 0, sizeof(unsigned long long) * GAL_NUM_COUNTERS));
+    }
+    b->rast.stats = on ? b->d_stats : nullptr;
+    return GAL_OK;
+}
+
+int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count)
+{
+    if (!b || !counters_host) return fail(GAL_EINVAL, "null argument");
+    if (count != GAL_NUM_COUNTERS) return fail(GAL_EINVAL, "need %d counters", GAL_NUM_COUNTERS);
+    if (!b->d_stats) {
+        memset(counters_host, 0, sizeof(int64_t) * GAL_NUM_COUNTERS);
+        return GAL_OK;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(counters_host, b->d_stats, sizeof(int64_t) * GAL_NUM_COUNTERS, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(b->d_stats, 0, sizeof(unsigned long long) * GAL_NUM_COUNTERS));
     return GAL_OK;
 }
 

@@ -97,10 +97,16 @@ struct RenderMesh {
 
 struct RasterParams {
     float near_m;
-    float invn;       // 1/near
-    float kd;         // (2^24-1) / (1/near - 1/far)
-    int32_t region;   // square region edge rendered by one workgroup (<= 128)
-    int32_t small_max;// bbox pixel count rasterised by a single lane
+    float invn;        // 1/near
+    float kd;          // (2^24-1) / (1/near - 1/far)
+    int32_t region;    // square region edge rendered by one workgroup (<= 128)
+    int32_t lane_max;  // bbox pixel count rasterised by the triangle's own lane
+    int32_t small_max; // bbox pixel count rasterised by the balanced wave pass
+    int32_t block;     // threads per workgroup: 256, 512 or 1024
+    int32_t refresh;   // clusters a wave draws between occlusion-bound refreshes
+    int32_t occlusion; // 1 = cull clusters hidden behind the z-buffer bounds
+    int32_t prologue;  // clusters drawn before occlusion culling starts
+    unsigned long long *stats; // optional work counters [8] (null = off)
 };
 
 // Launchers (defined in the .hip files).

@@ -34,6 +34,7 @@ namespace {
 
 constexpr uint32_t kFar = 0xFFFFFFu;
 constexpr uint32_t kClipBits = 0x1Fu;
+constexpr int kVisCap = 4096;   // clusters per visibility window (u16 list in LDS)
 
 struct Cam {
     float px, py, pz, rx, ry, rz, dx, dy, dz, fx, fy, fz;
@@ -136,11 +137,12 @@ __device__ __noinline__ void clip_polygon(Poly &p, float near_m)
 }
 
 // Triangle set up for rasterisation: snapped vertices (after the winding
-// swap), depth plane, pixel bbox clipped to the region.
+// swap), per-vertex depth scaled by 1/A2 (barycentric weights are the edge
+// functions), pixel bbox clipped to the region.
 struct Setup {
     int x0, y0, x1, y1, x2, y2;
     int bias;                 // bit k set: edge k is not top-left (needs E >= 1)
-    float d0, a, b;
+    float q0, q1, q2;         // vertex depth / A2
     int px0, px1, py0, py1;
 };
 
@@ -152,10 +154,9 @@ __device__ __forceinline__ int setup_triangle(int x0, int y0, float d0, int x1, 
     const int A2 = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
     if (A2 >= 0) return 0;   // back face or degenerate
     // front face: swap v1 and v2 so the signed area is positive
-    S.x0 = x0; S.y0 = y0; S.d0 = d0;
+    S.x0 = x0; S.y0 = y0;
     S.x1 = x2; S.y1 = y2;
     S.x2 = x1; S.y2 = y1;
-    const float e1 = d2 - d0, e2 = d1 - d0;
     const int minx = min(x0, min(x1, x2)), maxx = max(x0, max(x1, x2));
     const int miny = min(y0, min(y1, y2)), maxy = max(y0, max(y1, y2));
     S.px0 = max((minx + 7) >> 4, rx0);
@@ -178,12 +179,17 @@ __device__ __forceinline__ int setup_triangle(int x0, int y0, float d0, int x1, 
         if (!((ey < 0) || (ey == 0 && ex > 0))) bias |= 4;
     }
     S.bias = bias;
-    const float fx1 = (float)(S.x1 - S.x0), fy1 = (float)(S.y1 - S.y0);
-    const float fx2 = (float)(S.x2 - S.x0), fy2 = (float)(S.y2 - S.y0);
-    const float fA = (float)(-A2);
-    S.a = (e1 * fy2 - e2 * fy1) / fA;
-    S.b = (e2 * fx1 - e1 * fx2) / fA;
+    const float invA = 1.0f / (float)(-A2);
+    S.q0 = d0 * invA;
+    S.q1 = d2 * invA;   // swapped vertex 1 is the original vertex 2
+    S.q2 = d1 * invA;
     return 1;
+}
+
+__device__ __forceinline__ uint32_t frag_depth(int e0, int e1, int e2, float q0, float q1, float q2)
+{
+    const float dv = ((float)e0 * q0 + (float)e1 * q1) + (float)e2 * q2;
+    return depth24(dv);
 }
 
 __device__ __forceinline__ void raster_small(const Setup &S, int rx0, int ry0, int R,
@@ -195,17 +201,15 @@ __device__ __forceinline__ void raster_small(const Setup &S, int rx0, int ry0, i
     const int ex2 = S.x1 - S.x0, ey2 = S.y1 - S.y0;
     const int b0 = S.bias & 1, b1 = (S.bias >> 1) & 1, b2 = (S.bias >> 2) & 1;
     const int Px0 = 16 * S.px0 + 8;
-    int Py = 16 * S.py0 + 8;
-    int r0 = ex0 * (Py - S.y1) - ey0 * (Px0 - S.x1);
-    int r1 = ex1 * (Py - S.y2) - ey1 * (Px0 - S.x2);
-    int r2 = ex2 * (Py - S.y0) - ey2 * (Px0 - S.x0);
-    for (int py = S.py0; py <= S.py1; ++py, Py += 16) {
+    const int Py0 = 16 * S.py0 + 8;
+    int r0 = ex0 * (Py0 - S.y1) - ey0 * (Px0 - S.x1);
+    int r1 = ex1 * (Py0 - S.y2) - ey1 * (Px0 - S.x2);
+    int r2 = ex2 * (Py0 - S.y0) - ey2 * (Px0 - S.x0);
+    for (int py = S.py0; py <= S.py1; ++py) {
         int e0 = r0, e1 = r1, e2 = r2;
-        int Px = Px0;
-        for (int px = S.px0; px <= S.px1; ++px, Px += 16) {
+        for (int px = S.px0; px <= S.px1; ++px) {
             if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
-                const float dv = S.d0 + (S.a * (float)(Px - S.x0) + S.b * (float)(Py - S.y0));
-                const uint32_t D = depth24(dv);
+                const uint32_t D = frag_depth(e0, e1, e2, S.q0, S.q1, S.q2);
                 if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
             }
             e0 -= 16 * ey0;
@@ -232,7 +236,7 @@ __device__ __forceinline__ void raster_big(const Setup &S, int L, int lane, int 
     const int x1 = rl(S.x1, L), y1 = rl(S.y1, L);
     const int x2 = rl(S.x2, L), y2 = rl(S.y2, L);
     const int bias = rl(S.bias, L);
-    const float d0 = rlf(S.d0, L), a = rlf(S.a, L), b = rlf(S.b, L);
+    const float q0 = rlf(S.q0, L), q1 = rlf(S.q1, L), q2 = rlf(S.q2, L);
     const int px0 = rl(S.px0, L), px1 = rl(S.px1, L);
     const int py0 = rl(S.py0, L), py1 = rl(S.py1, L);
     const int ex0 = x2 - x1, ey0 = y2 - y1;
@@ -251,10 +255,72 @@ __device__ __forceinline__ void raster_big(const Setup &S, int L, int lane, int 
             const int e1 = ex1 * (Py - y2) - ey1 * (Px - x2);
             const int e2 = ex2 * (Py - y0) - ey2 * (Px - x0);
             if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
-                const float dv = d0 + (a * (float)(Px - x0) + b * (float)(Py - y0));
-                const uint32_t D = depth24(dv);
+                const uint32_t D = frag_depth(e0, e1, e2, q0, q1, q2);
                 if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
             }
+        }
+    }
+}
+
+__device__ __forceinline__ int wave_incl_sum(int v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(v, d, 64);
+        if (lane >= d) v += y;
+    }
+    return v;
+}
+
+// Load-balanced rasterisation of every lane's triangle at once: the pixels of
+// all bboxes are numbered by a wave prefix sum, lane l takes pixels
+// l, l + 64, ... and finds the owning triangle by binary search over the
+// prefix (ds_bpermute); the triangle's record is fetched from its lane.
+__device__ __forceinline__ void raster_balanced(const Setup &S, bool mine, int lane, int rx0,
+                                                int ry0, int R, uint32_t *zbuf)
+{
+    const int w = mine ? S.px1 - S.px0 + 1 : 0;
+    const int h = mine ? S.py1 - S.py0 + 1 : 0;
+    const int cnt = w * h;
+    const int incl = wave_incl_sum(cnt, lane);
+    const int excl = incl - cnt;
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    if (total == 0) return;
+    // packed record of this lane's triangle
+    const int xy0 = (S.x0 & 0xFFFF) | (S.y0 << 16);
+    const int xy1 = (S.x1 & 0xFFFF) | (S.y1 << 16);
+    const int xy2 = (S.x2 & 0xFFFF) | (S.y2 << 16);
+    const int meta = S.px0 | (S.py0 << 9) | ((w - 1) << 18) | (S.bias << 27);
+    const float invw = 1.0f / (float)(w > 0 ? w : 1);
+    for (int base = 0; base < total; base += 64) {
+        const int g = base + lane;
+        int t = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int ex = __shfl(excl, t + step, 64);
+            if (ex <= g) t += step;
+        }
+        const int local = g - __shfl(excl, t, 64);
+        const int txy0 = __shfl(xy0, t, 64), txy1 = __shfl(xy1, t, 64), txy2 = __shfl(xy2, t, 64);
+        const int tmeta = __shfl(meta, t, 64);
+        const float tq0 = __shfl(S.q0, t, 64), tq1 = __shfl(S.q1, t, 64), tq2 = __shfl(S.q2, t, 64);
+        const float tinvw = __shfl(invw, t, 64);
+        if (g >= total) continue;
+        const int tw = ((tmeta >> 18) & 0x1FF) + 1;
+        const int oy = (int)(((float)local + 0.5f) * tinvw);
+        const int ox = local - oy * tw;
+        const int px = (tmeta & 0x1FF) + ox, py = ((tmeta >> 9) & 0x1FF) + oy;
+        const int x0 = (int)(short)(txy0 & 0xFFFF), y0 = txy0 >> 16;
+        const int x1 = (int)(short)(txy1 & 0xFFFF), y1 = txy1 >> 16;
+        const int x2 = (int)(short)(txy2 & 0xFFFF), y2 = txy2 >> 16;
+        const int tb = tmeta >> 27;
+        const int Px = 16 * px + 8, Py = 16 * py + 8;
+        const int e0 = (x2 - x1) * (Py - y1) - (y2 - y1) * (Px - x1);
+        const int e1 = (x0 - x2) * (Py - y2) - (y0 - y2) * (Px - x2);
+        const int e2 = (x1 - x0) * (Py - y0) - (y1 - y0) * (Px - x0);
+        if (e0 >= (tb & 1) && e1 >= ((tb >> 1) & 1) && e2 >= ((tb >> 2) & 1)) {
+            const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
+            if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
         }
     }
 }
@@ -269,7 +335,6 @@ __device__ __forceinline__ int wave_max(int v)
 // Conservative frustum test of a cluster AABB (world) against the near plane
 // and the region's four side planes; margins cover float rounding.
 struct RegionPlanes {
-    // plane value = nx*(p-c).x + ... in camera terms; stored as world normals
     float n[5][3];
     float off[5];
 };
@@ -288,8 +353,253 @@ __device__ __forceinline__ bool aabb_visible(const RegionPlanes &P, float lx, fl
     return true;
 }
 
+// Occlusion bounds: maxima of the z-buffer over 8x8 tiles and 32x32 blocks.
+// Every stored value is an upper bound of the current maximum (the z-buffer
+// only decreases), refreshed with ds_min so concurrent refreshes stay valid.
+struct Occl {
+    uint32_t *tilemax;   // [TW*TW]
+    uint32_t *blockmax;  // [BW*BW]
+    int TW, BW;
+};
+
+// True when every fragment the cluster could produce in the region is
+// provably behind the current z-buffer.  Fragment depths are convex
+// combinations of vertex depths (a few LSB of rounding), vertex depth grows
+// with camera distance, and all vertices lie in the AABB; the screen bbox of
+// the projected AABB (plus a pixel) contains every covered pixel centre.
+__device__ __forceinline__ bool cluster_hidden(const Cam &cam, const Proj &pj, const Occl &oc,
+                                               int rx0, int ry0, int R, float lx, float ly,
+                                               float lz, float hx, float hy, float hz)
+{
+    const float ddx = lx - cam.px, ddy = ly - cam.py, ddz = lz - cam.pz;
+    const float X0 = cam.rx * ddx + cam.ry * ddy + cam.rz * ddz;
+    const float Y0 = cam.dx * ddx + cam.dy * ddy + cam.dz * ddz;
+    const float Z0 = cam.fx * ddx + cam.fy * ddy + cam.fz * ddz;
+    const float ex = hx - lx, ey = hy - ly, ez = hz - lz;
+    const float aX = cam.rx * ex, bX = cam.ry * ey, cX = cam.rz * ez;
+    const float aY = cam.dx * ex, bY = cam.dy * ey, cY = cam.dz * ez;
+    const float aZ = cam.fx * ex, bZ = cam.fy * ey, cZ = cam.fz * ez;
+    const float zmin = Z0 + fminf(aZ, 0.f) + fminf(bZ, 0.f) + fminf(cZ, 0.f);
+    if (!(zmin > 1.01f * pj.near_m + 1e-3f)) return false;
+    float nxmin = 1e30f, nxmax = -1e30f, nymin = 1e30f, nymax = -1e30f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float X = X0 + ((c & 1) ? aX : 0.f) + ((c & 2) ? bX : 0.f) + ((c & 4) ? cX : 0.f);
+        const float Y = Y0 + ((c & 1) ? aY : 0.f) + ((c & 2) ? bY : 0.f) + ((c & 4) ? cY : 0.f);
+        const float Z = Z0 + ((c & 1) ? aZ : 0.f) + ((c & 2) ? bZ : 0.f) + ((c & 4) ? cZ : 0.f);
+        const float r = __builtin_amdgcn_rcpf(Z);
+        nxmin = fminf(nxmin, X * r);
+        nxmax = fmaxf(nxmax, X * r);
+        nymin = fminf(nymin, Y * r);
+        nymax = fmaxf(nymax, Y * r);
+    }
+    const float fx0 = pj.hw + pj.hw * nxmin, fx1 = pj.hw + pj.hw * nxmax;
+    const float fy0 = pj.hw + pj.hw * nymin, fy1 = pj.hw + pj.hw * nymax;
+    // pixel ranges relative to the region, one pixel of margin
+    const int px0 = max((int)floorf(fmaxf(fx0, -1e6f)) - 1 - rx0, 0);
+    const int px1 = min((int)floorf(fminf(fx1, 1e6f)) + 1 - rx0, R - 1);
+    const int py0 = max((int)floorf(fmaxf(fy0, -1e6f)) - 1 - ry0, 0);
+    const int py1 = min((int)floorf(fminf(fy1, 1e6f)) + 1 - ry0, R - 1);
+    if (px0 > px1 || py0 > py1) return true;   // projects outside the region
+    const float zlb = zmin * (1.0f - 1e-5f) - 1e-4f;
+    const float dlb = (pj.invn - 1.0f / zlb) * pj.kd - 16.0f;
+    uint32_t m = 0;
+    const int tx0 = px0 >> 3, tx1 = px1 >> 3, ty0 = py0 >> 3, ty1 = py1 >> 3;
+    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 16) {
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) m = max(m, oc.tilemax[ty * oc.TW + tx]);
+    } else {
+        for (int by = py0 >> 5; by <= (py1 >> 5); ++by)
+            for (int bx = px0 >> 5; bx <= (px1 >> 5); ++bx) m = max(m, oc.blockmax[by * oc.BW + bx]);
+    }
+    return dlb > (float)m;
+}
+
+// Same test for one cluster, evaluated by the whole wave (wave-uniform result).
+__device__ __forceinline__ bool cluster_hidden_wave(const Cam &cam, const Proj &pj, const Occl &oc,
+                                                    int rx0, int ry0, int R, const float4 &w0,
+                                                    const float4 &w1)
+{
+    // every lane computes the same bound; the scalar unit handles the uniform values
+    return cluster_hidden(cam, pj, oc, rx0, ry0, R, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z);
+}
+
+// This wave's share of the bound refresh: tiles w, w+W, ..., then blocks.
+__device__ __forceinline__ void refresh_bounds(const uint32_t *zbuf, const Occl &oc, int R,
+                                               int wave, int nwaves, int lane)
+{
+    const int lx = lane & 7, ly = lane >> 3;
+    for (int t = wave; t < oc.TW * oc.TW; t += nwaves) {
+        const int tx = t % oc.TW, ty = t / oc.TW;
+        const int px = tx * 8 + lx, py = ty * 8 + ly;
+        const int v = (px < R && py < R) ? (int)zbuf[py * R + px] : 0;
+        const int m = wave_max(v);
+        if (lane == 0) atomicMin(&oc.tilemax[t], (uint32_t)m);
+    }
+    for (int b = wave; b < oc.BW * oc.BW; b += nwaves) {
+        const int bx = b % oc.BW, by = b / oc.BW;
+        const int tx = bx * 4 + (lane & 3), ty = by * 4 + ((lane >> 2) & 3);
+        const int v = (lane < 16 && tx < oc.TW && ty < oc.TW) ? (int)oc.tilemax[ty * oc.TW + tx] : 0;
+        const int m = wave_max(v);
+        if (lane == 0) atomicMin(&oc.blockmax[b], (uint32_t)m);
+    }
+}
+
+// Everything a wave needs to draw clusters of one (env, region) item.
+struct Ctx {
+    Cam cam;
+    Proj pj;
+    float kl, kr, kt, kb;
+    int rx0, ry0, R;
+    int small_max;   // bbox pixels: <= lane_max per lane, <= small_max balanced, else tiles
+    int lane_max;
+};
+
+// One cluster's per-lane inputs: lane l holds vertex l and triangle l.
+struct ClusterData {
+    float vx, vy, vz;
+    uint32_t packed;
+    int nv, nt;
+};
+
+__device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint32_t vbase, uint32_t tbase,
+                                              uint32_t cnt, int lane, ClusterData &d)
+{
+    d.nv = (int)(cnt & 0xFF);
+    d.nt = (int)((cnt >> 8) & 0xFF);
+    d.vx = d.vy = d.vz = 0.f;
+    d.packed = 0u;
+    if (lane < d.nv) {
+        const float *v = m.cverts + ((size_t)vbase + lane) * 3;
+        d.vx = v[0];
+        d.vy = v[1];
+        d.vz = v[2];
+    }
+    if (lane < d.nt) d.packed = m.ctris[(size_t)tbase + lane];
+}
+
+// Work counters (debug / roofline accounting), summed per wave.
+enum {
+    kStatBatchClusters = 0,  // clusters tested against the frustum
+    kStatFrustumVisible,     // ... inside it
+    kStatOccluded,           // ... and then proven hidden
+    kStatDrawn,              // clusters drawn
+    kStatTrisValid,          // triangles surviving trivial rejection
+    kStatTrisClipped,        // ... of which clipped
+    kStatTrisSetup,          // front-facing (sub)triangles with pixels in the region
+    kStatCandPixels,         // their bbox pixels
+    kNumStats
+};
+
+__device__ __forceinline__ void stat_add(unsigned long long *stats, int k, int lane, uint64_t v)
+{
+    if (stats && lane == 0 && v) atomicAdd(&stats[k], (unsigned long long)v);
+}
+
+// Draw one cluster.
+__device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, uint32_t *zbuf,
+                             unsigned long long *stats)
+{
+    const Cam &cam = c.cam;
+    const int nv = d.nv, nt = d.nt;
+
+    // ---- per vertex: camera space, outcodes, projection
+    float X = 0.f, Y = 0.f, Z = 1.f;
+    uint32_t oc = 0;
+    int xi = 0, yi = 0;
+    float dv = 0.f;
+    if (lane < nv) {
+        const float ddx = d.vx - cam.px, ddy = d.vy - cam.py, ddz = d.vz - cam.pz;
+        X = (cam.rx * ddx + cam.ry * ddy) + cam.rz * ddz;
+        Y = (cam.dx * ddx + cam.dy * ddy) + cam.dz * ddz;
+        Z = (cam.fx * ddx + cam.fy * ddy) + cam.fz * ddz;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            if (clip_plane(X, Y, Z, k, c.pj.near_m) < 0.0f) oc |= 1u << k;
+        if (X - c.kl * Z < 0.0f) oc |= 1u << 5;
+        if (c.kr * Z - X < 0.0f) oc |= 1u << 6;
+        if (Y - c.kt * Z < 0.0f) oc |= 1u << 7;
+        if (c.kb * Z - Y < 0.0f) oc |= 1u << 8;
+        if ((oc & 1u) == 0) project(c.pj, X, Y, Z, xi, yi, dv);
+    }
+
+    // ---- per triangle
+    const uint32_t packed = d.packed;
+    const int i0 = (int)(packed & 0xFF), i1 = (int)((packed >> 8) & 0xFF),
+              i2 = (int)((packed >> 16) & 0xFF);
+    const uint32_t o0 = (uint32_t)__shfl((int)oc, i0, 64);
+    const uint32_t o1 = (uint32_t)__shfl((int)oc, i1, 64);
+    const uint32_t o2 = (uint32_t)__shfl((int)oc, i2, 64);
+    const bool valid = lane < nt && (o0 & o1 & o2) == 0u;
+    const bool allin = valid && ((o0 | o1 | o2) & kClipBits) == 0u;
+    const bool clipped = valid && !allin;
+    const uint64_t vmask = __ballot(valid);
+    if (!vmask) return;
+    const uint64_t cmask = __ballot(clipped);
+    stat_add(stats, kStatTrisValid, lane, __popcll(vmask));
+    stat_add(stats, kStatTrisClipped, lane, __popcll(cmask));
+    const int vx0 = __shfl(xi, i0, 64), vy0 = __shfl(yi, i0, 64);
+    const int vx1 = __shfl(xi, i1, 64), vy1 = __shfl(yi, i1, 64);
+    const int vx2 = __shfl(xi, i2, 64), vy2 = __shfl(yi, i2, 64);
+    const float vd0 = __shfl(dv, i0, 64), vd1 = __shfl(dv, i1, 64), vd2 = __shfl(dv, i2, 64);
+
+    int nsub = allin ? 1 : 0;
+    Poly poly;
+    poly.n = 0;
+    if (cmask) {
+        const float X0 = __shfl(X, i0, 64), Y0 = __shfl(Y, i0, 64), Z0 = __shfl(Z, i0, 64);
+        const float X1 = __shfl(X, i1, 64), Y1 = __shfl(Y, i1, 64), Z1 = __shfl(Z, i1, 64);
+        const float X2 = __shfl(X, i2, 64), Y2 = __shfl(Y, i2, 64), Z2 = __shfl(Z, i2, 64);
+        if (clipped) {
+            poly.n = 3;
+            poly.X[0] = X0; poly.Y[0] = Y0; poly.Z[0] = Z0;
+            poly.X[1] = X1; poly.Y[1] = Y1; poly.Z[1] = Z1;
+            poly.X[2] = X2; poly.Y[2] = Y2; poly.Z[2] = Z2;
+            clip_polygon(poly, c.pj.near_m);
+            nsub = poly.n >= 3 ? poly.n - 2 : 0;
+        }
+    }
+    const int maxsub = cmask ? wave_max(nsub) : 1;
+    for (int s = 0; s < maxsub; ++s) {
+        Setup S = {};
+        int ok = 0;
+        if (s < nsub) {
+            if (allin) {
+                ok = setup_triangle(vx0, vy0, vd0, vx1, vy1, vd1, vx2, vy2, vd2, c.rx0, c.ry0, c.R, S);
+            } else {
+                int ax, ay, bx, by, cx2, cy2;
+                float ad, bd, cd;
+                project(c.pj, poly.X[0], poly.Y[0], poly.Z[0], ax, ay, ad);
+                project(c.pj, poly.X[s + 1], poly.Y[s + 1], poly.Z[s + 1], bx, by, bd);
+                project(c.pj, poly.X[s + 2], poly.Y[s + 2], poly.Z[s + 2], cx2, cy2, cd);
+                ok = setup_triangle(ax, ay, ad, bx, by, bd, cx2, cy2, cd, c.rx0, c.ry0, c.R, S);
+            }
+        }
+        bool big = false, bal = false;
+        int npx = 0;
+        if (ok) {
+            npx = (S.px1 - S.px0 + 1) * (S.py1 - S.py0 + 1);
+            if (npx <= c.lane_max) raster_small(S, c.rx0, c.ry0, c.R, zbuf);
+            else if (npx <= c.small_max) bal = true;
+            else big = true;
+        }
+        if (stats) {
+            stat_add(stats, kStatTrisSetup, lane, __popcll(__ballot(ok != 0)));
+            const int tot = wave_incl_sum(npx, lane);
+            stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
+        }
+        if (__ballot(bal)) raster_balanced(S, bal, lane, c.rx0, c.ry0, c.R, zbuf);
+        uint64_t bmask = __ballot(big);
+        while (bmask) {
+            const int L = __ffsll((unsigned long long)bmask) - 1;
+            bmask &= bmask - 1;
+            raster_big(S, L, lane, c.rx0, c.ry0, c.R, zbuf);
+        }
+    }
+}
+
 template <int kBlock>
-__global__ __launch_bounds__(kBlock) void k_raster(RenderMesh m, RasterParams rp,
+__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(RenderMesh m, RasterParams rp,
                                                    const float *__restrict__ camera,
                                                    const int32_t *__restrict__ env_res,
                                                    const uint64_t *__restrict__ env_depth_off,
@@ -297,43 +607,61 @@ __global__ __launch_bounds__(kBlock) void k_raster(RenderMesh m, RasterParams rp
                                                    uint32_t *__restrict__ depth)
 {
     __shared__ uint32_t zbuf[kMaxRegion * kMaxRegion];
+    __shared__ uint32_t tilemax[(kMaxRegion / 8) * (kMaxRegion / 8)];
+    __shared__ uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
+    __shared__ uint16_t vis[kVisCap];
+    __shared__ int wave_cnt[kBlock / 64];
+    __shared__ int next;
+    constexpr int kWaves = kBlock / 64;
     const uint32_t item = work[blockIdx.x];
     const int env = (int)(item & 0xFFFFFu);
     const int reg = (int)(item >> 20);
     const int res = env_res[env];
-    const int R = min(res, rp.region);
-    const int nr = res / R;
-    const int rx0 = (reg % nr) * R, ry0 = (reg / nr) * R;
+    Ctx c;
+    c.R = min(res, rp.region);
+    const int nr = res / c.R;
+    c.rx0 = (reg % nr) * c.R;
+    c.ry0 = (reg / nr) * c.R;
+    c.small_max = rp.small_max;
+    c.lane_max = rp.lane_max;
+    const int R = c.R;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    constexpr int kWaves = kBlock / 64;
+    Occl oc;
+    oc.tilemax = tilemax;
+    oc.blockmax = blockmax;
+    oc.TW = (R + 7) >> 3;
+    oc.BW = (R + 31) >> 5;
 
     for (int i = threadIdx.x; i < R * R; i += kBlock) zbuf[i] = kFar;
+    for (int i = threadIdx.x; i < oc.TW * oc.TW; i += kBlock) tilemax[i] = kFar;
+    for (int i = threadIdx.x; i < oc.BW * oc.BW; i += kBlock) blockmax[i] = kFar;
 
-    Cam cam;
     {
-        const float *c = camera + (size_t)env * 12;
-        cam.px = c[0]; cam.py = c[1]; cam.pz = c[2];
-        cam.rx = c[3]; cam.ry = c[4]; cam.rz = c[5];
-        cam.dx = c[6]; cam.dy = c[7]; cam.dz = c[8];
-        cam.fx = c[9]; cam.fy = c[10]; cam.fz = c[11];
+        const float *cp = camera + (size_t)env * 12;
+        c.cam.px = cp[0]; c.cam.py = cp[1]; c.cam.pz = cp[2];
+        c.cam.rx = cp[3]; c.cam.ry = cp[4]; c.cam.rz = cp[5];
+        c.cam.dx = cp[6]; c.cam.dy = cp[7]; c.cam.dz = cp[8];
+        c.cam.fx = cp[9]; c.cam.fy = cp[10]; c.cam.fz = cp[11];
     }
-    Proj pj;
-    pj.hw = (float)res * 0.5f;
-    pj.near_m = rp.near_m;
-    pj.invn = rp.invn;
-    pj.kd = rp.kd;
+    const Cam &cam = c.cam;
+    c.pj.hw = (float)res * 0.5f;
+    c.pj.near_m = rp.near_m;
+    c.pj.invn = rp.invn;
+    c.pj.kd = rp.kd;
     // region side planes in normalised device units: x_ndc in [kl, kr]
-    const float kl = ((float)rx0 - pj.hw) / pj.hw, kr = ((float)(rx0 + R) - pj.hw) / pj.hw;
-    const float kt = ((float)ry0 - pj.hw) / pj.hw, kb = ((float)(ry0 + R) - pj.hw) / pj.hw;
+    c.kl = ((float)c.rx0 - c.pj.hw) / c.pj.hw;
+    c.kr = ((float)(c.rx0 + R) - c.pj.hw) / c.pj.hw;
+    c.kt = ((float)c.ry0 - c.pj.hw) / c.pj.hw;
+    c.kb = ((float)(c.ry0 + R) - c.pj.hw) / c.pj.hw;
     RegionPlanes P;
     {
         // camera-space plane  a*X + b*Y + c*Z + e >= 0  ->  world normal, offset
-        const float pa[5][4] = {{0.f, 0.f, 1.f, -pj.near_m},
-                                {1.f, 0.f, -kl, 0.f},
-                                {-1.f, 0.f, kr, 0.f},
-                                {0.f, 1.f, -kt, 0.f},
-                                {0.f, -1.f, kb, 0.f}};
+        const float pa[5][4] = {{0.f, 0.f, 1.f, -c.pj.near_m},
+                                {1.f, 0.f, -c.kl, 0.f},
+                                {-1.f, 0.f, c.kr, 0.f},
+                                {0.f, 1.f, -c.kt, 0.f},
+                                {0.f, -1.f, c.kb, 0.f}};
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             const float nx = pa[k][0] * cam.rx + pa[k][1] * cam.dx + pa[k][2] * cam.fx;
@@ -348,116 +676,105 @@ __global__ __launch_bounds__(kBlock) void k_raster(RenderMesh m, RasterParams rp
     __syncthreads();
 
     const uint64_t c0 = m.env_cluster_off[env], c1 = m.env_cluster_off[env + 1];
-    for (uint64_t cb = c0 + (uint64_t)wave * 64; cb < c1; cb += (uint64_t)kWaves * 64) {
-        bool vis = false;
-        const uint64_t myc = cb + lane;
-        if (myc < c1) {
-            const float4 w0 = m.clusters[myc * 3 + 0];
-            const float4 w1 = m.clusters[myc * 3 + 1];
-            vis = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z);
+    unsigned long long *stats = rp.stats;
+    // Clusters are processed in windows of up to kVisCap: the workgroup tests
+    // a window against the region frustum and compacts the visible ones, in
+    // mesh order, into an LDS list; waves then pull list entries one at a
+    // time (LDS counter), prefetching the next while drawing the current, and
+    // test each against the occlusion bounds just before drawing it.
+    for (uint64_t wbase = c0; wbase < c1; wbase += kVisCap) {
+        const int wn = (int)min((uint64_t)kVisCap, c1 - wbase);
+        // ---- ordered compaction of the frustum-visible clusters
+        int vis_total = 0;
+        for (int off = 0; off < wn; off += kBlock) {
+            const int k = off + (int)threadIdx.x;
+            bool fr = false;
+            if (k < wn) {
+                const uint64_t ci = wbase + k;
+                const float4 w0 = m.clusters[ci * 3 + 0];
+                const float4 w1 = m.clusters[ci * 3 + 1];
+                fr = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z);
+            }
+            const uint64_t bm = __ballot(fr);
+            if (lane == 0) wave_cnt[wave] = __popcll(bm);
+            __syncthreads();
+            int before = vis_total;
+            for (int w = 0; w < wave; ++w) before += wave_cnt[w];
+            int all = vis_total;
+            for (int w = 0; w < kWaves; ++w) all += wave_cnt[w];
+            if (fr) {
+                const int rank = __popcll(bm & ((1ull << lane) - 1ull));
+                vis[before + rank] = (uint16_t)k;
+            }
+            __syncthreads();
+            vis_total = all;
         }
-        uint64_t vmask = __ballot(vis);
-        while (vmask) {
-            const int bit = __ffsll((unsigned long long)vmask) - 1;
-            vmask &= vmask - 1;
-            const uint64_t ci = cb + bit;
-            const float4 w0 = m.clusters[ci * 3 + 0];
-            const float4 w1 = m.clusters[ci * 3 + 1];
+        if (stats) {
+            if (threadIdx.x == 0) {
+                atomicAdd(&stats[kStatBatchClusters], (unsigned long long)wn);
+                atomicAdd(&stats[kStatFrustumVisible], (unsigned long long)vis_total);
+            }
+        }
+        if (threadIdx.x == 0) next = 0;
+        __syncthreads();
+        // ---- waves pull visible clusters
+        int drawn = 0, hidden = 0;
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&next, 1);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        ClusterData cd;
+        float4 cw0, cw1;
+        if (idx < vis_total) {
+            const uint64_t ci = wbase + vis[idx];
+            cw0 = m.clusters[ci * 3 + 0];
+            cw1 = m.clusters[ci * 3 + 1];
             const float4 w2 = m.clusters[ci * 3 + 2];
-            const uint32_t vbase = __float_as_uint(w0.w);
-            const uint32_t tbase = __float_as_uint(w1.w);
-            const uint32_t cnt = __float_as_uint(w2.x);
-            const int nv = (int)(cnt & 0xFF), nt = (int)((cnt >> 8) & 0xFF);
-
-            // ---- per vertex: camera space, outcodes, projection
-            float X = 0.f, Y = 0.f, Z = 1.f;
-            uint32_t oc = 0;
-            int xi = 0, yi = 0;
-            float dv = 0.f;
-            if (lane < nv) {
-                const float *v = m.cverts + ((size_t)vbase + lane) * 3;
-                const float ddx = v[0] - cam.px, ddy = v[1] - cam.py, ddz = v[2] - cam.pz;
-                X = (cam.rx * ddx + cam.ry * ddy) + cam.rz * ddz;
-                Y = (cam.dx * ddx + cam.dy * ddy) + cam.dz * ddz;
-                Z = (cam.fx * ddx + cam.fy * ddy) + cam.fz * ddz;
-#pragma unroll
-                for (int k = 0; k < 5; ++k)
-                    if (clip_plane(X, Y, Z, k, pj.near_m) < 0.0f) oc |= 1u << k;
-                if (X - kl * Z < 0.0f) oc |= 1u << 5;
-                if (kr * Z - X < 0.0f) oc |= 1u << 6;
-                if (Y - kt * Z < 0.0f) oc |= 1u << 7;
-                if (kb * Z - Y < 0.0f) oc |= 1u << 8;
-                if ((oc & 1u) == 0) project(pj, X, Y, Z, xi, yi, dv);
-            }
-
-            // ---- per triangle
-            const uint32_t packed = lane < nt ? m.ctris[(size_t)tbase + lane] : 0u;
-            const int i0 = (int)(packed & 0xFF), i1 = (int)((packed >> 8) & 0xFF),
-                      i2 = (int)((packed >> 16) & 0xFF);
-            const uint32_t o0 = (uint32_t)__shfl((int)oc, i0, 64);
-            const uint32_t o1 = (uint32_t)__shfl((int)oc, i1, 64);
-            const uint32_t o2 = (uint32_t)__shfl((int)oc, i2, 64);
-            const bool valid = lane < nt && (o0 & o1 & o2) == 0u;
-            const bool allin = valid && ((o0 | o1 | o2) & kClipBits) == 0u;
-            const bool clipped = valid && !allin;
-            const int vx0 = __shfl(xi, i0, 64), vy0 = __shfl(yi, i0, 64);
-            const int vx1 = __shfl(xi, i1, 64), vy1 = __shfl(yi, i1, 64);
-            const int vx2 = __shfl(xi, i2, 64), vy2 = __shfl(yi, i2, 64);
-            const float vd0 = __shfl(dv, i0, 64), vd1 = __shfl(dv, i1, 64), vd2 = __shfl(dv, i2, 64);
-
-            int nsub = allin ? 1 : 0;
-            Poly poly;
-            poly.n = 0;
-            if (__ballot(clipped)) {
-                const float X0 = __shfl(X, i0, 64), Y0 = __shfl(Y, i0, 64), Z0 = __shfl(Z, i0, 64);
-                const float X1 = __shfl(X, i1, 64), Y1 = __shfl(Y, i1, 64), Z1 = __shfl(Z, i1, 64);
-                const float X2 = __shfl(X, i2, 64), Y2 = __shfl(Y, i2, 64), Z2 = __shfl(Z, i2, 64);
-                if (clipped) {
-                    poly.n = 3;
-                    poly.X[0] = X0; poly.Y[0] = Y0; poly.Z[0] = Z0;
-                    poly.X[1] = X1; poly.Y[1] = Y1; poly.Z[1] = Z1;
-                    poly.X[2] = X2; poly.Y[2] = Y2; poly.Z[2] = Z2;
-                    clip_polygon(poly, pj.near_m);
-                    nsub = poly.n >= 3 ? poly.n - 2 : 0;
-                }
-            }
-            const int maxsub = wave_max(nsub);
-            for (int s = 0; s < maxsub; ++s) {
-                Setup S;
-                int ok = 0;
-                if (s < nsub) {
-                    if (allin) {
-                        ok = setup_triangle(vx0, vy0, vd0, vx1, vy1, vd1, vx2, vy2, vd2, rx0, ry0,
-                                            R, S);
-                    } else {
-                        int ax, ay, bx, by, cx2, cy2;
-                        float ad, bd, cd;
-                        project(pj, poly.X[0], poly.Y[0], poly.Z[0], ax, ay, ad);
-                        project(pj, poly.X[s + 1], poly.Y[s + 1], poly.Z[s + 1], bx, by, bd);
-                        project(pj, poly.X[s + 2], poly.Y[s + 2], poly.Z[s + 2], cx2, cy2, cd);
-                        ok = setup_triangle(ax, ay, ad, bx, by, bd, cx2, cy2, cd, rx0, ry0, R, S);
-                    }
-                }
-                bool big = false;
-                if (ok) {
-                    const int npx = (S.px1 - S.px0 + 1) * (S.py1 - S.py0 + 1);
-                    if (npx <= rp.small_max) raster_small(S, rx0, ry0, R, zbuf);
-                    else big = true;
-                }
-                uint64_t bmask = __ballot(big);
-                while (bmask) {
-                    const int L = __ffsll((unsigned long long)bmask) - 1;
-                    bmask &= bmask - 1;
-                    raster_big(S, L, lane, rx0, ry0, R, zbuf);
-                }
-            }
+            fetch_cluster(m, __float_as_uint(cw0.w), __float_as_uint(cw1.w), __float_as_uint(w2.x),
+                          lane, cd);
         }
+        int since_refresh = 0;
+        while (idx < vis_total) {
+            int nidx = 0;
+            if (lane == 0) nidx = atomicAdd(&next, 1);
+            nidx = __builtin_amdgcn_readfirstlane(nidx);
+            ClusterData nd;
+            float4 nw0, nw1;
+            if (nidx < vis_total) {
+                const uint64_t ci = wbase + vis[nidx];
+                nw0 = m.clusters[ci * 3 + 0];
+                nw1 = m.clusters[ci * 3 + 1];
+                const float4 w2 = m.clusters[ci * 3 + 2];
+                fetch_cluster(m, __float_as_uint(nw0.w), __float_as_uint(nw1.w),
+                              __float_as_uint(w2.x), lane, nd);
+            }
+            const bool hide = rp.occlusion && idx >= rp.prologue &&
+                              cluster_hidden_wave(cam, c.pj, oc, c.rx0, c.ry0, R, cw0, cw1);
+            if (!hide) {
+                draw_cluster(c, cd, lane, zbuf, stats);
+                ++drawn;
+                if (rp.occlusion && ++since_refresh >= rp.refresh) {
+                    refresh_bounds(zbuf, oc, R, wave, kWaves, lane);
+                    since_refresh = 0;
+                }
+            } else {
+                ++hidden;
+            }
+            idx = nidx;
+            cd = nd;
+            cw0 = nw0;
+            cw1 = nw1;
+        }
+        if (stats) {
+            stat_add(stats, kStatOccluded, lane, (uint64_t)hidden);
+            stat_add(stats, kStatDrawn, lane, (uint64_t)drawn);
+        }
+        __syncthreads();
     }
     __syncthreads();
     uint32_t *dst = depth + env_depth_off[env];
     for (int i = threadIdx.x; i < R * R; i += kBlock) {
         const int y = i / R, x = i - y * R;
-        dst[(size_t)(ry0 + y) * res + (rx0 + x)] = zbuf[i];
+        dst[(size_t)(c.ry0 + y) * res + (c.rx0 + x)] = zbuf[i];
     }
 }
 
@@ -468,8 +785,20 @@ hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const floa
                          const uint32_t *work, int32_t num_work, uint32_t *depth, hipStream_t s)
 {
     if (num_work <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster<256>, dim3(num_work), dim3(256), 0, s, m, rp, camera, env_res,
-                       env_depth_off, work, depth);
+    switch (rp.block) {
+    case 256:
+        hipLaunchKernelGGL(k_raster<256>, dim3(num_work), dim3(256), 0, s, m, rp, camera, env_res,
+                           env_depth_off, work, depth);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(k_raster<1024>, dim3(num_work), dim3(1024), 0, s, m, rp, camera,
+                           env_res, env_depth_off, work, depth);
+        break;
+    default:
+        hipLaunchKernelGGL(k_raster<512>, dim3(num_work), dim3(512), 0, s, m, rp, camera, env_res,
+                           env_depth_off, work, depth);
+        break;
+    }
     return hipGetLastError();
 }
 

@@ -51,6 +51,12 @@ class GalConfig(C.Structure):
                 ("episode_len", C.c_int32), ("flags", C.c_uint32)]
 
 
+class GalTuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("region", C.c_int32), ("lane_max", C.c_int32),
+                ("small_max", C.c_int32),
+                ("refresh", C.c_int32), ("occlusion", C.c_int32), ("prologue", C.c_int32)]
+
+
 class GalOutputs(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("rgb", C.c_void_p), ("contact_static", C.c_void_p),
                 ("contact_object", C.c_void_p), ("accepted", C.c_void_p), ("state", C.c_void_p),
@@ -83,6 +89,10 @@ def load_library():
         L.gal_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        _i64p]
         L.gal_mesh_info.argtypes = [C.c_void_p, _i64p, _i64p, _i64p]
+        L.gal_counters_enable.argtypes = [C.c_void_p, C.c_int]
+        L.gal_counters_read.argtypes = [C.c_void_p, _i64p, C.c_size_t]
+        L.gal_get_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
+        L.gal_set_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
         L.gal_destroy.argtypes = [C.c_void_p]
         L.gal_destroy.restype = None
         L.gal_last_error.restype = C.c_char_p
@@ -189,11 +199,17 @@ class Batch:
         self.depth_off = off
         self.res = np.asarray(S.res, np.int32).copy()
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            load_library().gal_destroy(h)
-            self._h = None
+        if h is not None and h.value and _lib is not None:
+            _lib.gal_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def alloc_outputs(self, device="cuda") -> Dict[str, "object"]:
         import torch
@@ -249,6 +265,28 @@ class Batch:
         _check(L.gal_get_grid(self._h, env, cls, _p(offs, _u32p), offs.size, _p(lay, _fp),
                               n.value, C.byref(n)))
         return offs, lay[:n.value]
+
+    def get_tuning(self) -> dict:
+        t = GalTuning()
+        _check(load_library().gal_get_tuning(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in GalTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = GalTuning(**cur)
+        _check(load_library().gal_set_tuning(self._h, C.byref(t)))
+
+    COUNTERS = ("clusters_tested", "clusters_in_frustum", "clusters_occluded", "clusters_drawn",
+                "tris_valid", "tris_clipped", "tris_setup", "cand_pixels")
+
+    def counters(self, on: bool):
+        _check(load_library().gal_counters_enable(self._h, 1 if on else 0))
+
+    def counters_read(self) -> dict:
+        v = np.zeros(len(self.COUNTERS), np.int64)
+        _check(load_library().gal_counters_read(self._h, _p(v, _i64p), v.size))
+        return dict(zip(self.COUNTERS, (int(x) for x in v)))
 
     def profile(self, on: bool):
         _check(load_library().gal_profile_enable(self._h, 1 if on else 0))

@@ -176,3 +176,30 @@ def test_repeatable(torch_cuda):
         torch.cuda.synchronize()
         res.append(u32(out["depth"]).copy())
     assert np.array_equal(res[0], res[1])
+
+
+TUNINGS = [
+    dict(block=256, region=128, lane_max=16, small_max=16, refresh=4, occlusion=0, prologue=0),
+    dict(block=512, region=64, lane_max=0, small_max=1024, refresh=16, occlusion=1, prologue=8),
+    dict(block=1024, region=32, lane_max=4096, small_max=4096, refresh=1, occlusion=1, prologue=0),
+    dict(block=512, region=128, lane_max=8, small_max=64, refresh=64, occlusion=1, prologue=64),
+    dict(block=512, region=128, lane_max=0, small_max=65536, refresh=16, occlusion=1, prologue=8),
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=[f"t{i}" for i in range(len(TUNINGS))])
+def test_tuning_invariance(torch_cuda, tuning):
+    """Every launch configuration the autotuner may pick gives the oracle's bits
+    (paper-scale scenes, 128x128 and 256x256)."""
+    torch = torch_cuda
+    print(f"case: tuning {tuning}", flush=True)
+    cfg = sg.scaled_config(2, 12, tri_target=(20000.0, 80000.0))
+    b, ob, scenes, robot = make_pair(cfg, oracle_envs=list(range(12)))
+    b.set_tuning(**tuning)
+    assert b.get_tuning() == tuning
+    out = b.alloc_outputs()
+    for k in range(3):
+        a = sg.actions(cfg, k, num_envs=12)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        compare_step(b, ob, out, ob.step(a), label=f"step {k}")

@@ -287,3 +287,31 @@ def test_backfaces_are_culled(oracle_lib):
     v, t = sg.quad_mesh((2.0, -0.5, -0.5), (0, 1.0, 0), (0, 0, 1.0))
     d, _, _, st = render(O, v, t, cam, 64)
     assert (d == 0xFFFFFF).all() and st["tris_front"] == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fragment_depth_within_vertex_range_for_slivers(oracle_lib, seed):
+    """Depth is a convex combination of the vertex depths (barycentric
+    weights from the integer edge functions): even for long, thin triangles
+    spanning a large depth range, every covered pixel lies within the FP32
+    budget of the analytic vertex-depth range."""
+    O = oracle_lib
+    rng = np.random.default_rng(900 + seed)
+    cam = cam_look([0, 0, 0], 0.0)
+    hits = 0
+    for _ in range(150):
+        a = np.array([rng.uniform(0.15, 1.0), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5)])
+        b = np.array([rng.uniform(3, 9.5), rng.uniform(-6, 6), rng.uniform(-6, 6)])
+        c = a + (b - a) * rng.uniform(0.1, 0.9) + rng.normal(0, 10 ** rng.uniform(-6, -3), 3)
+        v = np.array([a, b, c], np.float32)
+        for t in (np.array([[0, 1, 2]]), np.array([[0, 2, 1]])):
+            depth, _, cov, _ = render(O, v, t, cam, 128, want_cover=True)
+            if cov.sum() == 0:
+                continue
+            hits += 1
+            Z = v[:, 0].astype(np.float64)            # camera forward = world +x
+            lo, hi = d24_exact(Z.min()), d24_exact(Z.max())
+            got = depth[cov > 0].astype(np.float64)
+            slack = 1.0 + 8.0 * REL_BUDGET * hi
+            assert got.min() >= lo - slack and got.max() <= hi + slack
+    assert hits > 20
