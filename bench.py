@@ -18,6 +18,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(kernel_sources, record):
+    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE record,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", record)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                for f in kernel_sources)).hexdigest()
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == h else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -131,8 +144,13 @@ def main():
     raster_bytes = mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4 + 4 * b.depth_pixels
     raster_s = raster_ms / nsteps / 1e3
     achieved = raster_bytes / raster_s / 1e9
+    traffic = None
+    if args.config == 1 and not cfg.color:
+        traffic = measured_traffic(["paper_2306_07552_amd/csrc/k_raster.hip",
+                                    "paper_2306_07552_amd/csrc/gal_internal.h"],
+                                   "k_raster_1024env_128px_traffic.json")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_raster", "algorithmic_bytes_per_launch": int(raster_bytes),
                 "avg_launch_ms": round(raster_ms / nsteps, 5)}
 

@@ -157,6 +157,7 @@ struct gal_batch {
     uint64_t *d_depth_off = nullptr;
     uint32_t *d_work = nullptr;
     int32_t num_work = 0;
+    int32_t max_res = 0;
     int64_t n_clusters = 0, n_cverts = 0, n_tris = 0;
     unsigned long long *d_stats = nullptr;  // raster work counters (allocated on demand)
     std::vector<int64_t> cl_count_host;    // clusters per env
@@ -332,6 +333,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         if (r > gal::kMaxRegion && (r % gal::kMaxRegion) != 0)
             return cleanup(fail(GAL_EINVAL, "env %d: resolution %d must be a multiple of %d", e, r, gal::kMaxRegion));
         b->res_host[e] = r;
+        b->max_res = std::max(b->max_res, r);
         b->depth_off_host[e + 1] = b->depth_off_host[e] + (int64_t)r * r;
     }
     for (int64_t i = 0; i < sc->box_offset[N]; ++i) {
@@ -585,6 +587,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         for (int e = 0; e <= N; ++e) doff[e] = (uint64_t)b->depth_off_host[e];
         HIP_TRY(hipMemcpy(b->d_depth_off, doff.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
         if ((rc = build_work(b))) return cleanup(rc);
+        HIP_TRY(gal::raster_prepare());
     }
 
     // ---- initial state: episode 0 at the first start pose (reset from episode -1)
@@ -633,7 +636,7 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
     HIP_TRY(gal::launch_robot_step(b->rp, b->sb, actions_dev, so, s));
     if (b->profiling) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
-                               b->num_work, out->depth, s));
+                               b->num_work, b->max_res, out->depth, out->rgb, s));
     if (b->profiling) {
         HIP_TRY(hipEventRecord(ev[2], s));
         b->ev_rec.insert(b->ev_rec.end(), ev, ev + 3);

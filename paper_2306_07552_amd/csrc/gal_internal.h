@@ -114,10 +114,11 @@ hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const 
                              const StepOutputs &out, hipStream_t s);
 hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
                         hipStream_t s);
+hipError_t raster_prepare();   // raises the dynamic-LDS limit of the raster kernels
 hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
                          const int32_t *env_res, const uint64_t *env_depth_off,
-                         const uint32_t *work, int32_t num_work, uint32_t *depth,
-                         hipStream_t s);
+                         const uint32_t *work, int32_t num_work, int32_t max_region,
+                         uint32_t *depth, uint8_t *rgb, hipStream_t s);
 hipError_t launch_grid_count(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
                              int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
                              int32_t max_cols, uint32_t *counts, int32_t *overflow, hipStream_t s);

@@ -28,6 +28,8 @@
 // triangles that cannot cover a pixel centre of the region.
 #include "gal_internal.h"
 
+#include <type_traits>
+
 namespace gal {
 
 namespace {
@@ -192,8 +194,32 @@ __device__ __forceinline__ uint32_t frag_depth(int e0, int e1, int e2, float q0,
     return depth24(dv);
 }
 
-__device__ __forceinline__ void raster_small(const Setup &S, int rx0, int ry0, int R,
-                                             uint32_t *zbuf)
+// Z-buffer sinks in LDS: depth only (u32, 24-bit depth) or depth and colour
+// (u64 key = depth << 32 | triangle id: the smallest depth wins, ties go to
+// the smallest triangle id).
+struct DepthSink {
+    uint32_t *z;
+    __device__ __forceinline__ void put(int p, uint32_t D, uint32_t) const { atomicMin(&z[p], D); }
+    __device__ __forceinline__ uint32_t depth_at(int p) const { return z[p]; }
+    __device__ __forceinline__ void clear(int p) const { z[p] = kFar; }
+};
+
+struct ColorSink {
+    unsigned long long *k;
+    __device__ __forceinline__ void put(int p, uint32_t D, uint32_t id) const
+    {
+        atomicMin(&k[p], ((unsigned long long)D << 32) | (unsigned long long)id);
+    }
+    __device__ __forceinline__ uint32_t depth_at(int p) const { return (uint32_t)(k[p] >> 32); }
+    __device__ __forceinline__ void clear(int p) const
+    {
+        k[p] = ((unsigned long long)kFar << 32) | 0xFFFFFFFFull;
+    }
+};
+
+template <class Sink>
+__device__ __forceinline__ void raster_small(const Setup &S, uint32_t id, int rx0, int ry0, int R,
+                                             const Sink &zb)
 {
     // edge k from vertex i to j: E = (xj-xi)(Py-yi) - (yj-yi)(Px-xi)
     const int ex0 = S.x2 - S.x1, ey0 = S.y2 - S.y1;
@@ -210,7 +236,7 @@ __device__ __forceinline__ void raster_small(const Setup &S, int rx0, int ry0, i
         for (int px = S.px0; px <= S.px1; ++px) {
             if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
                 const uint32_t D = frag_depth(e0, e1, e2, S.q0, S.q1, S.q2);
-                if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
+                if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, id);
             }
             e0 -= 16 * ey0;
             e1 -= 16 * ey1;
@@ -229,9 +255,11 @@ __device__ __forceinline__ float rlf(float v, int l)
 }
 
 // The whole wave rasterises lane L's triangle, one 8x8 tile at a time.
-__device__ __forceinline__ void raster_big(const Setup &S, int L, int lane, int rx0, int ry0,
-                                           int R, uint32_t *zbuf)
+template <class Sink>
+__device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L, int lane, int rx0,
+                                           int ry0, int R, const Sink &zb)
 {
+    const uint32_t id = (uint32_t)rl((int)myid, L);
     const int x0 = rl(S.x0, L), y0 = rl(S.y0, L);
     const int x1 = rl(S.x1, L), y1 = rl(S.y1, L);
     const int x2 = rl(S.x2, L), y2 = rl(S.y2, L);
@@ -256,7 +284,7 @@ __device__ __forceinline__ void raster_big(const Setup &S, int L, int lane, int 
             const int e2 = ex2 * (Py - y0) - ey2 * (Px - x0);
             if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
                 const uint32_t D = frag_depth(e0, e1, e2, q0, q1, q2);
-                if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
+                if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, id);
             }
         }
     }
@@ -276,8 +304,9 @@ __device__ __forceinline__ int wave_incl_sum(int v, int lane)
 // all bboxes are numbered by a wave prefix sum, lane l takes pixels
 // l, l + 64, ... and finds the owning triangle by binary search over the
 // prefix (ds_bpermute); the triangle's record is fetched from its lane.
-__device__ __forceinline__ void raster_balanced(const Setup &S, bool mine, int lane, int rx0,
-                                                int ry0, int R, uint32_t *zbuf)
+template <class Sink>
+__device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, bool mine, int lane,
+                                                int rx0, int ry0, int R, const Sink &zb)
 {
     const int w = mine ? S.px1 - S.px0 + 1 : 0;
     const int h = mine ? S.py1 - S.py0 + 1 : 0;
@@ -305,6 +334,7 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, bool mine, int l
         const int tmeta = __shfl(meta, t, 64);
         const float tq0 = __shfl(S.q0, t, 64), tq1 = __shfl(S.q1, t, 64), tq2 = __shfl(S.q2, t, 64);
         const float tinvw = __shfl(invw, t, 64);
+        const uint32_t tid = (uint32_t)__shfl((int)myid, t, 64);
         if (g >= total) continue;
         const int tw = ((tmeta >> 18) & 0x1FF) + 1;
         const int oy = (int)(((float)local + 0.5f) * tinvw);
@@ -320,7 +350,7 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, bool mine, int l
         const int e2 = (x1 - x0) * (Py - y0) - (y1 - y0) * (Px - x0);
         if (e0 >= (tb & 1) && e1 >= ((tb >> 1) & 1) && e2 >= ((tb >> 2) & 1)) {
             const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
-            if (D < kFar) atomicMin(&zbuf[(py - ry0) * R + (px - rx0)], D);
+            if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, tid);
         }
     }
 }
@@ -425,14 +455,15 @@ __device__ __forceinline__ bool cluster_hidden_wave(const Cam &cam, const Proj &
 }
 
 // This wave's share of the bound refresh: tiles w, w+W, ..., then blocks.
-__device__ __forceinline__ void refresh_bounds(const uint32_t *zbuf, const Occl &oc, int R,
+template <class Sink>
+__device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, int R,
                                                int wave, int nwaves, int lane)
 {
     const int lx = lane & 7, ly = lane >> 3;
     for (int t = wave; t < oc.TW * oc.TW; t += nwaves) {
         const int tx = t % oc.TW, ty = t / oc.TW;
         const int px = tx * 8 + lx, py = ty * 8 + ly;
-        const int v = (px < R && py < R) ? (int)zbuf[py * R + px] : 0;
+        const int v = (px < R && py < R) ? (int)zb.depth_at(py * R + px) : 0;
         const int m = wave_max(v);
         if (lane == 0) atomicMin(&oc.tilemax[t], (uint32_t)m);
     }
@@ -460,11 +491,13 @@ struct ClusterData {
     float vx, vy, vz;
     uint32_t packed;
     int nv, nt;
+    uint32_t first;   // env-local index of the cluster's first triangle
 };
 
 __device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint32_t vbase, uint32_t tbase,
-                                              uint32_t cnt, int lane, ClusterData &d)
+                                              uint32_t cnt, uint32_t first, int lane, ClusterData &d)
 {
+    d.first = first;
     d.nv = (int)(cnt & 0xFF);
     d.nt = (int)((cnt >> 8) & 0xFF);
     d.vx = d.vy = d.vz = 0.f;
@@ -497,9 +530,11 @@ __device__ __forceinline__ void stat_add(unsigned long long *stats, int k, int l
 }
 
 // Draw one cluster.
-__device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, uint32_t *zbuf,
+template <class Sink>
+__device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const Sink &zb,
                              unsigned long long *stats)
 {
+    const uint32_t myid = d.first + (uint32_t)lane;
     const Cam &cam = c.cam;
     const int nv = d.nv, nt = d.nt;
 
@@ -579,7 +614,7 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, uint3
         int npx = 0;
         if (ok) {
             npx = (S.px1 - S.px0 + 1) * (S.py1 - S.py0 + 1);
-            if (npx <= c.lane_max) raster_small(S, c.rx0, c.ry0, c.R, zbuf);
+            if (npx <= c.lane_max) raster_small(S, myid, c.rx0, c.ry0, c.R, zb);
             else if (npx <= c.small_max) bal = true;
             else big = true;
         }
@@ -588,25 +623,31 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, uint3
             const int tot = wave_incl_sum(npx, lane);
             stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
         }
-        if (__ballot(bal)) raster_balanced(S, bal, lane, c.rx0, c.ry0, c.R, zbuf);
+        if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.R, zb);
         uint64_t bmask = __ballot(big);
         while (bmask) {
             const int L = __ffsll((unsigned long long)bmask) - 1;
             bmask &= bmask - 1;
-            raster_big(S, L, lane, c.rx0, c.ry0, c.R, zbuf);
+            raster_big(S, myid, L, lane, c.rx0, c.ry0, c.R, zb);
         }
     }
 }
 
-template <int kBlock>
+template <int kBlock, bool kColor>
 __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(RenderMesh m, RasterParams rp,
                                                    const float *__restrict__ camera,
                                                    const int32_t *__restrict__ env_res,
                                                    const uint64_t *__restrict__ env_depth_off,
                                                    const uint32_t *__restrict__ work,
-                                                   uint32_t *__restrict__ depth)
+                                                   uint32_t *__restrict__ depth,
+                                                   uint8_t *__restrict__ rgb)
 {
-    __shared__ uint32_t zbuf[kMaxRegion * kMaxRegion];
+    // the region's z-buffer: dynamic LDS of R*R u32 (depth) or u64 (colour)
+    extern __shared__ unsigned long long zdyn[];
+    using SinkT = typename std::conditional<kColor, ColorSink, DepthSink>::type;
+    SinkT zb;
+    if constexpr (kColor) zb.k = zdyn;
+    else zb.z = reinterpret_cast<uint32_t *>(zdyn);
     __shared__ uint32_t tilemax[(kMaxRegion / 8) * (kMaxRegion / 8)];
     __shared__ uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
     __shared__ uint16_t vis[kVisCap];
@@ -633,7 +674,7 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(Rend
     oc.TW = (R + 7) >> 3;
     oc.BW = (R + 31) >> 5;
 
-    for (int i = threadIdx.x; i < R * R; i += kBlock) zbuf[i] = kFar;
+    for (int i = threadIdx.x; i < R * R; i += kBlock) zb.clear(i);
     for (int i = threadIdx.x; i < oc.TW * oc.TW; i += kBlock) tilemax[i] = kFar;
     for (int i = threadIdx.x; i < oc.BW * oc.BW; i += kBlock) blockmax[i] = kFar;
 
@@ -730,7 +771,7 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(Rend
             cw1 = m.clusters[ci * 3 + 1];
             const float4 w2 = m.clusters[ci * 3 + 2];
             fetch_cluster(m, __float_as_uint(cw0.w), __float_as_uint(cw1.w), __float_as_uint(w2.x),
-                          lane, cd);
+                          __float_as_uint(w2.y), lane, cd);
         }
         int since_refresh = 0;
         while (idx < vis_total) {
@@ -745,15 +786,15 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(Rend
                 nw1 = m.clusters[ci * 3 + 1];
                 const float4 w2 = m.clusters[ci * 3 + 2];
                 fetch_cluster(m, __float_as_uint(nw0.w), __float_as_uint(nw1.w),
-                              __float_as_uint(w2.x), lane, nd);
+                              __float_as_uint(w2.x), __float_as_uint(w2.y), lane, nd);
             }
             const bool hide = rp.occlusion && idx >= rp.prologue &&
                               cluster_hidden_wave(cam, c.pj, oc, c.rx0, c.ry0, R, cw0, cw1);
             if (!hide) {
-                draw_cluster(c, cd, lane, zbuf, stats);
+                draw_cluster(c, cd, lane, zb, stats);
                 ++drawn;
                 if (rp.occlusion && ++since_refresh >= rp.refresh) {
-                    refresh_bounds(zbuf, oc, R, wave, kWaves, lane);
+                    refresh_bounds(zb, oc, R, wave, kWaves, lane);
                     since_refresh = 0;
                 }
             } else {
@@ -771,35 +812,89 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(Rend
         __syncthreads();
     }
     __syncthreads();
-    uint32_t *dst = depth + env_depth_off[env];
+    const uint64_t doff = env_depth_off[env];
+    uint32_t *dst = depth + doff;
     for (int i = threadIdx.x; i < R * R; i += kBlock) {
         const int y = i / R, x = i - y * R;
-        dst[(size_t)(c.ry0 + y) * res + (c.rx0 + x)] = zbuf[i];
+        const size_t o = (size_t)(c.ry0 + y) * res + (c.rx0 + x);
+        if constexpr (kColor) {
+            const unsigned long long key = zdyn[i];
+            const uint32_t D = (uint32_t)(key >> 32);
+            dst[o] = D;
+            if (rgb) {
+                uint8_t r = 0, g = 0, bch = 0;
+                if (D < kFar) {
+                    const uint8_t *cc = m.tri_rgb + (m.env_tri_off[env] + (key & 0xFFFFFFFFull)) * 3;
+                    r = cc[0];
+                    g = cc[1];
+                    bch = cc[2];
+                }
+                uint8_t *px = rgb + (doff + o) * 3;
+                px[0] = r;
+                px[1] = g;
+                px[2] = bch;
+            }
+        } else {
+            dst[o] = zb.depth_at(i);
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
-                         const int32_t *env_res, const uint64_t *env_depth_off,
-                         const uint32_t *work, int32_t num_work, uint32_t *depth, hipStream_t s)
+template <bool kColor>
+hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const float *camera,
+                           const int32_t *env_res, const uint64_t *env_depth_off,
+                           const uint32_t *work, int32_t num_work, uint32_t *depth, uint8_t *rgb,
+                           size_t lds, hipStream_t s)
 {
-    if (num_work <= 0) return hipSuccess;
     switch (rp.block) {
     case 256:
-        hipLaunchKernelGGL(k_raster<256>, dim3(num_work), dim3(256), 0, s, m, rp, camera, env_res,
-                           env_depth_off, work, depth);
+        hipLaunchKernelGGL((k_raster<256, kColor>), dim3(num_work), dim3(256), lds, s, m, rp, camera,
+                           env_res, env_depth_off, work, depth, rgb);
         break;
     case 1024:
-        hipLaunchKernelGGL(k_raster<1024>, dim3(num_work), dim3(1024), 0, s, m, rp, camera,
-                           env_res, env_depth_off, work, depth);
+        hipLaunchKernelGGL((k_raster<1024, kColor>), dim3(num_work), dim3(1024), lds, s, m, rp,
+                           camera, env_res, env_depth_off, work, depth, rgb);
         break;
     default:
-        hipLaunchKernelGGL(k_raster<512>, dim3(num_work), dim3(512), 0, s, m, rp, camera, env_res,
-                           env_depth_off, work, depth);
+        hipLaunchKernelGGL((k_raster<512, kColor>), dim3(num_work), dim3(512), lds, s, m, rp, camera,
+                           env_res, env_depth_off, work, depth, rgb);
         break;
     }
     return hipGetLastError();
+}
+
+template <bool kColor>
+hipError_t allow_lds(const void *f)
+{
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kMaxRegion * kMaxRegion * (kColor ? 8 : 4)));
+}
+
+hipError_t raster_prepare()
+{
+    hipError_t e;
+    if ((e = allow_lds<false>((const void *)k_raster<256, false>)) != hipSuccess) return e;
+    if ((e = allow_lds<false>((const void *)k_raster<512, false>)) != hipSuccess) return e;
+    if ((e = allow_lds<false>((const void *)k_raster<1024, false>)) != hipSuccess) return e;
+    if ((e = allow_lds<true>((const void *)k_raster<256, true>)) != hipSuccess) return e;
+    if ((e = allow_lds<true>((const void *)k_raster<512, true>)) != hipSuccess) return e;
+    return allow_lds<true>((const void *)k_raster<1024, true>);
+}
+
+hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
+                         const int32_t *env_res, const uint64_t *env_depth_off,
+                         const uint32_t *work, int32_t num_work, int32_t max_region,
+                         uint32_t *depth, uint8_t *rgb, hipStream_t s)
+{
+    if (num_work <= 0) return hipSuccess;
+    const int R = max_region < rp.region ? max_region : rp.region;
+    if (rgb)
+        return launch_raster_t<true>(m, rp, camera, env_res, env_depth_off, work, num_work, depth,
+                                     rgb, (size_t)R * R * 8, s);
+    return launch_raster_t<false>(m, rp, camera, env_res, env_depth_off, work, num_work, depth,
+                                  nullptr, (size_t)R * R * 4, s);
 }
 
 }  // namespace gal

@@ -203,3 +203,31 @@ def test_tuning_invariance(torch_cuda, tuning):
         b.step(torch.from_numpy(a).cuda(), out)
         torch.cuda.synchronize()
         compare_step(b, ob, out, ob.step(a), label=f"step {k}")
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(block=512, region=128, lane_max=4, small_max=256, refresh=4, occlusion=0, prologue=8),
+    dict(block=256, region=64, lane_max=0, small_max=64, refresh=4, occlusion=1, prologue=8),
+], ids=["r128", "r64-occl"])
+def test_color_parity(torch_cuda, tuning):
+    """Flat colour: the winning triangle (smallest depth, then smallest id)
+    and its seeded colour, mixed scene sizes and 64/128/256 resolutions."""
+    torch = torch_cuda
+    print(f"case: colour {tuning}", flush=True)
+    cfg = sg.scaled_config(4, 10, tri_target=(2000.0, 60000.0))
+    scenes = sg.make_scene_set(cfg)
+    scenes.res[:] = [128, 64, 256, 128, 128, 64, 256, 128, 64, 128]
+    from oracle import oracle as O
+    from paper_2306_07552_amd import gal
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    b = gal.Batch(robot, scenes, consts, color=True)
+    b.set_tuning(**tuning)
+    ob = O.OracleBatch(robot, scenes, consts, color=True)
+    out = b.alloc_outputs()
+    assert "rgb" in out
+    for k in range(3):
+        a = sg.actions(cfg, k, num_envs=10)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        compare_step(b, ob, out, ob.step(a), label=f"step {k}")
