@@ -198,6 +198,14 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *  occlusion  1 = skip clusters provably hidden behind conservative z-buffer
  *             bounds, 0 = frustum culling only
  *  prologue   clusters drawn before occlusion culling starts (>= 0)
+ *  persistent 1 = one persistent raster kernel whose workgroups drain the
+ *             (env, region) work queue, longest items first; 0 = one
+ *             workgroup per item
+ *  robot_lanes lanes per environment in the robot-step kernel: 64 (one env
+ *             per wave) or 32 (two envs per wave)
+ *  graph      1 = gal_step replays the whole step as a captured hipGraph
+ *             (re-captured when the action/output pointers or the tuning
+ *             change; not used while gal_profile is enabled)
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -207,12 +215,28 @@ typedef struct gal_tuning {
     int32_t refresh;
     int32_t occlusion;
     int32_t prologue;
+    int32_t persistent;
+    int32_t robot_lanes;
+    int32_t graph;
 } gal_tuning;
 
 int gal_get_tuning(const gal_batch *b, gal_tuning *t);
 /* Errors: GAL_EINVAL for values out of range.  Not to be called while a step
  * on the batch is in flight on another stream. */
 int gal_set_tuning(gal_batch *b, const gal_tuning *t);
+
+/*
+ * Autotuner: times the candidate launch configurations (raster workgroup
+ * size, region, small-triangle thresholds, occlusion culling, persistent
+ * queue, robot lanes per env) on this batch with the given actions and
+ * outputs (`steps` timed steps each, HIP events), checks that every
+ * candidate produces the same depth bits from the same state, keeps the
+ * fastest (also written to *best, with its time per step in *best_ms) and
+ * restores the simulation state it started from.  The outputs' contents are
+ * overwritten.  Synchronous.  GAL_ESTATE if a candidate's output differs.
+ */
+int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream,
+                 int32_t steps, gal_tuning *best, double *best_ms);
 
 /* Number of environments, spheres, contact words, and the packed depth size. */
 int gal_batch_info(const gal_batch *b, int32_t *num_envs, int32_t *num_spheres,

@@ -162,6 +162,18 @@ struct gal_batch {
     unsigned long long *d_stats = nullptr;  // raster work counters (allocated on demand)
     std::vector<int64_t> cl_count_host;    // clusters per env
     int32_t work_cap = 0;
+    uint32_t *d_queue = nullptr;            // persistent raster work-queue counter
+    int32_t persist_grid = 0;
+    int32_t robot_lanes = 64;
+    int32_t use_graph = 0;
+    uint64_t tune_gen = 1;                  // bumps on every tuning change
+    // captured step graph and what it was captured for
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const float *g_actions = nullptr;
+    gal_outputs g_out{};
+    uint64_t g_gen = 0;
     // per-kernel timing
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;     // free events
@@ -170,6 +182,15 @@ struct gal_batch {
     {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_rec) (void)hipEventDestroy(e);
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
     }
     hipEvent_t take_event()
     {
@@ -185,6 +206,9 @@ struct gal_batch {
 };
 
 namespace {
+
+int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s,
+                 hipEvent_t *ev);
 
 // (env, region) work items, longest envs first (so the tail of the launch is
 // short), regions of one env 8 items apart (same XCD, shared L2).
@@ -241,6 +265,9 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->refresh = b->rast.refresh;
     t->occlusion = b->rast.occlusion;
     t->prologue = b->rast.prologue;
+    t->persistent = b->rast.persistent;
+    t->robot_lanes = b->robot_lanes;
+    t->graph = b->use_graph;
     return GAL_OK;
 }
 
@@ -258,6 +285,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->lane_max < 0 || t->lane_max > 4096) return fail(GAL_EINVAL, "lane_max out of range");
     if (t->refresh < 1 || t->refresh > 1024) return fail(GAL_EINVAL, "refresh must be in 1..1024");
     if (t->prologue < 0) return fail(GAL_EINVAL, "prologue must be >= 0");
+    if (t->robot_lanes != 32 && t->robot_lanes != 64) return fail(GAL_EINVAL, "robot_lanes must be 32 or 64");
     const bool rebuild = t->region != b->rast.region;
     b->rast.block = t->block;
     b->rast.region = t->region;
@@ -266,10 +294,127 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->rast.refresh = t->refresh;
     b->rast.occlusion = t->occlusion ? 1 : 0;
     b->rast.prologue = t->prologue;
+    b->rast.persistent = t->persistent ? 1 : 0;
+    b->robot_lanes = t->robot_lanes;
+    b->use_graph = t->graph ? 1 : 0;
+    b->tune_gen += 1;
+    b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
+    if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");
     if (rebuild) {
         HIP_TRY(hipDeviceSynchronize());
         return build_work(b);
     }
+    return GAL_OK;
+}
+
+int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream,
+                 int32_t steps, gal_tuning *best, double *best_ms)
+{
+    if (!b || !actions_dev || !out || !out->depth) return fail(GAL_EINVAL, "null argument");
+    if (steps < 1) return fail(GAL_EINVAL, "steps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    gal_tuning orig;
+    gal_get_tuning(b, &orig);
+    const bool was_profiling = b->profiling;
+    b->profiling = false;
+    // saved simulation state (restored before every candidate and at the end)
+    float *st0 = nullptr;
+    int32_t *cnt0 = nullptr;
+    unsigned long long *hash = nullptr;
+    int rc;
+    if ((rc = b->mem.alloc(&st0, (size_t)b->N * 10)) || (rc = b->mem.alloc(&cnt0, (size_t)b->N * 2)) ||
+        (rc = b->mem.alloc(&hash, 1)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(st0, b->sb.state, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(cnt0, b->sb.counters, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
+    auto restore = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(b->sb.state, st0, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->sb.counters, cnt0, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
+        return GAL_OK;
+    };
+    std::vector<gal_tuning> cands;
+    const int regions[2] = {64, 128};
+    for (int block : {256, 512, 1024})
+        for (int region : regions)
+            for (int lane_max : {0, 4, 8})
+                for (int small_max : {64, 256})
+                    for (int occl : {0, 1})
+                        for (int persist : {0, 1})
+                            for (int rl : {32, 64}) {
+                                bool ok = true;
+                                for (int e = 0; e < b->N && ok; ++e)
+                                    if (b->res_host[e] > region && b->res_host[e] % region) ok = false;
+                                if (!ok) continue;
+                                gal_tuning t = orig;
+                                t.block = block;
+                                t.region = region;
+                                t.lane_max = lane_max;
+                                t.small_max = small_max;
+                                t.occlusion = occl;
+                                t.refresh = 4;
+                                t.persistent = persist;
+                                t.robot_lanes = rl;
+                                t.graph = 0;
+                                cands.push_back(t);
+                            }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best_t = 1e30;
+    gal_tuning best_c = orig;
+    unsigned long long ref_hash = 0;
+    bool have_ref = false;
+    int result = GAL_OK;
+    for (const gal_tuning &t : cands) {
+        if ((result = gal_set_tuning(b, &t))) break;
+        if ((result = restore())) break;
+        if ((result = enqueue_step(b, actions_dev, out, s, nullptr))) break;
+        // output of one step from the saved state must not depend on the tuning
+        if (hipSuccess != gal::launch_hash_u32(out->depth, (uint64_t)b->depth_off_host[b->N], hash, s)) {
+            result = fail(GAL_EDEVICE, "hash launch failed");
+            break;
+        }
+        unsigned long long h = 0;
+        if (hipMemcpyAsync(&h, hash, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            result = fail(GAL_EDEVICE, "autotune: device error");
+            break;
+        }
+        if (!have_ref) {
+            ref_hash = h;
+            have_ref = true;
+        } else if (h != ref_hash) {
+            result = fail(GAL_ESTATE, "autotune: candidate (block %d region %d lane_max %d small_max %d "
+                          "occlusion %d persistent %d) changed the output bits",
+                          t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent);
+            break;
+        }
+        (void)hipEventRecord(e0, s);
+        for (int k = 0; k < steps && result == GAL_OK; ++k) result = enqueue_step(b, actions_dev, out, s, nullptr);
+        (void)hipEventRecord(e1, s);
+        if (result) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            result = fail(GAL_EDEVICE, "autotune: event timing failed");
+            break;
+        }
+        if (ms / steps < best_t) {
+            best_t = ms / steps;
+            best_c = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    best_c.graph = orig.graph;
+    int rc2 = gal_set_tuning(b, result == GAL_OK ? &best_c : &orig);
+    int rc3 = restore();
+    (void)hipStreamSynchronize(s);
+    b->profiling = was_profiling;
+    if (result) return result;
+    if (rc2) return rc2;
+    if (rc3) return rc3;
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
     return GAL_OK;
 }
 
@@ -588,6 +733,11 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         HIP_TRY(hipMemcpy(b->d_depth_off, doff.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
         if ((rc = build_work(b))) return cleanup(rc);
         HIP_TRY(gal::raster_prepare());
+        b->rast.persistent = 0;
+        if ((rc = b->mem.alloc(&b->d_queue, 1))) return cleanup(rc);
+        HIP_TRY(hipMemset(b->d_queue, 0, sizeof(uint32_t)));
+        b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (cfg->flags & GAL_COLOR) != 0);
+        HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     }
 
     // ---- initial state: episode 0 at the first start pose (reset from episode -1)
@@ -612,13 +762,14 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream)
     return GAL_OK;
 }
 
-int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Enqueue one step (robot kernel, then raster) on stream s.
+int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s,
+                 hipEvent_t *ev)
 {
-    if (!b || !actions_dev || !out || !out->depth)
-        return fail(GAL_EINVAL, "gal_step needs a batch, actions and a depth output");
-    if (out->rgb && !(b->flags & GAL_COLOR))
-        return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
-    hipStream_t s = (hipStream_t)stream;
     gal::StepOutputs so;
     so.contact_static = out->contact_static;
     so.contact_object = out->contact_object;
@@ -627,21 +778,70 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
     so.frames = out->frames;
     so.counters = out->counters;
     so.done = out->done;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(gal::launch_robot_step(b->rp, b->sb, actions_dev, so, b->d_queue, b->robot_lanes, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
+                               b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,
+                               out->rgb, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    return GAL_OK;
+}
+
+bool same_outputs(const gal_outputs &a, const gal_outputs &c)
+{
+    return a.depth == c.depth && a.rgb == c.rgb && a.contact_static == c.contact_static &&
+           a.contact_object == c.contact_object && a.accepted == c.accepted && a.state == c.state &&
+           a.frames == c.frames && a.counters == c.counters && a.done == c.done;
+}
+
+// Replay the step graph, capturing it first if the pointers or tuning changed.
+int graph_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s)
+{
+    if (!b->graph_exec || b->g_actions != actions_dev || !same_outputs(b->g_out, *out) ||
+        b->g_gen != b->tune_gen) {
+        b->drop_graph();
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(b, actions_dev, out, b->cap_stream, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (rc != GAL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(GAL_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+        b->g_actions = actions_dev;
+        b->g_out = *out;
+        b->g_gen = b->tune_gen;
+    }
+    HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+    return GAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream)
+{
+    if (!b || !actions_dev || !out || !out->depth)
+        return fail(GAL_EINVAL, "gal_step needs a batch, actions and a depth output");
+    if (out->rgb && !(b->flags & GAL_COLOR))
+        return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
+    hipStream_t s = (hipStream_t)stream;
     if (b->profiling) {
+        hipEvent_t ev[3];
         for (int i = 0; i < 3; ++i)
             if (!(ev[i] = b->take_event())) return fail(GAL_EDEVICE, "hipEventCreate failed");
-        HIP_TRY(hipEventRecord(ev[0], s));
-    }
-    HIP_TRY(gal::launch_robot_step(b->rp, b->sb, actions_dev, so, s));
-    if (b->profiling) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
-                               b->num_work, b->max_res, out->depth, out->rgb, s));
-    if (b->profiling) {
-        HIP_TRY(hipEventRecord(ev[2], s));
+        int rc = enqueue_step(b, actions_dev, out, s, ev);
         b->ev_rec.insert(b->ev_rec.end(), ev, ev + 3);
+        return rc;
     }
-    return GAL_OK;
+    if (b->use_graph) return graph_step(b, actions_dev, out, s);
+    return enqueue_step(b, actions_dev, out, s, nullptr);
 }
 
 int gal_profile_enable(gal_batch *b, int on)

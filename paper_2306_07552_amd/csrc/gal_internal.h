@@ -106,19 +106,25 @@ struct RasterParams {
     int32_t refresh;   // clusters a wave draws between occlusion-bound refreshes
     int32_t occlusion; // 1 = cull clusters hidden behind the z-buffer bounds
     int32_t prologue;  // clusters drawn before occlusion culling starts
+    int32_t persistent;// 1 = persistent kernel draining the work queue
     unsigned long long *stats; // optional work counters [8] (null = off)
 };
 
 // Launchers (defined in the .hip files).
 hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
-                             const StepOutputs &out, hipStream_t s);
+                             const StepOutputs &out, uint32_t *queue_reset, int lanes_per_env,
+                             hipStream_t s);
 hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
                         hipStream_t s);
 hipError_t raster_prepare();   // raises the dynamic-LDS limit of the raster kernels
+// Workgroups of the persistent raster kernel that fit on the device at once.
+int raster_persistent_grid(const RasterParams &rp, int max_region, bool color);
 hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
                          const int32_t *env_res, const uint64_t *env_depth_off,
                          const uint32_t *work, int32_t num_work, int32_t max_region,
-                         uint32_t *depth, uint8_t *rgb, hipStream_t s);
+                         uint32_t *queue, int32_t persistent_grid, uint32_t *depth, uint8_t *rgb,
+                         hipStream_t s);
+hipError_t launch_hash_u32(const uint32_t *a, uint64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_grid_count(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
                              int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
                              int32_t max_cols, uint32_t *counts, int32_t *overflow, hipStream_t s);

@@ -633,28 +633,37 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
     }
 }
 
+// LDS of one workgroup besides the z-buffer.
+template <int kBlock>
+struct ItemShared {
+    uint32_t tilemax[(kMaxRegion / 8) * (kMaxRegion / 8)];
+    uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
+    uint16_t vis[kVisCap];
+    int wave_cnt[kBlock / 64];
+    int next;
+    int queue_item;
+};
+
+// Render one (env, region) work item into the depth (and colour) output.
 template <int kBlock, bool kColor>
-__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(RenderMesh m, RasterParams rp,
-                                                   const float *__restrict__ camera,
-                                                   const int32_t *__restrict__ env_res,
-                                                   const uint64_t *__restrict__ env_depth_off,
-                                                   const uint32_t *__restrict__ work,
-                                                   uint32_t *__restrict__ depth,
-                                                   uint8_t *__restrict__ rgb)
+__device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterParams &rp,
+                                            const float *__restrict__ camera,
+                                            const int32_t *__restrict__ env_res,
+                                            const uint64_t *__restrict__ env_depth_off,
+                                            uint32_t item, uint32_t *__restrict__ depth,
+                                            uint8_t *__restrict__ rgb, unsigned long long *zdyn,
+                                            ItemShared<kBlock> &sh)
 {
-    // the region's z-buffer: dynamic LDS of R*R u32 (depth) or u64 (colour)
-    extern __shared__ unsigned long long zdyn[];
     using SinkT = typename std::conditional<kColor, ColorSink, DepthSink>::type;
     SinkT zb;
     if constexpr (kColor) zb.k = zdyn;
     else zb.z = reinterpret_cast<uint32_t *>(zdyn);
-    __shared__ uint32_t tilemax[(kMaxRegion / 8) * (kMaxRegion / 8)];
-    __shared__ uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
-    __shared__ uint16_t vis[kVisCap];
-    __shared__ int wave_cnt[kBlock / 64];
-    __shared__ int next;
+    uint32_t *tilemax = sh.tilemax;
+    uint32_t *blockmax = sh.blockmax;
+    uint16_t *vis = sh.vis;
+    int *wave_cnt = sh.wave_cnt;
+    int &next = sh.next;
     constexpr int kWaves = kBlock / 64;
-    const uint32_t item = work[blockIdx.x];
     const int env = (int)(item & 0xFFFFFu);
     const int reg = (int)(item >> 20);
     const int res = env_res[env];
@@ -838,63 +847,133 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(Rend
             dst[o] = zb.depth_at(i);
         }
     }
+    __syncthreads();   // the LDS is reused by the next item
+}
+
+// One workgroup per work item.
+template <int kBlock, bool kColor>
+__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(
+    RenderMesh m, RasterParams rp, const float *__restrict__ camera,
+    const int32_t *__restrict__ env_res, const uint64_t *__restrict__ env_depth_off,
+    const uint32_t *__restrict__ work, int32_t num_work, uint32_t *__restrict__ queue,
+    uint32_t *__restrict__ depth, uint8_t *__restrict__ rgb)
+{
+    extern __shared__ unsigned long long zdyn[];
+    __shared__ ItemShared<kBlock> sh;
+    raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[blockIdx.x], depth, rgb,
+                                zdyn, sh);
+}
+
+// Persistent: as many workgroups as fit on the chip drain the work queue
+// (items in longest-first order; the counter is reset by the robot kernel
+// that precedes this launch in the step).
+template <int kBlock, bool kColor>
+__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_persistent(
+    RenderMesh m, RasterParams rp, const float *__restrict__ camera,
+    const int32_t *__restrict__ env_res, const uint64_t *__restrict__ env_depth_off,
+    const uint32_t *__restrict__ work, int32_t num_work, uint32_t *__restrict__ queue,
+    uint32_t *__restrict__ depth, uint8_t *__restrict__ rgb)
+{
+    extern __shared__ unsigned long long zdyn[];
+    __shared__ ItemShared<kBlock> sh;
+    for (;;) {
+        if (threadIdx.x == 0) sh.queue_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int i = sh.queue_item;
+        __syncthreads();
+        if (i >= num_work) break;
+        raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[i], depth, rgb, zdyn,
+                                    sh);
+    }
+}
+
+template <bool kColor, bool kPersist>
+hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const float *camera,
+                           const int32_t *env_res, const uint64_t *env_depth_off,
+                           const uint32_t *work, int32_t num_work, uint32_t *queue,
+                           uint32_t *depth, uint8_t *rgb, size_t lds, int grid, hipStream_t s)
+{
+    const int g = kPersist ? grid : num_work;
+#define GAL_RASTER_LAUNCH(B)                                                                     \
+    hipLaunchKernelGGL((kPersist ? k_raster_persistent<B, kColor> : k_raster<B, kColor>), dim3(g), \
+                       dim3(B), lds, s, m, rp, camera, env_res, env_depth_off, work, num_work,     \
+                       queue, depth, rgb)
+    switch (rp.block) {
+    case 256: GAL_RASTER_LAUNCH(256); break;
+    case 1024: GAL_RASTER_LAUNCH(1024); break;
+    default: GAL_RASTER_LAUNCH(512); break;
+    }
+#undef GAL_RASTER_LAUNCH
+    return hipGetLastError();
+}
+
+size_t lds_bytes(int region, bool color) { return (size_t)region * region * (color ? 8 : 4); }
+
+template <class K>
+hipError_t allow(K f, bool color)
+{
+    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds_bytes(kMaxRegion, color));
 }
 
 }  // namespace
 
-template <bool kColor>
-hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const float *camera,
-                           const int32_t *env_res, const uint64_t *env_depth_off,
-                           const uint32_t *work, int32_t num_work, uint32_t *depth, uint8_t *rgb,
-                           size_t lds, hipStream_t s)
-{
-    switch (rp.block) {
-    case 256:
-        hipLaunchKernelGGL((k_raster<256, kColor>), dim3(num_work), dim3(256), lds, s, m, rp, camera,
-                           env_res, env_depth_off, work, depth, rgb);
-        break;
-    case 1024:
-        hipLaunchKernelGGL((k_raster<1024, kColor>), dim3(num_work), dim3(1024), lds, s, m, rp,
-                           camera, env_res, env_depth_off, work, depth, rgb);
-        break;
-    default:
-        hipLaunchKernelGGL((k_raster<512, kColor>), dim3(num_work), dim3(512), lds, s, m, rp, camera,
-                           env_res, env_depth_off, work, depth, rgb);
-        break;
-    }
-    return hipGetLastError();
-}
-
-template <bool kColor>
-hipError_t allow_lds(const void *f)
-{
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(kMaxRegion * kMaxRegion * (kColor ? 8 : 4)));
-}
-
 hipError_t raster_prepare()
 {
-    hipError_t e;
-    if ((e = allow_lds<false>((const void *)k_raster<256, false>)) != hipSuccess) return e;
-    if ((e = allow_lds<false>((const void *)k_raster<512, false>)) != hipSuccess) return e;
-    if ((e = allow_lds<false>((const void *)k_raster<1024, false>)) != hipSuccess) return e;
-    if ((e = allow_lds<true>((const void *)k_raster<256, true>)) != hipSuccess) return e;
-    if ((e = allow_lds<true>((const void *)k_raster<512, true>)) != hipSuccess) return e;
-    return allow_lds<true>((const void *)k_raster<1024, true>);
+    hipError_t e = hipSuccess;
+#define GAL_ALLOW(B, C)                                                                  \
+    if ((e = allow(k_raster<B, C>, C)) != hipSuccess) return e;                          \
+    if ((e = allow(k_raster_persistent<B, C>, C)) != hipSuccess) return e;
+    GAL_ALLOW(256, false) GAL_ALLOW(512, false) GAL_ALLOW(1024, false)
+    GAL_ALLOW(256, true) GAL_ALLOW(512, true) GAL_ALLOW(1024, true)
+#undef GAL_ALLOW
+    return e;
+}
+
+int raster_persistent_grid(const RasterParams &rp, int max_region, bool color)
+{
+    const int R = max_region < rp.region ? max_region : rp.region;
+    const size_t lds = lds_bytes(R, color);
+    int per_cu = 0;
+    hipError_t e = hipSuccess;
+#define GAL_OCC(B)                                                                              \
+    e = color ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, true>, B, lds) \
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, false>, B, lds)
+    switch (rp.block) {
+    case 256: GAL_OCC(256); break;
+    case 1024: GAL_OCC(1024); break;
+    default: GAL_OCC(512); break;
+    }
+#undef GAL_OCC
+    int dev = 0, cus = 0;
+    if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    return (per_cu < 1 ? 1 : per_cu) * cus;
 }
 
 hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
                          const int32_t *env_res, const uint64_t *env_depth_off,
                          const uint32_t *work, int32_t num_work, int32_t max_region,
-                         uint32_t *depth, uint8_t *rgb, hipStream_t s)
+                         uint32_t *queue, int32_t persistent_grid, uint32_t *depth, uint8_t *rgb,
+                         hipStream_t s)
 {
     if (num_work <= 0) return hipSuccess;
     const int R = max_region < rp.region ? max_region : rp.region;
-    if (rgb)
-        return launch_raster_t<true>(m, rp, camera, env_res, env_depth_off, work, num_work, depth,
-                                     rgb, (size_t)R * R * 8, s);
-    return launch_raster_t<false>(m, rp, camera, env_res, env_depth_off, work, num_work, depth,
-                                  nullptr, (size_t)R * R * 4, s);
+    const size_t lds = lds_bytes(R, rgb != nullptr);
+    const bool persist = rp.persistent && queue && persistent_grid > 0;
+    if (rgb) {
+        if (persist)
+            return launch_raster_t<true, true>(m, rp, camera, env_res, env_depth_off, work, num_work,
+                                               queue, depth, rgb, lds, persistent_grid, s);
+        return launch_raster_t<true, false>(m, rp, camera, env_res, env_depth_off, work, num_work,
+                                            queue, depth, rgb, lds, 0, s);
+    }
+    if (persist)
+        return launch_raster_t<false, true>(m, rp, camera, env_res, env_depth_off, work, num_work,
+                                            queue, depth, nullptr, lds, persistent_grid, s);
+    return launch_raster_t<false, false>(m, rp, camera, env_res, env_depth_off, work, num_work,
+                                         queue, depth, nullptr, lds, 0, s);
 }
 
 }  // namespace gal

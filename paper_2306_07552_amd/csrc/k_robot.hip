@@ -1,18 +1,16 @@
 // Robot step kernel: action decode, kinematic update, forward kinematics,
 // sphere-proxy collision against the column grid and the object boxes,
 // resolution, episode bookkeeping and the head-camera pose (Galactic,
-// Section 3.2 and Appendix G).  One wave64 per environment: the chain of
-// seven joint frames is evaluated redundantly by every lane (it is a short
-// serial chain), each lane owns spheres lane, lane+64, ..., and the
-// accept/reject decision is a wave ballot.
+// Section 3.2 and Appendix G).  One wave64 (or half-wave) per environment:
+// the chain of seven joint frames is evaluated redundantly by every lane (it
+// is a short serial chain), each lane owns every 64th (32nd) sphere, and the
+// accept/reject decision is a ballot.
 #include "gal_internal.h"
 #include "gal_math.h"
 
 namespace gal {
 
 namespace {
-
-constexpr int kWavesPerBlock = 4;
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi)
 {
@@ -125,12 +123,27 @@ __device__ __forceinline__ void write_camera(const RobotParams &rp, const Frame 
     fvec(F0, cp, 0.0f, -sp, cam[9], cam[10], cam[11]);
 }
 
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
-    RobotParams rp, SimBuffers sb, const float *__restrict__ actions, StepOutputs out)
+// kLanes lanes per environment: 64 (one env per wave, spheres lane + 64k) or
+// 32 (two envs per wave, spheres lane + 32k); the ballot's 32-bit halves are
+// then exactly the envs' contact words.
+template <int kLanes>
+__global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers sb,
+                                                    const float *__restrict__ actions,
+                                                    StepOutputs out, uint32_t *queue_reset)
 {
+    // the raster work queue of this step starts empty (a kernel store rather
+    // than a memset, so the step can be captured as a graph)
+    if (queue_reset && blockIdx.x == 0 && threadIdx.x == 0) *queue_reset = 0u;
+    constexpr int kEnvsPerBlock = 256 / kLanes;
     const int lane = threadIdx.x & 63;
-    const int env = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if (env >= sb.num_envs) return;
+    const int sub = (int)threadIdx.x % kLanes;
+    const int half = kLanes == 32 ? (lane >> 5) : 0;
+    int env = (int)blockIdx.x * kEnvsPerBlock + (int)threadIdx.x / kLanes;
+    if (kLanes == 64) env = __builtin_amdgcn_readfirstlane(env);
+    if (kLanes == 64 && env >= sb.num_envs) return;
+    // with two envs per wave, a half-wave past the end still joins the ballots
+    const bool active = env < sb.num_envs;
+    if (!active) env = 0;
 
     float st[10];
 #pragma unroll
@@ -167,10 +180,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
     const bool held = sb.held ? (sb.held[env] != 0) : false;
     const float *objs = sb.objects + (size_t)env * rp.num_objects * 8;
     bool any = false;
-    for (int base = 0; base < rp.num_spheres; base += 64) {
-        const int s = base + lane;
+    for (int base = 0; base < rp.num_spheres; base += kLanes) {
+        const int s = base + sub;
         bool hit_static = false, hit_object = false;
-        if (s < rp.num_spheres) {
+        if (active && s < rp.num_spheres) {
             const Sphere sp = sb.spheres[s];
             if (!(sp.held_only && !held)) {
                 Frame F = pick(fk, sp.link);
@@ -190,21 +203,31 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
         }
         const uint64_t ms = __ballot(hit_static);
         const uint64_t mo = __ballot(hit_object);
-        any = any || (ms | mo) != 0;
-        if (lane == 0) {
-            const int w = base >> 5;
-            if (out.contact_static) {
-                uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
-                if (w < rp.contact_words) cs[w] = (uint32_t)ms;
-                if (w + 1 < rp.contact_words) cs[w + 1] = (uint32_t)(ms >> 32);
+        const int w = base >> 5;
+        if (kLanes == 64) {
+            any = any || (ms | mo) != 0;
+            if (lane == 0) {
+                if (out.contact_static) {
+                    uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
+                    if (w < rp.contact_words) cs[w] = (uint32_t)ms;
+                    if (w + 1 < rp.contact_words) cs[w + 1] = (uint32_t)(ms >> 32);
+                }
+                if (out.contact_object) {
+                    uint32_t *co = out.contact_object + (size_t)env * rp.contact_words;
+                    if (w < rp.contact_words) co[w] = (uint32_t)mo;
+                    if (w + 1 < rp.contact_words) co[w + 1] = (uint32_t)(mo >> 32);
+                }
             }
-            if (out.contact_object) {
-                uint32_t *co = out.contact_object + (size_t)env * rp.contact_words;
-                if (w < rp.contact_words) co[w] = (uint32_t)mo;
-                if (w + 1 < rp.contact_words) co[w + 1] = (uint32_t)(mo >> 32);
+        } else {
+            const uint32_t hs = (uint32_t)(ms >> (32 * half)), ho = (uint32_t)(mo >> (32 * half));
+            any = any || (hs | ho) != 0u;
+            if (sub == 0 && active && w < rp.contact_words) {
+                if (out.contact_static) out.contact_static[(size_t)env * rp.contact_words + w] = hs;
+                if (out.contact_object) out.contact_object[(size_t)env * rp.contact_words + w] = ho;
             }
         }
     }
+    if (!active) return;
 
     // 3. resolve: any overlap rejects the whole move
     const bool accepted = !any;
@@ -225,7 +248,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
 
     // 5. frames and camera of the final state
     if (!accepted || done) forward_kinematics(rp, st, fk);
-    if (lane == 0) {
+    if (sub == 0) {
 #pragma unroll
         for (int k = 0; k < 10; ++k) sb.state[(size_t)env * 10 + k] = st[k];
         sb.counters[(size_t)env * 2 + 0] = t;
@@ -245,9 +268,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_robot_step(
         if (out.accepted) out.accepted[env] = accepted ? 1 : 0;
         if (out.done) out.done[env] = done ? 1 : 0;
     }
-    if (out.frames && lane < 8) {
-        Frame F = pick(fk, lane);
-        float *dst = out.frames + ((size_t)env * 8 + lane) * 12;
+    if (out.frames && sub < 8) {
+        Frame F = pick(fk, sub);
+        float *dst = out.frames + ((size_t)env * 8 + sub) * 12;
 #pragma unroll
         for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
     }
@@ -280,11 +303,18 @@ __global__ void k_reset(RobotParams rp, SimBuffers sb, const uint8_t *__restrict
 }  // namespace
 
 hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
-                             const StepOutputs &out, hipStream_t s)
+                             const StepOutputs &out, uint32_t *queue_reset, int lanes_per_env,
+                             hipStream_t s)
 {
-    const int blocks = (sb.num_envs + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_robot_step, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, rp, sb,
-                       actions, out);
+    if (lanes_per_env == 32) {
+        const int blocks = (sb.num_envs + 7) / 8;
+        hipLaunchKernelGGL(k_robot_step<32>, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
+                           queue_reset);
+    } else {
+        const int blocks = (sb.num_envs + 3) / 4;
+        hipLaunchKernelGGL(k_robot_step<64>, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
+                           queue_reset);
+    }
     return hipGetLastError();
 }
 

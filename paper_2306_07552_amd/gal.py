@@ -54,7 +54,8 @@ class GalConfig(C.Structure):
 class GalTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("region", C.c_int32), ("lane_max", C.c_int32),
                 ("small_max", C.c_int32),
-                ("refresh", C.c_int32), ("occlusion", C.c_int32), ("prologue", C.c_int32)]
+                ("refresh", C.c_int32), ("occlusion", C.c_int32), ("prologue", C.c_int32),
+                ("persistent", C.c_int32), ("robot_lanes", C.c_int32), ("graph", C.c_int32)]
 
 
 class GalOutputs(C.Structure):
@@ -91,6 +92,8 @@ def load_library():
         L.gal_mesh_info.argtypes = [C.c_void_p, _i64p, _i64p, _i64p]
         L.gal_counters_enable.argtypes = [C.c_void_p, C.c_int]
         L.gal_counters_read.argtypes = [C.c_void_p, _i64p, C.c_size_t]
+        L.gal_autotune.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(GalOutputs), C.c_void_p,
+                                   C.c_int32, C.POINTER(GalTuning), C.POINTER(C.c_double)]
         L.gal_get_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
         L.gal_set_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
         L.gal_destroy.argtypes = [C.c_void_p]
@@ -228,14 +231,29 @@ class Batch:
             out["rgb"] = torch.empty((self.depth_pixels, 3), dtype=torch.uint8, device=device)
         return out
 
-    def step(self, actions, out: Dict[str, "object"], stream=None):
+    @staticmethod
+    def _outputs(out) -> GalOutputs:
         o = GalOutputs()
         for k in ("depth", "rgb", "contact_static", "contact_object", "accepted", "state",
                   "frames", "counters", "done"):
             setattr(o, k, _ptr(out.get(k)))
+        return o
+
+    def step(self, actions, out: Dict[str, "object"], stream=None):
+        o = self._outputs(out)
         assert actions.is_contiguous() and actions.dtype.is_floating_point
         _check(load_library().gal_step(self._h, actions.data_ptr(), C.byref(o),
                                        _stream_handle(stream)))
+
+    def autotune(self, actions, out: Dict[str, "object"], steps: int = 5, stream=None):
+        """Pick the fastest launch configuration (same bits for all); returns
+        (tuning dict, ms per step)."""
+        o = self._outputs(out)
+        t = GalTuning()
+        ms = C.c_double()
+        _check(load_library().gal_autotune(self._h, actions.data_ptr(), C.byref(o),
+                                           _stream_handle(stream), steps, C.byref(t), C.byref(ms)))
+        return {k: getattr(t, k) for k, _ in GalTuning._fields_}, ms.value
 
     def reset(self, mask=None, stream=None):
         _check(load_library().gal_reset(self._h, _ptr(mask), _stream_handle(stream)))
