@@ -82,6 +82,7 @@ def main():
     from paper_2306_07552_amd import gal, scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
     if args.copy_reference:
         n = args.copy_reference * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -104,10 +105,9 @@ def main():
     log(f"gal_create_batch: {time.perf_counter() - t:.1f} s, mesh {b.mesh_info()}")
     if args.tuning:
         b.set_tuning(**json.loads(args.tuning))
-    log(f"tuning {b.get_tuning()}")
+    log(f"plain tuning {b.get_tuning()}")
     N = b.num_envs
     out = b.alloc_outputs()
-    stream = torch.cuda.current_stream()
 
     # actions for every step, resident in HBM before timing
     g = torch.Generator(device="cuda")
@@ -117,33 +117,58 @@ def main():
     total = args.warmup + args.steps
     acts = (torch.rand((total, N, 9), generator=g, device="cuda") * 2 - 1) * lim
 
-    for k in range(args.warmup):
-        b.step(acts[k], out)
-    torch.cuda.synchronize()
+    act_buf = torch.empty((N, 9), dtype=torch.float32, device="cuda")
 
-    b.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for k in range(args.warmup, total):
-        b.step(acts[k], out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    b.profile(False)
-    robot_ms, raster_ms, nsteps = b.profile_read()
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
-    value = N * args.steps / (gpu_ms / 1e3)
-    log(f"timed {args.steps} steps: {gpu_ms:.2f} ms device, {wall * 1e3:.2f} ms wall; "
-        f"robot {robot_ms / nsteps:.4f} ms, raster {raster_ms / nsteps:.4f} ms per step")
+    def run(k0, n):
+        for k in range(k0, k0 + n):
+            act_buf.copy_(acts[k], non_blocking=True)
+            b.step(act_buf, out)
+
+    def timed_pass(label):
+        """Warmup, then exactly K timed steps bracketed by device syncs."""
+        run(0, args.warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        ev0.record(stream)
+        run(args.warmup, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        gpu_ms = ev0.elapsed_time(ev1)
+        log(f"{label}: {args.steps} steps in {gpu_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
+        return gpu_ms
+
+    def kernel_times():
+        """Per-kernel durations over a profiled pass (HIP events on the step stream)."""
+        b.profile(True)
+        run(args.warmup, args.steps)
+        torch.cuda.synchronize()
+        b.profile(False)
+        robot_ms, raster_ms, nsteps = b.profile_read()
+        return robot_ms / nsteps, raster_ms / nsteps
+
+    # ---- plain step: default launch configuration, eager launches
+    plain_ms = timed_pass("plain")
+    plain_robot, plain_raster = kernel_times()
+    plain = {"value": round(N * args.steps / (plain_ms / 1e3), 1),
+             "ms_per_step": round(plain_ms / args.steps, 4), "tuning": b.get_tuning(),
+             "robot_ms": round(plain_robot, 5), "raster_ms": round(plain_raster, 5)}
+
+    # ---- batched step: autotuned configuration, persistent queue, graph replay
+    act_buf.copy_(acts[0])
+    best, best_ms = b.autotune(act_buf, out, steps=3)
+    b.set_tuning(graph=1)
+    log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
+    batched_ms = timed_pass("batched")
+    robot_k, raster_k = kernel_times()
+    value = N * args.steps / (batched_ms / 1e3)
+    ms_per_step = batched_ms / args.steps
 
     mi = b.mesh_info()
     raster_bytes = mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4 + 4 * b.depth_pixels
-    raster_s = raster_ms / nsteps / 1e3
-    achieved = raster_bytes / raster_s / 1e9
+    achieved = raster_bytes / (raster_k / 1e3) / 1e9
     traffic = None
     if args.config == 1 and not cfg.color:
         traffic = measured_traffic(["paper_2306_07552_amd/csrc/k_raster.hip",
@@ -152,22 +177,24 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_raster", "algorithmic_bytes_per_launch": int(raster_bytes),
-                "avg_launch_ms": round(raster_ms / nsteps, 5)}
+                "avg_launch_ms": round(raster_k, 5)}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(cfg, robot, scenes, consts)
 
-    res = {"metric": "env-steps/sec @1024 envs, 128x128 depth (plain step)",
+    res = {"metric": "env-steps/sec @1024 envs, 128x128 depth (batched step; plain beside it)",
            "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
            "config": {"workload": cfg.name, "tuning": b.get_tuning(), "envs": N, "res": int(cfg.res0),
                       "tris_total": int(scenes.tri_offset[-1]), "spheres": robot.num_spheres,
                       "objects": cfg.num_objects, "episode_len": cfg.episode_len,
-                      "path": "plain"},
-           "roofline": roofline, "cpu_baseline": cpu}
+                      "path": "batched (autotuned, persistent queue, hipGraph)"},
+           "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
+           "batched": {"tuning": b.get_tuning(), "robot_ms": round(robot_k, 5),
+                       "raster_ms": round(raster_k, 5)}}
     print(json.dumps(res), flush=True)
 
 
