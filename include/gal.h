@@ -175,8 +175,9 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
  *  4. the step counter advances; at episode_len the env auto-resets
  *     (gal_reset semantics) and `done` is set;
  *  5. frames and the depth (and colour) image are produced for the final
- *     state.
- * Errors: GAL_EINVAL (NULL batch/actions/depth, rgb without GAL_COLOR),
+ *     state.  With out->depth NULL only the physics runs (no image).
+ * Errors: GAL_EINVAL (NULL batch/actions/outputs, rgb without GAL_COLOR or
+ * without depth),
  * GAL_EDEVICE (launch failure).
  */
 int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream);
@@ -292,6 +293,71 @@ int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count);
  * (per-cluster unique) vertices, and triangles. */
 int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
                   int64_t *tris);
+
+/*
+ * ---- Collision surrogate (a learned pre-filter; not in the paper) ----
+ *
+ * A small MLP predicts, for each environment's next move, whether its
+ * candidate pose overlaps the static scene (the column-grid test of Section
+ * 3.2).  Input (2080 BF16 values, gal_features): 7 joint angles, the 7 joint
+ * offsets and 2 base offsets of the action normalised by their limits, the
+ * base pose normalised by the grid extent (and yaw / pi), 13 zeros, then the
+ * 16 x 16 x 8 occupancy patch around the base (cells of 2 x 2 grid cells and
+ * 0.25 m, 1 = blocked for the smallest sphere class; outside the grid
+ * counts as blocked).  Network 2080 -> 256 -> 256 -> 256 -> 256 -> 1 with
+ * ReLU, BF16 weights and activations, FP32 accumulation (matrix cores).
+ * Parameters are FP32 [W1 (256 x 2080), b1, W2, b2, W3, b3, W4, b4,
+ * W5 (1 x 256), b5], each W one row per output unit.
+ */
+typedef struct gal_mlp gal_mlp;
+#define GAL_MLP_IN 2080
+
+/* Total parameter count (729,601). */
+int gal_mlp_num_params(int64_t *n);
+/* Device MLP for up to max_rows rows per call; He-uniform initial weights
+ * from `seed`, zero biases, Adam state cleared.  Synchronous. */
+int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out);
+/* Host FP32 parameters in the layout above (count = gal_mlp_num_params);
+ * set also clears the Adam state.  Synchronous. */
+int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count);
+int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
+/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2080]). */
+int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
+/* Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
+ * w_i = pos_weight for labels 1, into grads_dev (device f32, parameter
+ * layout; may be NULL) and the loss into loss_dev (device f32[1]; may be
+ * NULL).  Labels are device f32 0/1. */
+int gal_mlp_gradients(gal_mlp *m, const uint16_t *x_dev, const float *labels_dev, int32_t rows,
+                      float pos_weight, float *grads_dev, float *loss_dev, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on those gradients. */
+int gal_mlp_train_step(gal_mlp *m, const uint16_t *x_dev, const float *labels_dev, int32_t rows,
+                       float pos_weight, float lr, float *loss_dev, void *stream);
+/* The MLP's BF16 matrix-core GEMM alone, FP32 output (for verification):
+ * variant 3: C = A B^T, 4: C = A B, 5: C = A^T B, operands BF16 bits with
+ * leading dimensions lda / ldb (elements), C [M][ldc]. */
+int gal_mlp_gemm_test(int32_t variant, const uint16_t *a_dev, const uint16_t *b_dev, int32_t M,
+                      int32_t N, int32_t K, int32_t lda, int32_t ldb, float *c_dev, int32_t ldc,
+                      void *stream);
+void gal_mlp_destroy(gal_mlp *m);
+
+/* Surrogate inputs of every env's next move under actions_dev (device BF16
+ * u16 [N][2080]).  Builds the occupancy lattice on first use (synchronous
+ * then). */
+int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *stream);
+/*
+ * Put the MLP in front of the static check of gal_step: an env whose
+ * predicted contact probability is <= skip_below skips the column-grid test
+ * (its static contact mask is then 0), except a hashed 1-in-audit_period
+ * sample of those (audit_period 1 = all, 0 = none), for which the exact
+ * test runs and a contact counts as a mismatch.  Object checks always run.
+ * The MLP must hold >= N rows and outlive the attachment.
+ */
+int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t audit_period,
+                         void *stream);
+int gal_surrogate_detach(gal_batch *b);
+/* stats_host[4] = queries, skipped, audited, audit mismatches since the last
+ * reset (synchronises the device; reset != 0 clears them). */
+int gal_surrogate_stats(gal_batch *b, int64_t *stats_host, int reset);
 
 void gal_destroy(gal_batch *b);
 

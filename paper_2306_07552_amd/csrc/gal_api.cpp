@@ -3,6 +3,7 @@
 // device) and the asynchronous step / reset launches.
 #include "gal.h"
 #include "gal_internal.h"
+#include "gal_mlp.h"
 
 #include <algorithm>
 #include <atomic>
@@ -141,6 +142,22 @@ void parallel_for(int64_t n, F &&f)
 
 }  // namespace
 
+namespace gal {
+int api_fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s);
+const float *mlp_logits(const gal_mlp *m);
+int mlp_max_rows(const gal_mlp *m);
+}  // namespace gal
+
 struct gal_batch {
     DevAlloc mem;
     int32_t N = 0, S = 0, K = 0, O = 0, P = 0, words = 0;
@@ -163,6 +180,17 @@ struct gal_batch {
     std::vector<int64_t> cl_count_host;    // clusters per env
     int32_t work_cap = 0;
     uint32_t *d_queue = nullptr;            // persistent raster work-queue counter
+    // surrogate pre-filter
+    gal_mlp *sur = nullptr;
+    float sur_thr_logit = 0.0f;
+    uint32_t sur_audit = 16;
+    uint16_t *d_feat = nullptr;             // [N][2080] BF16 inputs of the step's queries
+    uint8_t *d_flags = nullptr;             // [N] routing
+    unsigned long long *d_sur_stats = nullptr;
+    uint8_t *d_occ = nullptr;               // occupancy lattice (built on first use)
+    uint64_t *d_occ_off = nullptr;
+    int32_t *d_occ_dims = nullptr;
+    int32_t occ_max_cells = 0;
     int32_t persist_grid = 0;
     int32_t robot_lanes = 64;
     int32_t use_graph = 0;
@@ -766,6 +794,44 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream)
 
 namespace {
 
+gal::OccGrid occ_grid(const gal_batch *b)
+{
+    gal::OccGrid og;
+    og.occ = b->d_occ;
+    og.occ_off = b->d_occ_off;
+    og.occ_dims = b->d_occ_dims;
+    og.occ_cell = 2.0f * b->sb.cell;
+    return og;
+}
+
+// Occupancy lattice of the surrogate features (built once per batch).
+int ensure_occupancy(gal_batch *b, hipStream_t s)
+{
+    if (b->d_occ) return GAL_OK;
+    std::vector<uint64_t> off(b->N);
+    std::vector<int32_t> dims(2 * (size_t)b->N);
+    uint64_t tot = 0;
+    int32_t maxc = 0;
+    for (int e = 0; e < b->N; ++e) {
+        const int ox = (b->meta_host[e].nx + 1) / 2, oy = (b->meta_host[e].ny + 1) / 2;
+        dims[2 * e] = ox;
+        dims[2 * e + 1] = oy;
+        off[e] = tot;
+        tot += (uint64_t)ox * oy * gal::kPatchZ;
+        maxc = std::max(maxc, ox * oy * gal::kPatchZ);
+    }
+    int rc;
+    if ((rc = b->mem.alloc(&b->d_occ, tot)) || (rc = b->mem.alloc(&b->d_occ_off, (size_t)b->N)) ||
+        (rc = b->mem.alloc(&b->d_occ_dims, 2 * (size_t)b->N)))
+        return rc;
+    HIP_TRY(hipMemcpy(b->d_occ_off, off.data(), sizeof(uint64_t) * b->N, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_occ_dims, dims.data(), sizeof(int32_t) * 2 * b->N, hipMemcpyHostToDevice));
+    b->occ_max_cells = maxc;
+    HIP_TRY(gal::launch_occ_build(b->sb, occ_grid(b), b->N, b->K, maxc, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return GAL_OK;
+}
+
 // Enqueue one step (robot kernel, then raster) on stream s.
 int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s,
                  hipEvent_t *ev)
@@ -779,11 +845,23 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     so.counters = out->counters;
     so.done = out->done;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(gal::launch_robot_step(b->rp, b->sb, actions_dev, so, b->d_queue, b->robot_lanes, s));
+    gal::SimBuffers sb = b->sb;
+    if (b->sur) {
+        // surrogate pre-filter: features -> MLP -> routing flags for the robot kernel
+        HIP_TRY(gal::launch_features(b->rp, b->sb, occ_grid(b), actions_dev, b->d_feat, s));
+        int rc = gal::mlp_forward_rows(b->sur, b->d_feat, b->N, s);
+        if (rc) return rc;
+        HIP_TRY(gal::launch_route(gal::mlp_logits(b->sur), b->sb.counters, b->N, b->sur_thr_logit,
+                                  b->sur_audit, b->d_flags, b->d_sur_stats, s));
+        sb.skip_flags = b->d_flags;
+        sb.sur_stats = b->d_sur_stats;
+    }
+    HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
-                               b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,
-                               out->rgb, s));
+    if (out->depth)
+        HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
+                                   b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,
+                                   out->rgb, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     return GAL_OK;
 }
@@ -827,8 +905,9 @@ extern "C" {
 
 int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream)
 {
-    if (!b || !actions_dev || !out || !out->depth)
-        return fail(GAL_EINVAL, "gal_step needs a batch, actions and a depth output");
+    if (!b || !actions_dev || !out)
+        return fail(GAL_EINVAL, "gal_step needs a batch, actions and outputs");
+    if (out->rgb && !out->depth) return fail(GAL_EINVAL, "rgb output needs the depth output");
     if (out->rgb && !(b->flags & GAL_COLOR))
         return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
     hipStream_t s = (hipStream_t)stream;
@@ -896,6 +975,62 @@ int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count)
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(counters_host, b->d_stats, sizeof(int64_t) * GAL_NUM_COUNTERS, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemset(b->d_stats, 0, sizeof(unsigned long long) * GAL_NUM_COUNTERS));
+    return GAL_OK;
+}
+
+int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *stream)
+{
+    if (!b || !actions_dev || !x_dev) return fail(GAL_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_occupancy(b, s);
+    if (rc) return rc;
+    HIP_TRY(gal::launch_features(b->rp, b->sb, occ_grid(b), actions_dev, x_dev, s));
+    return GAL_OK;
+}
+
+int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t audit_period,
+                         void *stream)
+{
+    if (!b || !m) return fail(GAL_EINVAL, "null argument");
+    if (!(skip_below >= 0.0f && skip_below < 1.0f)) return fail(GAL_EINVAL, "skip_below must be in [0, 1)");
+    if (gal::mlp_max_rows(m) < b->N)
+        return fail(GAL_EINVAL, "the MLP was created for %d rows, the batch has %d envs", gal::mlp_max_rows(m), b->N);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_occupancy(b, s);
+    if (rc) return rc;
+    if (!b->d_feat) {
+        if ((rc = b->mem.alloc(&b->d_feat, (size_t)b->N * gal::kMlpIn)) ||
+            (rc = b->mem.alloc(&b->d_flags, (size_t)b->N)) || (rc = b->mem.alloc(&b->d_sur_stats, 4)))
+            return rc;
+        HIP_TRY(hipMemset(b->d_feat, 0, sizeof(uint16_t) * (size_t)b->N * gal::kMlpIn));
+        HIP_TRY(hipMemset(b->d_sur_stats, 0, sizeof(unsigned long long) * 4));
+    }
+    b->sur = m;
+    // skip iff sigmoid(z) <= skip_below  <=>  z <= logit(skip_below)
+    b->sur_thr_logit = skip_below > 0.0f ? std::log(skip_below / (1.0f - skip_below)) : -INFINITY;
+    b->sur_audit = audit_period;
+    b->tune_gen += 1;   // the captured graph changes
+    return GAL_OK;
+}
+
+int gal_surrogate_detach(gal_batch *b)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    b->sur = nullptr;
+    b->tune_gen += 1;
+    return GAL_OK;
+}
+
+int gal_surrogate_stats(gal_batch *b, int64_t *stats_host, int reset)
+{
+    if (!b || !stats_host) return fail(GAL_EINVAL, "null argument");
+    if (!b->d_sur_stats) {
+        memset(stats_host, 0, sizeof(int64_t) * 4);
+        return GAL_OK;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(stats_host, b->d_sur_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost));
+    if (reset) HIP_TRY(hipMemset(b->d_sur_stats, 0, sizeof(unsigned long long) * 4));
     return GAL_OK;
 }
 

@@ -68,6 +68,9 @@ struct SimBuffers {
     float cell;
     float inv_cell;
     int32_t num_envs;
+    const uint8_t *skip_flags;       // [N] surrogate routing (null = exact check for all):
+                                     // 1 = skip the static check, 2 = skipped but audited
+    unsigned long long *sur_stats;   // [4] queries, skipped, audited, audit mismatches
 };
 
 // Step outputs (device, caller-owned).

@@ -179,7 +179,10 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
     const GridMeta gm = sb.grid_meta[env];
     const bool held = sb.held ? (sb.held[env] != 0) : false;
     const float *objs = sb.objects + (size_t)env * rp.num_objects * 8;
-    bool any = false;
+    // surrogate routing: 1 = static check skipped (no contact assumed),
+    // 2 = skipped but audited (exact check runs; a contact is a mismatch)
+    const int route = sb.skip_flags ? sb.skip_flags[env] : 0;
+    bool any = false, any_static = false;
     for (int base = 0; base < rp.num_spheres; base += kLanes) {
         const int s = base + sub;
         bool hit_static = false, hit_object = false;
@@ -191,8 +194,9 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
                 fpoint(F, sp.px, sp.py, sp.pz, cx, cy, cz);
                 const float r = rp.class_radius[sp.cls];
                 const size_t gk = (size_t)env * rp.num_classes + sp.cls;
-                hit_static = grid_contact(sb, gm, sb.grid_off_base[gk], sb.grid_layer_base[gk],
-                                          cx, cy, cz);
+                if (route != 1)
+                    hit_static = grid_contact(sb, gm, sb.grid_off_base[gk], sb.grid_layer_base[gk],
+                                              cx, cy, cz);
                 for (int o = 0; o < rp.num_objects; ++o) {
                     if (obb_contact(objs + 8 * o, cx, cy, cz, r)) {
                         hit_object = true;
@@ -206,6 +210,7 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         const int w = base >> 5;
         if (kLanes == 64) {
             any = any || (ms | mo) != 0;
+            any_static = any_static || ms != 0;
             if (lane == 0) {
                 if (out.contact_static) {
                     uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
@@ -221,6 +226,7 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         } else {
             const uint32_t hs = (uint32_t)(ms >> (32 * half)), ho = (uint32_t)(mo >> (32 * half));
             any = any || (hs | ho) != 0u;
+            any_static = any_static || hs != 0u;
             if (sub == 0 && active && w < rp.contact_words) {
                 if (out.contact_static) out.contact_static[(size_t)env * rp.contact_words + w] = hs;
                 if (out.contact_object) out.contact_object[(size_t)env * rp.contact_words + w] = ho;
@@ -228,6 +234,7 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         }
     }
     if (!active) return;
+    if (route == 2 && any_static && sub == 0) atomicAdd(&sb.sur_stats[3], 1ull);
 
     // 3. resolve: any overlap rejects the whole move
     const bool accepted = !any;

@@ -95,6 +95,24 @@ def load_library():
         L.gal_autotune.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(GalOutputs), C.c_void_p,
                                    C.c_int32, C.POINTER(GalTuning), C.POINTER(C.c_double)]
         L.gal_get_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
+        L.gal_mlp_num_params.argtypes = [_i64p]
+        L.gal_mlp_create.argtypes = [C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]
+        L.gal_mlp_set_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
+        L.gal_mlp_get_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
+        L.gal_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.gal_mlp_gradients.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gal_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                         C.c_float, C.c_void_p, C.c_void_p]
+        L.gal_mlp_gemm_test.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                        C.c_void_p]
+        L.gal_mlp_destroy.argtypes = [C.c_void_p]
+        L.gal_mlp_destroy.restype = None
+        L.gal_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gal_surrogate_attach.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_uint32, C.c_void_p]
+        L.gal_surrogate_detach.argtypes = [C.c_void_p]
+        L.gal_surrogate_stats.argtypes = [C.c_void_p, _i64p, C.c_int]
         L.gal_set_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
         L.gal_destroy.argtypes = [C.c_void_p]
         L.gal_destroy.restype = None
@@ -284,6 +302,28 @@ class Batch:
                               n.value, C.byref(n)))
         return offs, lay[:n.value]
 
+    # ---- collision surrogate
+    def features(self, actions, x, stream=None):
+        """BF16 surrogate inputs (torch int16 [N][2080]) of the next move."""
+        _check(load_library().gal_features(self._h, actions.data_ptr(), x.data_ptr(),
+                                           _stream_handle(stream)))
+
+    def attach_surrogate(self, mlp: "Mlp", skip_below: float, audit_period: int = 16,
+                         stream=None):
+        _check(load_library().gal_surrogate_attach(self._h, mlp._h, float(skip_below),
+                                                   int(audit_period), _stream_handle(stream)))
+        self._mlp = mlp   # keep it alive while attached
+
+    def detach_surrogate(self):
+        _check(load_library().gal_surrogate_detach(self._h))
+        self._mlp = None
+
+    def surrogate_stats(self, reset: bool = False) -> dict:
+        v = np.zeros(4, np.int64)
+        _check(load_library().gal_surrogate_stats(self._h, _p(v, _i64p), 1 if reset else 0))
+        return dict(queries=int(v[0]), skipped=int(v[1]), audited=int(v[2]),
+                    mismatches=int(v[3]))
+
     def get_tuning(self) -> dict:
         t = GalTuning()
         _check(load_library().gal_get_tuning(self._h, C.byref(t)))
@@ -323,3 +363,72 @@ class Batch:
     def env_depth(self, depth_flat, e: int):
         r = int(self.res[e])
         return depth_flat[int(self.depth_off[e]):int(self.depth_off[e + 1])].reshape(r, r)
+
+
+class Mlp:
+    """The collision-surrogate MLP on the device (see include/gal.h)."""
+    IN = 2080
+
+    def __init__(self, max_rows: int, seed: int = 0):
+        L = load_library()
+        h = C.c_void_p()
+        _check(L.gal_mlp_create(int(max_rows), int(seed), C.byref(h)))
+        self._h = h
+        self.max_rows = int(max_rows)
+        n = C.c_int64()
+        _check(L.gal_mlp_num_params(C.byref(n)))
+        self.num_params = n.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gal_mlp_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.num_params, np.float32)
+        _check(load_library().gal_mlp_get_weights(self._h, _p(w, _fp), w.size))
+        return w
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(load_library().gal_mlp_set_weights(self._h, _p(w, _fp), w.size))
+
+    def forward(self, x, logits, rows=None, stream=None):
+        rows = x.shape[0] if rows is None else rows
+        _check(load_library().gal_mlp_forward(self._h, x.data_ptr(), int(rows), logits.data_ptr(),
+                                              _stream_handle(stream)))
+
+    def gradients(self, x, y, pos_weight, grads=None, loss=None, stream=None):
+        _check(load_library().gal_mlp_gradients(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                                float(pos_weight), _ptr(grads), _ptr(loss),
+                                                _stream_handle(stream)))
+
+    def train_step(self, x, y, pos_weight, lr, loss=None, stream=None):
+        _check(load_library().gal_mlp_train_step(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                                 float(pos_weight), float(lr), _ptr(loss),
+                                                 _stream_handle(stream)))
+
+    @staticmethod
+    def layout():
+        """(offset, shape) of W1, b1, ..., W5, b5 in the flat parameter vector."""
+        dims = [2080, 256, 256, 256, 256, 1]
+        out, off = [], 0
+        for l in range(5):
+            n = dims[l + 1] * dims[l]
+            out.append((off, (dims[l + 1], dims[l])))
+            off += n
+            out.append((off, (dims[l + 1],)))
+            off += dims[l + 1]
+        return out
+
+
+def gemm_test(variant, a, b, M, N, K, lda, ldb, c, ldc, stream=None):
+    _check(load_library().gal_mlp_gemm_test(variant, a.data_ptr(), b.data_ptr(), M, N, K, lda, ldb,
+                                            c.data_ptr(), ldc, _stream_handle(stream)))

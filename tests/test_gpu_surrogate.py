@@ -1,0 +1,257 @@
+"""GPU tests of the collision surrogate: the MFMA GEMM against numpy, the
+MLP forward pass and gradients against the FP64 oracle on the same BF16
+tensors, the feature builder against a CPU recomputation, training, the
+routing (exact results under a full audit) and the measured gain."""
+import numpy as np
+import pytest
+
+from paper_2306_07552_amd import scenegen as sg
+from parity_util import compare_step, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def bf16_bits(a: np.ndarray) -> np.ndarray:
+    from oracle.oracle_mlp import bf16_round_f32
+    r = bf16_round_f32(np.asarray(a, np.float32))
+    return (r.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def bits_to_f64(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("variant,M,N,K", [(3, 130, 70, 96), (4, 77, 130, 64), (5, 96, 66, 200),
+                                           (3, 64, 256, 2080)])
+def test_mfma_gemm_matches_numpy(torch_cuda, variant, M, N, K):
+    torch = torch_cuda
+    print(f"case: gemm variant {variant} {M}x{N}x{K}", flush=True)
+    rng = np.random.default_rng(variant * 1000 + M)
+    # operand storage: 3 = A[M][K], B^T[N][K]; 4 = A[M][K], B[K][N]; 5 = A^T[K][M], B[K][N]
+    if variant == 3:
+        a, b, lda, ldb = rng.normal(size=(M, K)), rng.normal(size=(N, K)), K, K
+    elif variant == 4:
+        a, b, lda, ldb = rng.normal(size=(M, K)), rng.normal(size=(K, N)), K, N
+    else:
+        a, b, lda, ldb = rng.normal(size=(K, M)), rng.normal(size=(K, N)), M, N
+    ab, bb = bf16_bits(a), bf16_bits(b)
+    A, B = bits_to_f64(ab), bits_to_f64(bb)
+    opA = A.T if variant == 5 else A
+    opB = B.T if variant == 3 else B
+    ref = opA @ opB
+    bound = (np.abs(opA) @ np.abs(opB)) * (K + 2) * 2.0 ** -24
+    from paper_2306_07552_amd import gal
+    ta = torch.from_numpy(ab.view(np.int16)).cuda()
+    tb = torch.from_numpy(bb.view(np.int16)).cuda()
+    c = torch.full((M, N), np.nan, dtype=torch.float32, device="cuda")
+    gal.gemm_test(variant, ta, tb, M, N, K, lda, ldb, c, N)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bound + 1e-30)
+
+
+def small_batch(n=16):
+    cfg = sg.scaled_config(1, n)
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    return cfg, scenes, robot, sg.config_constants(cfg)
+
+
+def test_features_match_cpu(torch_cuda):
+    """Scalars and the occupancy patch, recomputed on the CPU from the
+    oracle's column grid (class 0), are bit-identical."""
+    torch = torch_cuda
+    print("case: features", flush=True)
+    from oracle import oracle as O
+    from oracle.oracle_mlp import bf16_round_f32
+    from paper_2306_07552_amd import gal
+    cfg, scenes, robot, consts = small_batch(6)
+    b = gal.Batch(robot, scenes, consts)
+    a = sg.actions(cfg, 3, num_envs=6)
+    a[0, 2] = np.nan
+    x = torch.empty((6, 2080), dtype=torch.int16, device="cuda")
+    b.features(torch.from_numpy(a).cuda(), x)
+    torch.cuda.synchronize()
+    X = x.cpu().numpy().view(np.uint16)
+    st, _ = b.get_state()
+    ob = O.OracleBatch(robot, scenes, consts)
+    lim = np.float32(cfg.act_lim[2])
+    f32 = np.float32
+    for e in range(6):
+        q = st[e, 3:10]
+        aj = np.nan_to_num(a[e, 2:9], nan=0.0).astype(np.float32)
+        aj = np.clip(aj, -lim, lim) / lim
+        a0 = np.clip(np.nan_to_num(a[e, 0:1]), -f32(cfg.act_lim[0]), f32(cfg.act_lim[0])) / f32(cfg.act_lim[0])
+        a1 = np.clip(np.nan_to_num(a[e, 1:2]), -f32(cfg.act_lim[1]), f32(cfg.act_lim[1])) / f32(cfg.act_lim[1])
+        x0, y0 = scenes.grid_origin[e]
+        nx, ny = scenes.grid_dims[e]
+        cell = f32(sg.CELL)
+        sc = np.concatenate([q, aj, a0, a1,
+                             [(st[e, 0] - x0) / (f32(nx) * cell), (st[e, 1] - y0) / (f32(ny) * cell),
+                              st[e, 2] * f32(0.31830988618)]]).astype(np.float32)
+        want = np.zeros(2080, np.uint16)
+        want[:19] = (bf16_round_f32(sc).view(np.uint32) >> 16).astype(np.uint16)
+        oc = f32(2.0) * cell
+        ci = int(np.floor((st[e, 0] - x0) / oc))
+        cj = int(np.floor((st[e, 1] - y0) / oc))
+        ox, oy = (nx + 1) // 2, (ny + 1) // 2
+        env = ob._env_structs[e]
+        import ctypes as C
+        for pa in range(16):
+            for pb in range(16):
+                i, j = ci + pa - 8, cj + pb - 8
+                for k in range(8):
+                    if 0 <= i < ox and 0 <= j < oy:
+                        cx = f32(x0 + (f32(i) + f32(0.5)) * oc)
+                        cy = f32(y0 + (f32(j) + f32(0.5)) * oc)
+                        cz = f32((f32(k) + f32(0.5)) * f32(0.25))
+                        blocked = O.lib().o_grid_query(C.byref(env), 0, float(cx), float(cy), float(cz))
+                    else:
+                        blocked = 1
+                    want[32 + (pa * 16 + pb) * 8 + k] = 0x3F80 if blocked else 0
+        assert np.array_equal(X[e], want), f"env {e}: {np.flatnonzero(X[e] != want)[:10]}"
+
+
+def oracle_net(w):
+    from oracle.oracle_mlp import OracleMLP, bf16_round_f32
+    from paper_2306_07552_amd.gal import Mlp
+    W, B = [], []
+    for k, (off, shape) in enumerate(Mlp.layout()):
+        v = w[off:off + int(np.prod(shape))].reshape(shape)
+        (W if k % 2 == 0 else B).append(bf16_round_f32(v).astype(np.float64) if k % 2 == 0
+                                        else v.astype(np.float64))
+    return OracleMLP(W, B)
+
+
+def test_forward_and_gradients_match_oracle(torch_cuda):
+    """Same BF16 inputs and weights: logits and every parameter gradient of
+    the device MLP agree with the FP64 oracle (which rounds activations and
+    pre-activation gradients to BF16 at the same points) to a relative L2 of
+    1e-3; the differences come from FP32 vs FP64 accumulation flipping an
+    occasional BF16 rounding."""
+    torch = torch_cuda
+    print("case: mlp forward/backward vs oracle", flush=True)
+    from paper_2306_07552_amd import gal
+    cfg, scenes, robot, consts = small_batch(16)
+    b = gal.Batch(robot, scenes, consts)
+    rows = 96
+    X = torch.empty((rows, 2080), dtype=torch.int16, device="cuda")
+    for k in range(rows // 16):
+        b.features(torch.from_numpy(sg.actions(cfg, k, num_envs=16)).cuda(), X[16 * k:16 * (k + 1)])
+        b.step(torch.from_numpy(sg.actions(cfg, k, num_envs=16)).cuda(),
+               {kk: v for kk, v in b.alloc_outputs().items() if kk != "depth"})
+    rng = np.random.default_rng(0)
+    y = (rng.uniform(size=rows) < 0.3).astype(np.float32)
+    mlp = gal.Mlp(max_rows=128, seed=11)
+    # a trained-looking point: a few Adam steps first
+    yt = torch.from_numpy(y).cuda()
+    for _ in range(3):
+        mlp.train_step(X, yt, 4.0, 1e-3)
+    torch.cuda.synchronize()
+    w = mlp.get_weights()
+    z = torch.empty(rows, dtype=torch.float32, device="cuda")
+    mlp.forward(X, z)
+    grads = torch.empty(mlp.num_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    mlp.gradients(X, yt, 4.0, grads, loss)
+    torch.cuda.synchronize()
+    net = oracle_net(w)
+    x64 = bits_to_f64(X.cpu().numpy().view(np.uint16))
+    zo = net.forward(x64, round_bf16=True)
+    zg = z.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(zg - zo) <= 1e-3 * np.linalg.norm(zo)
+    lo, dW, db = net.backward(x64, y.astype(np.float64), 4.0, round_bf16=True)
+    assert abs(float(loss.cpu()[0]) - lo) <= 1e-3 * abs(lo)
+    g = grads.cpu().numpy().astype(np.float64)
+    for k, (off, shape) in enumerate(gal.Mlp.layout()):
+        ref = (dW if k % 2 == 0 else db)[k // 2].reshape(-1)
+        got = g[off:off + ref.size]
+        assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-12, f"param block {k}"
+
+
+def test_training_reduces_loss(torch_cuda):
+    torch = torch_cuda
+    print("case: training", flush=True)
+    from paper_2306_07552_amd import gal, surrogate
+    cfg = sg.scaled_config(1, 256)
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    b = gal.Batch(robot, scenes, sg.config_constants(cfg))
+    X, y = surrogate.generate(b, 65536, cfg.act_lim, seed=1)
+    rate = float(y.mean())
+    assert 0.0 < rate < 1.0
+    mlp = gal.Mlp(max_rows=4096, seed=3)
+    h = surrogate.train(mlp, X, y, epochs=3, batch_size=4096, lr=1e-3, pos_weight=4.0)
+    assert h["loss"][-1] < h["loss"][0]
+
+
+@pytest.fixture(scope="module")
+def trained(torch_cuda):
+    """MLP trained on rollouts of 512 training envs, calibrated on 256
+    held-out envs (different scenes)."""
+    from paper_2306_07552_amd import gal, surrogate
+    cfg = sg.scaled_config(1, 512)
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    tr = gal.Batch(robot, sg.make_scene_set(cfg, range(0, 512)), consts)
+    X, y = surrogate.generate(tr, 1 << 20, cfg.act_lim, seed=7)
+    mlp = gal.Mlp(max_rows=4096, seed=5)
+    hist = surrogate.train(mlp, X, y, epochs=4, batch_size=4096, lr=1e-3, pos_weight=8.0)
+    del X, y
+    ho = gal.Batch(robot, sg.make_scene_set(cfg, range(512, 768)), consts)
+    Xh, yh = surrogate.generate(ho, 1 << 18, cfg.act_lim, seed=8)
+    skip_below, info = surrogate.calibrate(mlp, Xh, yh, chunk=4096)
+    print(f"trained: {hist}, calibration {info}", flush=True)
+    return mlp, skip_below, info
+
+
+def test_routing_full_audit_is_exact(torch_cuda, trained):
+    """With every skipped query audited the step's outputs are the oracle's
+    bit for bit, and the counters add up."""
+    torch = torch_cuda
+    print("case: routing with full audit", flush=True)
+    mlp, skip_below, info = trained
+    cfg = sg.scaled_config(1, 24)
+    b, ob, scenes, robot = make_pair(cfg, envs=range(900, 924), oracle_envs=list(range(24)))
+    b.attach_surrogate(mlp, max(skip_below, 0.2), audit_period=1)
+    out = b.alloc_outputs()
+    for k in range(12):
+        a = sg.actions(cfg, 100 + k, num_envs=24)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        compare_step(b, ob, out, ob.step(a), label=f"step {k}")
+    st = b.surrogate_stats()
+    assert st["queries"] == 24 * 12 and st["audited"] == st["skipped"]
+
+
+def test_surrogate_gain_zero_mismatches(torch_cuda, trained):
+    """On fresh scenes and motions, with a full audit: no skipped query had a
+    contact (mismatches 0), and the fraction of exact static checks the
+    surrogate removes is reported (the gain)."""
+    torch = torch_cuda
+    print("case: surrogate gain", flush=True)
+    mlp, skip_below, info = trained
+    from paper_2306_07552_amd import gal
+    cfg = sg.scaled_config(1, 1024)
+    robot = sg.make_robot_for(cfg)
+    b = gal.Batch(robot, sg.make_scene_set(cfg, range(2000, 3024)), sg.config_constants(cfg))
+    b.attach_surrogate(mlp, skip_below, audit_period=1)
+    out = {k: v for k, v in b.alloc_outputs().items() if k != "depth"}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(99)
+    lim = torch.tensor([0.1, 0.1] + [0.05] * 7, device="cuda")
+    for _ in range(64):
+        b.step(((torch.rand((1024, 9), generator=g, device="cuda") * 2 - 1) * lim).contiguous(), out)
+    st = b.surrogate_stats()
+    frac = st["skipped"] / st["queries"]
+    print(f"gain: {frac:.3f} of exact static checks skippable; stats {st}; calibration {info}",
+          flush=True)
+    assert st["mismatches"] == 0
+    assert frac > 0.0
