@@ -64,26 +64,14 @@ def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
                 sample=f"{len(envs)} envs of the same workload x {k} steps ({dt:.1f} s)")
 
 
-def train_surrogate(cfg, robot, consts, n_train_envs=512, samples=1 << 20):
-    """Surrogate trained on rollouts of scenes the benchmark does not use."""
-    from paper_2306_07552_amd import gal, scenegen as sg, surrogate
+def train_surrogate(cfg, robot, consts, n_train_envs=2048):
+    """Surrogate trained and calibrated on rollouts of scenes the benchmark
+    does not use."""
+    from paper_2306_07552_amd import surrogate
     base = cfg.num_envs
-    t0 = time.perf_counter()
-    tr = gal.Batch(robot, sg.make_scene_set(cfg, range(base, base + n_train_envs)), consts)
-    X, y = surrogate.generate(tr, samples, cfg.act_lim, seed=7)
-    mlp = gal.Mlp(max_rows=max(4096, cfg.num_envs), seed=5)
-    hist = surrogate.train(mlp, X, y, epochs=4, batch_size=4096, lr=1e-3, pos_weight=8.0)
-    pos_rate = float(y.mean())
-    del X, y, tr
-    ho = gal.Batch(robot, sg.make_scene_set(cfg, range(base + n_train_envs,
-                                                       base + n_train_envs + 256)), consts)
-    Xh, yh = surrogate.generate(ho, 1 << 18, cfg.act_lim, seed=8)
-    skip_below, info = surrogate.calibrate(mlp, Xh, yh, chunk=4096)
-    del Xh, yh, ho
-    info.update(train_samples=samples, train_loss=[round(v, 5) for v in hist["loss"]],
-                train_seconds=round(hist["seconds"], 2), positive_rate=round(pos_rate, 4),
-                setup_seconds=round(time.perf_counter() - t0, 1))
-    return mlp, skip_below, info
+    return surrogate.fit(robot, consts, cfg, range(base, base + n_train_envs),
+                         range(base + n_train_envs, base + n_train_envs + 512),
+                         max_rows=max(4096, cfg.num_envs))
 
 
 def main():

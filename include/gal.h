@@ -299,20 +299,27 @@ int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
  *
  * A small MLP predicts, for each environment's next move, whether its
  * candidate pose overlaps the static scene (the column-grid test of Section
- * 3.2).  Input (2080 BF16 values, gal_features): 7 joint angles, the 7 joint
- * offsets and 2 base offsets of the action normalised by their limits, the
- * base pose normalised by the grid extent (and yaw / pi), 13 zeros, then the
- * 16 x 16 x 8 occupancy patch around the base (cells of 2 x 2 grid cells and
- * 0.25 m, 1 = blocked for the smallest sphere class; outside the grid
- * counts as blocked).  Network 2080 -> 256 -> 256 -> 256 -> 256 -> 1 with
+ * 3.2).  Input (2112 BF16 values, gal_features): [0..6] the candidate
+ * joint angles; [7..13] the joint offsets and [14..15] the base offsets of
+ * the action, normalised by their limits; [16..18] the base pose normalised
+ * by the grid extent (and yaw / pi); [19] the held-object flag; [20..40] the
+ * origins of joint frames 1..7 and [41..43] the end-effector z axis of the
+ * candidate arm pose in the base frame (metres); [44..63] zeros; then
+ * [64..2111] a 16 x 16 x 8 occupancy patch [a][b][layer] in the frame of the
+ * candidate base pose: cells 0.1 m wide centred on ((a - 7.5) 0.1 m,
+ * (b - 7.5) 0.1 m) around the base, layers of 0.25 m from the floor.  A
+ * patch cell is 1 (blocked) when any grid column under the bounding box of
+ * its rotated footprint has, at one of four heights inside the layer (none
+ * below 0.125 m), no free layer of the batch's last radius class (the
+ * largest in a plain batch), or when that box leaves the grid.  Network 2112 -> 256 -> 256 -> 256 -> 256 -> 1 with
  * ReLU, BF16 weights and activations, FP32 accumulation (matrix cores).
- * Parameters are FP32 [W1 (256 x 2080), b1, W2, b2, W3, b3, W4, b4,
+ * Parameters are FP32 [W1 (256 x 2112), b1, W2, b2, W3, b3, W4, b4,
  * W5 (1 x 256), b5], each W one row per output unit.
  */
 typedef struct gal_mlp gal_mlp;
-#define GAL_MLP_IN 2080
+#define GAL_MLP_IN 2112
 
-/* Total parameter count (729,601). */
+/* Total parameter count (738,561). */
 int gal_mlp_num_params(int64_t *n);
 /* Device MLP for up to max_rows rows per call; He-uniform initial weights
  * from `seed`, zero biases, Adam state cleared.  Synchronous. */
@@ -321,7 +328,7 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out);
  * set also clears the Adam state.  Synchronous. */
 int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count);
 int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
-/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2080]). */
+/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112]). */
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
 /* Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
  * w_i = pos_weight for labels 1, into grads_dev (device f32, parameter
@@ -340,9 +347,9 @@ int gal_mlp_gemm_test(int32_t variant, const uint16_t *a_dev, const uint16_t *b_
                       void *stream);
 void gal_mlp_destroy(gal_mlp *m);
 
-/* Surrogate inputs of every env's next move under actions_dev (device BF16
- * u16 [N][2080]).  Builds the occupancy lattice on first use (synchronous
- * then). */
+/* Surrogate inputs of every env's next move under actions_dev into x_dev
+ * (device BF16 u16 [N][2112], 16-byte aligned).  Builds the occupancy
+ * lattice on first use (synchronous then). */
 int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *stream);
 /*
  * Put the MLP in front of the static check of gal_step: an env whose

@@ -184,7 +184,7 @@ struct gal_batch {
     gal_mlp *sur = nullptr;
     float sur_thr_logit = 0.0f;
     uint32_t sur_audit = 16;
-    uint16_t *d_feat = nullptr;             // [N][2080] BF16 inputs of the step's queries
+    uint16_t *d_feat = nullptr;             // [N][2112] BF16 inputs of the step's queries
     uint8_t *d_flags = nullptr;             // [N] routing
     unsigned long long *d_sur_stats = nullptr;
     uint8_t *d_occ = nullptr;               // occupancy lattice (built on first use)
@@ -800,7 +800,7 @@ gal::OccGrid occ_grid(const gal_batch *b)
     og.occ = b->d_occ;
     og.occ_off = b->d_occ_off;
     og.occ_dims = b->d_occ_dims;
-    og.occ_cell = 2.0f * b->sb.cell;
+    og.occ_cell = b->sb.cell;
     return og;
 }
 
@@ -813,7 +813,7 @@ int ensure_occupancy(gal_batch *b, hipStream_t s)
     uint64_t tot = 0;
     int32_t maxc = 0;
     for (int e = 0; e < b->N; ++e) {
-        const int ox = (b->meta_host[e].nx + 1) / 2, oy = (b->meta_host[e].ny + 1) / 2;
+        const int ox = b->meta_host[e].nx, oy = b->meta_host[e].ny;
         dims[2 * e] = ox;
         dims[2 * e + 1] = oy;
         off[e] = tot;
@@ -981,6 +981,7 @@ int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count)
 int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *stream)
 {
     if (!b || !actions_dev || !x_dev) return fail(GAL_EINVAL, "null argument");
+    if ((uintptr_t)x_dev % 16) return fail(GAL_EINVAL, "x_dev must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     int rc = ensure_occupancy(b, s);
     if (rc) return rc;

@@ -8,12 +8,12 @@
 
 namespace gal {
 
-constexpr int kMlpIn = 2080;       // 19 scalars, 13 zeros, 16 x 16 x 8 occupancy patch
+constexpr int kMlpIn = 2112;       // 44 scalars, 20 zeros, 16 x 16 x 8 occupancy patch
 constexpr int kMlpHidden = 256;
 constexpr int kMlpLayers = 5;      // 4 hidden + logit head
 constexpr int kPatch = 16;         // patch edge in occupancy cells
 constexpr int kPatchZ = 8;         // occupancy layers of 0.25 m from the floor
-constexpr int kFeatPatchBase = 32; // first patch feature
+constexpr int kFeatPatchBase = 64; // first patch feature
 
 enum { kEpiF32 = 0, kEpiBiasReluBf16 = 1, kEpiMaskBf16 = 2 };
 enum { kGemmFwd = 0, kGemmDx, kGemmDw, kGemmNtF32, kGemmNnF32, kGemmTnF32 };
@@ -34,10 +34,10 @@ hipError_t mlp_to_bf16(const float *a, int64_t n, uint16_t *out, hipStream_t s);
 
 // Surrogate plumbing of a batch.
 struct OccGrid {
-    uint8_t *occ;              // per env [oy][ox][8] blocked flags of the class-0 grid
+    uint8_t *occ;              // per env [ny][nx][8] blocked flags of the class-0 grid
     const uint64_t *occ_off;   // [N] base of each env's block
-    const int32_t *occ_dims;   // [N][2] ox, oy
-    float occ_cell;            // lateral occupancy cell (2 grid cells)
+    const int32_t *occ_dims;   // [N][2] nx, ny (the column grid's)
+    float occ_cell;            // lateral cell (the column grid's)
 };
 
 hipError_t launch_occ_build(const SimBuffers &sb, const OccGrid &og, int num_envs, int num_classes,

@@ -144,7 +144,7 @@ namespace gal {
 const float *mlp_logits(const gal_mlp *m) { return m->z; }
 int mlp_max_rows(const gal_mlp *m) { return m->max_rows; }
 
-// forward pass of rows inputs (BF16 [rows][2080]) into m->h[1..4] and m->z
+// forward pass of rows inputs (BF16 [rows][2112]) into m->h[1..4] and m->z
 int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s)
 {
     const uint16_t *in = x;

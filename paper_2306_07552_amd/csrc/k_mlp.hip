@@ -2,7 +2,7 @@
 //
 // The surrogate is this build's learned pre-filter for the static-scene
 // overlap test of the kinematic step (Section 3.2 of the paper describes the
-// exact test it stands in front of).  Network: 2080 inputs -> 4 x 256 ReLU ->
+// exact test it stands in front of).  Network: 2112 inputs -> 4 x 256 ReLU ->
 // 1 logit.  Weights and activations are BF16 (round to nearest even after
 // bias + ReLU), accumulation FP32, biases and master weights FP32.
 //

@@ -5,6 +5,7 @@
 // the chain of seven joint frames is evaluated redundantly by every lane (it
 // is a short serial chain), each lane owns every 64th (32nd) sphere, and the
 // accept/reject decision is a ballot.
+#include "gal_fk.h"
 #include "gal_internal.h"
 #include "gal_math.h"
 
@@ -21,41 +22,6 @@ __device__ __forceinline__ float sanitize(float a, float lim)
 {
     if (a != a) a = 0.0f;
     return clampf(a, -lim, lim);
-}
-
-// Frame of link `link` for pose `st` (10 floats).  All eight frames are built
-// in order; the requested ones are kept by predicated copies so no register
-// array is indexed dynamically.
-struct Fk {
-    Frame f[8];
-};
-
-__device__ __forceinline__ void forward_kinematics(const RobotParams &rp, const float *st, Fk &out)
-{
-    float s, c;
-    dsincos(st[2], s, c);
-    Frame F0;
-    F0.m[0] = c;    F0.m[1] = -s;   F0.m[2] = 0.0f;  F0.m[3] = st[0];
-    F0.m[4] = s;    F0.m[5] = c;    F0.m[6] = 0.0f;  F0.m[7] = st[1];
-    F0.m[8] = 0.0f; F0.m[9] = 0.0f; F0.m[10] = 1.0f; F0.m[11] = 0.0f;
-    Frame T;
-    T.m[0] = 1.0f; T.m[1] = 0.0f; T.m[2] = 0.0f;  T.m[3] = rp.mount[0];
-    T.m[4] = 0.0f; T.m[5] = 1.0f; T.m[6] = 0.0f;  T.m[7] = rp.mount[1];
-    T.m[8] = 0.0f; T.m[9] = 0.0f; T.m[10] = 1.0f; T.m[11] = rp.mount[2];
-    out.f[0] = F0;
-    Frame prev = fmul(F0, T);
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        float sq, cq;
-        dsincos(st[3 + j], sq, cq);
-        const float a = rp.dh[j][0], d = rp.dh[j][1], ca = rp.dh[j][2], sa = rp.dh[j][3];
-        Frame A;
-        A.m[0] = cq;   A.m[1] = -(sq * ca); A.m[2] = sq * sa;     A.m[3] = a * cq;
-        A.m[4] = sq;   A.m[5] = cq * ca;    A.m[6] = -(cq * sa);  A.m[7] = a * sq;
-        A.m[8] = 0.0f; A.m[9] = sa;         A.m[10] = ca;         A.m[11] = d;
-        prev = fmul(prev, A);
-        out.f[j + 1] = prev;
-    }
 }
 
 __device__ __forceinline__ Frame pick(const Fk &fk, int link)

@@ -1,13 +1,24 @@
 // Surrogate inputs and routing on the device.
 //
-// Occupancy: a world-aligned lattice of cells (2 x 2 column-grid cells
-// laterally, 0.25 m vertically, 8 layers from the floor); a cell is blocked
-// when its centre is in contact for the smallest sphere class in the column
-// grid (Appendix G's structure, queried as in the step).  Features of one
-// env's next move: joint angles, normalised joint / base offsets, normalised
-// base pose, and the 16 x 16 x 8 occupancy patch around the base.
+// Occupancy: per column of the grid and per layer of 0.25 m from the floor
+// (8 layers), blocked when the column holds no free layer of the batch's
+// last radius class (its largest in a plain batch) at any of four heights
+// inside the layer (0.0625 m apart, none below 0.125 m so that the floor
+// alone blocks nothing).  Every smaller class's blocked set lies inside the
+// largest class's, so a sphere in contact sits in a blocked column
+// (Appendix G's structure, summarised).
+// Features of one env's next move: the candidate joint angles, normalised
+// joint and base offsets, normalised base pose, the held-object flag, the
+// origins of the seven joint frames and the end-effector z axis of the
+// candidate arm pose in the base frame (the step's own kinematics), and a
+// 16 x 16 x 8 patch in the frame of the candidate base pose (0.1 m cells
+// centred on the base, so it covers the arm's reach); a patch cell is
+// blocked when any column under its rotated footprint's bounding box is, or
+// when that box leaves the grid.
 // Routing: the exact static check of an env is skipped when the logit is at
 // or below the threshold, except for a hashed 1-in-period audit sample.
+#include "gal_fk.h"
+#include "gal_math.h"
 #include "gal_mlp.h"
 
 namespace gal {
@@ -32,32 +43,34 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
+// free-space test of one column of an env's class-0 grid at height z
+__device__ __forceinline__ bool column_free(const SimBuffers &sb, const GridMeta &gm, size_t ek,
+                                            int ci, int cj, float z)
+{
+    if (ci >= gm.nx || cj >= gm.ny) return false;
+    const uint32_t *off = sb.grid_offsets + sb.grid_off_base[ek] + (size_t)cj * gm.nx + ci;
+    const float2 *lay = sb.grid_layers + sb.grid_layer_base[ek];
+    for (uint32_t l = off[0]; l < off[1]; ++l) {
+        const float2 L = lay[l];
+        if (L.x <= z && z <= L.y) return true;
+    }
+    return false;
+}
+
 __global__ void k_occ_build(SimBuffers sb, OccGrid og, int num_envs, int max_cells, int num_classes)
 {
     const int env = blockIdx.y;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;   // (j * ox + i) * 8 + k
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;   // (j * nx + i) * 8 + k
     if (env >= num_envs) return;
     const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
     if (cell >= ox * oy * kPatchZ) return;
     const int k = cell % kPatchZ, ij = cell / kPatchZ, i = ij % ox, j = ij / ox;
     const GridMeta gm = sb.grid_meta[env];
-    const float x = gm.x0 + ((float)i + 0.5f) * og.occ_cell;
-    const float y = gm.y0 + ((float)j + 0.5f) * og.occ_cell;
-    const float z = ((float)k + 0.5f) * 0.25f;
-    bool blocked = true;
-    const float fx = (x - gm.x0) * sb.inv_cell, fy = (y - gm.y0) * sb.inv_cell;
-    if (fx >= 0.0f && fx < (float)gm.nx && fy >= 0.0f && fy < (float)gm.ny) {
-        const int ci = (int)floorf(fx), cj = (int)floorf(fy);
-        const size_t ek = (size_t)env * num_classes + 0;
-        const uint32_t *off = sb.grid_offsets + sb.grid_off_base[ek] + (size_t)cj * gm.nx + ci;
-        const float2 *lay = sb.grid_layers + sb.grid_layer_base[ek];
-        for (uint32_t l = off[0]; l < off[1]; ++l) {
-            const float2 L = lay[l];
-            if (L.x <= z && z <= L.y) {
-                blocked = false;
-                break;
-            }
-        }
+    const size_t ek = (size_t)env * num_classes + (num_classes - 1);
+    bool blocked = false;
+    for (int m = 0; m < 4 && !blocked; ++m) {
+        const float z = fmaxf((float)k * 0.25f + 0.0625f * (float)(m + 1), 0.125f);
+        blocked = !column_free(sb, gm, ek, i, j, z);
     }
     og.occ[og.occ_off[env] + cell] = blocked ? 1 : 0;
 }
@@ -73,33 +86,75 @@ __global__ void k_features(RobotParams rp, SimBuffers sb, OccGrid og, const floa
     const float *a = actions + (size_t)env * 9;
     uint16_t *row = x + (size_t)env * kMlpIn;
     const GridMeta gm = sb.grid_meta[env];
-    if (lane < 32) {
+    const float a0 = sanitize(a[0], rp.act_lim[0]), a1 = sanitize(a[1], rp.act_lim[1]);
+    if (lane < 20) {
         float v = 0.f;
-        if (lane < 7) v = st[3 + lane];
+        if (lane < 7)
+            v = clampf(st[3 + lane] + sanitize(a[2 + lane], rp.act_lim[2]), rp.qlim[lane][0],
+                       rp.qlim[lane][1]);
         else if (lane < 14) v = sanitize(a[2 + lane - 7], rp.act_lim[2]) / rp.act_lim[2];
-        else if (lane == 14) v = sanitize(a[0], rp.act_lim[0]) / rp.act_lim[0];
-        else if (lane == 15) v = sanitize(a[1], rp.act_lim[1]) / rp.act_lim[1];
+        else if (lane == 14) v = a0 / rp.act_lim[0];
+        else if (lane == 15) v = a1 / rp.act_lim[1];
         else if (lane == 16) v = (st[0] - gm.x0) / ((float)gm.nx * sb.cell);
         else if (lane == 17) v = (st[1] - gm.y0) / ((float)gm.ny * sb.cell);
         else if (lane == 18) v = st[2] * 0.31830988618f;
+        else if (lane == 19) v = sb.held[env] ? 1.0f : 0.0f;
         row[lane] = f2bf(v);
     }
+    {
+        // arm frames of the candidate joint angles with the base at the origin
+        float q[10] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            q[3 + j] = clampf(st[3 + j] + sanitize(a[2 + j], rp.act_lim[2]), rp.qlim[j][0], rp.qlim[j][1]);
+        Fk fk;
+        forward_kinematics(rp, q, fk);
+        // lanes 20..40: origin of frame 1 + (l - 20) / 3, lanes 41..43: z axis of frame 7
+        float v = 0.f;
+#pragma unroll
+        for (int j = 1; j < 8; ++j)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                if (lane == 20 + 3 * (j - 1) + r) v = fk.f[j].m[4 * r + 3];
+                if (j == 7 && lane == 41 + r) v = fk.f[7].m[4 * r + 2];
+            }
+        if (lane >= 20 && lane < kFeatPatchBase) row[lane] = f2bf(v);
+    }
+    // candidate base pose, in the robot step's own operation order
+    const float pi_f = 0x1.921fb6p+1f, two_pi_f = 0x1.921fb6p+2f;
+    float yaw = st[2] + a1;
+    if (yaw > pi_f) yaw = yaw - two_pi_f;
+    else if (yaw < -pi_f) yaw = yaw + two_pi_f;
+    float sy, cy;
+    dsincos(yaw, sy, cy);
+    const float bx = st[0] + a0 * cy, by = st[1] + a0 * sy;
     const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
-    const int ci = (int)floorf((st[0] - gm.x0) / og.occ_cell), cj = (int)floorf((st[1] - gm.y0) / og.occ_cell);
     const uint8_t *occ = og.occ + og.occ_off[env];
     // 256 (a, b) cells of 8 layers; lane takes 4 of them
+    const float hx = 0.05f * (fabsf(cy) + fabsf(sy));   // half-extent of a rotated cell's box
     for (int c = lane; c < kPatch * kPatch; c += 64) {
         const int pa = c / kPatch, pb = c % kPatch;
-        const int i = ci + pa - kPatch / 2, j = cj + pb - kPatch / 2;
-        uint64_t bits = 0x0101010101010101ull;   // outside the lattice: blocked
-        if (i >= 0 && i < ox && j >= 0 && j < oy)
-            bits = *reinterpret_cast<const uint64_t *>(occ + ((size_t)j * ox + i) * kPatchZ);
-        uint16_t v[8];
+        const float px = ((float)pa - 7.5f) * 0.1f, py = ((float)pb - 7.5f) * 0.1f;
+        const float wx = bx + (cy * px - sy * py), wy = by + (sy * px + cy * py);
+        const float fi0 = floorf(((wx - hx) - gm.x0) / og.occ_cell);
+        const float fi1 = floorf(((wx + hx) - gm.x0) / og.occ_cell);
+        const float fj0 = floorf(((wy - hx) - gm.y0) / og.occ_cell);
+        const float fj1 = floorf(((wy + hx) - gm.y0) / og.occ_cell);
+        uint64_t bits = 0x0101010101010101ull;   // box leaves the grid: blocked
+        // the box is under 3 cells wide, so at most 4 x 4 columns
+        if (fi0 >= 0.0f && fj0 >= 0.0f && fi1 < (float)ox && fj1 < (float)oy && fi1 - fi0 < 4.0f &&
+            fj1 - fj0 < 4.0f) {
+            bits = 0;
+            for (int j = (int)fj0; j <= (int)fj1; ++j)
+                for (int i = (int)fi0; i <= (int)fi1; ++i)
+                    bits |= *reinterpret_cast<const uint64_t *>(occ + ((size_t)j * ox + i) * kPatchZ);
+        }
+        uint32_t w[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = ((bits >> (8 * k)) & 0xFF) ? 0x3F80u : 0u;
-        uint16_t *dst = row + kFeatPatchBase + c * kPatchZ;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) dst[k] = v[k];
+        for (int k = 0; k < 4; ++k)
+            w[k] = (((bits >> (16 * k)) & 0xFF) ? 0x3F80u : 0u) |
+                   ((((bits >> (16 * k + 8)) & 0xFF) ? 0x3F80u : 0u) << 16);
+        *reinterpret_cast<uint4 *>(row + kFeatPatchBase + c * kPatchZ) = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 

@@ -304,7 +304,7 @@ class Batch:
 
     # ---- collision surrogate
     def features(self, actions, x, stream=None):
-        """BF16 surrogate inputs (torch int16 [N][2080]) of the next move."""
+        """BF16 surrogate inputs (torch int16 [N][2112]) of the next move."""
         _check(load_library().gal_features(self._h, actions.data_ptr(), x.data_ptr(),
                                            _stream_handle(stream)))
 
@@ -367,7 +367,7 @@ class Batch:
 
 class Mlp:
     """The collision-surrogate MLP on the device (see include/gal.h)."""
-    IN = 2080
+    IN = 2112
 
     def __init__(self, max_rows: int, seed: int = 0):
         L = load_library()
@@ -418,7 +418,7 @@ class Mlp:
     @staticmethod
     def layout():
         """(offset, shape) of W1, b1, ..., W5, b5 in the flat parameter vector."""
-        dims = [2080, 256, 256, 256, 256, 1]
+        dims = [2112, 256, 256, 256, 256, 1]
         out, off = [], 0
         for l in range(5):
             n = dims[l + 1] * dims[l]

@@ -1,12 +1,20 @@
 """Training of the collision surrogate on motions labelled by the simulator.
 
 Every sample is one environment's next move: the features of (state, action)
-from ``gal_features`` and, as the label, whether the exact column-grid test
-of that move's candidate pose found a static contact (any bit of the step's
-static contact mask).  The simulator itself generates the motions (random
-actions, physics-only steps); the device MLP trains with its own MFMA
-forward/backward kernels and Adam.  Calibration picks the skip threshold so
-that no held-out positive would be skipped, with a safety factor.
+from ``gal_features`` and, as the label, whether the column-grid test of that
+move's candidate pose found a static contact (any bit of the step's static
+contact mask).  The simulator itself generates the motions (random actions,
+physics-only steps) and labels them; the device MLP trains with its own MFMA
+forward/backward kernels and Adam.
+
+Training labels carry a safety margin: they come from a labelling batch of
+the same scenes whose sphere classes are the real radii plus ``label_margin``
+(every sphere inflated), with the real largest radius appended as its last
+class so that its occupancy lattice, and hence every feature, is the one a
+plain batch computes.  The network thus learns a band around every obstacle
+as "contact", and true contacts sit inside that band rather than on its edge.
+Calibration uses true labels: the skip threshold is a safety fraction of the
+smallest held-out true-positive probability.
 """
 from __future__ import annotations
 
@@ -18,11 +26,11 @@ import numpy as np
 
 
 def generate(batch, num_samples: int, act_lim, seed: int = 0, device="cuda"):
-    """(X int16 [n][2080] BF16 bits, y float32 [n]) from random-action rollouts."""
+    """(X int16 [n][2112] BF16 bits, y float32 [n]) from random-action rollouts."""
     import torch
     N = batch.num_envs
     steps = (num_samples + N - 1) // N
-    X = torch.empty((steps * N, 2080), dtype=torch.int16, device=device)
+    X = torch.empty((steps * N, 2112), dtype=torch.int16, device=device)
     y = torch.empty(steps * N, dtype=torch.float32, device=device)
     out = {k: v for k, v in batch.alloc_outputs().items() if k not in ("depth", "rgb")}
     g = torch.Generator(device=device)
@@ -75,15 +83,61 @@ def probabilities(mlp, X, chunk: int) -> "object":
     return torch.sigmoid(z)
 
 
-def calibrate(mlp, X, y, chunk: int, safety: float = 0.5, margin: float = 0.1) -> Tuple[float, dict]:
-    """skip_below = min(tau - margin, safety * min positive probability), with
-    tau the smallest probability of a held-out positive (no held-out positive
-    may fall in the skip region)."""
+def calibrate(mlp, X, y, chunk: int, safety: float = 0.25, margin: float = 0.1) -> Tuple[float, dict]:
+    """Skip threshold from true-labelled held-out data.
+
+    tau is the smallest probability of a held-out positive; the exact check
+    is skipped for p <= skip_below = safety * tau, so no held-out positive is
+    skipped and the unseen tail keeps a factor 1/safety of room.  Predicted
+    contacts (p >= skip_below + margin) and the band between the two, the
+    margin, both run the exact check, so only skip_below routes work."""
+    import torch
     p = probabilities(mlp, X, chunk)
     pos = p[y > 0.5]
     neg = p[y <= 0.5]
     tau = float(pos.min()) if pos.numel() else 1.0
-    skip_below = max(0.0, min(tau - margin, safety * tau))
+    skip_below = safety * tau
     frac = float((neg <= skip_below).float().mean()) if neg.numel() else 0.0
-    return skip_below, {"tau": tau, "skip_below": skip_below, "positives": int(pos.numel()),
-                        "negatives": int(neg.numel()), "neg_skip_fraction": frac}
+    q = torch.tensor([0.0, 0.001, 0.01, 0.1], device=p.device)
+    pq = [round(float(v), 6) for v in torch.quantile(pos.double(), q.double())] if pos.numel() else []
+    return skip_below, {"tau": tau, "skip_below": skip_below, "decide_contact_above": skip_below + margin,
+                        "positives": int(pos.numel()), "negatives": int(neg.numel()),
+                        "neg_skip_fraction": frac, "pos_quantiles_0_0.1_1_10pct": pq}
+
+
+def labelling_consts(consts: dict, label_margin: float) -> dict:
+    """Batch constants whose sphere classes are inflated by ``label_margin``,
+    with the real largest radius as the last class (the lattice class)."""
+    rc = [float(r) for r in consts["radius_classes"]]
+    out = dict(consts)
+    out["radius_classes"] = tuple([r + label_margin for r in rc] + [rc[-1]])
+    return out
+
+
+def fit(robot, consts, cfg, train_envs, holdout_envs, samples: int = 1 << 24, epochs: int = 4,
+        holdout_samples: int = 1 << 20, pos_weight: float = 8.0, lr: float = 1e-3,
+        label_margin: float = 0.12, max_rows: int = 4096, seed: int = 5, log=None):
+    """The surrogate recipe: rollouts of ``train_envs`` labelled with the
+    safety margin, weighted logistic loss with Adam (cosine schedule), then
+    the conservative calibration on true-labelled rollouts of
+    ``holdout_envs`` (other scenes).  Returns (mlp, skip_below, info)."""
+    import torch
+    from . import gal, scenegen as sg
+    t0 = time.perf_counter()
+    tr = gal.Batch(robot, sg.make_scene_set(cfg, train_envs),
+                   labelling_consts(consts, label_margin) if label_margin > 0 else consts)
+    X, y = generate(tr, samples, cfg.act_lim, seed=seed + 2)
+    pos_rate = float(y.mean())
+    mlp = gal.Mlp(max_rows=max_rows, seed=seed)
+    hist = train(mlp, X, y, epochs=epochs, batch_size=4096, lr=lr, pos_weight=pos_weight, log=log)
+    del X, y, tr
+    torch.cuda.empty_cache()
+    ho = gal.Batch(robot, sg.make_scene_set(cfg, holdout_envs), consts)
+    Xh, yh = generate(ho, holdout_samples, cfg.act_lim, seed=seed + 3)
+    skip_below, info = calibrate(mlp, Xh, yh, chunk=4096)
+    del Xh, yh, ho
+    info.update(train_samples=samples, epochs=epochs, pos_weight=pos_weight, label_margin=label_margin,
+                train_loss=[round(v, 5) for v in hist["loss"]],
+                train_seconds=round(hist["seconds"], 2), positive_rate=round(pos_rate, 4),
+                setup_seconds=round(time.perf_counter() - t0, 1))
+    return mlp, skip_below, info

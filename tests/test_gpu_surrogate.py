@@ -64,9 +64,23 @@ def small_batch(n=16):
     return cfg, scenes, robot, sg.config_constants(cfg)
 
 
+def lattice_cell(offs, lay, nx, i, j, k) -> bool:
+    """Occupancy of grid column (i, j) in layer k: blocked when at one of
+    four heights inside the layer (none below 0.125 m) it has no free layer
+    of the largest sphere class."""
+    f32 = np.float32
+    c = j * nx + i
+    lo_hi = lay[offs[c]:offs[c + 1]]
+    for m in range(4):
+        z = max(f32(f32(k) * f32(0.25)) + f32(f32(0.0625) * f32(m + 1)), f32(0.125))
+        if not np.any((lo_hi[:, 0] <= z) & (z <= lo_hi[:, 1])):
+            return True
+    return False
+
+
 def test_features_match_cpu(torch_cuda):
     """Scalars and the occupancy patch, recomputed on the CPU from the
-    oracle's column grid (class 0), are bit-identical."""
+    oracle's column grid (class 0) and its sincos, are bit-identical."""
     torch = torch_cuda
     print("case: features", flush=True)
     from oracle import oracle as O
@@ -74,49 +88,72 @@ def test_features_match_cpu(torch_cuda):
     from paper_2306_07552_amd import gal
     cfg, scenes, robot, consts = small_batch(6)
     b = gal.Batch(robot, scenes, consts)
-    a = sg.actions(cfg, 3, num_envs=6)
+    # move the robots off their start poses first, so yaw and position vary
+    out = {k: v for k, v in b.alloc_outputs().items() if k != "depth"}
+    for k in range(5):
+        b.step(torch.from_numpy(sg.actions(cfg, k, num_envs=6) * 4).cuda(), out)
+    a = sg.actions(cfg, 7, num_envs=6)
     a[0, 2] = np.nan
-    x = torch.empty((6, 2080), dtype=torch.int16, device="cuda")
+    a[1, 1] = np.nan
+    a[2, 1] = 5.0
+    x = torch.full((6, 2112), 0x7F7F, dtype=torch.int16, device="cuda")   # every value written
     b.features(torch.from_numpy(a).cuda(), x)
     torch.cuda.synchronize()
     X = x.cpu().numpy().view(np.uint16)
     st, _ = b.get_state()
     ob = O.OracleBatch(robot, scenes, consts)
-    lim = np.float32(cfg.act_lim[2])
     f32 = np.float32
+    lim = [f32(v) for v in cfg.act_lim]
+    pi_f, two_pi_f = f32(np.pi), f32(2 * np.pi)
+    blocked_total = 0
     for e in range(6):
-        q = st[e, 3:10]
-        aj = np.nan_to_num(a[e, 2:9], nan=0.0).astype(np.float32)
-        aj = np.clip(aj, -lim, lim) / lim
-        a0 = np.clip(np.nan_to_num(a[e, 0:1]), -f32(cfg.act_lim[0]), f32(cfg.act_lim[0])) / f32(cfg.act_lim[0])
-        a1 = np.clip(np.nan_to_num(a[e, 1:2]), -f32(cfg.act_lim[1]), f32(cfg.act_lim[1])) / f32(cfg.act_lim[1])
-        x0, y0 = scenes.grid_origin[e]
-        nx, ny = scenes.grid_dims[e]
+        san = np.clip(np.nan_to_num(a[e], nan=0.0).astype(np.float32),
+                      -np.array([lim[0], lim[1]] + [lim[2]] * 7, np.float32),
+                      np.array([lim[0], lim[1]] + [lim[2]] * 7, np.float32))
+        q = np.clip((st[e, 3:10] + san[2:9]).astype(np.float32), robot.qlim[:, 0], robot.qlim[:, 1])
+        x0, y0 = (f32(v) for v in scenes.grid_origin[e])
+        nx, ny = (int(v) for v in scenes.grid_dims[e])
         cell = f32(sg.CELL)
-        sc = np.concatenate([q, aj, a0, a1,
+        sc = np.concatenate([q, san[2:9] / lim[2], [san[0] / lim[0], san[1] / lim[1]],
                              [(st[e, 0] - x0) / (f32(nx) * cell), (st[e, 1] - y0) / (f32(ny) * cell),
-                              st[e, 2] * f32(0.31830988618)]]).astype(np.float32)
-        want = np.zeros(2080, np.uint16)
-        want[:19] = (bf16_round_f32(sc).view(np.uint32) >> 16).astype(np.uint16)
-        oc = f32(2.0) * cell
-        ci = int(np.floor((st[e, 0] - x0) / oc))
-        cj = int(np.floor((st[e, 1] - y0) / oc))
-        ox, oy = (nx + 1) // 2, (ny + 1) // 2
-        env = ob._env_structs[e]
-        import ctypes as C
+                              st[e, 2] * f32(0.31830988618), f32(scenes.held[e] != 0)]]).astype(np.float32)
+        want = np.zeros(2112, np.uint16)
+        want[:20] = (bf16_round_f32(sc).view(np.uint32) >> 16).astype(np.uint16)
+        # frames of the candidate arm pose with the base at the origin (the oracle's FK)
+        fr = O.fk(robot, np.concatenate([np.zeros(3, np.float32), q]).astype(np.float32)).reshape(8, 3, 4)
+        arm = np.concatenate([fr[1:, :, 3].reshape(-1), fr[7, :, 2]]).astype(np.float32)
+        want[20:44] = (bf16_round_f32(arm).view(np.uint32) >> 16).astype(np.uint16)
+        yaw = f32(st[e, 2] + san[1])
+        if yaw > pi_f:
+            yaw = f32(yaw - two_pi_f)
+        elif yaw < -pi_f:
+            yaw = f32(yaw + two_pi_f)
+        sy, cy = (f32(v[0]) for v in O.sincos(np.array([yaw], np.float32)))
+        bx, by = f32(st[e, 0] + f32(san[0] * cy)), f32(st[e, 1] + f32(san[0] * sy))
+        offs, lay = ob.grid(e, len(consts["radius_classes"]) - 1)
+        cache = {}
+        hx = f32(f32(0.05) * f32(abs(cy) + abs(sy)))
         for pa in range(16):
             for pb in range(16):
-                i, j = ci + pa - 8, cj + pb - 8
+                px, py = f32(f32(pa) - f32(7.5)) * f32(0.1), f32(f32(pb) - f32(7.5)) * f32(0.1)
+                wx = f32(bx + f32(f32(cy * px) - f32(sy * py)))
+                wy = f32(by + f32(f32(sy * px) + f32(cy * py)))
+                i0, i1 = (np.floor(f32(f32(f32(wx + d) - x0) / cell)) for d in (-hx, hx))
+                j0, j1 = (np.floor(f32(f32(f32(wy + d) - y0) / cell)) for d in (-hx, hx))
+                inside = i0 >= 0 and j0 >= 0 and i1 < nx and j1 < ny
+                assert not inside or (i1 - i0 < 4 and j1 - j0 < 4)
                 for k in range(8):
-                    if 0 <= i < ox and 0 <= j < oy:
-                        cx = f32(x0 + (f32(i) + f32(0.5)) * oc)
-                        cy = f32(y0 + (f32(j) + f32(0.5)) * oc)
-                        cz = f32((f32(k) + f32(0.5)) * f32(0.25))
-                        blocked = O.lib().o_grid_query(C.byref(env), 0, float(cx), float(cy), float(cz))
-                    else:
-                        blocked = 1
-                    want[32 + (pa * 16 + pb) * 8 + k] = 0x3F80 if blocked else 0
+                    blocked = not inside
+                    if inside:
+                        for j in range(int(j0), int(j1) + 1):
+                            for i in range(int(i0), int(i1) + 1):
+                                if (i, j, k) not in cache:
+                                    cache[(i, j, k)] = lattice_cell(offs, lay, nx, i, j, k)
+                                blocked = blocked or cache[(i, j, k)]
+                    want[64 + (pa * 16 + pb) * 8 + k] = 0x3F80 if blocked else 0
         assert np.array_equal(X[e], want), f"env {e}: {np.flatnonzero(X[e] != want)[:10]}"
+        blocked_total += int((want[64:] != 0).sum())
+    assert 0 < blocked_total < 6 * 2048, "the patches are all free or all blocked"
 
 
 def oracle_net(w):
@@ -142,7 +179,7 @@ def test_forward_and_gradients_match_oracle(torch_cuda):
     cfg, scenes, robot, consts = small_batch(16)
     b = gal.Batch(robot, scenes, consts)
     rows = 96
-    X = torch.empty((rows, 2080), dtype=torch.int16, device="cuda")
+    X = torch.empty((rows, 2112), dtype=torch.int16, device="cuda")
     for k in range(rows // 16):
         b.features(torch.from_numpy(sg.actions(cfg, k, num_envs=16)).cuda(), X[16 * k:16 * (k + 1)])
         b.step(torch.from_numpy(sg.actions(cfg, k, num_envs=16)).cuda(),
@@ -194,21 +231,15 @@ def test_training_reduces_loss(torch_cuda):
 
 @pytest.fixture(scope="module")
 def trained(torch_cuda):
-    """MLP trained on rollouts of 512 training envs, calibrated on 256
-    held-out envs (different scenes)."""
-    from paper_2306_07552_amd import gal, surrogate
-    cfg = sg.scaled_config(1, 512)
+    """MLP trained on margin-labelled rollouts of 2048 training envs and
+    calibrated on true-labelled rollouts of 512 held-out envs (other
+    scenes)."""
+    from paper_2306_07552_amd import surrogate
+    cfg = sg.scaled_config(1, 2048)
     robot = sg.make_robot_for(cfg)
-    consts = sg.config_constants(cfg)
-    tr = gal.Batch(robot, sg.make_scene_set(cfg, range(0, 512)), consts)
-    X, y = surrogate.generate(tr, 1 << 20, cfg.act_lim, seed=7)
-    mlp = gal.Mlp(max_rows=4096, seed=5)
-    hist = surrogate.train(mlp, X, y, epochs=4, batch_size=4096, lr=1e-3, pos_weight=8.0)
-    del X, y
-    ho = gal.Batch(robot, sg.make_scene_set(cfg, range(512, 768)), consts)
-    Xh, yh = surrogate.generate(ho, 1 << 18, cfg.act_lim, seed=8)
-    skip_below, info = surrogate.calibrate(mlp, Xh, yh, chunk=4096)
-    print(f"trained: {hist}, calibration {info}", flush=True)
+    mlp, skip_below, info = surrogate.fit(robot, sg.config_constants(cfg), cfg, range(0, 2048),
+                                          range(2048, 2560))
+    print(f"trained: {info}", flush=True)
     return mlp, skip_below, info
 
 
