@@ -87,6 +87,10 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters against known bytes) and exit")
     ap.add_argument("--tuning", type=str, default=None,
                     help="JSON dict of raster launch settings (gal_tuning fields) for the plain path")
+    ap.add_argument("--batched-tuning", type=str, default=None,
+                    help="JSON dict of gal_tuning fields for the batched paths instead of running "
+                         "the autotuner (profiling runs use this so every raster dispatch of the "
+                         "batched paths has one configuration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
@@ -176,9 +180,13 @@ def main():
 
     # ---- batched step: autotuned configuration, persistent queue, graph replay
     act_buf.copy_(acts[0])
-    best, best_ms = b.autotune(act_buf, out, steps=3)
+    if args.batched_tuning:
+        b.set_tuning(**json.loads(args.batched_tuning))
+        log(f"batched tuning given: {b.get_tuning()}")
+    else:
+        best, best_ms = b.autotune(act_buf, out, steps=3)
+        log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
     b.set_tuning(graph=1)
-    log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
     batched_ms = timed_pass("batched")
     pre_k, raster_k = kernel_times()
     batched = path_record(batched_ms, b.get_tuning(), pre_k, raster_k)

@@ -153,8 +153,7 @@ int api_fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
-int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s);
-const float *mlp_logits(const gal_mlp *m);
+int mlp_infer_rows(gal_mlp *m, const uint16_t *x, int rows, const RouteArgs *route, hipStream_t s);
 int mlp_max_rows(const gal_mlp *m);
 }  // namespace gal
 
@@ -849,10 +848,10 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     if (b->sur) {
         // surrogate pre-filter: features -> MLP -> routing flags for the robot kernel
         HIP_TRY(gal::launch_features(b->rp, b->sb, occ_grid(b), actions_dev, b->d_feat, s));
-        int rc = gal::mlp_forward_rows(b->sur, b->d_feat, b->N, s);
+        const gal::RouteArgs ra{b->sb.counters, b->sur_thr_logit, b->sur_audit, b->d_flags,
+                                b->d_sur_stats, 0};
+        int rc = gal::mlp_infer_rows(b->sur, b->d_feat, b->N, &ra, s);
         if (rc) return rc;
-        HIP_TRY(gal::launch_route(gal::mlp_logits(b->sur), b->sb.counters, b->N, b->sur_thr_logit,
-                                  b->sur_audit, b->d_flags, b->d_sur_stats, s));
         sb.skip_flags = b->d_flags;
         sb.sur_stats = b->d_sur_stats;
     }

@@ -44,8 +44,54 @@ hipError_t launch_occ_build(const SimBuffers &sb, const OccGrid &og, int num_env
                             int max_cells, hipStream_t s);
 hipError_t launch_features(const RobotParams &rp, const SimBuffers &sb, const OccGrid &og,
                            const float *actions, uint16_t *x, hipStream_t s);
-hipError_t launch_route(const float *z, const int32_t *counters, int num_envs, float thr_logit,
-                        uint32_t audit_period, uint8_t *flags, unsigned long long *stats,
-                        hipStream_t s);
+// Routing of the step's static checks by the surrogate's logits: env e is
+// skipped when z_e <= thr (NaN never is), and a skipped env is audited (its
+// exact check still runs and a disagreement is counted) when a hash of
+// (env, episode, step) is 0 mod period.  Flag 0 = exact, 1 = skip, 2 = audit.
+struct RouteArgs {
+    const int32_t *counters;    // [N][2] step in episode, episode
+    float thr;                  // logit threshold
+    uint32_t period;            // audit 1 in period skipped envs (0 = never)
+    uint8_t *flags;             // [N] out
+    unsigned long long *stats;  // [0] queries [1] skipped [2] audited (accumulated)
+    int base;                   // env index of the first row
+};
+
+__device__ __forceinline__ uint32_t route_hash(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint64_t x = ((uint64_t)a << 40) ^ ((uint64_t)b << 20) ^ (uint64_t)c;
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return (uint32_t)x;
+}
+
+// flag of env e (batch index) whose logit is z
+__device__ __forceinline__ int route_flag(const RouteArgs &ra, int e, float z)
+{
+    if (!(z <= ra.thr)) return 0;
+    const bool audit = ra.period > 0 &&
+                       route_hash((uint32_t)e, (uint32_t)ra.counters[2 * e + 1],
+                                  (uint32_t)ra.counters[2 * e]) % ra.period == 0;
+    return audit ? 2 : 1;
+}
+
+// Weights of inference: layer 1 (w0 BF16 [256][2112], b0), layers 2..4
+// (w[0..2] BF16 [256][256], b[0..2]) and the head (w[3] BF16 [256], b[3]).
+struct MlpTail {
+    const uint16_t *w0;
+    const float *b0;
+    const uint16_t *w[4];
+    const float *b[4];
+};
+// Logits of rows inputs x (BF16 [rows][2112]) into z [rows]; with route, also
+// the routing flags and counts of envs route->base .. route->base + rows - 1.
+// part: FP32 workspace of mlp_infer_workspace_floats() values.
+size_t mlp_infer_workspace_floats();
+hipError_t mlp_infer(const uint16_t *x, int rows, const MlpTail &t, float *part, float *z,
+                     const RouteArgs *route, hipStream_t s);
+
 
 }  // namespace gal

@@ -40,6 +40,7 @@ struct gal_mlp {
     uint16_t *h[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // h[1..4]
     uint16_t *dp[2] = {nullptr, nullptr};
     float *z = nullptr, *dz = nullptr, *loss = nullptr;
+    float *part = nullptr;   // split-K partial sums of inference
     int64_t t = 0;
     ~gal_mlp()
     {
@@ -89,6 +90,7 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out)
         (rc = m->alloc(&m->dp[0], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->dp[1], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->z, max_rows)) || (rc = m->alloc(&m->dz, max_rows)) ||
+        (rc = m->alloc(&m->part, gal::mlp_infer_workspace_floats())) ||
         (rc = m->alloc(&m->loss, 1))) {
         delete m;
         return rc;
@@ -141,7 +143,6 @@ int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count)
 
 namespace gal {
 
-const float *mlp_logits(const gal_mlp *m) { return m->z; }
 int mlp_max_rows(const gal_mlp *m) { return m->max_rows; }
 
 // forward pass of rows inputs (BF16 [rows][2112]) into m->h[1..4] and m->z
@@ -155,6 +156,21 @@ int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s)
         in = m->h[l + 1];
     }
     MLP_TRY(mlp_head_fwd(m->h[4], m->wb + m->off_w[4], m->w + m->off_b[4], rows, kMlpHidden, m->z, s));
+    return GAL_OK;
+}
+
+// inference: split-K first layer, then the fused layers 2..4, head and
+// (optional) routing; logits into m->z
+int mlp_infer_rows(gal_mlp *m, const uint16_t *x, int rows, const RouteArgs *route, hipStream_t s)
+{
+    MlpTail t;
+    t.w0 = m->wb + m->off_w[0];
+    t.b0 = m->w + m->off_b[0];
+    for (int l = 0; l < 4; ++l) {
+        t.w[l] = m->wb + m->off_w[l + 1];
+        t.b[l] = m->w + m->off_b[l + 1];
+    }
+    MLP_TRY(mlp_infer(x, rows, t, m->part, m->z, route, s));
     return GAL_OK;
 }
 
@@ -193,7 +209,7 @@ int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logi
 {
     if (!m || !x_dev || rows < 0 || rows > m->max_rows) return gal::api_fail(GAL_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    int rc = gal::mlp_forward_rows(m, x_dev, rows, s);
+    int rc = gal::mlp_infer_rows(m, x_dev, rows, nullptr, s);
     if (rc) return rc;
     if (logits_dev && rows > 0)
         MLP_TRY(hipMemcpyAsync(logits_dev, m->z, sizeof(float) * rows, hipMemcpyDeviceToDevice, s));

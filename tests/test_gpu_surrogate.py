@@ -195,6 +195,12 @@ def test_forward_and_gradients_match_oracle(torch_cuda):
     w = mlp.get_weights()
     z = torch.empty(rows, dtype=torch.float32, device="cuda")
     mlp.forward(X, z)
+    # a ragged batch (the last 16-row tile of the fused layers is partial)
+    # gives the same logits for the rows it has
+    z90 = torch.full((90,), np.nan, dtype=torch.float32, device="cuda")
+    mlp.forward(X, z90, rows=90)
+    torch.cuda.synchronize()
+    assert torch.equal(z90, z[:90])
     grads = torch.empty(mlp.num_params, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     mlp.gradients(X, yt, 4.0, grads, loss)
