@@ -194,11 +194,13 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *  small_max  larger ones up to this many pixels are rasterised together by
  *             the wave, pixels spread evenly over the lanes (0..65536); the
  *             rest one at a time by the whole wave, 8x8 tile by tile
- *  refresh    clusters a wave draws between refreshes of the occlusion
- *             bounds (1..1024)
+ *  refresh    occlusion rounds: how many times the z-buffer bounds are
+ *             refreshed and the clusters not drawn yet re-tested against
+ *             them (1..16); each round draws half of the survivors (at
+ *             least 64), the last one all of them
  *  occlusion  1 = skip clusters provably hidden behind conservative z-buffer
  *             bounds, 0 = frustum culling only
- *  prologue   clusters drawn before occlusion culling starts (>= 0)
+ *  prologue   clusters drawn before the first occlusion test (>= 0)
  *  persistent 1 = one persistent raster kernel whose workgroups drain the
  *             (env, region) work queue, longest items first; 0 = one
  *             workgroup per item

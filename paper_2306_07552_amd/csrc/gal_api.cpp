@@ -310,7 +310,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
             return fail(GAL_EINVAL, "region %d does not divide resolution %d", t->region, b->res_host[e]);
     if (t->small_max < 0 || t->small_max > 65536) return fail(GAL_EINVAL, "small_max out of range");
     if (t->lane_max < 0 || t->lane_max > 4096) return fail(GAL_EINVAL, "lane_max out of range");
-    if (t->refresh < 1 || t->refresh > 1024) return fail(GAL_EINVAL, "refresh must be in 1..1024");
+    if (t->refresh < 1 || t->refresh > 16) return fail(GAL_EINVAL, "refresh must be in 1..16");
     if (t->prologue < 0) return fail(GAL_EINVAL, "prologue must be >= 0");
     if (t->robot_lanes != 32 && t->robot_lanes != 64) return fail(GAL_EINVAL, "robot_lanes must be 32 or 64");
     const bool rebuild = t->region != b->rast.region;

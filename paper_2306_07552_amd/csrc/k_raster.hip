@@ -383,9 +383,9 @@ __device__ __forceinline__ bool aabb_visible(const RegionPlanes &P, float lx, fl
     return true;
 }
 
-// Occlusion bounds: maxima of the z-buffer over 8x8 tiles and 32x32 blocks.
-// Every stored value is an upper bound of the current maximum (the z-buffer
-// only decreases), refreshed with ds_min so concurrent refreshes stay valid.
+// Occlusion bounds: maxima of the z-buffer over 8x8 tiles and 32x32 blocks,
+// taken between drawing rounds; the z-buffer only decreases, so they stay
+// upper bounds of the current maxima while the next round draws.
 struct Occl {
     uint32_t *tilemax;   // [TW*TW]
     uint32_t *blockmax;  // [BW*BW]
@@ -445,16 +445,8 @@ __device__ __forceinline__ bool cluster_hidden(const Cam &cam, const Proj &pj, c
     return dlb > (float)m;
 }
 
-// Same test for one cluster, evaluated by the whole wave (wave-uniform result).
-__device__ __forceinline__ bool cluster_hidden_wave(const Cam &cam, const Proj &pj, const Occl &oc,
-                                                    int rx0, int ry0, int R, const float4 &w0,
-                                                    const float4 &w1)
-{
-    // every lane computes the same bound; the scalar unit handles the uniform values
-    return cluster_hidden(cam, pj, oc, rx0, ry0, R, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z);
-}
-
-// This wave's share of the bound refresh: tiles w, w+W, ..., then blocks.
+// Refresh of the occlusion bounds by the whole workgroup (no cluster is being
+// drawn): tiles w, w+W, ... per wave, then the blocks from the tiles.
 template <class Sink>
 __device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, int R,
                                                int wave, int nwaves, int lane)
@@ -465,15 +457,17 @@ __device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, i
         const int px = tx * 8 + lx, py = ty * 8 + ly;
         const int v = (px < R && py < R) ? (int)zb.depth_at(py * R + px) : 0;
         const int m = wave_max(v);
-        if (lane == 0) atomicMin(&oc.tilemax[t], (uint32_t)m);
+        if (lane == 0) oc.tilemax[t] = (uint32_t)m;
     }
+    __syncthreads();
     for (int b = wave; b < oc.BW * oc.BW; b += nwaves) {
         const int bx = b % oc.BW, by = b / oc.BW;
         const int tx = bx * 4 + (lane & 3), ty = by * 4 + ((lane >> 2) & 3);
         const int v = (lane < 16 && tx < oc.TW && ty < oc.TW) ? (int)oc.tilemax[ty * oc.TW + tx] : 0;
         const int m = wave_max(v);
-        if (lane == 0) atomicMin(&oc.blockmax[b], (uint32_t)m);
+        if (lane == 0) oc.blockmax[b] = (uint32_t)m;
     }
+    __syncthreads();
 }
 
 // Everything a wave needs to draw clusters of one (env, region) item.
@@ -765,57 +759,84 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                 atomicAdd(&stats[kStatFrustumVisible], (unsigned long long)vis_total);
             }
         }
-        if (threadIdx.x == 0) next = 0;
-        __syncthreads();
-        // ---- waves pull visible clusters
+        // ---- draw in rounds: without occlusion culling one round of every
+        // visible cluster; with it, the prologue first (the mesh order puts
+        // the large occluders early), then after each refresh of the bounds
+        // the remaining clusters are re-tested lane-parallel, the survivors
+        // compacted in order, and half of them (at least 64) drawn, until
+        // `refresh` refreshes have been spent and the rest is drawn
         int drawn = 0, hidden = 0;
-        int idx = 0;
-        if (lane == 0) idx = atomicAdd(&next, 1);
-        idx = __builtin_amdgcn_readfirstlane(idx);
-        ClusterData cd;
-        float4 cw0, cw1;
-        if (idx < vis_total) {
-            const uint64_t ci = wbase + vis[idx];
-            cw0 = m.clusters[ci * 3 + 0];
-            cw1 = m.clusters[ci * 3 + 1];
-            const float4 w2 = m.clusters[ci * 3 + 2];
-            fetch_cluster(m, __float_as_uint(cw0.w), __float_as_uint(cw1.w), __float_as_uint(w2.x),
-                          __float_as_uint(w2.y), lane, cd);
-        }
-        int since_refresh = 0;
-        while (idx < vis_total) {
-            int nidx = 0;
-            if (lane == 0) nidx = atomicAdd(&next, 1);
-            nidx = __builtin_amdgcn_readfirstlane(nidx);
-            ClusterData nd;
-            float4 nw0, nw1;
-            if (nidx < vis_total) {
-                const uint64_t ci = wbase + vis[nidx];
-                nw0 = m.clusters[ci * 3 + 0];
-                nw1 = m.clusters[ci * 3 + 1];
+        int pos = 0, V = vis_total, rounds = 0;
+        int end = rp.occlusion ? min(V, rp.prologue) : V;
+        for (;;) {
+            if (threadIdx.x == 0) next = pos;
+            __syncthreads();
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(&next, 1);
+            idx = __builtin_amdgcn_readfirstlane(idx);
+            ClusterData cd;
+            if (idx < end) {
+                const uint64_t ci = wbase + vis[idx];
+                const float4 w0 = m.clusters[ci * 3 + 0];
+                const float4 w1 = m.clusters[ci * 3 + 1];
                 const float4 w2 = m.clusters[ci * 3 + 2];
-                fetch_cluster(m, __float_as_uint(nw0.w), __float_as_uint(nw1.w),
-                              __float_as_uint(w2.x), __float_as_uint(w2.y), lane, nd);
+                fetch_cluster(m, __float_as_uint(w0.w), __float_as_uint(w1.w), __float_as_uint(w2.x),
+                              __float_as_uint(w2.y), lane, cd);
             }
-            const bool hide = rp.occlusion && idx >= rp.prologue &&
-                              cluster_hidden_wave(cam, c.pj, oc, c.rx0, c.ry0, R, cw0, cw1);
-            if (!hide) {
+            while (idx < end) {
+                int nidx = 0;
+                if (lane == 0) nidx = atomicAdd(&next, 1);
+                nidx = __builtin_amdgcn_readfirstlane(nidx);
+                ClusterData nd;
+                if (nidx < end) {
+                    const uint64_t ci = wbase + vis[nidx];
+                    const float4 w0 = m.clusters[ci * 3 + 0];
+                    const float4 w1 = m.clusters[ci * 3 + 1];
+                    const float4 w2 = m.clusters[ci * 3 + 2];
+                    fetch_cluster(m, __float_as_uint(w0.w), __float_as_uint(w1.w),
+                                  __float_as_uint(w2.x), __float_as_uint(w2.y), lane, nd);
+                }
                 draw_cluster(c, cd, lane, zb, stats);
                 ++drawn;
-                if (rp.occlusion && ++since_refresh >= rp.refresh) {
-                    refresh_bounds(zb, oc, R, wave, kWaves, lane);
-                    since_refresh = 0;
-                }
-            } else {
-                ++hidden;
+                idx = nidx;
+                cd = nd;
             }
-            idx = nidx;
-            cd = nd;
-            cw0 = nw0;
-            cw1 = nw1;
+            __syncthreads();
+            pos = end;
+            if (pos >= V) break;
+            refresh_bounds(zb, oc, R, wave, kWaves, lane);
+            // re-test vis[pos, V) against the fresh bounds, compacting in place
+            int kept = 0;
+            for (int base = pos; base < V; base += kBlock) {
+                const int k = base + (int)threadIdx.x;
+                bool keep = false;
+                uint16_t v = 0;
+                if (k < V) {
+                    v = vis[k];
+                    const uint64_t ci = wbase + v;
+                    const float4 w0 = m.clusters[ci * 3 + 0];
+                    const float4 w1 = m.clusters[ci * 3 + 1];
+                    keep = !cluster_hidden(cam, c.pj, oc, c.rx0, c.ry0, R, w0.x, w0.y, w0.z, w1.x, w1.y,
+                                           w1.z);
+                }
+                const uint64_t bm = __ballot(keep);
+                if (lane == 0) wave_cnt[wave] = __popcll(bm);
+                __syncthreads();
+                int before = pos + kept;
+                for (int w = 0; w < wave; ++w) before += wave_cnt[w];
+                int all = kept;
+                for (int w = 0; w < kWaves; ++w) all += wave_cnt[w];
+                if (keep) vis[before + __popcll(bm & ((1ull << lane) - 1ull))] = v;
+                __syncthreads();
+                kept = all;
+            }
+            hidden += (threadIdx.x == 0) ? (V - pos - kept) : 0;
+            V = pos + kept;
+            ++rounds;
+            end = rounds >= rp.refresh ? V : min(V, pos + max(64, (V - pos + 1) / 2));
         }
         if (stats) {
-            stat_add(stats, kStatOccluded, lane, (uint64_t)hidden);
+            if (threadIdx.x == 0 && hidden) atomicAdd(&stats[kStatOccluded], (unsigned long long)hidden);
             stat_add(stats, kStatDrawn, lane, (uint64_t)drawn);
         }
         __syncthreads();

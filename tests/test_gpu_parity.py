@@ -185,7 +185,7 @@ TUNINGS = [
          persistent=1, robot_lanes=32),
     dict(block=1024, region=32, lane_max=4096, small_max=4096, refresh=1, occlusion=1, prologue=0,
          persistent=1, robot_lanes=64),
-    dict(block=512, region=128, lane_max=8, small_max=64, refresh=64, occlusion=1, prologue=64,
+    dict(block=512, region=128, lane_max=8, small_max=64, refresh=2, occlusion=1, prologue=64,
          persistent=0, robot_lanes=32),
     dict(block=512, region=128, lane_max=0, small_max=65536, refresh=16, occlusion=1, prologue=8,
          persistent=1, robot_lanes=64),
