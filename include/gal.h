@@ -209,6 +209,9 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *  graph      1 = gal_step replays the whole step as a captured hipGraph
  *             (re-captured when the action/output pointers or the tuning
  *             change; not used while gal_profile is enabled)
+ * A new batch starts with block 512, region 128 (or the resolution, if
+ * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
+ * prologue 256, persistent 0, robot_lanes 64, graph 0.
  */
 typedef struct gal_tuning {
     int32_t block;

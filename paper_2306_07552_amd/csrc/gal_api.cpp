@@ -365,7 +365,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         for (int region : regions)
             for (int lane_max : {0, 4, 8})
                 for (int small_max : {64, 256})
-                    for (int occl : {0, 1})
+                    for (int occl : {0, 1})   // 1: one refresh after a 256-cluster prologue
                         for (int persist : {0, 1})
                             for (int rl : {32, 64}) {
                                 bool ok = true;
@@ -378,7 +378,8 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 t.lane_max = lane_max;
                                 t.small_max = small_max;
                                 t.occlusion = occl;
-                                t.refresh = 4;
+                                t.refresh = 1;
+                                t.prologue = 256;
                                 t.persistent = persist;
                                 t.robot_lanes = rl;
                                 t.graph = 0;
@@ -678,38 +679,42 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
             nv_tot += ec[e].verts.size() / 3;
             nt_tot += ec[e].tris.size();
         }
-        if (nv_tot >= (1ull << 32) || nt_tot >= (1ull << 32))
-            return cleanup(fail(GAL_EINVAL, "scene set too large for 32-bit cluster bases"));
+        // every cluster owns 64 vertex and 64 triangle slots, so the raster
+        // kernel addresses them from the cluster index alone and issues those
+        // loads together with the cluster record's (unused slots are zero)
+        const uint64_t slots = (uint64_t)cl_off[N] * gal::kClusterVerts;
+        if (slots >= (1ull << 32))
+            return cleanup(fail(GAL_EINVAL, "scene set too large for 32-bit cluster slots"));
         float4 *d_cl;
         float *d_cv;
         uint32_t *d_ct;
         uint64_t *d_cl_off, *d_tri_off;
-        if ((rc = b->mem.alloc(&d_cl, (size_t)cl_off[N] * 3)) || (rc = b->mem.alloc(&d_cv, nv_tot * 3)) ||
-            (rc = b->mem.alloc(&d_ct, nt_tot)) || (rc = b->mem.alloc(&d_cl_off, (size_t)N + 1)) ||
+        if ((rc = b->mem.alloc(&d_cl, (size_t)cl_off[N] * 3)) || (rc = b->mem.alloc(&d_cv, slots * 3)) ||
+            (rc = b->mem.alloc(&d_ct, slots)) || (rc = b->mem.alloc(&d_cl_off, (size_t)N + 1)) ||
             (rc = b->mem.alloc(&d_tri_off, (size_t)N + 1)))
             return cleanup(rc);
-        // rebase cluster vertex / triangle bases to global indices while copying
-        std::vector<uint64_t> vb(N + 1, 0);
-        for (int e = 0; e < N; ++e) vb[e + 1] = vb[e] + ec[e].verts.size() / 3;
         std::vector<float> cl_all((size_t)cl_off[N] * 12);
-        std::vector<float> cv_all(nv_tot * 3);
-        std::vector<uint32_t> ct_all(nt_tot);
+        std::vector<float> cv_all(slots * 3, 0.0f);
+        std::vector<uint32_t> ct_all(slots, 0u);
         parallel_for(N, [&](int64_t e) {
             EnvClusters &c = ec[e];
             const size_t nc = c.cl.size() / 12;
             for (size_t i = 0; i < nc; ++i) {
                 float *w = &c.cl[i * 12];
-                uint32_t v, t;
+                uint32_t v, t, cnt;
                 memcpy(&v, &w[3], 4);
                 memcpy(&t, &w[7], 4);
-                v += (uint32_t)vb[e];
-                t += (uint32_t)tri_off[e];
-                memcpy(&w[3], &v, 4);
-                memcpy(&w[7], &t, 4);
+                memcpy(&cnt, &w[8], 4);
+                const uint64_t slot = (cl_off[e] + i) * (uint64_t)gal::kClusterVerts;
+                const uint32_t nv = cnt & 0xFF, nt = (cnt >> 8) & 0xFF;
+                std::copy(c.verts.begin() + (size_t)v * 3, c.verts.begin() + (size_t)(v + nv) * 3,
+                          cv_all.begin() + slot * 3);
+                std::copy(c.tris.begin() + t, c.tris.begin() + t + nt, ct_all.begin() + slot);
+                const uint32_t s32 = (uint32_t)slot;
+                memcpy(&w[3], &s32, 4);
+                memcpy(&w[7], &s32, 4);
             }
             std::copy(c.cl.begin(), c.cl.end(), cl_all.begin() + cl_off[e] * 12);
-            std::copy(c.verts.begin(), c.verts.end(), cv_all.begin() + vb[e] * 3);
-            std::copy(c.tris.begin(), c.tris.end(), ct_all.begin() + tri_off[e]);
             std::vector<float>().swap(c.cl);
             std::vector<float>().swap(c.verts);
             std::vector<uint32_t>().swap(c.tris);
@@ -748,9 +753,9 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         b->rast.lane_max = 4;
         b->rast.small_max = 256;
         b->rast.block = 512;
-        b->rast.refresh = 4;
-        b->rast.occlusion = 0;
-        b->rast.prologue = 8;
+        b->rast.refresh = 1;
+        b->rast.occlusion = 1;
+        b->rast.prologue = 256;
         b->rast.stats = nullptr;
         if ((rc = b->mem.alloc(&b->d_res, (size_t)N)) || (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
             return cleanup(rc);

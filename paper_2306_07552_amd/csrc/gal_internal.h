@@ -90,10 +90,10 @@ struct StepOutputs {
 //   w1 = (aabb hi x, y, z, bits of triangle base)
 //   w2 = (bits of nverts | ntris << 8, bits of first triangle id, 0, 0)
 struct RenderMesh {
-    const float4 *clusters;          // [C][3]
+    const float4 *clusters;          // [C][3] AABB lo + slot, hi + slot, counts nv | nt<<8, first tri
     const uint64_t *env_cluster_off; // [N+1]
-    const float *cverts;             // [Vc][3] cluster-local vertex positions
-    const uint32_t *ctris;           // [T] packed local indices i0 | i1<<8 | i2<<16
+    const float *cverts;             // [C][64][3] vertex positions of each cluster (unused slots 0)
+    const uint32_t *ctris;           // [C][64] packed local indices i0 | i1<<8 | i2<<16
     const uint8_t *tri_rgb;          // [T][3] in original order per env, or null
     const uint64_t *env_tri_off;     // [N+1] for colour lookup
 };

@@ -488,21 +488,20 @@ struct ClusterData {
     uint32_t first;   // env-local index of the cluster's first triangle
 };
 
-__device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint32_t vbase, uint32_t tbase,
-                                              uint32_t cnt, uint32_t first, int lane, ClusterData &d)
+// Loads of cluster ci: its counts and first triangle (record word 8..9) and
+// its 64 vertex and triangle slots, addressed from ci alone so that all of
+// them are in flight at once; the counts only mask lanes later.
+__device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint64_t ci, int lane, ClusterData &d)
 {
-    d.first = first;
-    d.nv = (int)(cnt & 0xFF);
-    d.nt = (int)((cnt >> 8) & 0xFF);
-    d.vx = d.vy = d.vz = 0.f;
-    d.packed = 0u;
-    if (lane < d.nv) {
-        const float *v = m.cverts + ((size_t)vbase + lane) * 3;
-        d.vx = v[0];
-        d.vy = v[1];
-        d.vz = v[2];
-    }
-    if (lane < d.nt) d.packed = m.ctris[(size_t)tbase + lane];
+    const uint2 cf = *reinterpret_cast<const uint2 *>(&m.clusters[ci * 3 + 2]);
+    const size_t slot = (size_t)ci * kClusterVerts + lane;
+    d.vx = m.cverts[slot * 3 + 0];
+    d.vy = m.cverts[slot * 3 + 1];
+    d.vz = m.cverts[slot * 3 + 2];
+    d.packed = m.ctris[slot];
+    d.nv = (int)(cf.x & 0xFF);
+    d.nt = (int)((cf.x >> 8) & 0xFF);
+    d.first = cf.y;
 }
 
 // Work counters (debug / roofline accounting), summed per wave.
@@ -775,27 +774,13 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
             if (lane == 0) idx = atomicAdd(&next, 1);
             idx = __builtin_amdgcn_readfirstlane(idx);
             ClusterData cd;
-            if (idx < end) {
-                const uint64_t ci = wbase + vis[idx];
-                const float4 w0 = m.clusters[ci * 3 + 0];
-                const float4 w1 = m.clusters[ci * 3 + 1];
-                const float4 w2 = m.clusters[ci * 3 + 2];
-                fetch_cluster(m, __float_as_uint(w0.w), __float_as_uint(w1.w), __float_as_uint(w2.x),
-                              __float_as_uint(w2.y), lane, cd);
-            }
+            if (idx < end) fetch_cluster(m, wbase + vis[idx], lane, cd);
             while (idx < end) {
                 int nidx = 0;
                 if (lane == 0) nidx = atomicAdd(&next, 1);
                 nidx = __builtin_amdgcn_readfirstlane(nidx);
                 ClusterData nd;
-                if (nidx < end) {
-                    const uint64_t ci = wbase + vis[nidx];
-                    const float4 w0 = m.clusters[ci * 3 + 0];
-                    const float4 w1 = m.clusters[ci * 3 + 1];
-                    const float4 w2 = m.clusters[ci * 3 + 2];
-                    fetch_cluster(m, __float_as_uint(w0.w), __float_as_uint(w1.w),
-                                  __float_as_uint(w2.x), __float_as_uint(w2.y), lane, nd);
-                }
+                if (nidx < end) fetch_cluster(m, wbase + vis[nidx], lane, nd);
                 draw_cluster(c, cd, lane, zb, stats);
                 ++drawn;
                 idx = nidx;
