@@ -315,3 +315,49 @@ def test_fragment_depth_within_vertex_range_for_slivers(oracle_lib, seed):
             slack = 1.0 + 8.0 * REL_BUDGET * hi
             assert got.min() >= lo - slack and got.max() <= hi + slack
     assert hits > 20
+
+
+def golden_constants():
+    import os
+    vals = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "task_constants.txt")):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split()
+            vals[k] = int(v)
+    return vals
+
+
+def test_task_constants_match_the_paper():
+    g = golden_constants()
+    cfg = sg.CONFIGS[1]
+    consts = sg.config_constants(cfg)
+    assert cfg.res0 == g["camera_resolution"]
+    assert consts["episode_len"] == g["episode_horizon"]
+    assert cfg.num_envs == g["envs_total"]
+    robot = sg.make_robot_for(cfg)
+    assert robot.dh.shape[0] == g["arm_dof"] and robot.q_home.shape[0] == g["arm_dof"]
+    assert len(consts["act_lim"]) == 3   # base forward, base yaw, every joint
+
+
+@pytest.mark.parametrize("half_angle_tan,W", [(0.95, 128), (0.5, 128), (1.2, 64)])
+def test_field_of_view_is_ninety_degrees(oracle_lib, half_angle_tan, W):
+    """A fronto-parallel strip spanning +-atan(t) horizontally covers exactly
+    the pixel columns whose centre ray lies within it, the mapping of a 90
+    degree FoV (the image edge at 45 degrees, Section 4.1); t > 1 covers
+    every column."""
+    assert golden_constants()["camera_fov_deg"] == 90
+    D = 2.0
+    cam = cam_look([0, 0, 0], 0.0)
+    yl = half_angle_tan * D
+    # facing the camera: U x V = z x y = -x; camera right = -y
+    v, t = sg.quad_mesh((D, -yl, -0.2 * D), (0, 0, 0.4 * D), (0, 2 * yl, 0))
+    _, _, cov, _ = render(oracle_lib, v, t, cam, W, want_cover=True)
+    hw = W / 2
+    u = (np.arange(W) + 0.5 - hw) / hw        # tangent of each column's centre ray
+    inside = np.abs(u) < half_angle_tan - 1e-3
+    outside = np.abs(u) > half_angle_tan + 1e-3
+    cols = cov[W // 2]                         # middle row
+    assert (cols[inside] == 1).all() and (cols[outside] == 0).all()
+    if half_angle_tan > 1:
+        assert (cols == 1).all()
