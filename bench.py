@@ -214,7 +214,8 @@ def main():
     value = N * args.steps / (headline_ms / 1e3)
     raster_head = sur["raster_ms"] if sur else raster_k
     mi = b.mesh_info()
-    raster_bytes = mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4 + 4 * b.depth_pixels
+    raster_bytes = (mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4
+                    + (7 if cfg.color else 4) * b.depth_pixels)   # depth u32 (+ rgb8)
     achieved = raster_bytes / (raster_head / 1e3) / 1e9
     traffic = None
     if args.config == 1 and not cfg.color:

@@ -292,3 +292,32 @@ def test_surrogate_gain_zero_mismatches(torch_cuda, trained):
           flush=True)
     assert st["mismatches"] == 0
     assert frac > 0.0
+
+
+def test_benchmarked_configuration_matches_oracle(torch_cuda, trained):
+    """The headline path at full size on scenes the surrogate never saw:
+    1024 envs at 128x128, the persistent queue, hipGraph replay, two envs per
+    robot wave, occlusion culling and the surrogate with a 1-in-16 audit.  A
+    sample of envs (incl. the last) is followed by the oracle step by step,
+    bit for bit; the audit counts no mismatch."""
+    torch = torch_cuda
+    print("case: benchmarked configuration, 1024 fresh envs, graph + persistent + surrogate",
+          flush=True)
+    mlp, skip_below, info = trained
+    cfg = sg.CONFIGS[1]
+    sample = sorted(set(np.random.default_rng(3).choice(1024, 12, replace=False).tolist()) | {0, 1023})
+    b, ob, scenes, robot = make_pair(cfg, range(4096, 4096 + 1024), sample)
+    b.set_tuning(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1,
+                 prologue=256, persistent=1, robot_lanes=32, graph=1)
+    b.attach_surrogate(mlp, skip_below, audit_period=16)
+    out = b.alloc_outputs()
+    act = torch.empty((1024, 9), dtype=torch.float32, device="cuda")   # one buffer: graph replay
+    for k in range(6):
+        a = sg.actions(cfg, 200 + k)
+        act.copy_(torch.from_numpy(a))
+        b.step(act, out)
+        torch.cuda.synchronize()
+        compare_step(b, ob, out, ob.step(a[sample]), label=f"step {k}")
+    st = b.surrogate_stats()
+    print(f"benchmarked configuration: {st}", flush=True)
+    assert st["queries"] == 6 * 1024 and st["mismatches"] == 0 and st["skipped"] > 0
