@@ -38,6 +38,12 @@ constexpr uint32_t kFar = 0xFFFFFFu;
 constexpr uint32_t kClipBits = 0x1Fu;
 constexpr int kVisCap = 4096;   // clusters per visibility window (u16 list in LDS)
 
+// Products of edge-function terms: snapped coordinates lie in the guard band
+// (|x| < 3 * 16 * 256 / 2 < 2^13 at the largest resolution, 256), so every
+// factor fits in 24 signed bits and v_mul_i32_i24 (full rate) returns the same
+// low 32 bits as a 32-bit multiply, which is the exact product.
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
 struct Cam {
     float px, py, pz, rx, ry, rz, dx, dy, dz, fx, fy, fz;
 };
@@ -153,7 +159,7 @@ __device__ __forceinline__ int setup_triangle(int x0, int y0, float d0, int x1, 
                                               int x2, int y2, float d2, int rx0, int ry0, int R,
                                               Setup &S)
 {
-    const int A2 = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+    const int A2 = mul24(x1 - x0, y2 - y0) - mul24(x2 - x0, y1 - y0);
     if (A2 >= 0) return 0;   // back face or degenerate
     // front face: swap v1 and v2 so the signed area is positive
     S.x0 = x0; S.y0 = y0;
@@ -228,9 +234,9 @@ __device__ __forceinline__ void raster_small(const Setup &S, uint32_t id, int rx
     const int b0 = S.bias & 1, b1 = (S.bias >> 1) & 1, b2 = (S.bias >> 2) & 1;
     const int Px0 = 16 * S.px0 + 8;
     const int Py0 = 16 * S.py0 + 8;
-    int r0 = ex0 * (Py0 - S.y1) - ey0 * (Px0 - S.x1);
-    int r1 = ex1 * (Py0 - S.y2) - ey1 * (Px0 - S.x2);
-    int r2 = ex2 * (Py0 - S.y0) - ey2 * (Px0 - S.x0);
+    int r0 = mul24(ex0, Py0 - S.y1) - mul24(ey0, Px0 - S.x1);
+    int r1 = mul24(ex1, Py0 - S.y2) - mul24(ey1, Px0 - S.x2);
+    int r2 = mul24(ex2, Py0 - S.y0) - mul24(ey2, Px0 - S.x0);
     for (int py = S.py0; py <= S.py1; ++py) {
         int e0 = r0, e1 = r1, e2 = r2;
         for (int px = S.px0; px <= S.px1; ++px) {
@@ -254,7 +260,14 @@ __device__ __forceinline__ float rlf(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// The whole wave rasterises lane L's triangle, one 8x8 tile at a time.
+// The whole wave rasterises lane L's triangle, one 8x8 tile at a time (lane =
+// pixel).  The bbox's tiles (at most 16 per row in a 128-pixel region) are
+// first tested lane-parallel, four tile rows at a time: a tile is skipped when
+// some edge function is below its threshold even at the tile's pixel centre
+// where that edge is largest (the functions are linear), so only tiles that
+// can hold a covered pixel are visited.  Within a tile the edge values are the
+// tile origin's plus a per-lane offset (the same integers as evaluating them
+// per pixel).
 template <class Sink>
 __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L, int lane, int rx0,
                                            int ry0, int R, const Sink &zb)
@@ -272,19 +285,40 @@ __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L,
     const int ex2 = x1 - x0, ey2 = y1 - y0;
     const int b0 = bias & 1, b1 = (bias >> 1) & 1, b2 = (bias >> 2) & 1;
     const int lx = lane & 7, ly = lane >> 3;
-    for (int ty = py0 >> 3; ty <= (py1 >> 3); ++ty) {
-        const int py = ty * 8 + ly;
-        const int Py = 16 * py + 8;
-        for (int tx = px0 >> 3; tx <= (px1 >> 3); ++tx) {
-            const int px = tx * 8 + lx;
-            if (px < px0 || px > px1 || py < py0 || py > py1) continue;
-            const int Px = 16 * px + 8;
-            const int e0 = ex0 * (Py - y1) - ey0 * (Px - x1);
-            const int e1 = ex1 * (Py - y2) - ey1 * (Px - x2);
-            const int e2 = ex2 * (Py - y0) - ey2 * (Px - x0);
-            if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
+    // offset of pixel (lx, ly) from its tile's origin pixel, per edge
+    const int o0 = mul24(16 * ex0, ly) - mul24(16 * ey0, lx);
+    const int o1 = mul24(16 * ex1, ly) - mul24(16 * ey1, lx);
+    const int o2 = mul24(16 * ex2, ly) - mul24(16 * ey2, lx);
+    // corner offsets (in pixel-centre units) where each edge is largest
+    const int c0x = ey0 < 0 ? 112 : 0, c0y = ex0 > 0 ? 112 : 0;
+    const int c1x = ey1 < 0 ? 112 : 0, c1y = ex1 > 0 ? 112 : 0;
+    const int c2x = ey2 < 0 ? 112 : 0, c2y = ex2 > 0 ? 112 : 0;
+    const int tx0 = px0 >> 3, tx1 = px1 >> 3, ty0 = py0 >> 3, ty1 = py1 >> 3;
+    for (int tyb = ty0; tyb <= ty1; tyb += 4) {
+        bool live = false;
+        {
+            const int tx = tx0 + (lane & 15), ty = tyb + (lane >> 4);
+            if (tx <= tx1 && ty <= ty1) {
+                const int Pxb = 128 * tx + 8, Pyb = 128 * ty + 8;
+                const int m0 = mul24(ex0, Pyb + c0y - y1) - mul24(ey0, Pxb + c0x - x1);
+                const int m1 = mul24(ex1, Pyb + c1y - y2) - mul24(ey1, Pxb + c1x - x2);
+                const int m2 = mul24(ex2, Pyb + c2y - y0) - mul24(ey2, Pxb + c2x - x0);
+                live = m0 >= b0 && m1 >= b1 && m2 >= b2;
+            }
+        }
+        uint64_t mask = __ballot(live);
+        while (mask) {
+            const int k = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int tx = tx0 + (k & 15), ty = tyb + (k >> 4);
+            const int Pxb = 128 * tx + 8, Pyb = 128 * ty + 8;
+            const int e0 = mul24(ex0, Pyb - y1) - mul24(ey0, Pxb - x1) + o0;
+            const int e1 = mul24(ex1, Pyb - y2) - mul24(ey1, Pxb - x2) + o1;
+            const int e2 = mul24(ex2, Pyb - y0) - mul24(ey2, Pxb - x0) + o2;
+            const int px = tx * 8 + lx, py = ty * 8 + ly;
+            if (px >= px0 && px <= px1 && py >= py0 && py <= py1 && e0 >= b0 && e1 >= b1 && e2 >= b2) {
                 const uint32_t D = frag_depth(e0, e1, e2, q0, q1, q2);
-                if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, id);
+                if (D < kFar) zb.put(mul24(py - ry0, R) + (px - rx0), D, id);
             }
         }
     }
@@ -338,19 +372,19 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
         if (g >= total) continue;
         const int tw = ((tmeta >> 18) & 0x1FF) + 1;
         const int oy = (int)(((float)local + 0.5f) * tinvw);
-        const int ox = local - oy * tw;
+        const int ox = local - mul24(oy, tw);
         const int px = (tmeta & 0x1FF) + ox, py = ((tmeta >> 9) & 0x1FF) + oy;
         const int x0 = (int)(short)(txy0 & 0xFFFF), y0 = txy0 >> 16;
         const int x1 = (int)(short)(txy1 & 0xFFFF), y1 = txy1 >> 16;
         const int x2 = (int)(short)(txy2 & 0xFFFF), y2 = txy2 >> 16;
         const int tb = tmeta >> 27;
         const int Px = 16 * px + 8, Py = 16 * py + 8;
-        const int e0 = (x2 - x1) * (Py - y1) - (y2 - y1) * (Px - x1);
-        const int e1 = (x0 - x2) * (Py - y2) - (y0 - y2) * (Px - x2);
-        const int e2 = (x1 - x0) * (Py - y0) - (y1 - y0) * (Px - x0);
+        const int e0 = mul24(x2 - x1, Py - y1) - mul24(y2 - y1, Px - x1);
+        const int e1 = mul24(x0 - x2, Py - y2) - mul24(y0 - y2, Px - x2);
+        const int e2 = mul24(x1 - x0, Py - y0) - mul24(y1 - y0, Px - x0);
         if (e0 >= (tb & 1) && e1 >= ((tb >> 1) & 1) && e2 >= ((tb >> 2) & 1)) {
             const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
-            if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, tid);
+            if (D < kFar) zb.put(mul24(py - ry0, R) + (px - rx0), D, tid);
         }
     }
 }
