@@ -4,8 +4,8 @@
  * One batch object steps every environment at once, the way the paper's
  * single simulator instance steps physics for a whole batch of environments
  * and a single renderer produces one stacked image per sensor in GPU memory
- * that the learner consumes in place (Galactic, Section 3.1 "Batch
- * Simulation").  The step itself follows Section 3.2 "Approximate Kinematic
+ * that the learner consumes in place (Galactic, Section 3.1 "Batching").
+ * The step itself follows Section 3.2 "Approximate Kinematic
  * Simulation" and Appendix G: action offsets applied directly to the robot
  * state, forward kinematics of the articulated links, sphere-proxy overlap
  * tests against a static-scene column grid (one grid per sphere-radius
@@ -122,10 +122,13 @@ typedef struct gal_config {
 
 /*
  * Caller-owned device outputs of one step.  Per-env images are packed one
- * after the other (env e starts at gal_depth_offsets()[e] pixels); depth is
- * the 24-bit value floor((1/near - 1/z) * (2^24-1) / (1/near - 1/far)) of
- * the nearest surface's camera-space distance z, 0xFFFFFF where nothing was
- * hit.  Any pointer except `depth` may be NULL to skip that output.
+ * after the other (env e starts at gal_depth_offsets()[e] pixels).  Depth is
+ * the 24-bit encoding (1/near - 1/z) * (2^24-1) / (1/near - 1/far) of the
+ * camera-space distance z: computed at each triangle's vertices, combined at
+ * a pixel centre with the triangle's integer barycentric weights (edge
+ * functions / twice the area) in binary32, clamped and truncated; the
+ * smallest value over the covering front faces wins, 0xFFFFFF where nothing
+ * was hit.  Any pointer except `depth` may be NULL to skip that output.
  */
 typedef struct gal_outputs {
     uint32_t *depth;            /* [sum res^2]                               */
@@ -273,10 +276,11 @@ int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
 /*
  * Per-kernel timing of gal_step with HIP events recorded on the step's own
  * stream.  While enabled, every gal_step records an event before, between
- * and after its kernels (robot step, raster); gal_profile_read waits for the
- * recorded events, returns the summed milliseconds of each kernel and the
- * number of timed steps, and clears the record.  Adds no synchronisation to
- * gal_step itself.
+ * and after its two stages (everything before the raster: the surrogate's
+ * kernels when one is attached and the robot step; then the raster);
+ * gal_profile_read waits for the recorded events, returns the summed
+ * milliseconds of each stage (robot_ms, raster_ms) and the number of timed
+ * steps, and clears the record.  Adds no synchronisation to gal_step itself.
  */
 int gal_profile_enable(gal_batch *b, int on);
 int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps);
@@ -316,8 +320,9 @@ int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
  * patch cell is 1 (blocked) when any grid column under the bounding box of
  * its rotated footprint has, at one of four heights inside the layer (none
  * below 0.125 m), no free layer of the batch's last radius class (the
- * largest in a plain batch), or when that box leaves the grid.  Network 2112 -> 256 -> 256 -> 256 -> 256 -> 1 with
- * ReLU, BF16 weights and activations, FP32 accumulation (matrix cores).
+ * largest in a plain batch), or when that box leaves the grid.  Network
+ * 2112 -> 256 -> 256 -> 256 -> 256 -> 1 with ReLU, BF16 weights and
+ * activations, FP32 accumulation (matrix cores).
  * Parameters are FP32 [W1 (256 x 2112), b1, W2, b2, W3, b3, W4, b4,
  * W5 (1 x 256), b5], each W one row per output unit.
  */
@@ -333,7 +338,10 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out);
  * set also clears the Adam state.  Synchronous. */
 int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count);
 int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
-/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112]). */
+/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112],
+ * 16-byte aligned rows).  The inference kernels (split-K first layer, fused
+ * layers 2..4 and head) accumulate the first layer in 11 partial sums, so
+ * logits can differ from the training forward pass in the last bits. */
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
 /* Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
  * w_i = pos_weight for labels 1, into grads_dev (device f32, parameter

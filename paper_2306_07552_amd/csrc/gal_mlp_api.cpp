@@ -208,6 +208,7 @@ extern "C" {
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream)
 {
     if (!m || !x_dev || rows < 0 || rows > m->max_rows) return gal::api_fail(GAL_EINVAL, "bad arguments");
+    if ((uintptr_t)x_dev % 16) return gal::api_fail(GAL_EINVAL, "x_dev must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     int rc = gal::mlp_infer_rows(m, x_dev, rows, nullptr, s);
     if (rc) return rc;
