@@ -299,61 +299,76 @@ __global__ __launch_bounds__(256) void k_l0_part(const uint16_t *__restrict__ x,
 constexpr int kTailRows = 16;
 constexpr int kActPad = 8;
 
-__global__ __launch_bounds__(256) void k_mlp_tail(const float *__restrict__ part, int rows, MlpTail t,
-                                                  float *__restrict__ z, RouteArgs ra, int route)
+__global__ __launch_bounds__(256, 1) void k_mlp_tail(const float *__restrict__ part, int rows, MlpTail t,
+                                                     float *__restrict__ z, RouteArgs ra, int route)
 {
     constexpr int D = kMlpHidden;
     __shared__ __attribute__((aligned(16))) uint16_t act[2][kTailRows][D + kActPad];
     __shared__ float zs[kTailRows];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * kTailRows;
-    // first hidden layer: the split-K partial sums in split order, + bias,
-    // ReLU, BF16; a thread takes 4 adjacent columns of 4 rows, all 4 x 11
-    // partial loads issued together
-    {
-        const int c = (threadIdx.x % (D / 4)) * 4, rq = threadIdx.x / (D / 4);   // rq = 0..3
-        float4 pv[4][kL0Splits];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r = rq + 4 * k;
-            const bool live = row0 + r < rows;
-#pragma unroll
-            for (int sp = 0; sp < kL0Splits; ++sp)
-                pv[k][sp] = live ? *reinterpret_cast<const float4 *>(part + ((size_t)sp * rows + row0 + r) * D + c)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        const float4 bb = *reinterpret_cast<const float4 *>(t.b0 + c);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r = rq + 4 * k;
-            float4 v = pv[k][0];
-#pragma unroll
-            for (int sp = 1; sp < kL0Splits; ++sp) {
-                v.x += pv[k][sp].x;
-                v.y += pv[k][sp].y;
-                v.z += pv[k][sp].z;
-                v.w += pv[k][sp].w;
-            }
-            const bool live = row0 + r < rows;
-            act[0][r][c + 0] = f2bf(live ? relu(v.x + bb.x) : 0.f);
-            act[0][r][c + 1] = f2bf(live ? relu(v.y + bb.y) : 0.f);
-            act[0][r][c + 2] = f2bf(live ? relu(v.z + bb.z) : 0.f);
-            act[0][r][c + 3] = f2bf(live ? relu(v.w + bb.w) : 0.f);
-        }
-    }
-    __syncthreads();
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    int cur = 0;
-    for (int l = 0; l < 3; ++l) {
-        const uint16_t *W = t.w[l];
-        bf16x8 bfr[D / 32][4];
+    // a layer's weight fragments for this wave: K = 256 in 8 steps x 4 tiles
+    auto load_w = [&](const uint16_t *W, bf16x8 (&f)[D / 32][4]) {
 #pragma unroll
         for (int st = 0; st < D / 32; ++st)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                bfr[st][j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(64 * wave + 16 * j + r16) * D +
-                                                               32 * st + kq);
-        __builtin_amdgcn_sched_barrier(0);   // every fragment load issues before the first MFMA
+                f[st][j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(64 * wave + 16 * j + r16) * D +
+                                                             32 * st + kq);
+    };
+    // every weight, bias and head load is issued one stage ahead of its use,
+    // so the memory latencies of the layers overlap instead of adding up
+    bf16x8 fa[D / 32][4], fb[D / 32][4];
+    load_w(t.w[0], fa);
+    float bias[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias[l][j] = t.b[l][64 * wave + 16 * j + r16];
+    uint16_t hw[D / 64];
+#pragma unroll
+    for (int k = 0; k < D / 64; ++k) hw[k] = t.w[3][lane + 64 * k];
+    // first hidden layer: the split-K partial sums in split order, + bias,
+    // ReLU, BF16; a thread takes 4 adjacent columns of 4 rows, two rows' 2 x 11
+    // partial loads in flight at a time
+    {
+        const int c = (threadIdx.x % (D / 4)) * 4, rq = threadIdx.x / (D / 4);   // rq = 0..3
+        const float4 bb = *reinterpret_cast<const float4 *>(t.b0 + c);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; k2 += 2) {
+            float4 pv[2][kL0Splits];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int r = rq + 4 * (k2 + k);
+                const bool live = row0 + r < rows;
+#pragma unroll
+                for (int sp = 0; sp < kL0Splits; ++sp)
+                    pv[k][sp] = live ? *reinterpret_cast<const float4 *>(part + ((size_t)sp * rows + row0 + r) * D + c)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int r = rq + 4 * (k2 + k);
+                float4 v = pv[k][0];
+#pragma unroll
+                for (int sp = 1; sp < kL0Splits; ++sp) {
+                    v.x += pv[k][sp].x;
+                    v.y += pv[k][sp].y;
+                    v.z += pv[k][sp].z;
+                    v.w += pv[k][sp].w;
+                }
+                const bool live = row0 + r < rows;
+                act[0][r][c + 0] = f2bf(live ? relu(v.x + bb.x) : 0.f);
+                act[0][r][c + 1] = f2bf(live ? relu(v.y + bb.y) : 0.f);
+                act[0][r][c + 2] = f2bf(live ? relu(v.z + bb.z) : 0.f);
+                act[0][r][c + 3] = f2bf(live ? relu(v.w + bb.w) : 0.f);
+            }
+        }
+    }
+    __syncthreads();
+    // one hidden layer from act[cur] into act[cur ^ 1] with weights f
+    auto layer = [&](const bf16x8 (&f)[D / 32][4], const float (&bl)[4], int cur) {
         floatx4 acc[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -361,29 +376,30 @@ __global__ __launch_bounds__(256) void k_mlp_tail(const float *__restrict__ part
         for (int st = 0; st < D / 32; ++st) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[cur][r16][32 * st + kq]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[st][j], acc[j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, f[st][j], acc[j], 0, 0, 0);
         }
         // lane holds column n = 64 w + 16 j + lane % 16 of rows 4 (lane / 16) + 0..3
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = 64 * wave + 16 * j + r16;
-            const float bn = t.b[l][n];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float v = acc[j][r] + bn;
-                v = v > 0.f ? v : 0.f;
-                act[cur ^ 1][(lane >> 4) * 4 + r][n] = f2bf(v);
-            }
+            for (int r = 0; r < 4; ++r) act[cur ^ 1][(lane >> 4) * 4 + r][n] = f2bf(relu(acc[j][r] + bl[j]));
         }
         __syncthreads();
-        cur ^= 1;
-    }
+    };
+    load_w(t.w[1], fb);
+    layer(fa, bias[0], 0);
+    load_w(t.w[2], fa);
+    layer(fb, bias[1], 1);
+    layer(fa, bias[2], 0);
+    const int cur = 1;
     // head: wave w takes rows 4w .. 4w + 3
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int r = 4 * wave + rr;
         float acc = 0.f;
-        for (int j = lane; j < D; j += 64) acc += bf2f(act[cur][r][j]) * bf2f(t.w[3][j]);
+#pragma unroll
+        for (int k = 0; k < D / 64; ++k) acc += bf2f(act[cur][r][lane + 64 * k]) * bf2f(hw[k]);
         for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
         if (lane == 0) zs[r] = acc + t.b[3][0];
     }
