@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed passes of --steps steps per path; the median is reported")
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -144,20 +146,27 @@ def main():
             b.step(act_buf, out)
 
     def timed_pass(label):
-        """Warmup, then exactly K timed steps bracketed by device syncs."""
+        """Warmup, then `repeats` passes of exactly K timed steps, each
+        bracketed by device syncs; the median pass is reported."""
         run(0, args.warmup)
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        w0 = time.perf_counter()
-        ev0.record(stream)
-        run(args.warmup, args.steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        gpu_ms = ev0.elapsed_time(ev1)
-        log(f"{label}: {args.steps} steps in {gpu_ms:.2f} ms device, {wall * 1e3:.2f} ms wall")
-        return gpu_ms
+        times = []
+        for rep in range(args.repeats):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            w0 = time.perf_counter()
+            ev0.record(stream)
+            run(args.warmup, args.steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            times.append(ev0.elapsed_time(ev1))
+            log(f"{label} pass {rep}: {args.steps} steps in {times[-1]:.2f} ms device, "
+                f"{wall * 1e3:.2f} ms wall")
+        pass_ms[label] = [round(t, 3) for t in times]
+        return sorted(times)[len(times) // 2]
+
+    pass_ms = {}
 
     def kernel_times():
         """Per-kernel durations over a profiled pass (HIP events on the step stream):
@@ -243,7 +252,9 @@ def main():
                       "objects": cfg.num_objects, "episode_len": cfg.episode_len,
                       "path": path},
            "roofline": roofline, "cpu_baseline": cpu,
-           "plain": plain, "batched": batched, "batched_surrogate": sur}
+           "plain": plain, "batched": batched, "batched_surrogate": sur,
+           "timing": {"repeats": args.repeats, "reported": "median pass",
+                      "pass_ms": pass_ms}}
     print(json.dumps(res), flush=True)
 
 
