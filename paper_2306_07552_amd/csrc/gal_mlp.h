@@ -18,9 +18,13 @@ constexpr int kFeatPatchBase = 64; // first patch feature
 enum { kEpiF32 = 0, kEpiBiasReluBf16 = 1, kEpiMaskBf16 = 2 };
 enum { kGemmFwd = 0, kGemmDx, kGemmDw, kGemmNtF32, kGemmNnF32, kGemmTnF32 };
 
+// C = op(A) op(B) on the matrix cores (variants above).  The weight-gradient
+// variant splits its reduction over the rows into the FP32 workspace ws
+// (ws_floats values; NULL = no split) and sums the splits in a fixed order.
+constexpr int kMaxDwSplits = 16;
 hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda,
                     int ldb, const float *bias, const uint16_t *mask, int ldm, float *Cf,
-                    uint16_t *Cb, int ldc, hipStream_t s);
+                    uint16_t *Cb, int ldc, hipStream_t s, float *ws = nullptr, size_t ws_floats = 0);
 hipError_t mlp_head_fwd(const uint16_t *h, const uint16_t *w, const float *b, int rows, int D,
                         float *z, hipStream_t s);
 hipError_t mlp_loss(const float *z, const float *y, int rows, float pos_w, float *dz, float *loss,

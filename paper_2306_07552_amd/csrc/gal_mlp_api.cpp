@@ -41,6 +41,8 @@ struct gal_mlp {
     uint16_t *dp[2] = {nullptr, nullptr};
     float *z = nullptr, *dz = nullptr, *loss = nullptr;
     float *part = nullptr;   // split-K partial sums of inference
+    float *dw_part = nullptr;   // split-K partial sums of the weight gradients
+    size_t dw_part_floats = 0;
     int64_t t = 0;
     ~gal_mlp()
     {
@@ -91,6 +93,7 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out)
         (rc = m->alloc(&m->dp[1], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->z, max_rows)) || (rc = m->alloc(&m->dz, max_rows)) ||
         (rc = m->alloc(&m->part, gal::mlp_infer_workspace_floats())) ||
+        (rc = m->alloc(&m->dw_part, (m->dw_part_floats = (size_t)gal::kMaxDwSplits * kDims[1] * kDims[0]))) ||
         (rc = m->alloc(&m->loss, 1))) {
         delete m;
         return rc;
@@ -189,7 +192,7 @@ int mlp_gradients_rows(gal_mlp *m, const uint16_t *x, const float *y, int rows, 
         const uint16_t *hin = l == 0 ? x : m->h[l];
         // dW_l [dout][din] = dpre^T h_{l-1}
         MLP_TRY(mlp_gemm(kGemmDw, m->dp[cur], hin, dout, din, rows, dout, din, nullptr, nullptr, 0,
-                         m->g + m->off_w[l], nullptr, din, s));
+                         m->g + m->off_w[l], nullptr, din, s, m->dw_part, m->dw_part_floats));
         MLP_TRY(mlp_colsum(m->dp[cur], rows, dout, m->g + m->off_b[l], s));
         if (l > 0) {
             // dpre_{l-1} = bf16((dpre W_l) * [h_{l-1} > 0])

@@ -48,6 +48,10 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, co
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    // split-K: workgroup z reduces K range [kbeg, kend) into its own output slab
+    const int kchunk = ((K + (int)gridDim.z - 1) / (int)gridDim.z + kBK - 1) / kBK * kBK;
+    const int kbeg = (int)blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    if (gridDim.z > 1 && Cf) Cf += (size_t)blockIdx.z * M * ldc;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     floatx4 acc[2][2];
 #pragma unroll
@@ -55,30 +59,30 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, co
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < K; k0 += kBK) {
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         // ---- A tile (64 x 32) -> As[m][k]
         if (!TA) {
             const int r = t >> 2, kk = (t & 3) * 8;
             const int m = m0 + r, k = k0 + kk;
             uint16_t v[8];
-            if (m < M && k + 8 <= K && ((((size_t)m * lda + k) & 7) == 0)) {
+            if (m < M && k + 8 <= kend && ((((size_t)m * lda + k) & 7) == 0)) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(A + (size_t)m * lda + k);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (m < M && k + j < K) ? A[(size_t)m * lda + k + j] : 0;
+                for (int j = 0; j < 8; ++j) v[j] = (m < M && k + j < kend) ? A[(size_t)m * lda + k + j] : 0;
             }
             memcpy(&As[r][kk], v, 16);
         } else {
             const int kk = t >> 3, mm = (t & 7) * 8;
             const int k = k0 + kk, m = m0 + mm;
             uint16_t v[8];
-            if (k < K && m + 8 <= M && ((((size_t)k * lda + m) & 7) == 0)) {
+            if (k < kend && m + 8 <= M && ((((size_t)k * lda + m) & 7) == 0)) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(A + (size_t)k * lda + m);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (k < K && m + j < M) ? A[(size_t)k * lda + m + j] : 0;
+                for (int j = 0; j < 8; ++j) v[j] = (k < kend && m + j < M) ? A[(size_t)k * lda + m + j] : 0;
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) As[mm + j][kk] = v[j];
@@ -88,24 +92,24 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, co
             const int r = t >> 2, kk = (t & 3) * 8;
             const int n = n0 + r, k = k0 + kk;
             uint16_t v[8];
-            if (n < N && k + 8 <= K && ((((size_t)n * ldb + k) & 7) == 0)) {
+            if (n < N && k + 8 <= kend && ((((size_t)n * ldb + k) & 7) == 0)) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(B + (size_t)n * ldb + k);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (n < N && k + j < K) ? B[(size_t)n * ldb + k + j] : 0;
+                for (int j = 0; j < 8; ++j) v[j] = (n < N && k + j < kend) ? B[(size_t)n * ldb + k + j] : 0;
             }
             memcpy(&Bs[r][kk], v, 16);
         } else {
             const int kk = t >> 3, nn = (t & 7) * 8;
             const int k = k0 + kk, n = n0 + nn;
             uint16_t v[8];
-            if (k < K && n + 8 <= N && ((((size_t)k * ldb + n) & 7) == 0)) {
+            if (k < kend && n + 8 <= N && ((((size_t)k * ldb + n) & 7) == 0)) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(B + (size_t)k * ldb + n);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (k < K && n + j < N) ? B[(size_t)k * ldb + n + j] : 0;
+                for (int j = 0; j < 8; ++j) v[j] = (k < kend && n + j < N) ? B[(size_t)k * ldb + n + j] : 0;
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) Bs[nn + j][kk] = v[j];
@@ -426,12 +430,33 @@ __global__ __launch_bounds__(256, 1) void k_mlp_tail(const float *__restrict__ p
     }
 }
 
+// out[i] = sum over splits of part[sp][i], in split order (deterministic)
+__global__ void k_sum_splits(const float *__restrict__ part, int splits, int64_t n, float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = part[i];
+    for (int sp = 1; sp < splits; ++sp) v += part[(size_t)sp * n + i];
+    out[i] = v;
+}
+
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda, int ldb,
                 const float *bias, const uint16_t *mask, int ldm, float *Cf, uint16_t *Cb, int ldc,
-                hipStream_t s)
+                hipStream_t s, int splits = 1, float *part = nullptr)
 {
-    dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
+    dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM, splits > 1 ? splits : 1);
+    if (splits > 1) {
+        // each split into its own [M][N] slab of part, then their ordered sum into Cf
+        hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, B, M, N, K, lda, ldb, bias,
+                           mask, ldm, part, Cb, N);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t n = (int64_t)M * N;
+        if (ldc != N) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, splits, n, Cf);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, B, M, N, K, lda, ldb, bias,
                        mask, ldm, Cf, Cb, ldc);
     return hipGetLastError();
@@ -441,7 +466,7 @@ hipError_t gemm(const uint16_t *A, const uint16_t *B, int M, int N, int K, int l
 
 hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda,
                     int ldb, const float *bias, const uint16_t *mask, int ldm, float *Cf,
-                    uint16_t *Cb, int ldc, hipStream_t s)
+                    uint16_t *Cb, int ldc, hipStream_t s, float *ws, size_t ws_floats)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     switch (variant) {
@@ -449,8 +474,20 @@ hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, in
         return gemm<false, true, kEpiBiasReluBf16>(A, B, M, N, K, lda, ldb, bias, mask, ldm, Cf, Cb, ldc, s);
     case kGemmDx:     // dpre_prev = mask(dY W)
         return gemm<false, false, kEpiMaskBf16>(A, B, M, N, K, lda, ldb, bias, mask, ldm, Cf, Cb, ldc, s);
-    case kGemmDw:     // dW = dY^T X
-        return gemm<true, false, kEpiF32>(A, B, M, N, K, lda, ldb, bias, mask, ldm, Cf, Cb, ldc, s);
+    case kGemmDw: {   // dW = dY^T X, split over the rows (K) into the workspace when given
+        const int tiles = ((N + kBN - 1) / kBN) * ((M + kBM - 1) / kBM);
+        int splits = 1;
+        if (ws && ldc == N) {
+            splits = (int)(512 / tiles);                          // aim at >= 512 workgroups
+            splits = splits > K / 256 ? K / 256 : splits;         // >= 256 rows per split
+            const int64_t cap = (int64_t)(ws_floats / ((size_t)M * N));
+            splits = splits > cap ? (int)cap : splits;
+            splits = splits > kMaxDwSplits ? kMaxDwSplits : splits;
+            if (splits < 1) splits = 1;
+        }
+        return gemm<true, false, kEpiF32>(A, B, M, N, K, lda, ldb, bias, mask, ldm, Cf, Cb, ldc, s,
+                                          splits, ws);
+    }
     case kGemmNtF32:  // plain C = A B^T in FP32 (tests)
         return gemm<false, true, kEpiF32>(A, B, M, N, K, lda, ldb, bias, mask, ldm, Cf, Cb, ldc, s);
     case kGemmNnF32:

@@ -167,18 +167,19 @@ def oracle_net(w):
     return OracleMLP(W, B)
 
 
-def test_forward_and_gradients_match_oracle(torch_cuda):
+@pytest.mark.parametrize("rows", [96, 1024])
+def test_forward_and_gradients_match_oracle(torch_cuda, rows):
     """Same BF16 inputs and weights: logits and every parameter gradient of
     the device MLP agree with the FP64 oracle (which rounds activations and
     pre-activation gradients to BF16 at the same points) to a relative L2 of
     1e-3; the differences come from FP32 vs FP64 accumulation flipping an
-    occasional BF16 rounding."""
+    occasional BF16 rounding.  At 1024 rows the weight gradients take the
+    split-K path (3 splits for the first layer, 4 for the others)."""
     torch = torch_cuda
-    print("case: mlp forward/backward vs oracle", flush=True)
+    print(f"case: mlp forward/backward vs oracle, {rows} rows", flush=True)
     from paper_2306_07552_amd import gal
     cfg, scenes, robot, consts = small_batch(16)
     b = gal.Batch(robot, scenes, consts)
-    rows = 96
     X = torch.empty((rows, 2112), dtype=torch.int16, device="cuda")
     for k in range(rows // 16):
         b.features(torch.from_numpy(sg.actions(cfg, k, num_envs=16)).cuda(), X[16 * k:16 * (k + 1)])
@@ -186,7 +187,7 @@ def test_forward_and_gradients_match_oracle(torch_cuda):
                {kk: v for kk, v in b.alloc_outputs().items() if kk != "depth"})
     rng = np.random.default_rng(0)
     y = (rng.uniform(size=rows) < 0.3).astype(np.float32)
-    mlp = gal.Mlp(max_rows=128, seed=11)
+    mlp = gal.Mlp(max_rows=max(128, rows), seed=11)
     # a trained-looking point: a few Adam steps first
     yt = torch.from_numpy(y).cuda()
     for _ in range(3):
