@@ -389,11 +389,27 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
     }
 }
 
+// Row-shifted copy of v (DPP, no LDS traffic); lanes whose source lies
+// outside their row of 16 get `fill`.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_shift(int v, int fill)
+{
+    return __builtin_amdgcn_update_dpp(fill, v, kCtrl, 0xF, 0xF, false);
+}
+
+// Maximum over the (fully active) wave, returned to every lane: prefix
+// maxima within each row of 16 (DPP row_shr 1, 2, 4, 8), then the four row
+// maxima read from lanes 15, 31, 47 and 63.
 __device__ __forceinline__ int wave_max(int v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
+    constexpr int kMin = -2147483647 - 1;
+    v = max(v, dpp_shift<0x111>(v, kMin));
+    v = max(v, dpp_shift<0x112>(v, kMin));
+    v = max(v, dpp_shift<0x114>(v, kMin));
+    v = max(v, dpp_shift<0x118>(v, kMin));
+    const int a = max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31));
+    const int b = max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63));
+    return max(a, b);
 }
 
 // Conservative frustum test of a cluster AABB (world) against the near plane
