@@ -203,7 +203,9 @@ def main():
     # ---- batched + surrogate
     sur = None
     headline_ms = batched_ms
-    path = "batched (autotuned, persistent queue, hipGraph)"
+    launch = (("persistent queue" if batched["tuning"]["persistent"] else "one workgroup per item")
+              + (f", {batched['tuning']['split']} envs split" if batched["tuning"].get("split") else ""))
+    path = f"batched (autotuned: {launch}, hipGraph)"
     if not args.no_surrogate:
         mlp, skip_below, info = train_surrogate(cfg, robot, consts)
         log(f"surrogate: {info}")
@@ -218,7 +220,7 @@ def main():
                    skipped_fraction=round(st["skipped"] / max(st["queries"], 1), 4),
                    mismatch_rate=st["mismatches"] / max(st["audited"], 1))
         headline_ms = sur_ms
-        path = "batched+surrogate (autotuned, persistent queue, hipGraph, 1/16 audit)"
+        path = f"batched+surrogate (autotuned: {launch}, hipGraph, 1/16 audit)"
 
     value = N * args.steps / (headline_ms / 1e3)
     raster_head = sur["raster_ms"] if sur else raster_k
@@ -233,7 +235,8 @@ def main():
                                    "k_raster_1024env_128px_traffic.json")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_raster", "algorithmic_bytes_per_launch": int(raster_bytes),
+                "kernel": ("k_raster_persistent" if b.get_tuning()["persistent"] else "k_raster"),
+                "algorithmic_bytes_per_launch": int(raster_bytes),
                 "avg_launch_ms": round(raster_head, 5)}
 
     cpu = None

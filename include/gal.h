@@ -212,9 +212,14 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *  graph      1 = gal_step replays the whole step as a captured hipGraph
  *             (re-captured when the action/output pointers or the tuning
  *             change; not used while gal_profile is enabled)
+ *  split      number of envs (0..N), taken from the cheap end of the
+ *             longest-first item order, whose regions are halved (four
+ *             items per region instead of one) so that the last items of a
+ *             launch are short; envs whose region side is not a multiple of
+ *             16 are not split
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
- * prologue 256, persistent 0, robot_lanes 64, graph 0.
+ * prologue 256, persistent 0, robot_lanes 64, graph 0, split 0.
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -227,6 +232,7 @@ typedef struct gal_tuning {
     int32_t persistent;
     int32_t robot_lanes;
     int32_t graph;
+    int32_t split;
 } gal_tuning;
 
 int gal_get_tuning(const gal_batch *b, gal_tuning *t);
@@ -237,7 +243,8 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
 /*
  * Autotuner: times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
- * queue, robot lanes per env) on this batch with the given actions and
+ * queue, robot lanes per env; then, on the fastest, `split` at 1/16, 1/8, 1/4
+ * and 1/2 of the workgroups resident at once) on this batch with the given actions and
  * outputs (`steps` timed steps each, HIP events), checks that every
  * candidate produces the same depth bits from the same state, keeps the
  * fastest (also written to *best, with its time per step in *best_ms) and

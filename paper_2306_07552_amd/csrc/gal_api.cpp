@@ -193,6 +193,7 @@ struct gal_batch {
     int32_t persist_grid = 0;
     int32_t robot_lanes = 64;
     int32_t use_graph = 0;
+    int32_t split = 0;   // cheapest envs rendered with halved regions
     uint64_t tune_gen = 1;                  // bumps on every tuning change
     // captured step graph and what it was captured for
     hipStream_t cap_stream = nullptr;
@@ -237,8 +238,17 @@ namespace {
 int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s,
                  hipEvent_t *ev);
 
+// Region side of env e's items: the tuned region (or the resolution, if
+// smaller), halved for the `split` cheapest envs when it stays a multiple of 8.
+int item_region(const gal_batch *b, int e, bool half)
+{
+    const int R = std::min(b->res_host[e], b->rast.region);
+    return (half && R % 16 == 0) ? R / 2 : R;
+}
+
 // (env, region) work items, longest envs first (so the tail of the launch is
-// short), regions of one env 8 items apart (same XCD, shared L2).
+// short), regions of one env 8 items apart (same XCD, shared L2).  Item word:
+// env (bits 0..19), region index (20..30), halved region (31).
 int build_work(gal_batch *b)
 {
     const int N = b->N;
@@ -250,19 +260,22 @@ int build_work(gal_batch *b)
         return ca > cc;
     });
     std::vector<uint32_t> work;
+    const int first_half = N - std::min(std::max(b->split, 0), N);
     for (int g = 0; g < N; g += 8) {
         int maxreg = 0;
         for (int k = g; k < std::min(N, g + 8); ++k) {
             const int r = b->res_host[order[k]];
-            const int R = std::min(r, b->rast.region);
+            const int R = item_region(b, order[k], k >= first_half);
             maxreg = std::max(maxreg, (r / R) * (r / R));
         }
         for (int reg = 0; reg < maxreg; ++reg)
             for (int k = g; k < std::min(N, g + 8); ++k) {
                 const int e = order[k];
                 const int r = b->res_host[e];
-                const int R = std::min(r, b->rast.region);
-                if (reg < (r / R) * (r / R)) work.push_back((uint32_t)e | ((uint32_t)reg << 20));
+                const int R = item_region(b, e, k >= first_half);
+                const uint32_t half = R < std::min(r, b->rast.region) ? 1u : 0u;
+                if (reg < (r / R) * (r / R))
+                    work.push_back((uint32_t)e | ((uint32_t)reg << 20) | (half << 31));
             }
     }
     if ((int32_t)work.size() > b->work_cap) {
@@ -295,6 +308,7 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->persistent = b->rast.persistent;
     t->robot_lanes = b->robot_lanes;
     t->graph = b->use_graph;
+    t->split = b->split;
     return GAL_OK;
 }
 
@@ -313,7 +327,8 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->refresh < 1 || t->refresh > 16) return fail(GAL_EINVAL, "refresh must be in 1..16");
     if (t->prologue < 0) return fail(GAL_EINVAL, "prologue must be >= 0");
     if (t->robot_lanes != 32 && t->robot_lanes != 64) return fail(GAL_EINVAL, "robot_lanes must be 32 or 64");
-    const bool rebuild = t->region != b->rast.region;
+    if (t->split < 0 || t->split > b->N) return fail(GAL_EINVAL, "split must be in 0..num_envs");
+    const bool rebuild = t->region != b->rast.region || t->split != b->split;
     b->rast.block = t->block;
     b->rast.region = t->region;
     b->rast.lane_max = t->lane_max;
@@ -324,6 +339,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->rast.persistent = t->persistent ? 1 : 0;
     b->robot_lanes = t->robot_lanes;
     b->use_graph = t->graph ? 1 : 0;
+    b->split = t->split;
     b->tune_gen += 1;
     b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
     if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");
@@ -383,6 +399,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 t.persistent = persist;
                                 t.robot_lanes = rl;
                                 t.graph = 0;
+                                t.split = 0;
                                 cands.push_back(t);
                             }
     hipEvent_t e0, e1;
@@ -392,43 +409,59 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     gal_tuning best_c = orig;
     unsigned long long ref_hash = 0;
     bool have_ref = false;
-    int result = GAL_OK;
-    for (const gal_tuning &t : cands) {
-        if ((result = gal_set_tuning(b, &t))) break;
-        if ((result = restore())) break;
-        if ((result = enqueue_step(b, actions_dev, out, s, nullptr))) break;
-        // output of one step from the saved state must not depend on the tuning
-        if (hipSuccess != gal::launch_hash_u32(out->depth, (uint64_t)b->depth_off_host[b->N], hash, s)) {
-            result = fail(GAL_EDEVICE, "hash launch failed");
-            break;
-        }
+    // One candidate: one step from the saved state (its depth hash must equal
+    // the first candidate's), then `steps` timed steps.
+    auto evaluate = [&](const gal_tuning &t) -> int {
+        int r;
+        if ((r = gal_set_tuning(b, &t))) return r;
+        if ((r = restore())) return r;
+        if ((r = enqueue_step(b, actions_dev, out, s, nullptr))) return r;
+        if (hipSuccess != gal::launch_hash_u32(out->depth, (uint64_t)b->depth_off_host[b->N], hash, s))
+            return fail(GAL_EDEVICE, "hash launch failed");
         unsigned long long h = 0;
         if (hipMemcpyAsync(&h, hash, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            result = fail(GAL_EDEVICE, "autotune: device error");
-            break;
-        }
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(GAL_EDEVICE, "autotune: device error");
         if (!have_ref) {
             ref_hash = h;
             have_ref = true;
         } else if (h != ref_hash) {
-            result = fail(GAL_ESTATE, "autotune: candidate (block %d region %d lane_max %d small_max %d "
-                          "occlusion %d persistent %d) changed the output bits",
-                          t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent);
-            break;
+            return fail(GAL_ESTATE, "autotune: candidate (block %d region %d lane_max %d small_max %d "
+                        "occlusion %d persistent %d split %d) changed the output bits",
+                        t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent, t.split);
         }
         (void)hipEventRecord(e0, s);
-        for (int k = 0; k < steps && result == GAL_OK; ++k) result = enqueue_step(b, actions_dev, out, s, nullptr);
+        for (int k = 0; k < steps; ++k)
+            if ((r = enqueue_step(b, actions_dev, out, s, nullptr))) return r;
         (void)hipEventRecord(e1, s);
-        if (result) break;
         float ms = 0.f;
-        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            result = fail(GAL_EDEVICE, "autotune: event timing failed");
-            break;
-        }
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(GAL_EDEVICE, "autotune: event timing failed");
         if (ms / steps < best_t) {
             best_t = ms / steps;
             best_c = t;
+        }
+        return GAL_OK;
+    };
+    int result = GAL_OK;
+    for (const gal_tuning &t : cands)
+        if ((result = evaluate(t))) break;
+    // Second stage: halve the regions of the cheapest envs, in fractions of
+    // the number of workgroups resident at once (the launch's last items), so
+    // that the tail of the launch is made of short items; tried on the winner
+    // and on the winner with the other launch mode (queue or one workgroup
+    // per item), whose tails differ.
+    if (result == GAL_OK && (result = gal_set_tuning(b, &best_c)) == GAL_OK) {
+        const int slots = b->persist_grid;
+        const gal_tuning w = best_c;
+        for (int flip : {0, 1}) {
+            for (int div : {16, 8, 4, 2}) {
+                gal_tuning t = w;
+                if (flip) t.persistent = 1 - w.persistent;
+                t.split = std::min(b->N, std::max(1, slots / div));
+                if ((result = evaluate(t))) break;
+            }
+            if (result) break;
         }
     }
     (void)hipEventDestroy(e0);

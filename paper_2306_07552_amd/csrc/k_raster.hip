@@ -200,6 +200,12 @@ __device__ __forceinline__ uint32_t frag_depth(int e0, int e1, int e2, float q0,
     return depth24(dv);
 }
 
+// Row pitch (words) of a region's z-buffer in LDS: R padded so that 8
+// consecutive rows start 8 banks apart (pitch/8 odd), so the 64 pixels of an
+// 8x8 tile fall in 64 different banks instead of the 8 that a pitch of
+// R = 128 or 64 would give.
+__host__ __device__ constexpr int zpitch(int R) { return 8 * (((R >> 3) + 1) | 1); }
+
 // Z-buffer sinks in LDS: depth only (u32, 24-bit depth) or depth and colour
 // (u64 key = depth << 32 | triangle id: the smallest depth wins, ties go to
 // the smallest triangle id).
@@ -224,7 +230,7 @@ struct ColorSink {
 };
 
 template <class Sink>
-__device__ __forceinline__ void raster_small(const Setup &S, uint32_t id, int rx0, int ry0, int R,
+__device__ __forceinline__ void raster_small(const Setup &S, uint32_t id, int rx0, int ry0, int P,
                                              const Sink &zb)
 {
     // edge k from vertex i to j: E = (xj-xi)(Py-yi) - (yj-yi)(Px-xi)
@@ -242,7 +248,7 @@ __device__ __forceinline__ void raster_small(const Setup &S, uint32_t id, int rx
         for (int px = S.px0; px <= S.px1; ++px) {
             if (e0 >= b0 && e1 >= b1 && e2 >= b2) {
                 const uint32_t D = frag_depth(e0, e1, e2, S.q0, S.q1, S.q2);
-                if (D < kFar) zb.put((py - ry0) * R + (px - rx0), D, id);
+                if (D < kFar) zb.put((py - ry0) * P + (px - rx0), D, id);
             }
             e0 -= 16 * ey0;
             e1 -= 16 * ey1;
@@ -270,7 +276,7 @@ __device__ __forceinline__ float rlf(float v, int l)
 // per pixel).
 template <class Sink>
 __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L, int lane, int rx0,
-                                           int ry0, int R, const Sink &zb)
+                                           int ry0, int P, const Sink &zb)
 {
     const uint32_t id = (uint32_t)rl((int)myid, L);
     const int x0 = rl(S.x0, L), y0 = rl(S.y0, L);
@@ -318,7 +324,7 @@ __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L,
             const int px = tx * 8 + lx, py = ty * 8 + ly;
             if (px >= px0 && px <= px1 && py >= py0 && py <= py1 && e0 >= b0 && e1 >= b1 && e2 >= b2) {
                 const uint32_t D = frag_depth(e0, e1, e2, q0, q1, q2);
-                if (D < kFar) zb.put(mul24(py - ry0, R) + (px - rx0), D, id);
+                if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, id);
             }
         }
     }
@@ -340,7 +346,7 @@ __device__ __forceinline__ int wave_incl_sum(int v, int lane)
 // prefix (ds_bpermute); the triangle's record is fetched from its lane.
 template <class Sink>
 __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, bool mine, int lane,
-                                                int rx0, int ry0, int R, const Sink &zb)
+                                                int rx0, int ry0, int P, const Sink &zb)
 {
     const int w = mine ? S.px1 - S.px0 + 1 : 0;
     const int h = mine ? S.py1 - S.py0 + 1 : 0;
@@ -384,7 +390,7 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
         const int e2 = mul24(x1 - x0, Py - y0) - mul24(y1 - y0, Px - x0);
         if (e0 >= (tb & 1) && e1 >= ((tb >> 1) & 1) && e2 >= ((tb >> 2) & 1)) {
             const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
-            if (D < kFar) zb.put(mul24(py - ry0, R) + (px - rx0), D, tid);
+            if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, tid);
         }
     }
 }
@@ -440,6 +446,7 @@ struct Occl {
     uint32_t *tilemax;   // [TW*TW]
     uint32_t *blockmax;  // [BW*BW]
     int TW, BW;
+    int P;               // z-buffer row pitch
 };
 
 // True when every fragment the cluster could produce in the region is
@@ -505,7 +512,7 @@ __device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, i
     for (int t = wave; t < oc.TW * oc.TW; t += nwaves) {
         const int tx = t % oc.TW, ty = t / oc.TW;
         const int px = tx * 8 + lx, py = ty * 8 + ly;
-        const int v = (px < R && py < R) ? (int)zb.depth_at(py * R + px) : 0;
+        const int v = (px < R && py < R) ? (int)zb.depth_at(py * oc.P + px) : 0;
         const int m = wave_max(v);
         if (lane == 0) oc.tilemax[t] = (uint32_t)m;
     }
@@ -526,6 +533,7 @@ struct Ctx {
     Proj pj;
     float kl, kr, kt, kb;
     int rx0, ry0, R;
+    int P;           // z-buffer row pitch in LDS
     int small_max;   // bbox pixels: <= lane_max per lane, <= small_max balanced, else tiles
     int lane_max;
 };
@@ -657,7 +665,7 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
         int npx = 0;
         if (ok) {
             npx = (S.px1 - S.px0 + 1) * (S.py1 - S.py0 + 1);
-            if (npx <= c.lane_max) raster_small(S, myid, c.rx0, c.ry0, c.R, zb);
+            if (npx <= c.lane_max) raster_small(S, myid, c.rx0, c.ry0, c.P, zb);
             else if (npx <= c.small_max) bal = true;
             else big = true;
         }
@@ -666,12 +674,12 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
             const int tot = wave_incl_sum(npx, lane);
             stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
         }
-        if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.R, zb);
+        if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.P, zb);
         uint64_t bmask = __ballot(big);
         while (bmask) {
             const int L = __ffsll((unsigned long long)bmask) - 1;
             bmask &= bmask - 1;
-            raster_big(S, myid, L, lane, c.rx0, c.ry0, c.R, zb);
+            raster_big(S, myid, L, lane, c.rx0, c.ry0, c.P, zb);
         }
     }
 }
@@ -708,13 +716,14 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     int &next = sh.next;
     constexpr int kWaves = kBlock / 64;
     const int env = (int)(item & 0xFFFFFu);
-    const int reg = (int)(item >> 20);
+    const int reg = (int)((item >> 20) & 0x7FFu);
     const int res = env_res[env];
     Ctx c;
-    c.R = min(res, rp.region);
+    c.R = min(res, rp.region) >> (item >> 31);
     const int nr = res / c.R;
     c.rx0 = (reg % nr) * c.R;
     c.ry0 = (reg / nr) * c.R;
+    c.P = zpitch(c.R);
     c.small_max = rp.small_max;
     c.lane_max = rp.lane_max;
     const int R = c.R;
@@ -725,8 +734,9 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     oc.blockmax = blockmax;
     oc.TW = (R + 7) >> 3;
     oc.BW = (R + 31) >> 5;
+    oc.P = c.P;
 
-    for (int i = threadIdx.x; i < R * R; i += kBlock) zb.clear(i);
+    for (int i = threadIdx.x; i < R * c.P; i += kBlock) zb.clear(i);
     for (int i = threadIdx.x; i < oc.TW * oc.TW; i += kBlock) tilemax[i] = kFar;
     for (int i = threadIdx.x; i < oc.BW * oc.BW; i += kBlock) blockmax[i] = kFar;
 
@@ -882,8 +892,9 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     for (int i = threadIdx.x; i < R * R; i += kBlock) {
         const int y = i / R, x = i - y * R;
         const size_t o = (size_t)(c.ry0 + y) * res + (c.rx0 + x);
+        const int zi = y * c.P + x;
         if constexpr (kColor) {
-            const unsigned long long key = zdyn[i];
+            const unsigned long long key = zdyn[zi];
             const uint32_t D = (uint32_t)(key >> 32);
             dst[o] = D;
             if (rgb) {
@@ -900,7 +911,7 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                 px[2] = bch;
             }
         } else {
-            dst[o] = zb.depth_at(i);
+            dst[o] = zb.depth_at(zi);
         }
     }
     __syncthreads();   // the LDS is reused by the next item
@@ -963,7 +974,10 @@ hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const fl
     return hipGetLastError();
 }
 
-size_t lds_bytes(int region, bool color) { return (size_t)region * region * (color ? 8 : 4); }
+size_t lds_bytes(int region, bool color)
+{
+    return (size_t)region * zpitch(region) * (color ? 8 : 4);
+}
 
 template <class K>
 hipError_t allow(K f, bool color)

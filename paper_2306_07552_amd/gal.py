@@ -55,7 +55,8 @@ class GalTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("region", C.c_int32), ("lane_max", C.c_int32),
                 ("small_max", C.c_int32),
                 ("refresh", C.c_int32), ("occlusion", C.c_int32), ("prologue", C.c_int32),
-                ("persistent", C.c_int32), ("robot_lanes", C.c_int32), ("graph", C.c_int32)]
+                ("persistent", C.c_int32), ("robot_lanes", C.c_int32), ("graph", C.c_int32),
+                ("split", C.c_int32)]
 
 
 class GalOutputs(C.Structure):

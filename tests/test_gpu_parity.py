@@ -189,6 +189,11 @@ TUNINGS = [
          persistent=0, robot_lanes=32),
     dict(block=512, region=128, lane_max=0, small_max=65536, refresh=16, occlusion=1, prologue=8,
          persistent=1, robot_lanes=64),
+    # halved regions for the cheapest envs (all of them, then half)
+    dict(block=256, region=64, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=256,
+         persistent=1, robot_lanes=64, split=12),
+    dict(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=256,
+         persistent=1, robot_lanes=32, split=6),
 ]
 
 
