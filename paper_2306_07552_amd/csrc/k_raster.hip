@@ -330,24 +330,75 @@ __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L,
     }
 }
 
+// Row-shifted copy of v (DPP, no LDS traffic); lanes whose source lies
+// outside their row of 16 get `fill`.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_shift(int v, int fill)
+{
+    return __builtin_amdgcn_update_dpp(fill, v, kCtrl, 0xF, 0xF, false);
+}
+
+// Maximum over the (fully active) wave, returned to every lane: prefix
+// maxima within each row of 16 (DPP row_shr 1, 2, 4, 8), then the four row
+// maxima read from lanes 15, 31, 47 and 63.
+__device__ __forceinline__ int wave_max(int v)
+{
+    constexpr int kMin = -2147483647 - 1;
+    v = max(v, dpp_shift<0x111>(v, kMin));
+    v = max(v, dpp_shift<0x112>(v, kMin));
+    v = max(v, dpp_shift<0x114>(v, kMin));
+    v = max(v, dpp_shift<0x118>(v, kMin));
+    const int a = max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31));
+    const int b = max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63));
+    return max(a, b);
+}
+
+// Inclusive prefix sum / maximum over the (fully active) wave: prefixes within
+// each row of 16 lanes (DPP row_shr 1, 2, 4, 8), then the totals of the
+// earlier rows (lanes 15, 31, 47) folded into rows 1..3.
 __device__ __forceinline__ int wave_incl_sum(int v, int lane)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(v, d, 64);
-        if (lane >= d) v += y;
-    }
-    return v;
+    v += dpp_shift<0x111>(v, 0);
+    v += dpp_shift<0x112>(v, 0);
+    v += dpp_shift<0x114>(v, 0);
+    v += dpp_shift<0x118>(v, 0);
+    const int r0 = __builtin_amdgcn_readlane(v, 15);
+    const int r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47);
+    const int row = lane >> 4;
+    return v + (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
+}
+
+__device__ __forceinline__ int wave_incl_max(int v, int lane)
+{
+    constexpr int kMin = -2147483647 - 1;
+    v = max(v, dpp_shift<0x111>(v, kMin));
+    v = max(v, dpp_shift<0x112>(v, kMin));
+    v = max(v, dpp_shift<0x114>(v, kMin));
+    v = max(v, dpp_shift<0x118>(v, kMin));
+    const int r0 = __builtin_amdgcn_readlane(v, 15);
+    const int r1 = max(r0, __builtin_amdgcn_readlane(v, 31));
+    const int r2 = max(r1, __builtin_amdgcn_readlane(v, 47));
+    const int row = lane >> 4;
+    return max(v, row == 0 ? kMin : row == 1 ? r0 : row == 2 ? r1 : r2);
 }
 
 // Load-balanced rasterisation of every lane's triangle at once: the pixels of
-// all bboxes are numbered by a wave prefix sum, lane l takes pixels
-// l, l + 64, ... and finds the owning triangle by binary search over the
-// prefix (ds_bpermute); the triangle's record is fetched from its lane.
+// all bboxes are numbered by a wave prefix sum and lane l takes pixels
+// l, l + 64, ...  For each window of 64 pixels, every triangle starting inside
+// it writes (first pixel, lane) at its start position in the wave's 64 LDS
+// words `own`, and a wave maximum-scan over the positions gives every pixel
+// its triangle (the last start at or before it; position 0 inherits the
+// previous window's last owner).  The triangle's record is then fetched from
+// its lane.
 template <class Sink>
 __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, bool mine, int lane,
-                                                int rx0, int ry0, int P, const Sink &zb)
+                                                int rx0, int ry0, int P, int *own_generic,
+                                                const Sink &zb)
 {
+    // LDS pointer, volatile: the writes of other lanes must be re-read
+    typedef __attribute__((address_space(3))) volatile int lds_int;
+    lds_int *own = (lds_int *)own_generic;
     const int w = mine ? S.px1 - S.px0 + 1 : 0;
     const int h = mine ? S.py1 - S.py0 + 1 : 0;
     const int cnt = w * h;
@@ -361,15 +412,19 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
     const int xy2 = (S.x2 & 0xFFFF) | (S.y2 << 16);
     const int meta = S.px0 | (S.py0 << 9) | ((w - 1) << 18) | (S.bias << 27);
     const float invw = 1.0f / (float)(w > 0 ? w : 1);
+    // (first pixel << 6 | lane): increasing along the lanes with pixels
+    const int start = (excl << 6) | lane;
+    int carry = 0;
     for (int base = 0; base < total; base += 64) {
         const int g = base + lane;
-        int t = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const int ex = __shfl(excl, t + step, 64);
-            if (ex <= g) t += step;
-        }
-        const int local = g - __shfl(excl, t, 64);
+        own[lane] = -1;
+        if (cnt > 0 && excl >= base && excl < base + 64) own[excl - base] = start;
+        int o = own[lane];
+        if (lane == 0 && o < 0) o = carry;
+        const int packed = wave_incl_max(o, lane);
+        carry = __builtin_amdgcn_readlane(packed, 63);
+        const int t = packed & 63;
+        const int local = g - (packed >> 6);
         const int txy0 = __shfl(xy0, t, 64), txy1 = __shfl(xy1, t, 64), txy2 = __shfl(xy2, t, 64);
         const int tmeta = __shfl(meta, t, 64);
         const float tq0 = __shfl(S.q0, t, 64), tq1 = __shfl(S.q1, t, 64), tq2 = __shfl(S.q2, t, 64);
@@ -395,28 +450,6 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
     }
 }
 
-// Row-shifted copy of v (DPP, no LDS traffic); lanes whose source lies
-// outside their row of 16 get `fill`.
-template <int kCtrl>
-__device__ __forceinline__ int dpp_shift(int v, int fill)
-{
-    return __builtin_amdgcn_update_dpp(fill, v, kCtrl, 0xF, 0xF, false);
-}
-
-// Maximum over the (fully active) wave, returned to every lane: prefix
-// maxima within each row of 16 (DPP row_shr 1, 2, 4, 8), then the four row
-// maxima read from lanes 15, 31, 47 and 63.
-__device__ __forceinline__ int wave_max(int v)
-{
-    constexpr int kMin = -2147483647 - 1;
-    v = max(v, dpp_shift<0x111>(v, kMin));
-    v = max(v, dpp_shift<0x112>(v, kMin));
-    v = max(v, dpp_shift<0x114>(v, kMin));
-    v = max(v, dpp_shift<0x118>(v, kMin));
-    const int a = max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31));
-    const int b = max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63));
-    return max(a, b);
-}
 
 // Conservative frustum test of a cluster AABB (world) against the near plane
 // and the region's four side planes; margins cover float rounding.
@@ -534,6 +567,7 @@ struct Ctx {
     float kl, kr, kt, kb;
     int rx0, ry0, R;
     int P;           // z-buffer row pitch in LDS
+    int *own;        // this wave's 64 words of LDS scratch (balanced raster)
     int small_max;   // bbox pixels: <= lane_max per lane, <= small_max balanced, else tiles
     int lane_max;
 };
@@ -674,7 +708,7 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
             const int tot = wave_incl_sum(npx, lane);
             stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
         }
-        if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.P, zb);
+        if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.P, c.own, zb);
         uint64_t bmask = __ballot(big);
         while (bmask) {
             const int L = __ffsll((unsigned long long)bmask) - 1;
@@ -691,6 +725,7 @@ struct ItemShared {
     uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
     uint16_t vis[kVisCap];
     int wave_cnt[kBlock / 64];
+    int own[kBlock];   // 64 words per wave, balanced raster
     int next;
     int queue_item;
 };
@@ -724,6 +759,7 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     c.rx0 = (reg % nr) * c.R;
     c.ry0 = (reg / nr) * c.R;
     c.P = zpitch(c.R);
+    c.own = sh.own + (threadIdx.x & ~63);
     c.small_max = rp.small_max;
     c.lane_max = rp.lane_max;
     const int R = c.R;
