@@ -24,30 +24,74 @@ __device__ __forceinline__ float sanitize(float a, float lim)
     return clampf(a, -lim, lim);
 }
 
+// Frame of `link` (0..7), selected element by element.  Each candidate value
+// passes through an empty asm so that the compiler cannot turn the selects
+// into a load from a selected address, which would keep all eight frames in
+// scratch memory instead of registers.
 __device__ __forceinline__ Frame pick(const Fk &fk, int link)
 {
-    Frame r = fk.f[0];
+    Frame r;
 #pragma unroll
-    for (int j = 1; j < 8; ++j)
-        if (link == j) r = fk.f[j];
+    for (int k = 0; k < 12; ++k) {
+        float v = fk.f[0].m[k];
+        asm("" : "+v"(v));
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+            float c = fk.f[j].m[k];
+            asm("" : "+v"(c));
+            v = link == j ? c : v;
+        }
+        r.m[k] = v;
+    }
     return r;
 }
 
-__device__ __forceinline__ bool grid_contact(const SimBuffers &sb, const GridMeta &gm,
-                                             uint64_t off_base, uint64_t layer_base,
-                                             float x, float y, float z)
+// Column-grid test of one sphere centre, split into stages so that the
+// dependent loads of several spheres are in flight together: the column's
+// layer range, then its first two layers, then (rarely) the rest.  Contact
+// when the centre is outside the grid or inside no free layer [lo, hi]
+// (touching a layer bound counts as free).
+struct GridProbe {
+    bool outside;
+    uint32_t l0, l1;
+    float z;
+    float2 a, b;   // layers l0 and l0 + 1 when present
+};
+
+__device__ __forceinline__ void grid_probe_column(const SimBuffers &sb, const GridMeta &gm,
+                                                  uint64_t off_base, float x, float y, float z,
+                                                  GridProbe &g)
 {
-    float fx = (x - gm.x0) * sb.inv_cell;
-    float fy = (y - gm.y0) * sb.inv_cell;
-    if (!(fx >= 0.0f && fx < (float)gm.nx)) return true;
-    if (!(fy >= 0.0f && fy < (float)gm.ny)) return true;
-    int i = (int)floorf(fx), j = (int)floorf(fy);
-    uint64_t col = (uint64_t)j * (uint64_t)gm.nx + (uint64_t)i;
+    g.z = z;
+    g.l0 = g.l1 = 0;
+    const float fx = (x - gm.x0) * sb.inv_cell;
+    const float fy = (y - gm.y0) * sb.inv_cell;
+    g.outside = !(fx >= 0.0f && fx < (float)gm.nx) || !(fy >= 0.0f && fy < (float)gm.ny);
+    if (g.outside) return;
+    const int i = (int)floorf(fx), j = (int)floorf(fy);
+    const uint64_t col = (uint64_t)j * (uint64_t)gm.nx + (uint64_t)i;
     const uint32_t *off = sb.grid_offsets + off_base + col;
-    uint32_t l0 = off[0], l1 = off[1];
+    g.l0 = off[0];
+    g.l1 = off[1];
+}
+
+__device__ __forceinline__ void grid_probe_layers(const SimBuffers &sb, uint64_t layer_base, GridProbe &g)
+{
     const float2 *lay = sb.grid_layers + layer_base;
-    for (uint32_t l = l0; l < l1; ++l) {
-        float2 L = lay[l];
+    if (g.l0 < g.l1) g.a = lay[g.l0];
+    if (g.l0 + 1 < g.l1) g.b = lay[g.l0 + 1];
+}
+
+__device__ __forceinline__ bool grid_probe_contact(const SimBuffers &sb, uint64_t layer_base,
+                                                   const GridProbe &g)
+{
+    if (g.outside) return true;
+    const float z = g.z;
+    if (g.l0 < g.l1 && g.a.x <= z && z <= g.a.y) return false;
+    if (g.l0 + 1 < g.l1 && g.b.x <= z && z <= g.b.y) return false;
+    const float2 *lay = sb.grid_layers + layer_base;
+    for (uint32_t l = g.l0 + 2; l < g.l1; ++l) {
+        const float2 L = lay[l];
         if (L.x <= z && z <= L.y) return false;
     }
     return true;
@@ -87,6 +131,37 @@ __device__ __forceinline__ void write_camera(const RobotParams &rp, const Frame 
     fvec(F0, 0.0f, -1.0f, 0.0f, cam[3], cam[4], cam[5]);
     fvec(F0, -sp, 0.0f, -cp, cam[6], cam[7], cam[8]);
     fvec(F0, cp, 0.0f, -sp, cam[9], cam[10], cam[11]);
+}
+
+// The spheres of two consecutive passes owned by one lane: records, whether
+// they take part (a held-object proxy only while an object is held), and the
+// bases of their class's grid in the offset and layer tables.
+constexpr int kSlots = 2;
+struct SphereSlots {
+    Sphere sp[kSlots];
+    bool live[kSlots];
+    uint64_t off_base[kSlots], layer_base[kSlots];
+};
+
+template <int kLanes>
+__device__ __forceinline__ void load_slots(const RobotParams &rp, const SimBuffers &sb, int env, bool held,
+                                           bool active, int sub, int base, SphereSlots &sl)
+{
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        const int s = base + k * kLanes + sub;
+        sl.live[k] = false;
+        sl.off_base[k] = sl.layer_base[k] = 0;
+        if (active && s < rp.num_spheres) {
+            sl.sp[k] = sb.spheres[s];
+            if (!(sl.sp[k].held_only && !held)) {
+                sl.live[k] = true;
+                const size_t gk = (size_t)env * rp.num_classes + sl.sp[k].cls;
+                sl.off_base[k] = sb.grid_off_base[gk];
+                sl.layer_base[k] = sb.grid_layer_base[gk];
+            }
+        }
+    }
 }
 
 // kLanes lanes per environment: 64 (one env per wave, spheres lane + 64k) or
@@ -139,63 +214,88 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         }
     }
 
-    // 2. forward kinematics of the candidate, sphere tests
+    // 2. forward kinematics of the candidate, sphere tests.  Each lane owns
+    // spheres sub + kLanes * p; two passes p are processed together, and the
+    // sphere records and grid bases of the first two are loaded before the
+    // kinematics (they do not depend on it).
+    const bool held = sb.held ? (sb.held[env] != 0) : false;
+    SphereSlots sl;
+    load_slots<kLanes>(rp, sb, env, held, active, sub, 0, sl);
     Fk fk;
     forward_kinematics(rp, cand, fk);
     const GridMeta gm = sb.grid_meta[env];
-    const bool held = sb.held ? (sb.held[env] != 0) : false;
     const float *objs = sb.objects + (size_t)env * rp.num_objects * 8;
     // surrogate routing: 1 = static check skipped (no contact assumed),
     // 2 = skipped but audited (exact check runs; a contact is a mismatch)
     const int route = sb.skip_flags ? sb.skip_flags[env] : 0;
     bool any = false, any_static = false;
-    for (int base = 0; base < rp.num_spheres; base += kLanes) {
-        const int s = base + sub;
-        bool hit_static = false, hit_object = false;
-        if (active && s < rp.num_spheres) {
-            const Sphere sp = sb.spheres[s];
-            if (!(sp.held_only && !held)) {
-                Frame F = pick(fk, sp.link);
-                float cx, cy, cz;
-                fpoint(F, sp.px, sp.py, sp.pz, cx, cy, cz);
-                const float r = rp.class_radius[sp.cls];
-                const size_t gk = (size_t)env * rp.num_classes + sp.cls;
-                if (route != 1)
-                    hit_static = grid_contact(sb, gm, sb.grid_off_base[gk], sb.grid_layer_base[gk],
-                                              cx, cy, cz);
+    for (int base = 0; base < rp.num_spheres; base += kSlots * kLanes) {
+        GridProbe g[kSlots];
+        float cx[kSlots], cy[kSlots], cz[kSlots];
+        const bool grid = route != 1;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            g[k].outside = false;
+            g[k].l0 = g[k].l1 = 0;
+            cx[k] = cy[k] = cz[k] = 0.0f;
+            if (sl.live[k]) {
+                const Frame F = pick(fk, sl.sp[k].link);
+                fpoint(F, sl.sp[k].px, sl.sp[k].py, sl.sp[k].pz, cx[k], cy[k], cz[k]);
+                if (grid) grid_probe_column(sb, gm, sl.off_base[k], cx[k], cy[k], cz[k], g[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if (sl.live[k] && grid) grid_probe_layers(sb, sl.layer_base[k], g[k]);
+        bool hit_static[kSlots], hit_object[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            hit_static[k] = false;
+            hit_object[k] = false;
+            if (sl.live[k]) {
+                if (grid) hit_static[k] = grid_probe_contact(sb, sl.layer_base[k], g[k]);
+                const float r = rp.class_radius[sl.sp[k].cls];
                 for (int o = 0; o < rp.num_objects; ++o) {
-                    if (obb_contact(objs + 8 * o, cx, cy, cz, r)) {
-                        hit_object = true;
+                    if (obb_contact(objs + 8 * o, cx[k], cy[k], cz[k], r)) {
+                        hit_object[k] = true;
                         break;
                     }
                 }
             }
         }
-        const uint64_t ms = __ballot(hit_static);
-        const uint64_t mo = __ballot(hit_object);
-        const int w = base >> 5;
-        if (kLanes == 64) {
-            any = any || (ms | mo) != 0;
-            any_static = any_static || ms != 0;
-            if (lane == 0) {
-                if (out.contact_static) {
-                    uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
-                    if (w < rp.contact_words) cs[w] = (uint32_t)ms;
-                    if (w + 1 < rp.contact_words) cs[w + 1] = (uint32_t)(ms >> 32);
+        // records of the next two passes
+        if (base + kSlots * kLanes < rp.num_spheres)
+            load_slots<kLanes>(rp, sb, env, held, active, sub, base + kSlots * kLanes, sl);
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int pb = base + k * kLanes;
+            if (pb >= rp.num_spheres) break;
+            const uint64_t ms = __ballot(hit_static[k]);
+            const uint64_t mo = __ballot(hit_object[k]);
+            const int w = pb >> 5;
+            if (kLanes == 64) {
+                any = any || (ms | mo) != 0;
+                any_static = any_static || ms != 0;
+                if (lane == 0) {
+                    if (out.contact_static) {
+                        uint32_t *cs = out.contact_static + (size_t)env * rp.contact_words;
+                        if (w < rp.contact_words) cs[w] = (uint32_t)ms;
+                        if (w + 1 < rp.contact_words) cs[w + 1] = (uint32_t)(ms >> 32);
+                    }
+                    if (out.contact_object) {
+                        uint32_t *co = out.contact_object + (size_t)env * rp.contact_words;
+                        if (w < rp.contact_words) co[w] = (uint32_t)mo;
+                        if (w + 1 < rp.contact_words) co[w + 1] = (uint32_t)(mo >> 32);
+                    }
                 }
-                if (out.contact_object) {
-                    uint32_t *co = out.contact_object + (size_t)env * rp.contact_words;
-                    if (w < rp.contact_words) co[w] = (uint32_t)mo;
-                    if (w + 1 < rp.contact_words) co[w + 1] = (uint32_t)(mo >> 32);
+            } else {
+                const uint32_t hs = (uint32_t)(ms >> (32 * half)), ho = (uint32_t)(mo >> (32 * half));
+                any = any || (hs | ho) != 0u;
+                any_static = any_static || hs != 0u;
+                if (sub == 0 && active && w < rp.contact_words) {
+                    if (out.contact_static) out.contact_static[(size_t)env * rp.contact_words + w] = hs;
+                    if (out.contact_object) out.contact_object[(size_t)env * rp.contact_words + w] = ho;
                 }
-            }
-        } else {
-            const uint32_t hs = (uint32_t)(ms >> (32 * half)), ho = (uint32_t)(mo >> (32 * half));
-            any = any || (hs | ho) != 0u;
-            any_static = any_static || hs != 0u;
-            if (sub == 0 && active && w < rp.contact_words) {
-                if (out.contact_static) out.contact_static[(size_t)env * rp.contact_words + w] = hs;
-                if (out.contact_object) out.contact_object[(size_t)env * rp.contact_words + w] = ho;
             }
         }
     }
