@@ -296,15 +296,21 @@ __global__ __launch_bounds__(256) void k_l0_part(const uint16_t *__restrict__ x,
 
 // Hidden layers 2..4 + head (+ routing) for 16 rows per workgroup, starting
 // from layer 1's split-K partials.  The rows' activations stay in LDS between
-// layers; each of the 4 waves owns 64 output columns (4 MFMA 16x16 tiles) and
-// issues all of its weight-fragment loads for the layer (K = 256: 8 steps x 4
-// tiles of 16 bytes per lane) before the first MFMA.  The head sums in
-// k_head_fwd's order.
+// layers; each of the 8 waves owns 32 output columns (2 MFMA 16x16 tiles) and
+// issues all of its weight-fragment loads for the layer (K = 256: 8 steps x 2
+// tiles of 16 bytes per lane) before the first MFMA, so that a CU has twice
+// the loads in flight of a 4-wave layout.  The head sums in k_head_fwd's
+// order.
 constexpr int kTailRows = 16;
+constexpr int kTailThreads = 512;
+constexpr int kTailWaves = kTailThreads / 64;
+constexpr int kTailCols = kMlpHidden / kTailWaves;   // output columns per wave
+constexpr int kTailTiles = kTailCols / 16;
 constexpr int kActPad = 8;
 
-__global__ __launch_bounds__(256, 1) void k_mlp_tail(const float *__restrict__ part, int rows, MlpTail t,
-                                                     float *__restrict__ z, RouteArgs ra, int route)
+__global__ __launch_bounds__(kTailThreads, 1) void k_mlp_tail(const float *__restrict__ part, int rows,
+                                                              MlpTail t, float *__restrict__ z,
+                                                              RouteArgs ra, int route)
 {
     constexpr int D = kMlpHidden;
     __shared__ __attribute__((aligned(16))) uint16_t act[2][kTailRows][D + kActPad];
@@ -312,80 +318,79 @@ __global__ __launch_bounds__(256, 1) void k_mlp_tail(const float *__restrict__ p
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * kTailRows;
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    // a layer's weight fragments for this wave: K = 256 in 8 steps x 4 tiles
-    auto load_w = [&](const uint16_t *W, bf16x8 (&f)[D / 32][4]) {
+    // a layer's weight fragments for this wave: K = 256 in 8 steps x kTailTiles tiles
+    auto load_w = [&](const uint16_t *W, bf16x8 (&f)[D / 32][kTailTiles]) {
 #pragma unroll
         for (int st = 0; st < D / 32; ++st)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                f[st][j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(64 * wave + 16 * j + r16) * D +
-                                                             32 * st + kq);
+            for (int j = 0; j < kTailTiles; ++j)
+                f[st][j] = *reinterpret_cast<const bf16x8 *>(
+                    W + (size_t)(kTailCols * wave + 16 * j + r16) * D + 32 * st + kq);
     };
     // every weight, bias and head load is issued one stage ahead of its use,
     // so the memory latencies of the layers overlap instead of adding up
-    bf16x8 fa[D / 32][4], fb[D / 32][4];
+    bf16x8 fa[D / 32][kTailTiles], fb[D / 32][kTailTiles];
     load_w(t.w[0], fa);
-    float bias[3][4];
+    float bias[3][kTailTiles];
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bias[l][j] = t.b[l][64 * wave + 16 * j + r16];
+        for (int j = 0; j < kTailTiles; ++j) bias[l][j] = t.b[l][kTailCols * wave + 16 * j + r16];
     uint16_t hw[D / 64];
 #pragma unroll
     for (int k = 0; k < D / 64; ++k) hw[k] = t.w[3][lane + 64 * k];
     // first hidden layer: the split-K partial sums in split order, + bias,
-    // ReLU, BF16; a thread takes 4 adjacent columns of 4 rows, two rows' 2 x 11
-    // partial loads in flight at a time
+    // ReLU, BF16; a thread takes 4 adjacent columns of 2 rows, all 2 x 11
+    // partial loads in flight at once
     {
-        const int c = (threadIdx.x % (D / 4)) * 4, rq = threadIdx.x / (D / 4);   // rq = 0..3
+        constexpr int kRowsPerPass = kTailThreads / (D / 4);   // 8
+        const int c = (threadIdx.x % (D / 4)) * 4, rq = threadIdx.x / (D / 4);
         const float4 bb = *reinterpret_cast<const float4 *>(t.b0 + c);
+        float4 pv[kTailRows / kRowsPerPass][kL0Splits];
 #pragma unroll
-        for (int k2 = 0; k2 < 4; k2 += 2) {
-            float4 pv[2][kL0Splits];
+        for (int k = 0; k < kTailRows / kRowsPerPass; ++k) {
+            const int r = rq + kRowsPerPass * k;
+            const bool live = row0 + r < rows;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int r = rq + 4 * (k2 + k);
-                const bool live = row0 + r < rows;
+            for (int sp = 0; sp < kL0Splits; ++sp)
+                pv[k][sp] = live ? *reinterpret_cast<const float4 *>(part + ((size_t)sp * rows + row0 + r) * D + c)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
-                for (int sp = 0; sp < kL0Splits; ++sp)
-                    pv[k][sp] = live ? *reinterpret_cast<const float4 *>(part + ((size_t)sp * rows + row0 + r) * D + c)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int k = 0; k < kTailRows / kRowsPerPass; ++k) {
+            const int r = rq + kRowsPerPass * k;
+            float4 v = pv[k][0];
+#pragma unroll
+            for (int sp = 1; sp < kL0Splits; ++sp) {
+                v.x += pv[k][sp].x;
+                v.y += pv[k][sp].y;
+                v.z += pv[k][sp].z;
+                v.w += pv[k][sp].w;
             }
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int r = rq + 4 * (k2 + k);
-                float4 v = pv[k][0];
-#pragma unroll
-                for (int sp = 1; sp < kL0Splits; ++sp) {
-                    v.x += pv[k][sp].x;
-                    v.y += pv[k][sp].y;
-                    v.z += pv[k][sp].z;
-                    v.w += pv[k][sp].w;
-                }
-                const bool live = row0 + r < rows;
-                act[0][r][c + 0] = f2bf(live ? relu(v.x + bb.x) : 0.f);
-                act[0][r][c + 1] = f2bf(live ? relu(v.y + bb.y) : 0.f);
-                act[0][r][c + 2] = f2bf(live ? relu(v.z + bb.z) : 0.f);
-                act[0][r][c + 3] = f2bf(live ? relu(v.w + bb.w) : 0.f);
-            }
+            const bool live = row0 + r < rows;
+            act[0][r][c + 0] = f2bf(live ? relu(v.x + bb.x) : 0.f);
+            act[0][r][c + 1] = f2bf(live ? relu(v.y + bb.y) : 0.f);
+            act[0][r][c + 2] = f2bf(live ? relu(v.z + bb.z) : 0.f);
+            act[0][r][c + 3] = f2bf(live ? relu(v.w + bb.w) : 0.f);
         }
     }
     __syncthreads();
     // one hidden layer from act[cur] into act[cur ^ 1] with weights f
-    auto layer = [&](const bf16x8 (&f)[D / 32][4], const float (&bl)[4], int cur) {
-        floatx4 acc[4];
+    auto layer = [&](const bf16x8 (&f)[D / 32][kTailTiles], const float (&bl)[kTailTiles], int cur) {
+        floatx4 acc[kTailTiles];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < kTailTiles; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int st = 0; st < D / 32; ++st) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[cur][r16][32 * st + kq]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, f[st][j], acc[j], 0, 0, 0);
+            for (int j = 0; j < kTailTiles; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, f[st][j], acc[j], 0, 0, 0);
         }
-        // lane holds column n = 64 w + 16 j + lane % 16 of rows 4 (lane / 16) + 0..3
+        // lane holds column n = kTailCols w + 16 j + lane % 16 of rows 4 (lane / 16) + 0..3
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = 64 * wave + 16 * j + r16;
+        for (int j = 0; j < kTailTiles; ++j) {
+            const int n = kTailCols * wave + 16 * j + r16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) act[cur ^ 1][(lane >> 4) * 4 + r][n] = f2bf(relu(acc[j][r] + bl[j]));
         }
@@ -397,10 +402,10 @@ __global__ __launch_bounds__(256, 1) void k_mlp_tail(const float *__restrict__ p
     layer(fb, bias[1], 1);
     layer(fa, bias[2], 0);
     const int cur = 1;
-    // head: wave w takes rows 4w .. 4w + 3
+    // head: wave w takes rows kTailRows / kTailWaves * w + 0..
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int r = 4 * wave + rr;
+    for (int rr = 0; rr < kTailRows / kTailWaves; ++rr) {
+        const int r = (kTailRows / kTailWaves) * wave + rr;
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < D / 64; ++k) acc += bf2f(act[cur][r][lane + 64 * k]) * bf2f(hw[k]);
@@ -511,7 +516,7 @@ hipError_t mlp_infer(const uint16_t *x, int rows, const MlpTail &t, float *part,
                            x + (size_t)r0 * kMlpIn, n, t.w0, part);
         RouteArgs ra = route ? *route : RouteArgs{nullptr, 0.f, 0u, nullptr, nullptr, 0};
         ra.base += r0;
-        hipLaunchKernelGGL(k_mlp_tail, dim3((n + kTailRows - 1) / kTailRows), dim3(256), 0, s, part, n, t,
+        hipLaunchKernelGGL(k_mlp_tail, dim3((n + kTailRows - 1) / kTailRows), dim3(kTailThreads), 0, s, part, n, t,
                            z + r0, ra, route ? 1 : 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
