@@ -27,9 +27,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_sources, record):
+# Tuning keys that change what the raster kernel reads and writes (the others
+# only change how the same pixels are rasterised, or other kernels).
+TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split")
+
+
+def measured_traffic(kernel_sources, record, tuning):
     """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE record,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source changed since the counters were taken or
+    the launch configuration differs from the recorded one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -37,7 +43,11 @@ def measured_traffic(kernel_sources, record):
     rec = json.load(open(path))
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
                                 for f in kernel_sources)).hexdigest()
-    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == h else None
+    if rec.get("source_sha256") != h:
+        return None
+    if any(rec["tuning"].get(k) != tuning.get(k) for k in TRAFFIC_KEYS):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
@@ -193,7 +203,7 @@ def main():
         b.set_tuning(**json.loads(args.batched_tuning))
         log(f"batched tuning given: {b.get_tuning()}")
     else:
-        best, best_ms = b.autotune(act_buf, out, steps=3)
+        best, best_ms = b.autotune(act_buf, out, steps=5)
         log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
     b.set_tuning(graph=1)
     batched_ms = timed_pass("batched")
@@ -232,7 +242,7 @@ def main():
     if args.config == 1 and not cfg.color:
         traffic = measured_traffic(["paper_2306_07552_amd/csrc/k_raster.hip",
                                     "paper_2306_07552_amd/csrc/gal_internal.h"],
-                                   "k_raster_1024env_128px_traffic.json")
+                                   "k_raster_1024env_128px_traffic.json", b.get_tuning())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": ("k_raster_persistent" if b.get_tuning()["persistent"] else "k_raster"),

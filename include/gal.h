@@ -243,8 +243,9 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
 /*
  * Autotuner: times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
- * queue, robot lanes per env; then, on the fastest, `split` at 1/16, 1/8, 1/4
- * and 1/2 of the workgroups resident at once) on this batch with the given actions and
+ * queue, robot lanes per env; then, on the fastest and on it with the other
+ * launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the workgroups resident
+ * at once, timed in two interleaved rounds) on this batch with the given actions and
  * outputs (`steps` timed steps each, HIP events), checks that every
  * candidate produces the same depth bits from the same state, keeps the
  * fastest (also written to *best, with its time per step in *best_ms) and

@@ -450,18 +450,33 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     // the number of workgroups resident at once (the launch's last items), so
     // that the tail of the launch is made of short items; tried on the winner
     // and on the winner with the other launch mode (queue or one workgroup
-    // per item), whose tails differ.
+    // per item), whose tails differ.  The winner is timed again beside them
+    // (the first stage's minimum over many candidates is biased low by
+    // noise), in two interleaved rounds, each candidate keeping its best.
     if (result == GAL_OK && (result = gal_set_tuning(b, &best_c)) == GAL_OK) {
         const int slots = b->persist_grid;
         const gal_tuning w = best_c;
-        for (int flip : {0, 1}) {
-            for (int div : {16, 8, 4, 2}) {
+        std::vector<gal_tuning> c2;
+        for (int flip : {0, 1})
+            for (int div : {0, 16, 8, 4, 2}) {
                 gal_tuning t = w;
                 if (flip) t.persistent = 1 - w.persistent;
-                t.split = std::min(b->N, std::max(1, slots / div));
-                if ((result = evaluate(t))) break;
+                t.split = div ? std::min(b->N, std::max(1, slots / div)) : 0;
+                c2.push_back(t);
             }
-            if (result) break;
+        std::vector<double> t2(c2.size(), 1e30);
+        for (int round = 0; round < 2 && result == GAL_OK; ++round)
+            for (size_t i = 0; i < c2.size(); ++i) {
+                best_t = 1e30;
+                if ((result = evaluate(c2[i]))) break;
+                t2[i] = std::min(t2[i], best_t);
+            }
+        if (result == GAL_OK) {
+            size_t k = 0;
+            for (size_t i = 1; i < c2.size(); ++i)
+                if (t2[i] < t2[k]) k = i;
+            best_c = c2[k];
+            best_t = t2[k];
         }
     }
     (void)hipEventDestroy(e0);
