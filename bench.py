@@ -33,9 +33,9 @@ TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "spl
 
 
 def measured_traffic(kernel_sources, record, tuning):
-    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE record,
-    or None when the kernel source changed since the counters were taken or
-    the launch configuration differs from the recorded one."""
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE records
+    (one per launch configuration), or None when the kernel source changed
+    since the counters were taken or no record has this configuration."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -45,9 +45,10 @@ def measured_traffic(kernel_sources, record, tuning):
                                 for f in kernel_sources)).hexdigest()
     if rec.get("source_sha256") != h:
         return None
-    if any(rec["tuning"].get(k) != tuning.get(k) for k in TRAFFIC_KEYS):
-        return None
-    return rec["traffic_bytes_per_launch"]
+    for r in rec["records"]:
+        if all(r["tuning"].get(k) == tuning.get(k) for k in TRAFFIC_KEYS):
+            return r["traffic_bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
@@ -103,6 +104,10 @@ def main():
                     help="JSON dict of gal_tuning fields for the batched paths instead of running "
                          "the autotuner (profiling runs use this so every raster dispatch of the "
                          "batched paths has one configuration)")
+    ap.add_argument("--sweep-tunings", type=str, default=None,
+                    help="JSON list of gal_tuning dicts: run --steps untimed steps with each (after "
+                         "--warmup) and exit; for counter runs (rocprofv3 --pmc) over several "
+                         "launch configurations in one process, raster dispatches in list order")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
@@ -154,6 +159,16 @@ def main():
         for k in range(k0, k0 + n):
             act_buf.copy_(acts[k], non_blocking=True)
             b.step(act_buf, out)
+
+    if args.sweep_tunings:
+        sweep = json.loads(args.sweep_tunings)
+        for tun in sweep:
+            b.set_tuning(**tun)
+            run(0, args.warmup + args.steps)
+            torch.cuda.synchronize()
+        print(json.dumps({"sweep": [b_t for b_t in sweep], "warmup": args.warmup,
+                          "steps": args.steps}), flush=True)
+        return
 
     def timed_pass(label):
         """Warmup, then `repeats` passes of exactly K timed steps, each
