@@ -243,14 +243,15 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
 /*
  * Autotuner: times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
- * queue, robot lanes per env; then, on the fastest and on it with the other
- * launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the workgroups resident
- * at once, timed in two interleaved rounds) on this batch with the given actions and
- * outputs (`steps` timed steps each, HIP events), checks that every
- * candidate produces the same depth bits from the same state, keeps the
- * fastest (also written to *best, with its time per step in *best_ms) and
- * restores the simulation state it started from.  The outputs' contents are
- * overwritten.  Synchronous.  GAL_ESTATE if a candidate's output differs.
+ * queue, robot lanes per env) on this batch with the given actions and
+ * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
+ * it with the other launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the
+ * workgroups resident at once (3 x `steps` each, two interleaved rounds).  It
+ * checks that every candidate produces the same depth bits from the same
+ * state, keeps the fastest (also written to *best, with its time per step in
+ * *best_ms) and restores the simulation state it started from.  The outputs'
+ * contents are overwritten.  Synchronous.  GAL_ESTATE if a candidate's output
+ * differs.
  */
 int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream,
                  int32_t steps, gal_tuning *best, double *best_ms);

@@ -411,7 +411,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     bool have_ref = false;
     // One candidate: one step from the saved state (its depth hash must equal
     // the first candidate's), then `steps` timed steps.
-    auto evaluate = [&](const gal_tuning &t) -> int {
+    auto evaluate = [&](const gal_tuning &t, int nsteps) -> int {
         int r;
         if ((r = gal_set_tuning(b, &t))) return r;
         if ((r = restore())) return r;
@@ -431,28 +431,29 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                         t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent, t.split);
         }
         (void)hipEventRecord(e0, s);
-        for (int k = 0; k < steps; ++k)
+        for (int k = 0; k < nsteps; ++k)
             if ((r = enqueue_step(b, actions_dev, out, s, nullptr))) return r;
         (void)hipEventRecord(e1, s);
         float ms = 0.f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             return fail(GAL_EDEVICE, "autotune: event timing failed");
-        if (ms / steps < best_t) {
-            best_t = ms / steps;
+        if (ms / nsteps < best_t) {
+            best_t = ms / nsteps;
             best_c = t;
         }
         return GAL_OK;
     };
     int result = GAL_OK;
     for (const gal_tuning &t : cands)
-        if ((result = evaluate(t))) break;
+        if ((result = evaluate(t, steps))) break;
     // Second stage: halve the regions of the cheapest envs, in fractions of
     // the number of workgroups resident at once (the launch's last items), so
     // that the tail of the launch is made of short items; tried on the winner
     // and on the winner with the other launch mode (queue or one workgroup
     // per item), whose tails differ.  The winner is timed again beside them
     // (the first stage's minimum over many candidates is biased low by
-    // noise), in two interleaved rounds, each candidate keeping its best.
+    // noise), with three times the steps, in two interleaved rounds, each
+    // candidate keeping its best.
     if (result == GAL_OK && (result = gal_set_tuning(b, &best_c)) == GAL_OK) {
         const int slots = b->persist_grid;
         const gal_tuning w = best_c;
@@ -468,7 +469,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         for (int round = 0; round < 2 && result == GAL_OK; ++round)
             for (size_t i = 0; i < c2.size(); ++i) {
                 best_t = 1e30;
-                if ((result = evaluate(c2[i]))) break;
+                if ((result = evaluate(c2[i], 3 * steps))) break;
                 t2[i] = std::min(t2[i], best_t);
             }
         if (result == GAL_OK) {
