@@ -13,8 +13,9 @@ the same scenes whose sphere classes are the real radii plus ``label_margin``
 class so that its occupancy lattice, and hence every feature, is the one a
 plain batch computes.  The network thus learns a band around every obstacle
 as "contact", and true contacts sit inside that band rather than on its edge.
-Calibration uses true labels: the skip threshold is a safety fraction of the
-smallest held-out true-positive probability.
+Calibration uses true labels: the skip threshold lies below the smallest
+held-out true-positive probability, by a safety factor and by the spread of
+the observed lower tail of the positives (``skip_threshold``).
 """
 from __future__ import annotations
 
@@ -83,20 +84,41 @@ def probabilities(mlp, X, chunk: int) -> "object":
     return torch.sigmoid(z)
 
 
-def calibrate(mlp, X, y, chunk: int, safety: float = 0.25, margin: float = 0.1) -> Tuple[float, dict]:
-    """Skip threshold from true-labelled held-out data.
+def skip_threshold(pos_p, safety: float = 0.25, tail_quantile: float = 0.001) -> Tuple[float, float]:
+    """Skip threshold from the probabilities of true held-out contacts.
 
-    tau is the smallest probability of a held-out positive; the exact check
-    is skipped for p <= skip_below = safety * tau, so no held-out positive is
-    skipped and the unseen tail keeps a factor 1/safety of room.  Predicted
-    contacts (p >= skip_below + margin) and the band between the two, the
-    margin, both run the exact check, so only skip_below routes work."""
+    tau is the smallest of them.  The threshold is the lower of safety * tau
+    and the probability whose logit lies below tau's by the spread of the
+    observed tail (the logit distance from tau up to the positives'
+    ``tail_quantile`` quantile): the tail seen between that quantile and the
+    minimum is assumed to continue at least as far again below it, which is
+    where unseen contacts of a larger deployment fall.  Returns
+    (skip_below, tau)."""
+    import torch
+    pos = torch.as_tensor(pos_p).double().flatten()
+    if pos.numel() == 0:
+        return safety, 1.0
+    tau = float(pos.min())
+    q = float(torch.quantile(pos, tail_quantile))
+    eps = 1e-30
+    logit = lambda v: math.log(max(v, eps)) - math.log(max(1.0 - v, eps))
+    z = logit(tau) - max(logit(q) - logit(tau), 0.0)
+    ext = 1.0 / (1.0 + math.exp(-z))
+    return min(safety * tau, ext), tau
+
+
+def calibrate(mlp, X, y, chunk: int, safety: float = 0.25, margin: float = 0.1) -> Tuple[float, dict]:
+    """Skip threshold from true-labelled held-out data (``skip_threshold``):
+    the exact check is skipped for p <= skip_below, so no held-out positive
+    is skipped and the unseen tail keeps room below the smallest one.
+    Predicted contacts (p >= skip_below + margin) and the band between the
+    two, the margin, both run the exact check, so only skip_below routes
+    work."""
     import torch
     p = probabilities(mlp, X, chunk)
     pos = p[y > 0.5]
     neg = p[y <= 0.5]
-    tau = float(pos.min()) if pos.numel() else 1.0
-    skip_below = safety * tau
+    skip_below, tau = skip_threshold(pos, safety)
     frac = float((neg <= skip_below).float().mean()) if neg.numel() else 0.0
     q = torch.tensor([0.0, 0.001, 0.01, 0.1], device=p.device)
     pq = [round(float(v), 6) for v in torch.quantile(pos.double(), q.double())] if pos.numel() else []
@@ -115,7 +137,7 @@ def labelling_consts(consts: dict, label_margin: float) -> dict:
 
 
 def fit(robot, consts, cfg, train_envs, holdout_envs, samples: int = 1 << 24, epochs: int = 4,
-        holdout_samples: int = 1 << 20, pos_weight: float = 8.0, lr: float = 1e-3,
+        holdout_samples: int = 1 << 22, pos_weight: float = 8.0, lr: float = 1e-3,
         label_margin: float = 0.12, max_rows: int = 4096, seed: int = 5, log=None):
     """The surrogate recipe: rollouts of ``train_envs`` labelled with the
     safety margin, weighted logistic loss with Adam (cosine schedule), then
