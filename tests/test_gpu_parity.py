@@ -219,7 +219,9 @@ def test_tuning_invariance(torch_cuda, tuning):
 @pytest.mark.parametrize("tuning", [
     dict(block=512, region=128, lane_max=4, small_max=256, refresh=4, occlusion=0, prologue=8),
     dict(block=256, region=64, lane_max=0, small_max=64, refresh=4, occlusion=1, prologue=8),
-], ids=["r128", "r64-occl"])
+    dict(block=512, region=128, lane_max=8, small_max=256, refresh=1, occlusion=1, prologue=256,
+         persistent=1, split=5),
+], ids=["r128", "r64-occl", "r128-persistent-split"])
 def test_color_parity(torch_cuda, tuning):
     """Flat colour: the winning triangle (smallest depth, then smallest id)
     and its seeded colour, mixed scene sizes and 64/128/256 resolutions."""
