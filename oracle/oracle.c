@@ -554,8 +554,13 @@ static void raster_tri(o_rctx *cx, const o_cv *in, uint32_t id)
 
 /* Render one environment.  depth[H*W] (cleared to 0xFFFFFF here); tri_win
    (optional) receives the winning triangle id (0xFFFFFFFF = none); cover
-   (optional) counts covering fragments per pixel (saturating at 255). */
-O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, const float *cam,
+   (optional) counts covering fragments per pixel (saturating at 255).
+   tri_plane (optional, [ntri][4]): the outward unit normal n and offset w of
+   each triangle's face; a triangle whose face the camera position c is not
+   strictly in front of ((n0 c0 + n1 c1) + n2 c2 - w <= 0) is culled as a back
+   face, before the winding test of its snapped vertices. */
+O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, const float *tri_plane,
+                       const float *cam,
                        int W, int H, float near_m, float far_m, uint32_t *depth,
                        uint32_t *tri_win, uint8_t *cover, o_rstats *stats)
 {
@@ -580,6 +585,11 @@ O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, co
     }
     const float *P = cam, *Rt = cam + 3, *Dn = cam + 6, *Fw = cam + 9;
     for (int64_t t = 0; t < ntri; ++t) {
+        if (tri_plane) {
+            const float *pl = tri_plane + 4 * t;
+            const float side = ((pl[0] * P[0] + pl[1] * P[1]) + pl[2] * P[2]) - pl[3];
+            if (!(side > 0.0f)) continue;
+        }
         o_cv v[3];
         for (int k = 0; k < 3; ++k) {
             const float *w = verts + 3 * (int64_t)tris[3 * t + k];

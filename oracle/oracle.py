@@ -97,7 +97,7 @@ def _declare(L):
     L.o_robot_step.argtypes = [C.POINTER(ORobot), C.POINTER(OParams), C.POINTER(OEnv), _fp, _i32p,
                                _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp]
     L.o_reset_env.argtypes = [C.POINTER(ORobot), C.POINTER(OEnv), _fp, _i32p, C.c_int]
-    L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
+    L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
                            _u32p, _u32p, _u8p, C.POINTER(ORStats)]
 
 
@@ -172,15 +172,21 @@ def grid_build(boxes: np.ndarray, x0: float, y0: float, nx: int, ny: int, cell: 
     return offs, lay[:n]
 
 
-def render(verts, tris, cam, W, H, near, far, want_id=False, want_cover=False):
+def render(verts, tris, cam, W, H, near, far, want_id=False, want_cover=False, planes=None):
+    """Depth (and winning triangle / coverage) of one env.  ``planes``: f32 [T][4]
+    face planes of the triangles (outward normal, offset) for back-face culling
+    by the camera's side of each face, or None (winding test only)."""
     verts = np.ascontiguousarray(verts, np.float32)
     tris = np.ascontiguousarray(tris, np.int32)
+    if planes is not None:
+        planes = np.ascontiguousarray(planes, np.float32)
+        assert planes.shape == (tris.shape[0], 4)
     cam = np.ascontiguousarray(cam, np.float32)
     depth = np.empty((H, W), np.uint32)
     win = np.empty((H, W), np.uint32) if want_id else None
     cov = np.empty((H, W), np.uint8) if want_cover else None
     st = ORStats()
-    lib().o_render(ptr(verts, _fp), ptr(tris, _i32p), tris.shape[0], ptr(cam, _fp), W, H,
+    lib().o_render(ptr(verts, _fp), ptr(tris, _i32p), tris.shape[0], ptr(planes, _fp), ptr(cam, _fp), W, H,
                    float(np.float32(near)), float(np.float32(far)), ptr(depth, _u32p),
                    ptr(win, _u32p), ptr(cov, _u8p), C.byref(st))
     stats = dict(tris_in=st.tris_in, tris_front=st.tris_front, cand_px=st.cand_px,
@@ -277,7 +283,7 @@ class OracleBatch:
         res = int(self.scenes.res[e])
         v, t, _rgb = self.scenes.env_mesh(e)
         depth, win, _cov, stats = render(v, t, out["cam"][i], res, res, self.near, self.far,
-                                         want_id=self.color)
+                                         want_id=self.color, planes=self.scenes.env_planes(e))
         out["depth"][i] = depth
         if self.color:
             rgb = np.zeros((res, res, 3), np.uint8)

@@ -86,11 +86,20 @@ class SceneSet:
     starts: np.ndarray        # f32 [N][P][3] x, y, yaw
     held: np.ndarray          # u8 [N]
     res: np.ndarray           # i32 [N] square depth resolution per env
+    tri_plane: Optional[np.ndarray] = None   # f32 [T][4] outward unit normal, offset of each
+                                             # triangle's face (n . p = w on the face)
 
     def env_mesh(self, e: int):
         v0, v1 = int(self.vert_offset[e]), int(self.vert_offset[e + 1])
         t0, t1 = int(self.tri_offset[e]), int(self.tri_offset[e + 1])
         return self.verts[v0:v1], self.tris[t0:t1], self.tri_rgb[t0:t1]
+
+    def env_planes(self, e: int):
+        """Face planes of env e's triangles, or None."""
+        if self.tri_plane is None:
+            return None
+        t0, t1 = int(self.tri_offset[e]), int(self.tri_offset[e + 1])
+        return self.tri_plane[t0:t1]
 
     def env_boxes(self, e: int):
         b0, b1 = int(self.box_offset[e]), int(self.box_offset[e + 1])
@@ -263,6 +272,53 @@ def obb_mesh(centre, half, cpsi: float, spsi: float):
     return v.astype(np.float32), t
 
 
+def _plane_row(normal, point) -> np.ndarray:
+    """f32 [4]: the unit normal and the offset n . point of a face plane."""
+    n = np.asarray(normal, np.float64)
+    n = n / np.linalg.norm(n)
+    return np.array([n[0], n[1], n[2], float(n @ np.asarray(point, np.float64))], np.float32)
+
+
+def quad_planes(P0, U, V) -> np.ndarray:
+    """Face plane of ``quad_mesh(P0, U, V)``'s two triangles, f32 [2][4]."""
+    row = _plane_row(np.cross(np.asarray(U, np.float64), np.asarray(V, np.float64)), P0)
+    return np.repeat(row[None, :], 2, axis=0)
+
+
+def boxes_planes(lo, hi, n: int) -> np.ndarray:
+    """Face planes of ``boxes_mesh(lo, hi, n)``'s triangles, f32 [B * 12 n^2][4], in its
+    triangle order.  Each face's offset is the face coordinate of its vertices (the same
+    float), so the plane passes exactly through them."""
+    lo = np.asarray(lo, np.float64).reshape(-1, 3)
+    hi = np.asarray(hi, np.float64).reshape(-1, 3)
+    B = lo.shape[0]
+    per_face = 2 * n * n
+    rows = np.empty((B, 6, per_face, 4), np.float32)
+    for f, (_au, _av, ac, at_max, _flip) in enumerate(_FACES):
+        k = 1.0 if at_max else 0.0
+        c = (lo[:, ac] + (hi[:, ac] - lo[:, ac]) * k).astype(np.float32)   # as in boxes_mesh
+        sign = np.float32(1.0 if at_max else -1.0)
+        rows[:, f, :, :3] = 0.0
+        rows[:, f, :, ac] = sign
+        rows[:, f, :, 3] = (sign * c)[:, None]
+    return rows.reshape(-1, 4)
+
+
+def obb_planes(centre, half, cpsi: float, spsi: float) -> np.ndarray:
+    """Face planes of ``obb_mesh``'s 12 triangles, f32 [12][4]."""
+    R = np.array([[cpsi, -spsi, 0.0], [spsi, cpsi, 0.0], [0.0, 0.0, 1.0]])
+    half = np.asarray(half, np.float64)
+    centre = np.asarray(centre, np.float64)
+    rows = []
+    for (_au, _av, ac, at_max, _flip) in _FACES:
+        e = np.zeros(3)
+        e[ac] = 1.0 if at_max else -1.0
+        nrm = R @ e
+        rows.append(_plane_row(nrm, centre + nrm * half[ac]))
+        rows.append(rows[-1])
+    return np.stack(rows)
+
+
 # --------------------------------------------------------------------------
 # scenes
 # --------------------------------------------------------------------------
@@ -350,25 +406,27 @@ def make_scene(cfg: Config, env: int):
         objs.append((cx, cy, cz, half[0], half[1], half[2], math.cos(yaw), math.sin(yaw)))
 
     # ---------------- render mesh ----------------
-    parts_v, parts_t = [], []
+    parts_v, parts_t, parts_p = [], [], []
 
-    def add(v, t):
+    def add(v, t, pl):
         parts_v.append(v)
         parts_t.append(t)
+        parts_p.append(pl)
 
-    add(*quad_mesh((0, 0, 0), (W, 0, 0), (0, H, 0)))                 # floor, +z
-    add(*quad_mesh((0, 0, 0), (0, H, 0), (0, 0, WALL_H)))            # x=0 wall, +x
-    add(*quad_mesh((W, 0, 0), (0, 0, WALL_H), (0, H, 0)))            # x=W wall, -x
-    add(*quad_mesh((0, 0, 0), (0, 0, WALL_H), (W, 0, 0)))            # y=0 wall, +y
-    add(*quad_mesh((0, H, 0), (W, 0, 0), (0, 0, WALL_H)))            # y=H wall, -y
+    for q in (((0, 0, 0), (W, 0, 0), (0, H, 0)),                     # floor, +z
+              ((0, 0, 0), (0, H, 0), (0, 0, WALL_H)),                # x=0 wall, +x
+              ((W, 0, 0), (0, 0, WALL_H), (0, H, 0)),                # x=W wall, -x
+              ((0, 0, 0), (0, 0, WALL_H), (W, 0, 0)),                # y=0 wall, +y
+              ((0, H, 0), (W, 0, 0), (0, 0, WALL_H))):               # y=H wall, -y
+        add(*quad_mesh(*q), quad_planes(*q))
     if interior:
         ib = np.asarray(interior, np.float64)
-        add(*boxes_mesh(ib[:, :3], ib[:, 3:], 1))
+        add(*boxes_mesh(ib[:, :3], ib[:, 3:], 1), boxes_planes(ib[:, :3], ib[:, 3:], 1))
     if furniture:
         fb = np.asarray(furniture, np.float64)
-        add(*boxes_mesh(fb[:, :3], fb[:, 3:], n_sub))
+        add(*boxes_mesh(fb[:, :3], fb[:, 3:], n_sub), boxes_planes(fb[:, :3], fb[:, 3:], n_sub))
     for o in objs:
-        add(*obb_mesh(o[:3], o[3:6], o[6], o[7]))
+        add(*obb_mesh(o[:3], o[3:6], o[6], o[7]), obb_planes(o[:3], o[3:6], o[6], o[7]))
 
     verts, tris, base = [], [], 0
     for v, t in zip(parts_v, parts_t):
@@ -377,6 +435,8 @@ def make_scene(cfg: Config, env: int):
         base += v.shape[0]
     verts = np.concatenate(verts).astype(np.float32)
     tris = np.concatenate(tris).astype(np.int32)
+    planes = np.concatenate(parts_p).astype(np.float32)
+    assert planes.shape[0] == tris.shape[0]
     rgb = rng.integers(0, 256, size=(tris.shape[0], 3), dtype=np.uint8)
 
     starts = np.zeros((4, 3), np.float32)
@@ -390,7 +450,7 @@ def make_scene(cfg: Config, env: int):
     held = int(rng.uniform() < 0.5) if cfg.held_proxy else 0
     nx = int(round(W / CELL))
     ny = int(round(H / CELL))
-    return dict(verts=verts, tris=tris, rgb=rgb,
+    return dict(verts=verts, tris=tris, rgb=rgb, planes=planes,
                 boxes=np.asarray(static_boxes, np.float32).reshape(-1, 6),
                 objects=np.asarray(objs, np.float32).reshape(-1, 8),
                 grid_origin=np.array([0.0, 0.0], np.float32),
@@ -428,6 +488,7 @@ def make_scene_set(cfg: Config, envs: Optional[Sequence[int]] = None) -> SceneSe
         starts=np.ascontiguousarray(np.stack([s["starts"] for s in scenes])),
         held=np.asarray([s["held"] for s in scenes], np.uint8),
         res=np.asarray([s["res"] for s in scenes], np.int32),
+        tri_plane=np.ascontiguousarray(np.concatenate([s["planes"] for s in scenes])),
     )
 
 

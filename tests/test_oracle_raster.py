@@ -361,3 +361,47 @@ def test_field_of_view_is_ninety_degrees(oracle_lib, half_angle_tan, W):
     assert (cols[inside] == 1).all() and (cols[outside] == 0).all()
     if half_angle_tan > 1:
         assert (cols == 1).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_face_plane_culling_leaves_closed_boxes_unchanged(oracle_lib, seed):
+    """Culling by the camera's side of each face removes only faces that point
+    away from the camera; for closed boxes seen from outside those lie behind
+    front faces, so depth and winning triangles are the winding test's."""
+    O = oracle_lib
+    rng = np.random.default_rng(100 + seed)
+    lo, hi = scene_boxes(rng, 4)
+    v, t = sg.boxes_mesh(lo, hi, 2)
+    pl = sg.boxes_planes(lo, hi, 2)
+    cam = cam_look([0, 0, 0.8], rng.uniform(-0.3, 0.3), rng.uniform(-0.1, 0.3))
+    d0, w0, _, st0 = render(O, v, t, cam, 128, want_id=True)
+    d1, w1, _, st1 = render(O, v, t, cam, 128, want_id=True, planes=pl)
+    assert (d0 == d1).all() and (w0 == w1).all()
+    # the faces culled by their plane are exactly those the camera is behind (FP64)
+    c = cam[:3].astype(np.float64)
+    behind = (pl[:, :3].astype(np.float64) @ c - pl[:, 3]) <= 0
+    assert behind.any() and (~behind).any()
+    assert st1["tris_in"] < st0["tris_in"]
+
+
+def test_face_plane_overrides_winding(oracle_lib):
+    """A quad wound towards the camera but whose supplied face plane points
+    away is culled; with the plane pointing at the camera it is drawn, and a
+    camera exactly on the plane culls it (strictly in front is required)."""
+    O = oracle_lib
+    cam = cam_look([0, 0, 0], 0.0)
+    v, t = sg.quad_mesh((2.0, -0.5, -0.5), (0, 0, 1.0), (0, 1.0, 0))   # U x V = z x y = -x: towards the camera
+    toward = sg.quad_planes((2.0, -0.5, -0.5), (0, 0, 1.0), (0, 1.0, 0))
+    assert np.allclose(toward[0, :3], [-1, 0, 0]) and toward[0, 3] == np.float32(-2.0)
+    away = toward.copy()
+    away[:, :4] *= -1.0
+    d_none, _, _, _ = render(O, v, t, cam, 64)
+    d_toward, _, _, _ = render(O, v, t, cam, 64, planes=toward)
+    d_away, _, _, _ = render(O, v, t, cam, 64, planes=away)
+    assert (d_none < 0xFFFFFF).sum() > 100
+    assert (d_toward == d_none).all()
+    assert (d_away == 0xFFFFFF).all()
+    on_plane = toward.copy()
+    on_plane[:, 3] = np.float32(0.0)      # the camera (origin) on the plane x = 0
+    d_on, _, _, _ = render(O, v, t, cam, 64, planes=on_plane)
+    assert (d_on == 0xFFFFFF).all()
