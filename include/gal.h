@@ -47,6 +47,7 @@ extern "C" {
 
 #define GAL_MAX_CLASSES 8
 #define GAL_MAX_SPHERES 256
+#define GAL_MAX_PLANES 4096
 #define GAL_STATE_FLOATS 10 /* x, y, yaw, q0..q6 */
 
 /* flags of gal_config.flags */
@@ -107,6 +108,17 @@ typedef struct gal_scene_set {
     const int32_t *res;         /* [N] square depth resolution per env, or
                                    NULL for res0 everywhere; 8..256, a
                                    multiple of 8                             */
+    const float *tri_plane;     /* [T][4] or NULL: the plane of the face each
+                                   triangle lies on (outward unit normal n,
+                                   offset w = n . p on the face).  A triangle
+                                   whose face the camera position c is not
+                                   strictly in front of, (n0 c0 + n1 c1) +
+                                   n2 c2 - w <= 0 in FP32, is culled as a back
+                                   face before its winding test; triangles of
+                                   one face share one plane (bitwise), which
+                                   lets the renderer skip whole groups of them.
+                                   At most GAL_MAX_PLANES distinct planes per
+                                   env (GAL_EINVAL otherwise).               */
 } gal_scene_set;
 
 typedef struct gal_config {

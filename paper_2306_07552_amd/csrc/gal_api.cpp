@@ -13,7 +13,10 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
+
+static_assert(GAL_MAX_PLANES == gal::kMaxPlanes, "plane table bound of the ABI and the kernels");
 
 namespace {
 
@@ -57,16 +60,32 @@ struct DevAlloc {
     }
 };
 
-// Clusters of one env: <= 64 consecutive triangles using <= 64 unique vertices.
+// Clusters of one env: <= 64 consecutive triangles using <= 64 unique vertices
+// and lying on <= 4 distinct face planes.
 struct EnvClusters {
     std::vector<float> cl;        // [C][12] words (see RenderMesh), bases relative to env
     std::vector<float> verts;     // [Vc][3]
     std::vector<uint32_t> tris;   // [T]
-    int bad = 0;
+    std::vector<float> planes;    // [P][4] distinct face planes of the env (bit patterns)
+    int bad = 0;                  // 1 = triangle index out of range, 2 = too many planes
 };
 
+// Index of plane `pl` in the env's table (added when new), or -1 when the
+// table is full.
+int plane_index(const float *pl, std::vector<float> &table, std::unordered_map<std::string, int> &seen)
+{
+    const std::string key(reinterpret_cast<const char *>(pl), 4 * sizeof(float));
+    auto it = seen.find(key);
+    if (it != seen.end()) return it->second;
+    const int idx = (int)(table.size() / 4);
+    if (idx >= GAL_MAX_PLANES) return -1;
+    table.insert(table.end(), pl, pl + 4);
+    seen.emplace(key, idx);
+    return idx;
+}
+
 void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
-                        EnvClusters &out)
+                        const float *tri_plane, EnvClusters &out)
 {
     std::vector<int64_t> mark(std::max<int64_t>(nverts, 1), -1);
     std::vector<int32_t> lidx(std::max<int64_t>(nverts, 1), 0);
@@ -76,18 +95,29 @@ void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris,
     int nv = 0, nt = 0;
     int64_t vstart = 0, tstart = 0;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    // the cluster's face planes (env table indices); without planes every
+    // slot is gal::kNoPlane (never culled by a plane)
+    int cpl[gal::kClusterPlanes];
+    int ncpl = 0;
+    std::unordered_map<std::string, int> seen;
     auto close = [&]() {
         if (nt == 0) return;
         float w[12];
         uint32_t vb = (uint32_t)vstart, tb = (uint32_t)tstart, cnt = (uint32_t)nv | ((uint32_t)nt << 8);
-        uint32_t first = (uint32_t)tstart, zero = 0;
+        uint32_t first = (uint32_t)tstart;
+        // unused plane slots repeat the first plane, so "any plane in front" is unchanged
+        uint32_t ps[gal::kClusterPlanes];
+        for (int k = 0; k < gal::kClusterPlanes; ++k)
+            ps[k] = ncpl ? (uint32_t)cpl[k < ncpl ? k : 0] : gal::kNoPlane;
+        const uint32_t p01 = ps[0] | (ps[1] << 16), p23 = ps[2] | (ps[3] << 16);
         w[0] = lo[0]; w[1] = lo[1]; w[2] = lo[2]; memcpy(&w[3], &vb, 4);
         w[4] = hi[0]; w[5] = hi[1]; w[6] = hi[2]; memcpy(&w[7], &tb, 4);
-        memcpy(&w[8], &cnt, 4); memcpy(&w[9], &first, 4); memcpy(&w[10], &zero, 4);
-        memcpy(&w[11], &zero, 4);
+        memcpy(&w[8], &cnt, 4); memcpy(&w[9], &first, 4); memcpy(&w[10], &p01, 4);
+        memcpy(&w[11], &p23, 4);
         out.cl.insert(out.cl.end(), w, w + 12);
         ++cid;
         nv = nt = 0;
+        ncpl = 0;
         vstart = (int64_t)out.verts.size() / 3;
         tstart = (int64_t)out.tris.size();
         for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
@@ -98,12 +128,27 @@ void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris,
             if (v[k] < 0 || v[k] >= nverts) { out.bad = 1; return; }
         int fresh = 0;
         for (int k = 0; k < 3; ++k) {
-            bool seen = mark[v[k]] == cid;
-            for (int q = 0; q < k; ++q) seen = seen || v[q] == v[k];
-            fresh += seen ? 0 : 1;
+            bool was = mark[v[k]] == cid;
+            for (int q = 0; q < k; ++q) was = was || v[q] == v[k];
+            fresh += was ? 0 : 1;
         }
-        if (nt == gal::kClusterTris || nv + fresh > gal::kClusterVerts) close();
-        uint32_t packed = 0;
+        int pidx = -1, pslot = -1;
+        if (tri_plane) {
+            pidx = plane_index(tri_plane + 4 * t, out.planes, seen);
+            if (pidx < 0) { out.bad = 2; return; }
+            for (int k = 0; k < ncpl; ++k)
+                if (cpl[k] == pidx) pslot = k;
+        }
+        if (nt == gal::kClusterTris || nv + fresh > gal::kClusterVerts ||
+            (tri_plane && pslot < 0 && ncpl == gal::kClusterPlanes)) {
+            close();
+            pslot = -1;
+        }
+        if (tri_plane && pslot < 0) {
+            pslot = ncpl;
+            cpl[ncpl++] = pidx;
+        }
+        uint32_t packed = tri_plane ? (uint32_t)pslot << 24 : 0u;
         for (int k = 0; k < 3; ++k) {
             if (mark[v[k]] != cid) {
                 mark[v[k]] = cid;
@@ -717,12 +762,16 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         parallel_for(N, [&](int64_t e) {
             const int64_t v0 = sc->vert_offset[e], v1 = sc->vert_offset[e + 1];
             const int64_t t0 = sc->tri_offset[e], t1 = sc->tri_offset[e + 1];
-            build_env_clusters(sc->verts + 3 * v0, v1 - v0, sc->tris + 3 * t0, t1 - t0, ec[e]);
+            build_env_clusters(sc->verts + 3 * v0, v1 - v0, sc->tris + 3 * t0, t1 - t0,
+                               sc->tri_plane ? sc->tri_plane + 4 * t0 : nullptr, ec[e]);
         });
-        std::vector<uint64_t> cl_off(N + 1, 0), tri_off(N + 1, 0);
+        std::vector<uint64_t> cl_off(N + 1, 0), tri_off(N + 1, 0), pl_off(N + 1, 0);
         uint64_t nv_tot = 0, nt_tot = 0;
         for (int e = 0; e < N; ++e) {
-            if (ec[e].bad) return cleanup(fail(GAL_EINVAL, "env %d: triangle index out of range", e));
+            if (ec[e].bad == 1) return cleanup(fail(GAL_EINVAL, "env %d: triangle index out of range", e));
+            if (ec[e].bad == 2)
+                return cleanup(fail(GAL_EINVAL, "env %d: more than %d distinct face planes", e, GAL_MAX_PLANES));
+            pl_off[e + 1] = pl_off[e] + ec[e].planes.size() / 4;
             cl_off[e + 1] = cl_off[e] + ec[e].cl.size() / 12;
             tri_off[e + 1] = tri_off[e] + ec[e].tris.size();
             nv_tot += ec[e].verts.size() / 3;
@@ -734,14 +783,23 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         const uint64_t slots = (uint64_t)cl_off[N] * gal::kClusterVerts;
         if (slots >= (1ull << 32))
             return cleanup(fail(GAL_EINVAL, "scene set too large for 32-bit cluster slots"));
-        float4 *d_cl;
+        float4 *d_cl, *d_pl;
         float *d_cv;
         uint32_t *d_ct;
-        uint64_t *d_cl_off, *d_tri_off;
+        uint64_t *d_cl_off, *d_tri_off, *d_pl_off;
         if ((rc = b->mem.alloc(&d_cl, (size_t)cl_off[N] * 3)) || (rc = b->mem.alloc(&d_cv, slots * 3)) ||
             (rc = b->mem.alloc(&d_ct, slots)) || (rc = b->mem.alloc(&d_cl_off, (size_t)N + 1)) ||
-            (rc = b->mem.alloc(&d_tri_off, (size_t)N + 1)))
+            (rc = b->mem.alloc(&d_tri_off, (size_t)N + 1)) ||
+            (rc = b->mem.alloc(&d_pl, (size_t)std::max<uint64_t>(pl_off[N], 1))) ||
+            (rc = b->mem.alloc(&d_pl_off, (size_t)N + 1)))
             return cleanup(rc);
+        {
+            std::vector<float> pl_all((size_t)std::max<uint64_t>(pl_off[N], 1) * 4, 0.0f);
+            for (int e = 0; e < N; ++e)
+                std::copy(ec[e].planes.begin(), ec[e].planes.end(), pl_all.begin() + pl_off[e] * 4);
+            HIP_TRY(hipMemcpy(d_pl, pl_all.data(), sizeof(float) * pl_all.size(), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(d_pl_off, pl_off.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        }
         std::vector<float> cl_all((size_t)cl_off[N] * 12);
         std::vector<float> cv_all(slots * 3, 0.0f);
         std::vector<uint32_t> ct_all(slots, 0u);
@@ -767,6 +825,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
             std::vector<float>().swap(c.cl);
             std::vector<float>().swap(c.verts);
             std::vector<uint32_t>().swap(c.tris);
+            std::vector<float>().swap(c.planes);
         });
         HIP_TRY(hipMemcpy(d_cl, cl_all.data(), sizeof(float) * cl_all.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(d_cv, cv_all.data(), sizeof(float) * cv_all.size(), hipMemcpyHostToDevice));
@@ -778,6 +837,8 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         b->mesh.cverts = d_cv;
         b->mesh.ctris = d_ct;
         b->mesh.env_tri_off = d_tri_off;
+        b->mesh.planes = d_pl;
+        b->mesh.env_plane_off = d_pl_off;
         b->mesh.tri_rgb = nullptr;
         b->n_clusters = (int64_t)cl_off[N];
         b->cl_count_host.resize(N);

@@ -12,6 +12,9 @@ constexpr int kMaxSpheres = 256;
 constexpr int kMaxObjects = 64;
 constexpr int kClusterTris = 64;    // triangles per render cluster (one per lane)
 constexpr int kClusterVerts = 64;   // unique vertices per render cluster
+constexpr int kClusterPlanes = 4;    // distinct face planes per cluster (slot in ctris bits 24..25)
+constexpr uint32_t kNoPlane = 0xFFFF; // plane index of clusters built without face planes
+constexpr int kMaxPlanes = 4096;     // distinct face planes per env
 constexpr int kMaxRegion = 128;     // largest square region rendered by one workgroup
 constexpr int kGridIvCap = 64;      // blocking boxes one grid column may see
 
@@ -84,16 +87,24 @@ struct StepOutputs {
     uint8_t *done;
 };
 
-// Render cluster: up to 64 consecutive triangles of one env and the unique
-// vertices they use.  Three float4 words:
+// Render cluster: up to 64 consecutive triangles of one env, the unique
+// vertices they use and the (at most 4) face planes they lie on.  Three
+// float4 words:
 //   w0 = (aabb lo x, y, z, bits of vertex base)
 //   w1 = (aabb hi x, y, z, bits of triangle base)
-//   w2 = (bits of nverts | ntris << 8, bits of first triangle id, 0, 0)
+//   w2 = (bits of nverts | ntris << 8, bits of first triangle id,
+//         plane index p0 | p1 << 16, p2 | p3 << 16)
+// A triangle's slot word holds its three local vertex indices (bits 0..23)
+// and the slot of its plane among p0..p3 (bits 24..25); unused plane slots
+// repeat p0, and clusters built without planes hold kNoPlane.
 struct RenderMesh {
-    const float4 *clusters;          // [C][3] AABB lo + slot, hi + slot, counts nv | nt<<8, first tri
+    const float4 *clusters;          // [C][3] AABB lo + slot, hi + slot, counts nv | nt<<8, first tri,
+                                     // face-plane indices p0 | p1<<16, p2 | p3<<16
+    const float4 *planes;            // [P] distinct face planes per env (normal, offset)
+    const uint64_t *env_plane_off;   // [N+1]
     const uint64_t *env_cluster_off; // [N+1]
     const float *cverts;             // [C][64][3] vertex positions of each cluster (unused slots 0)
-    const uint32_t *ctris;           // [C][64] packed local indices i0 | i1<<8 | i2<<16
+    const uint32_t *ctris;           // [C][64] packed i0 | i1<<8 | i2<<16 | plane slot<<24
     const uint8_t *tri_rgb;          // [T][3] in original order per env, or null
     const uint64_t *env_tri_off;     // [N+1] for colour lookup
 };

@@ -560,6 +560,21 @@ __device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, i
     __syncthreads();
 }
 
+// Whether the camera is strictly in front of face plane p, from the item's
+// bits (kNoPlane: a mesh without face planes, never culled by a plane).
+__device__ __forceinline__ bool plane_front(const uint32_t *bits, uint32_t p)
+{
+    return p == kNoPlane || ((bits[p >> 5] >> (p & 31u)) & 1u) != 0u;
+}
+
+// Whether any of a cluster's face planes (p0 | p1 << 16, p2 | p3 << 16) faces
+// the camera; when none does, every triangle of the cluster is culled.
+__device__ __forceinline__ bool any_plane_front(const uint32_t *bits, uint32_t p01, uint32_t p23)
+{
+    return plane_front(bits, p01 & 0xFFFFu) || plane_front(bits, p01 >> 16) ||
+           plane_front(bits, p23 & 0xFFFFu) || plane_front(bits, p23 >> 16);
+}
+
 // Everything a wave needs to draw clusters of one (env, region) item.
 struct Ctx {
     Cam cam;
@@ -568,6 +583,7 @@ struct Ctx {
     int rx0, ry0, R;
     int P;           // z-buffer row pitch in LDS
     int *own;        // this wave's 64 words of LDS scratch (balanced raster)
+    const uint32_t *planefront;   // bit per env face plane: camera strictly in front
     int small_max;   // bbox pixels: <= lane_max per lane, <= small_max balanced, else tiles
     int lane_max;
 };
@@ -578,6 +594,7 @@ struct ClusterData {
     uint32_t packed;
     int nv, nt;
     uint32_t first;   // env-local index of the cluster's first triangle
+    uint32_t p01, p23; // face-plane indices p0 | p1 << 16, p2 | p3 << 16
 };
 
 // Loads of cluster ci: its counts and first triangle (record word 8..9) and
@@ -585,7 +602,7 @@ struct ClusterData {
 // them are in flight at once; the counts only mask lanes later.
 __device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint64_t ci, int lane, ClusterData &d)
 {
-    const uint2 cf = *reinterpret_cast<const uint2 *>(&m.clusters[ci * 3 + 2]);
+    const uint4 cf = *reinterpret_cast<const uint4 *>(&m.clusters[ci * 3 + 2]);
     const size_t slot = (size_t)ci * kClusterVerts + lane;
     d.vx = m.cverts[slot * 3 + 0];
     d.vy = m.cverts[slot * 3 + 1];
@@ -594,6 +611,8 @@ __device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint64_t ci, 
     d.nv = (int)(cf.x & 0xFF);
     d.nt = (int)((cf.x >> 8) & 0xFF);
     d.first = cf.y;
+    d.p01 = cf.z;
+    d.p23 = cf.w;
 }
 
 // Work counters (debug / roofline accounting), summed per wave.
@@ -650,7 +669,10 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
     const uint32_t o0 = (uint32_t)__shfl((int)oc, i0, 64);
     const uint32_t o1 = (uint32_t)__shfl((int)oc, i1, 64);
     const uint32_t o2 = (uint32_t)__shfl((int)oc, i2, 64);
-    const bool valid = lane < nt && (o0 & o1 & o2) == 0u;
+    // face plane of this triangle (its slot among the cluster's four)
+    const uint32_t pslot = (packed >> 24) & 3u;
+    const uint32_t pidx = ((pslot & 2u) ? d.p23 : d.p01) >> (16u * (pslot & 1u)) & 0xFFFFu;
+    const bool valid = lane < nt && (o0 & o1 & o2) == 0u && plane_front(c.planefront, pidx);
     const bool allin = valid && ((o0 | o1 | o2) & kClipBits) == 0u;
     const bool clipped = valid && !allin;
     const uint64_t vmask = __ballot(valid);
@@ -726,6 +748,7 @@ struct ItemShared {
     uint16_t vis[kVisCap];
     int wave_cnt[kBlock / 64];
     int own[kBlock];   // 64 words per wave, balanced raster
+    uint32_t planefront[kMaxPlanes / 32];   // camera strictly in front of face plane p
     int next;
     int queue_item;
 };
@@ -760,6 +783,7 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     c.ry0 = (reg / nr) * c.R;
     c.P = zpitch(c.R);
     c.own = sh.own + (threadIdx.x & ~63);
+    c.planefront = sh.planefront;
     c.small_max = rp.small_max;
     c.lane_max = rp.lane_max;
     const int R = c.R;
@@ -814,6 +838,28 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     }
     __syncthreads();
 
+    // ---- the env's face planes the camera is strictly in front of, one bit
+    // each ((n0 c0 + n1 c1) + n2 c2 - w > 0 at the camera position c)
+    {
+        const uint64_t pb = m.env_plane_off[env];
+        const int np = (int)(m.env_plane_off[env + 1] - pb);
+        for (int base = wave * 64; base < np; base += kBlock) {
+            const int k = base + lane;
+            bool front = false;
+            if (k < np) {
+                const float4 pl = m.planes[pb + k];
+                const float side = ((pl.x * cam.px + pl.y * cam.py) + pl.z * cam.pz) - pl.w;
+                front = side > 0.0f;
+            }
+            const uint64_t bm = __ballot(front);
+            if (lane == 0) {
+                sh.planefront[base >> 5] = (uint32_t)bm;
+                sh.planefront[(base >> 5) + 1] = (uint32_t)(bm >> 32);
+            }
+        }
+    }
+    __syncthreads();
+
     const uint64_t c0 = m.env_cluster_off[env], c1 = m.env_cluster_off[env + 1];
     unsigned long long *stats = rp.stats;
     // Clusters are processed in windows of up to kVisCap: the workgroup tests
@@ -832,7 +878,9 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                 const uint64_t ci = wbase + k;
                 const float4 w0 = m.clusters[ci * 3 + 0];
                 const float4 w1 = m.clusters[ci * 3 + 1];
-                fr = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z);
+                const uint4 w2 = *reinterpret_cast<const uint4 *>(&m.clusters[ci * 3 + 2]);
+                fr = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z) &&
+                     any_plane_front(sh.planefront, w2.z, w2.w);
             }
             const uint64_t bm = __ballot(fr);
             if (lane == 0) wave_cnt[wave] = __popcll(bm);

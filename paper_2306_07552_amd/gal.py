@@ -41,7 +41,8 @@ class GalSceneSet(C.Structure):
                 ("tri_offset", _i64p), ("tris", _i32p), ("tri_rgb", _u8p),
                 ("box_offset", _i64p), ("boxes", _fp), ("num_objects", C.c_int32),
                 ("objects", _fp), ("grid_origin", _fp), ("grid_dims", _i32p),
-                ("num_starts", C.c_int32), ("starts", _fp), ("held", _u8p), ("res", _i32p)]
+                ("num_starts", C.c_int32), ("starts", _fp), ("held", _u8p), ("res", _i32p),
+                ("tri_plane", _fp)]
 
 
 class GalConfig(C.Structure):
@@ -206,6 +207,8 @@ class Batch:
         s.starts = _p(arr(S.starts, np.float32), _fp)
         s.held = _p(arr(S.held, np.uint8), _u8p)
         s.res = _p(arr(S.res, np.int32), _i32p)
+        tp = getattr(S, "tri_plane", None)
+        s.tri_plane = _p(arr(tp, np.float32), _fp) if tp is not None else None
 
         h = C.c_void_p()
         _check(L.gal_create_batch(C.byref(cfg), C.byref(r), C.byref(s),
