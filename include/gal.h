@@ -231,7 +231,7 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             16 are not split
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
- * prologue 256, persistent 0, robot_lanes 64, graph 0, split 0.
+ * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0.
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -258,7 +258,8 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
  * queue, robot lanes per env) on this batch with the given actions and
  * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
  * it with the other launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the
- * workgroups resident at once (3 x `steps` each, two interleaved rounds).  It
+ * workgroups resident at once, each with an occlusion prologue of 128 and 256
+ * clusters (3 x `steps` each, two interleaved rounds).  It
  * checks that every candidate produces the same depth bits from the same
  * state, keeps the fastest (also written to *best, with its time per step in
  * *best_ms) and restores the simulation state it started from.  The outputs'

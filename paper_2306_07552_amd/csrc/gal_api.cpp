@@ -426,7 +426,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         for (int region : regions)
             for (int lane_max : {0, 4, 8})
                 for (int small_max : {64, 256})
-                    for (int occl : {0, 1})   // 1: one refresh after a 256-cluster prologue
+                    for (int occl : {0, 1})   // 1: one refresh after a 128-cluster prologue
                         for (int persist : {0, 1})
                             for (int rl : {32, 64}) {
                                 bool ok = true;
@@ -440,7 +440,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 t.small_max = small_max;
                                 t.occlusion = occl;
                                 t.refresh = 1;
-                                t.prologue = 256;
+                                t.prologue = 128;
                                 t.persistent = persist;
                                 t.robot_lanes = rl;
                                 t.graph = 0;
@@ -504,12 +504,15 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         const gal_tuning w = best_c;
         std::vector<gal_tuning> c2;
         for (int flip : {0, 1})
-            for (int div : {0, 16, 8, 4, 2}) {
-                gal_tuning t = w;
-                if (flip) t.persistent = 1 - w.persistent;
-                t.split = div ? std::min(b->N, std::max(1, slots / div)) : 0;
-                c2.push_back(t);
-            }
+            for (int div : {0, 16, 8, 4, 2})
+                for (int pro : {128, 256}) {
+                    if (!w.occlusion && pro != w.prologue) continue;
+                    gal_tuning t = w;
+                    if (flip) t.persistent = 1 - w.persistent;
+                    t.split = div ? std::min(b->N, std::max(1, slots / div)) : 0;
+                    if (w.occlusion) t.prologue = pro;
+                    c2.push_back(t);
+                }
         std::vector<double> t2(c2.size(), 1e30);
         for (int round = 0; round < 2 && result == GAL_OK; ++round)
             for (size_t i = 0; i < c2.size(); ++i) {
@@ -865,7 +868,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         b->rast.block = 512;
         b->rast.refresh = 1;
         b->rast.occlusion = 1;
-        b->rast.prologue = 256;
+        b->rast.prologue = 128;
         b->rast.stats = nullptr;
         if ((rc = b->mem.alloc(&b->d_res, (size_t)N)) || (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
             return cleanup(rc);
