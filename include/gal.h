@@ -229,9 +229,13 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             items per region instead of one) so that the last items of a
  *             launch are short; envs whose region side is not a multiple of
  *             16 are not split
+ *  order      with the persistent queue: 1 = each step drains the items in
+ *             the order of their times in the previous step, longest first
+ *             (measured on the device; up to 4096 items, the static order
+ *             beyond), 0 = the static order by cluster count
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
- * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0.
+ * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0.
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -245,6 +249,7 @@ typedef struct gal_tuning {
     int32_t robot_lanes;
     int32_t graph;
     int32_t split;
+    int32_t order;
 } gal_tuning;
 
 int gal_get_tuning(const gal_batch *b, gal_tuning *t);
@@ -259,7 +264,8 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
  * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
  * it with the other launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the
  * workgroups resident at once, each with an occlusion prologue of 128 and 256
- * clusters (3 x `steps` each, two interleaved rounds).  It
+ * clusters and, with the queue, both item orders (3 x `steps` each, two
+ * interleaved rounds).  It
  * checks that every candidate produces the same depth bits from the same
  * state, keeps the fastest (also written to *best, with its time per step in
  * *best_ms) and restores the simulation state it started from.  The outputs'

@@ -217,6 +217,8 @@ struct gal_batch {
     int32_t *d_res = nullptr;
     uint64_t *d_depth_off = nullptr;
     uint32_t *d_work = nullptr;
+    uint32_t *d_item_cost = nullptr;        // last step's time per work item
+    uint32_t *d_item_order = nullptr;       // queue position -> work item
     int32_t num_work = 0;
     int32_t max_res = 0;
     int64_t n_clusters = 0, n_cverts = 0, n_tris = 0;
@@ -324,13 +326,27 @@ int build_work(gal_batch *b)
             }
     }
     if ((int32_t)work.size() > b->work_cap) {
-        int rc = b->mem.alloc(&b->d_work, work.size());
-        if (rc) return rc;
+        int rc;
+        if ((rc = b->mem.alloc(&b->d_work, work.size())) || (rc = b->mem.alloc(&b->d_item_cost, work.size())) ||
+            (rc = b->mem.alloc(&b->d_item_order, work.size())))
+            return rc;
         b->work_cap = (int32_t)work.size();
     }
     b->num_work = (int32_t)work.size();
+    // until items have been timed: the static order (costs decreasing along it)
+    std::vector<uint32_t> cost(work.size()), ord(work.size());
+    for (size_t i = 0; i < work.size(); ++i) {
+        cost[i] = (uint32_t)(work.size() - i);
+        ord[i] = (uint32_t)i;
+    }
     hipError_t e = hipMemcpy(b->d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_item_cost, cost.data(), sizeof(uint32_t) * cost.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_item_order, ord.data(), sizeof(uint32_t) * ord.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(GAL_EDEVICE, "hipMemcpy(work) failed: %s", hipGetErrorString(e));
+    b->rast.item_cost = b->d_item_cost;
+    b->rast.item_order = b->d_item_order;
     return GAL_OK;
 }
 
@@ -354,6 +370,7 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->robot_lanes = b->robot_lanes;
     t->graph = b->use_graph;
     t->split = b->split;
+    t->order = b->rast.order;
     return GAL_OK;
 }
 
@@ -373,6 +390,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->prologue < 0) return fail(GAL_EINVAL, "prologue must be >= 0");
     if (t->robot_lanes != 32 && t->robot_lanes != 64) return fail(GAL_EINVAL, "robot_lanes must be 32 or 64");
     if (t->split < 0 || t->split > b->N) return fail(GAL_EINVAL, "split must be in 0..num_envs");
+    if (t->order != 0 && t->order != 1) return fail(GAL_EINVAL, "order must be 0 or 1");
     const bool rebuild = t->region != b->rast.region || t->split != b->split;
     b->rast.block = t->block;
     b->rast.region = t->region;
@@ -385,6 +403,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->robot_lanes = t->robot_lanes;
     b->use_graph = t->graph ? 1 : 0;
     b->split = t->split;
+    b->rast.order = t->order;
     b->tune_gen += 1;
     b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
     if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");
@@ -445,6 +464,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 t.robot_lanes = rl;
                                 t.graph = 0;
                                 t.split = 0;
+                                t.order = 0;
                                 cands.push_back(t);
                             }
     hipEvent_t e0, e1;
@@ -505,14 +525,17 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         std::vector<gal_tuning> c2;
         for (int flip : {0, 1})
             for (int div : {0, 16, 8, 4, 2})
-                for (int pro : {128, 256}) {
-                    if (!w.occlusion && pro != w.prologue) continue;
-                    gal_tuning t = w;
-                    if (flip) t.persistent = 1 - w.persistent;
-                    t.split = div ? std::min(b->N, std::max(1, slots / div)) : 0;
-                    if (w.occlusion) t.prologue = pro;
-                    c2.push_back(t);
-                }
+                for (int pro : {128, 256})
+                    for (int ord : {0, 1}) {
+                        if (!w.occlusion && pro != w.prologue) continue;
+                        gal_tuning t = w;
+                        if (flip) t.persistent = 1 - w.persistent;
+                        if (ord && !t.persistent) continue;
+                        t.split = div ? std::min(b->N, std::max(1, slots / div)) : 0;
+                        if (w.occlusion) t.prologue = pro;
+                        t.order = ord;
+                        c2.push_back(t);
+                    }
         std::vector<double> t2(c2.size(), 1e30);
         for (int round = 0; round < 2 && result == GAL_OK; ++round)
             for (size_t i = 0; i < c2.size(); ++i) {
@@ -869,6 +892,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         b->rast.refresh = 1;
         b->rast.occlusion = 1;
         b->rast.prologue = 128;
+        b->rast.order = 0;
         b->rast.stats = nullptr;
         if ((rc = b->mem.alloc(&b->d_res, (size_t)N)) || (rc = b->mem.alloc(&b->d_depth_off, (size_t)N + 1)))
             return cleanup(rc);
@@ -975,6 +999,8 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     }
     HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (out->depth && b->rast.persistent && b->rast.order && b->num_work <= gal::kOrderCap)
+        HIP_TRY(gal::launch_order_items(b->d_item_cost, b->num_work, b->d_item_order, s));
     if (out->depth)
         HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
                                    b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,

@@ -121,7 +121,10 @@ struct RasterParams {
     int32_t occlusion; // 1 = cull clusters hidden behind the z-buffer bounds
     int32_t prologue;  // clusters drawn before occlusion culling starts
     int32_t persistent;// 1 = persistent kernel draining the work queue
+    int32_t order;     // 1 = the queue follows the last step's item times, longest first
     unsigned long long *stats; // optional work counters [8] (null = off)
+    uint32_t *item_cost;        // [work] last time of each work item (wall-clock ticks)
+    const uint32_t *item_order; // [work] queue position -> work item
 };
 
 // Launchers (defined in the .hip files).
@@ -139,6 +142,9 @@ hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const floa
                          uint32_t *queue, int32_t persistent_grid, uint32_t *depth, uint8_t *rgb,
                          hipStream_t s);
 hipError_t launch_hash_u32(const uint32_t *a, uint64_t n, unsigned long long *out, hipStream_t s);
+// Queue order of `n` work items by descending cost, ties by index (n <= kOrderCap).
+constexpr int kOrderCap = 4096;
+hipError_t launch_order_items(const uint32_t *cost, int32_t n, uint32_t *order, hipStream_t s);
 hipError_t launch_grid_count(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
                              int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
                              int32_t max_cols, uint32_t *counts, int32_t *overflow, hipStream_t s);

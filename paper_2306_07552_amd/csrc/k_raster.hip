@@ -1033,9 +1033,53 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_pers
         const int i = sh.queue_item;
         __syncthreads();
         if (i >= num_work) break;
-        raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[i], depth, rgb, zdyn,
+        // the queue position's work item (static order: the position itself)
+        int idx = i;
+        if (rp.order && rp.item_order) {
+            idx = (int)rp.item_order[i];
+            if ((unsigned)idx >= (unsigned)num_work) idx = i;
+        }
+        const uint64_t t0 = wall_clock64();
+        raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[idx], depth, rgb, zdyn,
                                     sh);
+        // the item's time, which orders the next step's queue (raster_item
+        // ends with a barrier, so every wave is done)
+        if (threadIdx.x == 0 && rp.item_cost) {
+            const uint64_t dt = wall_clock64() - t0;
+            rp.item_cost[idx] = (uint32_t)(dt < 0xFFFFFFFFull ? dt : 0xFFFFFFFFull);
+        }
     }
+}
+
+// Queue order of the work items by descending cost (ties by index): bitonic
+// sort of (cost, ~index) keys in LDS by one workgroup.
+__global__ __launch_bounds__(1024) void k_order_items(const uint32_t *__restrict__ cost, int n,
+                                                      uint32_t *__restrict__ order)
+{
+    __shared__ unsigned long long key[kOrderCap];
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 1024)
+        key[i] = i < n ? ((unsigned long long)cost[i] << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i)
+                       : 0ull;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 1024) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    const bool desc = (i & k) == 0;
+                    if (desc ? a < b : a > b) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < n; i += 1024)
+        order[i] = 0xFFFFFFFFu - (uint32_t)(key[i] & 0xFFFFFFFFull);
 }
 
 template <bool kColor, bool kPersist>
@@ -1057,6 +1101,17 @@ hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const fl
 #undef GAL_RASTER_LAUNCH
     return hipGetLastError();
 }
+
+}  // namespace
+
+hipError_t launch_order_items(const uint32_t *cost, int32_t n, uint32_t *order, hipStream_t s)
+{
+    if (n <= 0 || n > kOrderCap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_order_items, dim3(1), dim3(1024), 0, s, cost, n, order);
+    return hipGetLastError();
+}
+
+namespace {
 
 size_t lds_bytes(int region, bool color)
 {

@@ -194,6 +194,9 @@ TUNINGS = [
          persistent=1, robot_lanes=64, split=12),
     dict(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=256,
          persistent=1, robot_lanes=32, split=6),
+    # queue ordered by the previous step's item times
+    dict(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=128,
+         persistent=1, robot_lanes=64, split=4, order=1),
 ]
 
 
@@ -220,7 +223,7 @@ def test_tuning_invariance(torch_cuda, tuning):
     dict(block=512, region=128, lane_max=4, small_max=256, refresh=4, occlusion=0, prologue=8),
     dict(block=256, region=64, lane_max=0, small_max=64, refresh=4, occlusion=1, prologue=8),
     dict(block=512, region=128, lane_max=8, small_max=256, refresh=1, occlusion=1, prologue=256,
-         persistent=1, split=5),
+         persistent=1, split=5, order=1),
 ], ids=["r128", "r64-occl", "r128-persistent-split"])
 def test_color_parity(torch_cuda, tuning):
     """Flat colour: the winning triangle (smallest depth, then smallest id)
