@@ -1051,35 +1051,60 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_pers
     }
 }
 
-// Queue order of the work items by descending cost (ties by index): bitonic
-// sort of (cost, ~index) keys in LDS by one workgroup.
+// Queue order of the work items by descending cost, to within 1/256 of the
+// largest cost: a counting sort of the costs quantised to 256 buckets (the
+// order inside a bucket is whatever the LDS atomics give; the order of the
+// items changes no output).
 __global__ __launch_bounds__(1024) void k_order_items(const uint32_t *__restrict__ cost, int n,
                                                       uint32_t *__restrict__ order)
 {
-    __shared__ unsigned long long key[kOrderCap];
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += 1024)
-        key[i] = i < n ? ((unsigned long long)cost[i] << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i)
-                       : 0ull;
+    constexpr int kBuckets = 256;
+    __shared__ uint32_t cmax;
+    __shared__ uint32_t count[kBuckets];
+    if (threadIdx.x == 0) cmax = 1u;
+    if (threadIdx.x < kBuckets) count[threadIdx.x] = 0u;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += 1024) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const unsigned long long a = key[i], b = key[l];
-                    const bool desc = (i & k) == 0;
-                    if (desc ? a < b : a > b) {
-                        key[i] = b;
-                        key[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
+    uint32_t c[kOrderCap / 1024];
+#pragma unroll
+    for (int r = 0; r < kOrderCap / 1024; ++r) {
+        const int i = (int)threadIdx.x + 1024 * r;
+        c[r] = i < n ? cost[i] : 0u;
+        if (i < n) atomicMax(&cmax, c[r]);
+    }
+    __syncthreads();
+    const uint64_t m = cmax;
+    uint32_t bucket[kOrderCap / 1024];
+#pragma unroll
+    for (int r = 0; r < kOrderCap / 1024; ++r) {
+        const int i = (int)threadIdx.x + 1024 * r;
+        // longest first: bucket 0 holds the largest costs
+        bucket[r] = (uint32_t)(kBuckets - 1) - (uint32_t)(((uint64_t)c[r] * (kBuckets - 1)) / m);
+        if (i < n) atomicAdd(&count[bucket[r]], 1u);
+    }
+    __syncthreads();
+    // exclusive prefix over the buckets (one wave, 4 buckets per lane)
+    if (threadIdx.x < 64) {
+        const int l = (int)threadIdx.x;
+        const uint32_t a = count[4 * l], b = count[4 * l + 1], d = count[4 * l + 2], e = count[4 * l + 3];
+        const uint32_t sum = a + b + d + e;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int k = 1; k < 64; k <<= 1) {
+            const uint32_t y = __shfl_up(incl, k, 64);
+            if (l >= k) incl += y;
         }
-    for (int i = threadIdx.x; i < n; i += 1024)
-        order[i] = 0xFFFFFFFFu - (uint32_t)(key[i] & 0xFFFFFFFFull);
+        const uint32_t ex = incl - sum;
+        count[4 * l] = ex;
+        count[4 * l + 1] = ex + a;
+        count[4 * l + 2] = ex + a + b;
+        count[4 * l + 3] = ex + a + b + d;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kOrderCap / 1024; ++r) {
+        const int i = (int)threadIdx.x + 1024 * r;
+        if (i < n) order[atomicAdd(&count[bucket[r]], 1u)] = (uint32_t)i;
+    }
 }
 
 template <bool kColor, bool kPersist>
