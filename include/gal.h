@@ -231,7 +231,7 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             16 are not split
  *  order      with the persistent queue: 1 = each step drains the items in
  *             the order of their times in the previous step, longest first
- *             (measured on the device; up to 4096 items, the static order
+ *             (measured on the device; up to 32768 items, the static order
  *             beyond), 0 = the static order by cluster count
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
