@@ -252,14 +252,17 @@ def test_color_parity(torch_cuda, tuning):
 def test_graph_replay_matches_eager(torch_cuda):
     """The step captured as a hipGraph and replayed gives the same bits as the
     eagerly launched step, replay after replay, with eager work and
-    synchronisations in between (actions refilled in place)."""
+    synchronisations in between (actions refilled in place).  Both run the
+    persistent queue in measured order, whose sort runs on a second stream
+    (a forked branch of the graph)."""
     torch = torch_cuda
     print("case: graph replay vs eager", flush=True)
     cfg = sg.scaled_config(1, 24)
     bg, ob, scenes, robot = make_pair(cfg, oracle_envs=[0, 7, 23])
     from paper_2306_07552_amd import gal
     be = gal.Batch(robot, scenes, sg.config_constants(cfg))
-    bg.set_tuning(graph=1, persistent=1)
+    bg.set_tuning(graph=1, persistent=1, order=1)
+    be.set_tuning(persistent=1, order=1)
     og, oe = bg.alloc_outputs(), be.alloc_outputs()
     act = torch.empty((24, 9), dtype=torch.float32, device="cuda")
     for k in range(6):
@@ -284,7 +287,7 @@ def test_uneven_batch_persistent_graph(torch_cuda):
     sample = [0, 3, 17, 39]
     b, ob, scenes, robot = make_pair(cfg, oracle_envs=sample)
     assert len(set(scenes.res.tolist())) > 1
-    b.set_tuning(persistent=1, graph=1, region=64)
+    b.set_tuning(persistent=1, graph=1, region=64, order=1)
     out = b.alloc_outputs()
     act = torch.empty((40, 9), dtype=torch.float32, device="cuda")
     for k in range(4):
