@@ -958,8 +958,8 @@ int ensure_occupancy(gal_batch *b, hipStream_t s)
         dims[2 * e] = ox;
         dims[2 * e + 1] = oy;
         off[e] = tot;
-        tot += (uint64_t)ox * oy * gal::kPatchZ;
-        maxc = std::max(maxc, ox * oy * gal::kPatchZ);
+        tot += (uint64_t)ox * oy;   // one byte per column, a bit per layer
+        maxc = std::max(maxc, ox * oy);
     }
     int rc;
     if ((rc = b->mem.alloc(&b->d_occ, tot)) || (rc = b->mem.alloc(&b->d_occ_off, (size_t)b->N)) ||

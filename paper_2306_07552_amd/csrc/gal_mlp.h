@@ -38,7 +38,7 @@ hipError_t mlp_to_bf16(const float *a, int64_t n, uint16_t *out, hipStream_t s);
 
 // Surrogate plumbing of a batch.
 struct OccGrid {
-    uint8_t *occ;              // per env [ny][nx][8] blocked flags of the class-0 grid
+    uint8_t *occ;              // per env [ny][nx]: bit k = layer k blocked (the last class's grid)
     const uint64_t *occ_off;   // [N] base of each env's block
     const int32_t *occ_dims;   // [N][2] nx, ny (the column grid's)
     float occ_cell;            // lateral cell (the column grid's)

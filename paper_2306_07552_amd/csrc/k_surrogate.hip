@@ -6,7 +6,7 @@
 // inside the layer (0.0625 m apart, none below 0.125 m so that the floor
 // alone blocks nothing).  Every smaller class's blocked set lies inside the
 // largest class's, so a sphere in contact sits in a blocked column
-// (Appendix G's structure, summarised).
+// (Appendix G's structure, summarised).  One byte per column, bit k = layer k.
 // Features of one env's next move: the candidate joint angles, normalised
 // joint and base offsets, normalised base pose, the held-object flag, the
 // origins of the seven joint frames and the end-effector z axis of the
@@ -55,22 +55,27 @@ __device__ __forceinline__ bool column_free(const SimBuffers &sb, const GridMeta
     return false;
 }
 
+// One thread per column: bit k of the column's byte = layer k blocked.
 __global__ void k_occ_build(SimBuffers sb, OccGrid og, int num_envs, int max_cells, int num_classes)
 {
     const int env = blockIdx.y;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;   // (j * nx + i) * 8 + k
+    const int ij = blockIdx.x * blockDim.x + threadIdx.x;   // j * nx + i
     if (env >= num_envs) return;
     const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
-    if (cell >= ox * oy * kPatchZ) return;
-    const int k = cell % kPatchZ, ij = cell / kPatchZ, i = ij % ox, j = ij / ox;
+    if (ij >= ox * oy) return;
+    const int i = ij % ox, j = ij / ox;
     const GridMeta gm = sb.grid_meta[env];
     const size_t ek = (size_t)env * num_classes + (num_classes - 1);
-    bool blocked = false;
-    for (int m = 0; m < 4 && !blocked; ++m) {
-        const float z = fmaxf((float)k * 0.25f + 0.0625f * (float)(m + 1), 0.125f);
-        blocked = !column_free(sb, gm, ek, i, j, z);
+    uint32_t bits = 0;
+    for (int k = 0; k < kPatchZ; ++k) {
+        bool blocked = false;
+        for (int m = 0; m < 4 && !blocked; ++m) {
+            const float z = fmaxf((float)k * 0.25f + 0.0625f * (float)(m + 1), 0.125f);
+            blocked = !column_free(sb, gm, ek, i, j, z);
+        }
+        if (blocked) bits |= 1u << k;
     }
-    og.occ[og.occ_off[env] + cell] = blocked ? 1 : 0;
+    og.occ[og.occ_off[env] + ij] = (uint8_t)bits;
 }
 
 // one workgroup of 256 threads per env: wave 0 writes the 64 scalars, every
@@ -137,20 +142,20 @@ __global__ __launch_bounds__(256) void k_features(RobotParams rp, SimBuffers sb,
     const float fi1 = floorf(((wx + hx) - gm.x0) / og.occ_cell);
     const float fj0 = floorf(((wy - hx) - gm.y0) / og.occ_cell);
     const float fj1 = floorf(((wy + hx) - gm.y0) / og.occ_cell);
-    uint64_t bits = 0x0101010101010101ull;   // box leaves the grid: blocked
+    uint32_t bits = 0xFFu;   // box leaves the grid: every layer blocked
     // the box is under 3 cells wide, so at most 4 x 4 columns: a fixed 4 x 4
     // block of loads (indices clamped into the lattice) issued together, the
     // columns past the box masked out
     if (fi0 >= 0.0f && fj0 >= 0.0f && fi1 < (float)ox && fj1 < (float)oy && fi1 - fi0 < 4.0f &&
         fj1 - fj0 < 4.0f) {
         const int i0 = (int)fi0, i1 = (int)fi1, j0 = (int)fj0, j1 = (int)fj1;
-        uint64_t v[4][4];
+        uint32_t v[4][4];
 #pragma unroll
         for (int dj = 0; dj < 4; ++dj)
 #pragma unroll
             for (int di = 0; di < 4; ++di) {
                 const int i = min(i0 + di, ox - 1), j = min(j0 + dj, oy - 1);
-                v[dj][di] = *reinterpret_cast<const uint64_t *>(occ + ((size_t)j * ox + i) * kPatchZ);
+                v[dj][di] = occ[(size_t)j * ox + i];
             }
         bits = 0;
 #pragma unroll
@@ -159,11 +164,11 @@ __global__ __launch_bounds__(256) void k_features(RobotParams rp, SimBuffers sb,
             for (int di = 0; di < 4; ++di)
                 if (i0 + di <= i1 && j0 + dj <= j1) bits |= v[dj][di];
     }
+    // layers 2k and 2k + 1 as BF16 ones or zeros in one word
     uint32_t w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        w[k] = (((bits >> (16 * k)) & 0xFF) ? 0x3F80u : 0u) |
-               ((((bits >> (16 * k + 8)) & 0xFF) ? 0x3F80u : 0u) << 16);
+        w[k] = (((bits >> (2 * k)) & 1u) ? 0x3F80u : 0u) | ((((bits >> (2 * k + 1)) & 1u) ? 0x3F80u : 0u) << 16);
     *reinterpret_cast<uint4 *>(row + kFeatPatchBase + t * kPatchZ) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(256) void k_features(RobotParams rp, SimBuffers sb,
 hipError_t launch_occ_build(const SimBuffers &sb, const OccGrid &og, int num_envs, int num_classes,
                             int max_cells, hipStream_t s)
 {
-    dim3 grid((max_cells + 255) / 256, num_envs);
+    dim3 grid((max_cells + 255) / 256, num_envs);   // max_cells: columns of the largest grid
     hipLaunchKernelGGL(k_occ_build, grid, dim3(256), 0, s, sb, og, num_envs, max_cells, num_classes);
     return hipGetLastError();
 }
