@@ -1,8 +1,10 @@
 // Depth rasteriser of the head camera (the per-env depth observation of
 // Galactic, Section 4.1: 90 degree FoV; the paper's batch renderer is
-// replaced by this fixed-point tile rasteriser).
+// replaced by this fixed-point rasteriser).
 //
 // Semantics (identical, bit for bit, for any launch shape):
+//  * a triangle whose face plane (supplied with the mesh) does not have the
+//    camera strictly in front of it is culled;
 //  * camera space X = right.(v-p), Y = down.(v-p), Z = fwd.(v-p);
 //  * trivial reject against the near plane Z = n and a guard band of half a
 //    viewport per side (X + 2Z, 2Z - X, Y + 2Z, 2Z - Y >= 0); triangles that
@@ -10,22 +12,29 @@
 //    each intersection computed from the endpoints in a canonical order) and
 //    fan-triangulated;
 //  * projection x = w/2 + (w/2) X/Z (focal length w/2 for 90 degrees),
-//    snapped to 1/16 pixel; back faces and zero-area triangles are culled;
+//    snapped to 1/16 pixel; triangles whose snapped winding is not front
+//    facing, or whose area is zero, are culled;
 //  * coverage at pixel centres by integer edge functions with the top-left
-//    rule; depth d = (1/n - 1/Z) (2^24-1)/(1/n - 1/f) per vertex,
-//    interpolated as a plane in screen space, clamped and truncated to 24
-//    bits; the image keeps the minimum (0xFFFFFF = nothing).
+//    rule; per-vertex depth d = (1/n - 1/Z) (2^24-1)/(1/n - 1/f), combined
+//    per pixel with the edge functions as barycentric weights, clamped and
+//    truncated to 24 bits; the image keeps the minimum (0xFFFFFF = nothing;
+//    with colour, the smallest (depth, triangle id)).
 //
-// Launch: one workgroup per (env, square region of <= 128x128 pixels); the
-// region's z-buffer lives in LDS and is updated with ds_min_u32.  The env's
-// mesh is stored as clusters of <= 64 consecutive triangles and <= 64 unique
-// vertices with an AABB.  Each wave culls 64 clusters at a time against the
-// region's frustum, then per cluster: lane = vertex (transform, outcodes,
+// Launch: one workgroup per (env, square region of <= 128x128 pixels), as a
+// grid of items or as a persistent queue (longest items first, by cluster
+// count or by the previous step's measured item times; the cheapest envs may
+// be split into quarter regions).  The region's z-buffer lives in LDS and is
+// updated with ds_min.  The env's mesh is stored as clusters of <= 64
+// consecutive triangles, <= 64 unique vertices and <= 4 face planes, with an
+// AABB.  The workgroup keeps the clusters inside the region's frustum with a
+// face plane towards the camera, draws them in mesh order and, after a
+// prologue, re-tests the rest against conservative z-buffer bounds
+// (occlusion culling).  Per cluster: lane = vertex (transform, outcodes,
 // projection once per vertex), lane = triangle (gathers its vertices with
 // ds_bpermute); triangles whose pixel bbox is small are rasterised by their
-// own lane, large ones by the whole wave, one 8x8 tile (lane = pixel) at a
-// time.  Every extra rejection (cluster AABB, region planes) only removes
-// triangles that cannot cover a pixel centre of the region.
+// own lane, mid-sized ones by the whole wave with the pixels spread over the
+// lanes, large ones one 8x8 tile (lane = pixel) at a time.  Every extra
+// rejection only removes triangles that cannot change a pixel of the region.
 #include "gal_internal.h"
 
 #include <type_traits>
