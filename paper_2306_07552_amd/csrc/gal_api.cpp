@@ -4,6 +4,7 @@
 #include "gal.h"
 #include "gal_internal.h"
 #include "gal_mlp.h"
+#include "gal_order.h"
 
 #include <algorithm>
 #include <atomic>
@@ -997,10 +998,13 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         sb.skip_flags = b->d_flags;
         sb.sur_stats = b->d_sur_stats;
     }
-    HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, s));
+    // the raster queue order (from the previous step's item times) is computed
+    // by an extra workgroup of the robot launch
+    const bool order_items =
+        out->depth && b->rast.persistent && b->rast.order && b->num_work <= gal::kOrderCap;
+    const gal::ItemOrder ord{b->d_item_cost, order_items ? b->num_work : 0, b->d_item_order};
+    HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, ord, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    if (out->depth && b->rast.persistent && b->rast.order && b->num_work <= gal::kOrderCap)
-        HIP_TRY(gal::launch_order_items(b->d_item_cost, b->num_work, b->d_item_order, s));
     if (out->depth)
         HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
                                    b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,

@@ -8,6 +8,7 @@
 #include "gal_fk.h"
 #include "gal_internal.h"
 #include "gal_math.h"
+#include "gal_order.h"
 
 namespace gal {
 
@@ -164,14 +165,61 @@ __device__ __forceinline__ void load_slots(const RobotParams &rp, const SimBuffe
     }
 }
 
+// Queue order of the raster work items by descending cost, to within 1/256
+// of the largest: a counting sort of the costs quantised to 256 buckets by
+// one 256-thread workgroup (three passes over the costs; the order inside a
+// bucket is whatever the LDS atomics give, and the order of the items changes
+// no output).
+__device__ void order_items_block(const ItemOrder &ord)
+{
+    constexpr int kBuckets = 256;
+    __shared__ uint32_t cmax;
+    __shared__ uint32_t count[kBuckets];
+    const int t = (int)threadIdx.x, n = ord.n;
+    if (t == 0) cmax = 1u;
+    count[t] = 0u;
+    __syncthreads();
+    for (int i = t; i < n; i += 256) atomicMax(&cmax, ord.cost[i]);
+    __syncthreads();
+    const uint64_t m = cmax;
+    auto bucket = [&](uint32_t c) {   // longest first: bucket 0 holds the largest costs
+        return (uint32_t)(kBuckets - 1) - (uint32_t)(((uint64_t)c * (kBuckets - 1)) / m);
+    };
+    for (int i = t; i < n; i += 256) atomicAdd(&count[bucket(ord.cost[i])], 1u);
+    __syncthreads();
+    if (t < 64) {   // exclusive prefix over the buckets, 4 per lane
+        const uint32_t a = count[4 * t], b = count[4 * t + 1], d = count[4 * t + 2], e = count[4 * t + 3];
+        const uint32_t sum = a + b + d + e;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int k = 1; k < 64; k <<= 1) {
+            const uint32_t y = __shfl_up(incl, k, 64);
+            if (t >= k) incl += y;
+        }
+        const uint32_t ex = incl - sum;
+        count[4 * t] = ex;
+        count[4 * t + 1] = ex + a;
+        count[4 * t + 2] = ex + a + b;
+        count[4 * t + 3] = ex + a + b + d;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += 256) ord.order[atomicAdd(&count[bucket(ord.cost[i])], 1u)] = (uint32_t)i;
+}
+
 // kLanes lanes per environment: 64 (one env per wave, spheres lane + 64k) or
 // 32 (two envs per wave, spheres lane + 32k); the ballot's 32-bit halves are
 // then exactly the envs' contact words.
 template <int kLanes>
 __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers sb,
                                                     const float *__restrict__ actions,
-                                                    StepOutputs out, uint32_t *queue_reset)
+                                                    StepOutputs out, uint32_t *queue_reset,
+                                                    ItemOrder ord)
 {
+    // the launch's extra last workgroup orders the raster queue
+    if (ord.n > 0 && blockIdx.x == gridDim.x - 1) {
+        order_items_block(ord);
+        return;
+    }
     // the raster work queue of this step starts empty (a kernel store rather
     // than a memset, so the step can be captured as a graph)
     if (queue_reset && blockIdx.x == 0 && threadIdx.x == 0) *queue_reset = 0u;
@@ -377,18 +425,29 @@ __global__ void k_reset(RobotParams rp, SimBuffers sb, const uint8_t *__restrict
 
 hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
                              const StepOutputs &out, uint32_t *queue_reset, int lanes_per_env,
-                             hipStream_t s)
+                             const ItemOrder &ord, hipStream_t s)
 {
+    if (ord.n < 0 || ord.n > kOrderCap || (ord.n > 0 && (!ord.cost || !ord.order)))
+        return hipErrorInvalidValue;
+    const int extra = ord.n > 0 ? 1 : 0;
     if (lanes_per_env == 32) {
-        const int blocks = (sb.num_envs + 7) / 8;
+        const int blocks = (sb.num_envs + 7) / 8 + extra;
         hipLaunchKernelGGL(k_robot_step<32>, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
-                           queue_reset);
+                           queue_reset, ord);
     } else {
-        const int blocks = (sb.num_envs + 3) / 4;
+        const int blocks = (sb.num_envs + 3) / 4 + extra;
         hipLaunchKernelGGL(k_robot_step<64>, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
-                           queue_reset);
+                           queue_reset, ord);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,
+                             const StepOutputs &out, uint32_t *queue_reset, int lanes_per_env,
+                             hipStream_t s)
+{
+    return launch_robot_step(rp, sb, actions, out, queue_reset, lanes_per_env, ItemOrder{nullptr, 0, nullptr},
+                             s);
 }
 
 hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
