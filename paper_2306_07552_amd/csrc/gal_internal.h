@@ -142,10 +142,8 @@ hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const floa
                          uint32_t *queue, int32_t persistent_grid, uint32_t *depth, uint8_t *rgb,
                          hipStream_t s);
 hipError_t launch_hash_u32(const uint32_t *a, uint64_t n, unsigned long long *out, hipStream_t s);
-// Queue order of `n` work items by descending cost, to within 1/256 of the
-// largest (n <= kOrderCap).
+// Work items the raster queue order handles (the static order beyond).
 constexpr int kOrderCap = 32768;
-hipError_t launch_order_items(const uint32_t *cost, int32_t n, uint32_t *order, hipStream_t s);
 hipError_t launch_grid_count(const SimBuffers &sb, const float *boxes, const uint64_t *box_off,
                              int32_t num_envs, int32_t num_classes, const ClassRadii &radii,
                              int32_t max_cols, uint32_t *counts, int32_t *overflow, hipStream_t s);

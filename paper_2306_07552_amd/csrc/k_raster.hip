@@ -1060,62 +1060,6 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_pers
     }
 }
 
-// Queue order of the work items by descending cost, to within 1/256 of the
-// largest cost: a counting sort of the costs quantised to 256 buckets (the
-// order inside a bucket is whatever the LDS atomics give; the order of the
-// items changes no output).
-__global__ __launch_bounds__(1024) void k_order_items(const uint32_t *__restrict__ cost, int n,
-                                                      uint32_t *__restrict__ order)
-{
-    constexpr int kBuckets = 256;
-    __shared__ uint32_t cmax;
-    __shared__ uint32_t count[kBuckets];
-    if (threadIdx.x == 0) cmax = 1u;
-    if (threadIdx.x < kBuckets) count[threadIdx.x] = 0u;
-    __syncthreads();
-    uint32_t c[kOrderCap / 1024];
-#pragma unroll
-    for (int r = 0; r < kOrderCap / 1024; ++r) {
-        const int i = (int)threadIdx.x + 1024 * r;
-        c[r] = i < n ? cost[i] : 0u;
-        if (i < n) atomicMax(&cmax, c[r]);
-    }
-    __syncthreads();
-    const uint64_t m = cmax;
-    uint32_t bucket[kOrderCap / 1024];
-#pragma unroll
-    for (int r = 0; r < kOrderCap / 1024; ++r) {
-        const int i = (int)threadIdx.x + 1024 * r;
-        // longest first: bucket 0 holds the largest costs
-        bucket[r] = (uint32_t)(kBuckets - 1) - (uint32_t)(((uint64_t)c[r] * (kBuckets - 1)) / m);
-        if (i < n) atomicAdd(&count[bucket[r]], 1u);
-    }
-    __syncthreads();
-    // exclusive prefix over the buckets (one wave, 4 buckets per lane)
-    if (threadIdx.x < 64) {
-        const int l = (int)threadIdx.x;
-        const uint32_t a = count[4 * l], b = count[4 * l + 1], d = count[4 * l + 2], e = count[4 * l + 3];
-        const uint32_t sum = a + b + d + e;
-        uint32_t incl = sum;
-#pragma unroll
-        for (int k = 1; k < 64; k <<= 1) {
-            const uint32_t y = __shfl_up(incl, k, 64);
-            if (l >= k) incl += y;
-        }
-        const uint32_t ex = incl - sum;
-        count[4 * l] = ex;
-        count[4 * l + 1] = ex + a;
-        count[4 * l + 2] = ex + a + b;
-        count[4 * l + 3] = ex + a + b + d;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kOrderCap / 1024; ++r) {
-        const int i = (int)threadIdx.x + 1024 * r;
-        if (i < n) order[atomicAdd(&count[bucket[r]], 1u)] = (uint32_t)i;
-    }
-}
-
 template <bool kColor, bool kPersist>
 hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const float *camera,
                            const int32_t *env_res, const uint64_t *env_depth_off,
@@ -1135,17 +1079,6 @@ hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const fl
 #undef GAL_RASTER_LAUNCH
     return hipGetLastError();
 }
-
-}  // namespace
-
-hipError_t launch_order_items(const uint32_t *cost, int32_t n, uint32_t *order, hipStream_t s)
-{
-    if (n <= 0 || n > kOrderCap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_order_items, dim3(1), dim3(1024), 0, s, cost, n, order);
-    return hipGetLastError();
-}
-
-namespace {
 
 size_t lds_bytes(int region, bool color)
 {
