@@ -159,7 +159,9 @@ typedef struct gal_outputs {
 typedef struct gal_batch gal_batch;   /* opaque, owned by the library */
 
 /*
- * Create a batch: validates the inputs, copies robot and scenes to the
+ * Create a batch (Section 3.1 "Batching": one simulator instance and one
+ * renderer serve every environment of the batch, and the observations stay
+ * stacked in GPU memory): validates the inputs, copies robot and scenes to the
  * device, builds the column grids (one per env and radius class) and the
  * clustered render meshes, and sets every env to episode 0 at its first
  * start pose with the arm at q_home.  Synchronous (returns when done).
@@ -171,6 +173,9 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot,
                      const gal_scene_set *scenes, void *stream, gal_batch **out);
 
 /*
+ * Episode reset (Section 4.1: episodes of at most 500 steps; the start pose
+ * and arm configuration are this build's reading, Section 3.2 places the
+ * robot, it does not say where).
  * Start a new episode in the envs selected by `env_mask_dev` (device u8[N],
  * nonzero = reset; NULL = all envs): episode += 1, pose = start pose
  * (episode mod P), arm at q_home, step counter 0.  Asynchronous on `stream`.
@@ -178,7 +183,10 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot,
 int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
 
 /*
- * One step of every environment (asynchronous on `stream`):
+ * One step of every environment (Section 3.2 "Approximate Kinematic
+ * Simulation" and Appendix G for steps 1-3; Section 4.1 for the horizon and
+ * the 90 degree head-camera depth observation of step 5), asynchronous on
+ * `stream`:
  *  1. actions_dev f32 [N][9] = forward offset (m), yaw offset (rad), 7 joint
  *     offsets (rad); NaN components count as 0, then each is clamped to
  *     +-act_lim.  Candidate: yaw' = yaw + a1 wrapped into [-pi, pi]; x, y move
@@ -198,8 +206,9 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
 int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream);
 
 /*
- * Launch configuration of the raster kernel.  Every setting produces the same
- * bits (the outputs are defined independently of how the work is split); the
+ * Launch configuration of the raster kernel (this build's extension of the
+ * batch renderer of Section 3.1; not in the paper).  Every setting produces
+ * the same bits (the outputs are defined independently of how the work is split); the
  * settings only change speed, and an autotuner picks among them.
  *  block      threads per workgroup: 256, 512 or 1024
  *  region     square pixel region owned by one workgroup: 32, 64 or 128 (must
@@ -252,13 +261,17 @@ typedef struct gal_tuning {
     int32_t order;
 } gal_tuning;
 
+/* Read / replace the launch configuration above (Section 3.1 batching
+ * extension).  gal_set_tuning errors: GAL_EINVAL for values out of range.
+ * Not to be called while a step on the batch is in flight on another
+ * stream. */
 int gal_get_tuning(const gal_batch *b, gal_tuning *t);
-/* Errors: GAL_EINVAL for values out of range.  Not to be called while a step
- * on the batch is in flight on another stream. */
 int gal_set_tuning(gal_batch *b, const gal_tuning *t);
 
 /*
- * Autotuner: times the candidate launch configurations (raster workgroup
+ * Autotuner (this build's extension of Section 3.1 "Batching": the paper
+ * fixes one batch size per GPU; here the split of the batch's work into
+ * workgroups is searched per batch): times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
  * queue, robot lanes per env) on this batch with the given actions and
  * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
@@ -275,15 +288,19 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
 int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out, void *stream,
                  int32_t steps, gal_tuning *best, double *best_ms);
 
-/* Number of environments, spheres, contact words, and the packed depth size. */
+/* Number of environments, spheres, contact words, and the packed depth size
+ * (the batch's shape, Section 3.1). */
 int gal_batch_info(const gal_batch *b, int32_t *num_envs, int32_t *num_spheres,
                    int32_t *contact_words, int64_t *depth_pixels);
 
-/* Host copy of the per-env pixel offsets of the packed depth output, [N+1]. */
+/* Host copy of the per-env pixel offsets of the packed depth output, [N+1]
+ * (one stacked image per sensor, Section 3.1; envs may differ in resolution). */
 int gal_depth_offsets(const gal_batch *b, int64_t *offsets_host, size_t count);
 
 /*
- * Checkpoint / restore of the simulation state (synchronises `stream`):
+ * Checkpoint / restore of the simulation state of Section 3.2 (the robot's
+ * base pose and joint angles; objects and scene are static in this step) and
+ * the episode counters of Section 4.1 (synchronises `stream`):
  * host buffer of N * (10 floats + 2 int32) bytes, laid out as f32 state
  * [N][10] followed by i32 counters [N][2].  GAL_ESTATE when `bytes` differs.
  */
@@ -291,8 +308,9 @@ int gal_get_state(gal_batch *b, void *host, size_t bytes, void *stream);
 int gal_set_state(gal_batch *b, const void *host, size_t bytes, void *stream);
 
 /*
- * Inspection of the column grid built on the device for env `env` and
- * radius class `cls` (synchronous): the layer count of every column as CSR
+ * Inspection of the column grid of Appendix G (free vertical layers per
+ * column, one grid per sphere-radius class) built on the device for env `env`
+ * and radius class `cls` (synchronous): the layer count of every column as CSR
  * offsets (host u32 [nx*ny+1]) and the free layers (host f32 [L][2] = lowest
  * and highest admissible sphere-centre height; the top one ends at +inf).
  * Pass layers_host = NULL to query L through *num_layers.
@@ -303,7 +321,8 @@ int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
 
 /*
  * Per-kernel timing of gal_step with HIP events recorded on the step's own
- * stream.  While enabled, every gal_step records an event before, between
+ * stream: the split of Appendix F's rollout-step timing table into physics
+ * and rendering, measured here on the device.  While enabled, every gal_step records an event before, between
  * and after its two stages (everything before the raster: the surrogate's
  * kernels when one is attached and the robot step; then the raster);
  * gal_profile_read waits for the recorded events, returns the summed
@@ -314,8 +333,9 @@ int gal_profile_enable(gal_batch *b, int on);
 int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps);
 
 /*
- * On-device work counters of the raster kernel, summed over the steps run
- * while enabled (reading synchronises the device and clears them).
+ * On-device work counters of the raster kernel (the rendering phase of
+ * Appendix F's timing table, broken down by culling stage), summed over the
+ * steps run while enabled (reading synchronises the device and clears them).
  * counters_host receives GAL_NUM_COUNTERS values: [0] clusters tested against
  * the frustum, [1] inside it, [2] of those proven hidden by the occlusion
  * bounds, [3] clusters drawn, [4] triangles surviving trivial rejection,
@@ -326,8 +346,9 @@ int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t 
 int gal_counters_enable(gal_batch *b, int on);
 int gal_counters_read(gal_batch *b, int64_t *counters_host, size_t count);
 
-/* Sizes of the device-resident render mesh: 64-triangle clusters, their
- * (per-cluster unique) vertices, and triangles. */
+/* Sizes of the device-resident render mesh of the batch renderer
+ * (Section 3.1): 64-triangle clusters, their (per-cluster unique) vertices,
+ * and triangles. */
 int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
                   int64_t *tris);
 
@@ -357,42 +378,56 @@ int gal_mesh_info(const gal_batch *b, int64_t *clusters, int64_t *cluster_verts,
 typedef struct gal_mlp gal_mlp;
 #define GAL_MLP_IN 2112
 
-/* Total parameter count (738,561). */
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Total parameter count (738,561). */
 int gal_mlp_num_params(int64_t *n);
-/* Device MLP for up to max_rows rows per call; He-uniform initial weights
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Device MLP for up to max_rows rows per call; He-uniform initial weights
  * from `seed`, zero biases, Adam state cleared.  Synchronous. */
 int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out);
-/* Host FP32 parameters in the layout above (count = gal_mlp_num_params);
- * set also clears the Adam state.  Synchronous. */
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Host FP32 parameters in the layout above (count = gal_mlp_num_params);
+ * set also clears the Adam state.  Synchronous.  (The weights arrive as a
+ * host array rather than a file path: the caller owns the file format.) */
 int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count);
 int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
-/* Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112],
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112],
  * 16-byte aligned rows).  The inference kernels (split-K first layer, fused
  * layers 2..4 and head) accumulate the first layer in 11 partial sums, so
  * logits can differ from the training forward pass in the last bits. */
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
-/* Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
  * w_i = pos_weight for labels 1, into grads_dev (device f32, parameter
  * layout; may be NULL) and the loss into loss_dev (device f32[1]; may be
  * NULL).  Labels are device f32 0/1. */
 int gal_mlp_gradients(gal_mlp *m, const uint16_t *x_dev, const float *labels_dev, int32_t rows,
                       float pos_weight, float *grads_dev, float *loss_dev, void *stream);
-/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on those gradients. */
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) on those
+ * gradients. */
 int gal_mlp_train_step(gal_mlp *m, const uint16_t *x_dev, const float *labels_dev, int32_t rows,
                        float pos_weight, float lr, float *loss_dev, void *stream);
-/* The MLP's BF16 matrix-core GEMM alone, FP32 output (for verification):
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * The MLP's BF16 matrix-core GEMM alone, FP32 output (for verification):
  * variant 3: C = A B^T, 4: C = A B, 5: C = A^T B, operands BF16 bits with
  * leading dimensions lda / ldb (elements), C [M][ldc]. */
 int gal_mlp_gemm_test(int32_t variant, const uint16_t *a_dev, const uint16_t *b_dev, int32_t M,
                       int32_t N, int32_t K, int32_t lda, int32_t ldb, float *c_dev, int32_t ldc,
                       void *stream);
+/* Surrogate of the Section 3.2 static-scene test (not in the paper): frees
+ * the MLP. */
 void gal_mlp_destroy(gal_mlp *m);
 
-/* Surrogate inputs of every env's next move under actions_dev into x_dev
+/* Surrogate of the Section 3.2 static-scene test (not in the paper); the
+ * patch samples the column grid of Appendix G.
+ * Surrogate inputs of every env's next move under actions_dev into x_dev
  * (device BF16 u16 [N][2112], 16-byte aligned).  Builds the occupancy
  * lattice on first use (synchronous then). */
 int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *stream);
 /*
+ * Surrogate of the Section 3.2 static-scene test (not in the paper).
  * Put the MLP in front of the static check of gal_step: an env whose
  * predicted contact probability is <= skip_below skips the column-grid test
  * (its static contact mask is then 0), except a hashed 1-in-audit_period
@@ -402,14 +437,19 @@ int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *
  */
 int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t audit_period,
                          void *stream);
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * Detach restores the exact test for every env. */
 int gal_surrogate_detach(gal_batch *b);
-/* stats_host[4] = queries, skipped, audited, audit mismatches since the last
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * stats_host[4] = queries, skipped, audited, audit mismatches since the last
  * reset (synchronises the device; reset != 0 clears them). */
 int gal_surrogate_stats(gal_batch *b, int64_t *stats_host, int reset);
 
+/* Frees a batch created by gal_create_batch (Section 3.1 batch object). */
 void gal_destroy(gal_batch *b);
 
-/* Message of the last failing call on this thread ("" if none). */
+/* Message of the last failing call on this thread ("" if none); the error
+ * convention of every entry point above (Section 3.1 boundary). */
 const char *gal_last_error(void);
 
 #ifdef __cplusplus

@@ -3,7 +3,7 @@
  *
  * The surrogate is not part of the paper: it is this build's learned
  * pre-filter for the static-scene overlap test of the kinematic step
- * (Section 3.2).  Network: input x (2080 values) -> 4 hidden layers of 256
+ * (Section 3.2).  Network: input x (2112 values) -> 4 hidden layers of 256
  * units with ReLU -> one logit z; p = sigmoid(z).  On the device, weights and
  * activations are BF16 with FP32 accumulation; this oracle evaluates the same
  * network in FP64 on the same BF16 values, rounding activations (and the

@@ -243,6 +243,10 @@ struct gal_batch {
     int32_t use_graph = 0;
     int32_t split = 0;   // cheapest envs rendered with halved regions
     uint64_t tune_gen = 1;                  // bumps on every tuning change
+    // autotuner scratch (allocated on the first gal_autotune, reused after)
+    float *tune_st0 = nullptr;
+    int32_t *tune_cnt0 = nullptr;
+    unsigned long long *tune_hash = nullptr;
     // captured step graph and what it was captured for
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -425,16 +429,28 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     gal_get_tuning(b, &orig);
     const bool was_profiling = b->profiling;
     b->profiling = false;
-    // saved simulation state (restored before every candidate and at the end)
-    float *st0 = nullptr;
-    int32_t *cnt0 = nullptr;
-    unsigned long long *hash = nullptr;
+    // saved simulation state (restored before every candidate and at the end);
+    // the buffers are allocated once per batch and reused by later calls
     int rc;
-    if ((rc = b->mem.alloc(&st0, (size_t)b->N * 10)) || (rc = b->mem.alloc(&cnt0, (size_t)b->N * 2)) ||
-        (rc = b->mem.alloc(&hash, 1)))
+    if (!b->tune_st0 &&
+        ((rc = b->mem.alloc(&b->tune_st0, (size_t)b->N * 10)) ||
+         (rc = b->mem.alloc(&b->tune_cnt0, (size_t)b->N * 2)) || (rc = b->mem.alloc(&b->tune_hash, 1))))
         return rc;
+    float *st0 = b->tune_st0;
+    int32_t *cnt0 = b->tune_cnt0;
+    unsigned long long *hash = b->tune_hash;
     HIP_TRY(hipMemcpyAsync(st0, b->sb.state, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(cnt0, b->sb.counters, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
+    // the surrogate's query counters are not the tuner's to change: saved here,
+    // restored at the end
+    unsigned long long sur_stats0[4] = {0, 0, 0, 0};
+    if (b->d_sur_stats) {
+        HIP_TRY(hipMemcpyAsync(sur_stats0, b->d_sur_stats, sizeof(sur_stats0), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // likewise the raster work counters: off while tuning
+    unsigned long long *stats_on = b->rast.stats;
+    b->rast.stats = nullptr;
     auto restore = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(b->sb.state, st0, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->sb.counters, cnt0, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
@@ -469,8 +485,11 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 cands.push_back(t);
                             }
     hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        b->rast.stats = stats_on;
+        b->profiling = was_profiling;
+        return fail(GAL_EDEVICE, "autotune: hipEventCreate failed");
+    }
     double best_t = 1e30;
     gal_tuning best_c = orig;
     unsigned long long ref_hash = 0;
@@ -559,6 +578,11 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     int rc3 = restore();
     (void)hipStreamSynchronize(s);
     b->profiling = was_profiling;
+    b->rast.stats = stats_on;
+    b->tune_gen += 1;
+    if (b->d_sur_stats &&
+        (hipMemcpy(b->d_sur_stats, sur_stats0, sizeof(sur_stats0), hipMemcpyHostToDevice) != hipSuccess))
+        return fail(GAL_EDEVICE, "autotune: restoring the surrogate counters failed");
     if (result) return result;
     if (rc2) return rc2;
     if (rc3) return rc3;
@@ -1108,6 +1132,7 @@ int gal_counters_enable(gal_batch *b, int on)
         HIP_TRY(hipMemset(b->d_stats, 0, sizeof(unsigned long long) * GAL_NUM_COUNTERS));
     }
     b->rast.stats = on ? b->d_stats : nullptr;
+    b->tune_gen += 1;   // a captured step graph holds the raster parameters by value
     return GAL_OK;
 }
 

@@ -141,6 +141,11 @@ def _p(a: Optional[np.ndarray], t):
     return a.ctypes.data_as(t)
 
 
+def _need(a, shape, name):
+    if tuple(np.shape(a)) != tuple(shape):
+        raise GalError(-1, f"{name}: shape {tuple(np.shape(a))}, expected {tuple(shape)}")
+
+
 def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         import torch
@@ -191,6 +196,25 @@ class Batch:
 
         s = GalSceneSet()
         S = scenes
+        # the C ABI takes the arrays without lengths: their shapes must agree
+        # with the offsets before the library reads them
+        N = int(S.num_envs)
+        T = int(np.asarray(S.tri_offset)[-1])
+        _need(S.vert_offset, (N + 1,), "vert_offset")
+        _need(S.tri_offset, (N + 1,), "tri_offset")
+        _need(S.box_offset, (N + 1,), "box_offset")
+        _need(S.verts, (int(np.asarray(S.vert_offset)[-1]), 3), "verts")
+        _need(S.tris, (T, 3), "tris")
+        _need(S.tri_rgb, (T, 3), "tri_rgb")
+        _need(S.boxes, (int(np.asarray(S.box_offset)[-1]), 6), "boxes")
+        _need(S.objects, (N, int(S.num_objects), 8), "objects")
+        _need(S.grid_origin, (N, 2), "grid_origin")
+        _need(S.grid_dims, (N, 2), "grid_dims")
+        _need(S.starts, (N, int(S.num_starts), 3), "starts")
+        _need(S.held, (N,), "held")
+        _need(S.res, (N,), "res")
+        if getattr(S, "tri_plane", None) is not None:
+            _need(S.tri_plane, (T, 4), "tri_plane")
         s.num_envs = int(S.num_envs)
         s.vert_offset = _p(arr(S.vert_offset, np.int64), _i64p)
         s.verts = _p(arr(S.verts, np.float32), _fp)

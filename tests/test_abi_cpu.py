@@ -67,3 +67,44 @@ def test_null_arguments(lib):
     assert lib.gal_step(None, None, None, None) == -1
     assert lib.gal_reset(None, None, None) == -1
     assert lib.gal_get_state(None, None, 0, None) == -1
+
+
+def declaration_comments():
+    """For every gal_* function declared in include/gal.h, the comment block
+    that documents it: the nearest block comment above its declaration (a
+    block may document a run of consecutive declarations)."""
+    text = open(os.path.join(ROOT, "include", "gal.h")).read()
+    out = {}
+    last_comment = None
+    token = re.compile(r"/\*.*?\*/|^(?:int|void|const char)\s*\*?\s*(gal_[a-z_]+)\s*\(",
+                       re.S | re.M)
+    for m in token.finditer(text):
+        if m.group(0).startswith("/*"):
+            last_comment = m.group(0)
+        else:
+            out[m.group(1)] = last_comment
+    return out
+
+
+def test_every_entry_point_cites_its_passage():
+    """Each declared entry point is documented by a comment that names the
+    passage of the paper it implements or extends (a Section, Appendix or
+    Table)."""
+    docs = declaration_comments()
+    assert set(docs) == set(header_functions())
+    cite = re.compile(r"\b(Section \d(\.\d)?|Appendix [A-I]|Table \d)\b")
+    missing = [n for n, c in docs.items() if c is None or not cite.search(c)]
+    assert not missing, f"entry points without a citation: {missing}"
+
+
+@pytest.mark.parametrize("field,cut", [("tri_plane", 1), ("tris", 1), ("tri_rgb", 2), ("boxes", 1),
+                                       ("verts", 3)])
+def test_array_lengths_must_match_offsets(lib, field, cut):
+    """The ABI takes the scene arrays without lengths; the binding refuses
+    arrays shorter than the offsets say, before the library reads them."""
+    robot, scenes, consts = _small_inputs()
+    a = getattr(scenes, field)
+    setattr(scenes, field, a[:-cut])
+    with pytest.raises(gal.GalError) as ei:
+        gal.Batch(robot, scenes, consts, stream=0)
+    assert field in str(ei.value)

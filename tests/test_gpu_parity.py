@@ -140,11 +140,14 @@ def test_mixed_resolutions_and_empty_scene(torch_cuda):
     cfg = sg.scaled_config(2, 9, tri_target=(2000.0, 6000.0))
     scenes = sg.make_scene_set(cfg)
     scenes.res[:] = [64, 128, 256, 256, 64, 128, 256, 64, 128]
-    # env 3: drop every triangle
+    # env 3: drop every triangle (and its face-plane rows, so that every other
+    # env keeps the planes of its own triangles)
     t0, t1 = int(scenes.tri_offset[3]), int(scenes.tri_offset[4])
     scenes.tris = np.concatenate([scenes.tris[:t0], scenes.tris[t1:]])
     scenes.tri_rgb = np.concatenate([scenes.tri_rgb[:t0], scenes.tri_rgb[t1:]])
+    scenes.tri_plane = np.concatenate([scenes.tri_plane[:t0], scenes.tri_plane[t1:]])
     scenes.tri_offset[4:] -= (t1 - t0)
+    assert_triangles_on_their_planes(scenes)
     from oracle import oracle as O
     from paper_2306_07552_amd import gal
     robot = sg.make_robot_for(cfg)
@@ -159,6 +162,45 @@ def test_mixed_resolutions_and_empty_scene(torch_cuda):
         oout = ob.step(a)
         compare_step(b, ob, out, oout, label=f"step {k}")
     assert (b.env_depth(u32(out["depth"]), 3) == 0xFFFFFF).all()
+
+
+def assert_triangles_on_their_planes(scenes):
+    """Every triangle's vertices lie on its face plane (|n . v - w| small),
+    and its winding agrees with the plane's outward normal."""
+    for e in range(scenes.num_envs):
+        v, t, _ = scenes.env_mesh(e)
+        pl = scenes.env_planes(e).astype(np.float64)
+        if t.shape[0] == 0:
+            continue
+        P = v.astype(np.float64)[t]                                # [T][3][3]
+        dist = np.einsum("tkc,tc->tk", P, pl[:, :3]) - pl[:, 3:4]
+        assert np.max(np.abs(dist)) < 1e-4, f"env {e}: triangle off its plane"
+        nrm = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+        assert np.all(np.einsum("tc,tc->t", nrm, pl[:, :3]) > 0), f"env {e}: winding"
+
+
+def test_without_face_planes(torch_cuda):
+    """Scenes given without face planes (tri_plane NULL): back faces are
+    culled by the winding of the snapped vertices alone, on both sides."""
+    torch = torch_cuda
+    print("case: tri_plane NULL", flush=True)
+    cfg = sg.scaled_config(2, 8, tri_target=(5000.0, 40000.0))
+    scenes = sg.make_scene_set(cfg)
+    scenes.tri_plane = None
+    from oracle import oracle as O
+    from paper_2306_07552_amd import gal
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    b = gal.Batch(robot, scenes, consts)
+    ob = O.OracleBatch(robot, scenes, consts)
+    for tuning in (dict(), dict(persistent=1, split=3, order=1, region=64, lane_max=8)):
+        b.set_tuning(**tuning)
+        out = b.alloc_outputs()
+        for k in range(3):
+            a = sg.actions(cfg, k, num_envs=8)
+            b.step(torch.from_numpy(a).cuda(), out)
+            torch.cuda.synchronize()
+            compare_step(b, ob, out, ob.step(a), label=f"{tuning} step {k}")
 
 
 def test_repeatable(torch_cuda):
@@ -253,8 +295,8 @@ def test_graph_replay_matches_eager(torch_cuda):
     """The step captured as a hipGraph and replayed gives the same bits as the
     eagerly launched step, replay after replay, with eager work and
     synchronisations in between (actions refilled in place).  Both run the
-    persistent queue in measured order, whose sort runs on a second stream
-    (a forked branch of the graph)."""
+    persistent queue in measured order (the queue is ordered by an extra
+    workgroup of the robot-step launch, inside the graph)."""
     torch = torch_cuda
     print("case: graph replay vs eager", flush=True)
     cfg = sg.scaled_config(1, 24)
