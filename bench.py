@@ -21,6 +21,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12          # 39.32
+# forward flops of one surrogate query: 2112 -> 256 -> 256 -> 256 -> 256 -> 1
+SURROGATE_FLOP_PER_ROW = 2 * (2112 * 256 + 3 * 256 * 256 + 256)
 
 
 def log(msg):
@@ -32,10 +35,12 @@ def log(msg):
 TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split")
 
 
-def measured_traffic(kernel_sources, record, tuning):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE records
-    (one per launch configuration), or None when the kernel source changed
-    since the counters were taken or no record has this configuration."""
+def counter_record(kernel_sources, record, tuning, field):
+    """One per-launch figure (HBM bytes from FETCH_SIZE / WRITE_SIZE, VALU
+    instructions from SQ_INSTS_VALU) from a committed rocprofv3 counter
+    record of the launch configuration being timed, or None when the kernel
+    source changed since the counters were taken or no record has this
+    configuration."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -46,17 +51,27 @@ def measured_traffic(kernel_sources, record, tuning):
     if rec.get("source_sha256") != h:
         return None
     for r in rec["records"]:
-        if all(r["tuning"].get(k) == tuning.get(k) for k in TRAFFIC_KEYS):
-            return r["traffic_bytes_per_launch"]
+        if field in r and all(r["tuning"].get(k) == tuning.get(k) for k in TRAFFIC_KEYS):
+            return r[field]
     return None
 
 
-def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
-    """The CPU oracle, as is, on a bounded sample of the same workload."""
+def host_threads():
+    """Threads the CPU baseline may use: the cores this process may run on,
+    at most 16 (the host share of one GPU on a shared box)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail)), avail
+
+
+def cpu_rate(cfg, robot, scenes, consts, threads, seconds, sample_envs):
+    """Env-steps/s of the CPU oracle, as is, stepping `sample_envs` envs of the
+    workload (one oracle batch per env) on `threads` threads for ~`seconds`."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_2306_07552_amd import scenegen as sg
-    threads = max(1, min(16, os.cpu_count() or 1))
     envs = list(range(min(sample_envs, scenes.num_envs)))
     with ThreadPoolExecutor(threads) as ex:
         obs = list(ex.map(lambda e: O.OracleBatch(robot, scenes, consts, envs=[e],
@@ -71,8 +86,19 @@ def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
             done += len(envs)
             k += 1
     dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"{len(envs)} envs of the same workload x {k} steps ({dt:.1f} s)")
+    return done / dt, len(envs), k, dt
+
+
+def cpu_baseline(cfg, robot, scenes, consts, seconds=10.0, sample_envs=32):
+    """The CPU oracle, as is, on a bounded sample of the same workload: on
+    every core it may use (capped at 16), and on one thread."""
+    threads, avail = host_threads()
+    v, n, k, dt = cpu_rate(cfg, robot, scenes, consts, threads, seconds, sample_envs)
+    v1, n1, k1, dt1 = cpu_rate(cfg, robot, scenes, consts, 1, seconds / 2, min(sample_envs, 8))
+    return dict(value=round(v, 1), unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"{n} envs of the same workload x {k} steps ({dt:.1f} s) on {threads} threads",
+                nproc=os.cpu_count(), affinity_cores=avail,
+                one_thread=dict(value=round(v1, 1), sample=f"{n1} envs x {k1} steps ({dt1:.1f} s)"))
 
 
 def train_surrogate(cfg, robot, consts, n_train_envs=2048):
@@ -194,19 +220,20 @@ def main():
     pass_ms = {}
 
     def kernel_times():
-        """Per-kernel durations over a profiled pass (HIP events on the step stream):
-        everything before the raster kernel, and the raster kernel."""
+        """Per-stage durations over a profiled pass (HIP events on the step stream):
+        the surrogate's kernels, the robot step and the raster kernel."""
         b.profile(True)
         run(args.warmup, args.steps)
         torch.cuda.synchronize()
         b.profile(False)
-        pre_ms, raster_ms, nsteps = b.profile_read()
-        return pre_ms / nsteps, raster_ms / nsteps
+        sur_ms, robot_ms, raster_ms, nsteps = b.profile_read_stages()
+        return sur_ms / nsteps, robot_ms / nsteps, raster_ms / nsteps
 
-    def path_record(ms, tuning, pre, raster):
+    def path_record(ms, tuning, sur_ms, robot_ms, raster):
         return {"value": round(N * args.steps / (ms / 1e3), 1),
                 "ms_per_step": round(ms / args.steps, 4), "tuning": tuning,
-                "pre_raster_ms": round(pre, 5), "raster_ms": round(raster, 5)}
+                "surrogate_ms": round(sur_ms, 5), "robot_ms": round(robot_ms, 5),
+                "pre_raster_ms": round(sur_ms + robot_ms, 5), "raster_ms": round(raster, 5)}
 
     # ---- plain step
     plain_ms = timed_pass("plain")
@@ -222,8 +249,8 @@ def main():
         log(f"autotuned {best} ({best_ms:.4f} ms/step in the tuner)")
     b.set_tuning(graph=1)
     batched_ms = timed_pass("batched")
-    pre_k, raster_k = kernel_times()
-    batched = path_record(batched_ms, b.get_tuning(), pre_k, raster_k)
+    sur_k, robot_k, raster_k = kernel_times()
+    batched = path_record(batched_ms, b.get_tuning(), sur_k, robot_k, raster_k)
 
     # ---- batched + surrogate
     sur = None
@@ -238,8 +265,8 @@ def main():
         b.surrogate_stats(reset=True)
         sur_ms = timed_pass("batched+surrogate")
         st = b.surrogate_stats(reset=True)
-        pre_s, raster_s = kernel_times()
-        sur = path_record(sur_ms, b.get_tuning(), pre_s, raster_s)
+        sur_s, robot_s, raster_s = kernel_times()
+        sur = path_record(sur_ms, b.get_tuning(), sur_s, robot_s, raster_s)
         sur.update(skip_below=skip_below, calibration=info,
                    stats_timed_region=st,
                    skipped_fraction=round(st["skipped"] / max(st["queries"], 1), 4),
@@ -249,20 +276,53 @@ def main():
 
     value = N * args.steps / (headline_ms / 1e3)
     raster_head = sur["raster_ms"] if sur else raster_k
+    tuning = b.get_tuning()
     mi = b.mesh_info()
-    raster_bytes = (mi["clusters"] * 48 + mi["cluster_verts"] * 12 + mi["tris"] * 4
-                    + (7 if cfg.color else 4) * b.depth_pixels)   # depth u32 (+ rgb8)
+    # algorithmic bytes of one raster launch (what a rasteriser without a
+    # culling hierarchy reads and writes): 12 B per triangle (3 indices) and
+    # per scene vertex (3 floats), 4 B per depth pixel (+ 3 B of colour)
+    tris = int(scenes.tri_offset[-1])
+    verts = int(scenes.vert_offset[-1])
+    raster_bytes = 12 * tris + 12 * verts + (7 if cfg.color else 4) * b.depth_pixels
     achieved = raster_bytes / (raster_head / 1e3) / 1e9
-    traffic = None
+    kernel = "k_raster_persistent" if tuning["persistent"] else "k_raster"
+    traffic = valu = None
     if args.config == 1 and not cfg.color:
-        traffic = measured_traffic(["paper_2306_07552_amd/csrc/k_raster.hip",
-                                    "paper_2306_07552_amd/csrc/gal_internal.h"],
-                                   "k_raster_1024env_128px_traffic.json", b.get_tuning())
+        srcs = ["paper_2306_07552_amd/csrc/k_raster.hip", "paper_2306_07552_amd/csrc/gal_internal.h"]
+        traffic = counter_record(srcs, "k_raster_1024env_128px_traffic.json", tuning,
+                                 "traffic_bytes_per_launch")
+        valu = counter_record(srcs, "k_raster_1024env_128px_sq.json", tuning,
+                              "sq_insts_valu_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ("k_raster_persistent" if b.get_tuning()["persistent"] else "k_raster"),
-                "algorithmic_bytes_per_launch": int(raster_bytes),
-                "avg_launch_ms": round(raster_head, 5)}
+                "kernel": kernel, "algorithmic_bytes_per_launch": int(raster_bytes),
+                "algorithmic_bytes": "12 B x triangles + 12 B x scene vertices + "
+                                     + ("7" if cfg.color else "4") + " B x pixels",
+                "avg_launch_ms": round(raster_head, 5),
+                "culled_traffic_frac": (round(traffic / raster_bytes, 4) if traffic else None),
+                "mesh": mi}
+    # issue-rate bound: one wave64 VALU instruction per CU per clock
+    # (4 SIMDs x 16 lanes), 256 CUs at 2.4 GHz = 39.3 T lane-ops/s
+    alu_peak = VALU_PEAK_TOPS
+    if valu:
+        alu_ach = valu * 64 / (raster_head / 1e3) / 1e12
+        roofline["alu"] = {"achieved": round(alu_ach, 2), "peak": alu_peak,
+                           "unit": "T VALU lane-ops/s", "frac": round(alu_ach / alu_peak, 4),
+                           "sq_insts_valu_per_launch": valu}
+    else:
+        roofline["alu"] = None
+    if roofline["alu"] and roofline["alu"]["frac"] > roofline["frac"]:
+        roofline["binding"] = "alu"
+    else:
+        roofline["binding"] = "hbm"
+    if sur:
+        flop = N * SURROGATE_FLOP_PER_ROW
+        roofline["surrogate"] = {
+            "bound": "mfma", "kernels": "features + MLP inference + routing",
+            "flop_per_step": flop, "stage_ms": sur["surrogate_ms"],
+            "achieved": round(flop / (sur["surrogate_ms"] / 1e3) / 1e12, 2),
+            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(flop / (sur["surrogate_ms"] / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 5)}
 
     cpu = None
     if not args.no_cpu_baseline:

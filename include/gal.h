@@ -331,6 +331,11 @@ int gal_get_grid(gal_batch *b, int32_t env, int32_t cls, uint32_t *offsets_host,
  */
 int gal_profile_enable(gal_batch *b, int on);
 int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps);
+/* The same record split three ways (Appendix F's physics / rendering split,
+ * with the learned pre-filter of this build apart): stage_ms_host[0] = the
+ * surrogate's kernels (0 when none is attached), [1] = the robot step, [2] =
+ * the raster; count must be 3.  Reading clears the record, as above. */
+int gal_profile_read_stages(gal_batch *b, double *stage_ms_host, size_t count, int64_t *steps);
 
 /*
  * On-device work counters of the raster kernel (the rendering phase of

@@ -21,6 +21,10 @@ static_assert(GAL_MAX_PLANES == gal::kMaxPlanes, "plane table bound of the ABI a
 
 namespace {
 
+// events of one profiled step: before the surrogate, before the robot step,
+// before the raster, after the raster
+constexpr int kProfileEvents = 4;
+
 thread_local std::string g_last_error;
 
 int fail(int code, const char *fmt, ...)
@@ -1022,18 +1026,19 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         sb.skip_flags = b->d_flags;
         sb.sur_stats = b->d_sur_stats;
     }
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     // the raster queue order (from the previous step's item times) is computed
     // by an extra workgroup of the robot launch
     const bool order_items =
         out->depth && b->rast.persistent && b->rast.order && b->num_work <= gal::kOrderCap;
     const gal::ItemOrder ord{b->d_item_cost, order_items ? b->num_work : 0, b->d_item_order};
     HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, ord, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (out->depth)
         HIP_TRY(gal::launch_raster(b->mesh, b->rast, b->sb.camera, b->d_res, b->d_depth_off, b->d_work,
                                    b->num_work, b->max_res, b->d_queue, b->persist_grid, out->depth,
                                    out->rgb, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return GAL_OK;
 }
 
@@ -1083,11 +1088,11 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
         return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
     hipStream_t s = (hipStream_t)stream;
     if (b->profiling) {
-        hipEvent_t ev[3];
-        for (int i = 0; i < 3; ++i)
+        hipEvent_t ev[kProfileEvents];
+        for (int i = 0; i < kProfileEvents; ++i)
             if (!(ev[i] = b->take_event())) return fail(GAL_EDEVICE, "hipEventCreate failed");
         int rc = enqueue_step(b, actions_dev, out, s, ev);
-        b->ev_rec.insert(b->ev_rec.end(), ev, ev + 3);
+        b->ev_rec.insert(b->ev_rec.end(), ev, ev + kProfileEvents);
         return rc;
     }
     if (b->use_graph) return graph_step(b, actions_dev, out, s);
@@ -1101,25 +1106,36 @@ int gal_profile_enable(gal_batch *b, int on)
     return GAL_OK;
 }
 
-int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps)
+int gal_profile_read_stages(gal_batch *b, double *stage_ms, size_t count, int64_t *steps)
 {
-    if (!b) return fail(GAL_EINVAL, "null batch");
-    double r0 = 0.0, r1 = 0.0;
-    const size_t n = b->ev_rec.size() / 3;
+    if (!b || (count && !stage_ms)) return fail(GAL_EINVAL, "null argument");
+    if (count != 3) return fail(GAL_EINVAL, "need 3 stage times");
+    double acc[3] = {0.0, 0.0, 0.0};
+    const size_t n = b->ev_rec.size() / kProfileEvents;
     for (size_t i = 0; i < n; ++i) {
-        hipEvent_t *e = &b->ev_rec[3 * i];
-        HIP_TRY(hipEventSynchronize(e[2]));
-        float a = 0.f, c = 0.f;
-        HIP_TRY(hipEventElapsedTime(&a, e[0], e[1]));
-        HIP_TRY(hipEventElapsedTime(&c, e[1], e[2]));
-        r0 += a;
-        r1 += c;
+        hipEvent_t *e = &b->ev_rec[kProfileEvents * i];
+        HIP_TRY(hipEventSynchronize(e[kProfileEvents - 1]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+            acc[k] += ms;
+        }
     }
     b->ev_pool.insert(b->ev_pool.end(), b->ev_rec.begin(), b->ev_rec.end());
     b->ev_rec.clear();
-    if (robot_ms) *robot_ms = r0;
-    if (raster_ms) *raster_ms = r1;
+    for (int k = 0; k < 3; ++k) stage_ms[k] = acc[k];
     if (steps) *steps = (int64_t)n;
+    return GAL_OK;
+}
+
+int gal_profile_read(gal_batch *b, double *robot_ms, double *raster_ms, int64_t *steps)
+{
+    if (!b) return fail(GAL_EINVAL, "null batch");
+    double st[3];
+    const int rc = gal_profile_read_stages(b, st, 3, steps);
+    if (rc) return rc;
+    if (robot_ms) *robot_ms = st[0] + st[1];
+    if (raster_ms) *raster_ms = st[2];
     return GAL_OK;
 }
 

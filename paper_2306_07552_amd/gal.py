@@ -91,6 +91,7 @@ def load_library():
         L.gal_profile_enable.argtypes = [C.c_void_p, C.c_int]
         L.gal_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        _i64p]
+        L.gal_profile_read_stages.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_size_t, _i64p]
         L.gal_mesh_info.argtypes = [C.c_void_p, _i64p, _i64p, _i64p]
         L.gal_counters_enable.argtypes = [C.c_void_p, C.c_int]
         L.gal_counters_read.argtypes = [C.c_void_p, _i64p, C.c_size_t]
@@ -382,6 +383,13 @@ class Batch:
         a, b, n = C.c_double(), C.c_double(), C.c_int64()
         _check(load_library().gal_profile_read(self._h, C.byref(a), C.byref(b), C.byref(n)))
         return a.value, b.value, n.value
+
+    def profile_read_stages(self):
+        """(surrogate ms, robot-step ms, raster ms, steps) summed over the recorded steps."""
+        v = (C.c_double * 3)()
+        n = C.c_int64()
+        _check(load_library().gal_profile_read_stages(self._h, v, 3, C.byref(n)))
+        return v[0], v[1], v[2], n.value
 
     def mesh_info(self):
         c, v, t = C.c_int64(), C.c_int64(), C.c_int64()
