@@ -134,6 +134,10 @@ def main():
                     help="JSON list of gal_tuning dicts: run --steps untimed steps with each (after "
                          "--warmup) and exit; for counter runs (rocprofv3 --pmc) over several "
                          "launch configurations in one process, raster dispatches in list order")
+    ap.add_argument("--sweep-surrogate", action="store_true",
+                    help="with --sweep-tunings: attach an untrained surrogate that skips nothing")
+    ap.add_argument("--work-counters", action="store_true",
+                    help="with --sweep-tunings: print the raster's on-device work counters per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the step shards by "
@@ -188,12 +192,25 @@ def main():
 
     if args.sweep_tunings:
         sweep = json.loads(args.sweep_tunings)
+        if args.sweep_surrogate:
+            # an untrained network that skips nothing: the inference kernel's
+            # cost does not depend on the weights
+            mlp = gal.Mlp(max_rows=N, seed=1)
+            b.attach_surrogate(mlp, 0.0, audit_period=0)
+        counts = []
         for tun in sweep:
             b.set_tuning(**tun)
+            if args.work_counters:
+                b.counters(True)
             run(0, args.warmup + args.steps)
             torch.cuda.synchronize()
+            if args.work_counters:
+                c = b.counters_read()
+                b.counters(False)
+                counts.append({k: v / (args.warmup + args.steps) for k, v in c.items()})
         print(json.dumps({"sweep": [b_t for b_t in sweep], "warmup": args.warmup,
-                          "steps": args.steps}), flush=True)
+                          "steps": args.steps, "surrogate": bool(args.sweep_surrogate),
+                          "work_counters_per_step": counts or None}), flush=True)
         return
 
     def timed_pass(label):

@@ -398,9 +398,12 @@ int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count);
 int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
 /* Surrogate of the Section 3.2 static-scene test (not in the paper).
  * Logits (device f32 [rows]) of x_dev (device BF16 bits, u16 [rows][2112],
- * 16-byte aligned rows).  The inference kernels (split-K first layer, fused
- * layers 2..4 and head) accumulate the first layer in 11 partial sums, so
- * logits can differ from the training forward pass in the last bits. */
+ * 16-byte aligned rows).  Up to 8192 rows, the first layer's
+ * sum over the 2112 inputs is split over 2, 4 or 8 workgroups per 32 rows
+ * whose FP32 partial sums are added in a fixed order, so logits depend on
+ * the row count in the last bits and can differ from the training forward
+ * pass in the last bits; they are reproducible for a given row count.  The
+ * partial sums live in the MLP object: calls on one MLP must not overlap. */
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
 /* Surrogate of the Section 3.2 static-scene test (not in the paper).
  * Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
@@ -442,6 +445,12 @@ int gal_features(gal_batch *b, const float *actions_dev, uint16_t *x_dev, void *
  */
 int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t audit_period,
                          void *stream);
+/* Surrogate of the Section 3.2 static-scene test (not in the paper).
+ * The attached MLP's logits (device f32 [N]) for every env's next move under
+ * actions_dev, from the features gal_features would write, computed inside
+ * the inference launch the step uses (no routing, no counts).
+ * GAL_EINVAL when no surrogate is attached. */
+int gal_surrogate_logits(gal_batch *b, const float *actions_dev, float *logits_dev, void *stream);
 /* Surrogate of the Section 3.2 static-scene test (not in the paper).
  * Detach restores the exact test for every env. */
 int gal_surrogate_detach(gal_batch *b);

@@ -203,7 +203,6 @@ int api_fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
-int mlp_infer_rows(gal_mlp *m, const uint16_t *x, int rows, const RouteArgs *route, hipStream_t s);
 int mlp_max_rows(const gal_mlp *m);
 }  // namespace gal
 
@@ -235,7 +234,6 @@ struct gal_batch {
     gal_mlp *sur = nullptr;
     float sur_thr_logit = 0.0f;
     uint32_t sur_audit = 16;
-    uint16_t *d_feat = nullptr;             // [N][2112] BF16 inputs of the step's queries
     uint8_t *d_flags = nullptr;             // [N] routing
     unsigned long long *d_sur_stats = nullptr;
     uint8_t *d_occ = nullptr;               // occupancy lattice (built on first use)
@@ -1002,6 +1000,18 @@ int ensure_occupancy(gal_batch *b, hipStream_t s)
     return GAL_OK;
 }
 
+// The feature source of the fused surrogate inference: every env of the
+// batch, its next move under actions_dev.
+gal::SurInferArgs batch_features(const gal_batch *b, const float *actions_dev)
+{
+    gal::SurInferArgs a{};
+    a.rp = b->rp;
+    a.sb = b->sb;
+    a.og = occ_grid(b);
+    a.actions = actions_dev;
+    return a;
+}
+
 // Enqueue one step (robot kernel, then raster) on stream s.
 int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, hipStream_t s,
                  hipEvent_t *ev)
@@ -1017,11 +1027,12 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     gal::SimBuffers sb = b->sb;
     if (b->sur) {
-        // surrogate pre-filter: features -> MLP -> routing flags for the robot kernel
-        HIP_TRY(gal::launch_features(b->rp, b->sb, occ_grid(b), actions_dev, b->d_feat, s));
+        // surrogate pre-filter: features -> MLP -> routing flags for the robot
+        // kernel, one launch
         const gal::RouteArgs ra{b->sb.counters, b->sur_thr_logit, b->sur_audit, b->d_flags,
                                 b->d_sur_stats, 0};
-        int rc = gal::mlp_infer_rows(b->sur, b->d_feat, b->N, &ra, s);
+        const gal::SurInferArgs src = batch_features(b, actions_dev);
+        int rc = gal::mlp_infer_rows(b->sur, nullptr, &src, b->N, nullptr, &ra, s);
         if (rc) return rc;
         sb.skip_flags = b->d_flags;
         sb.sur_stats = b->d_sur_stats;
@@ -1187,11 +1198,9 @@ int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t au
     hipStream_t s = (hipStream_t)stream;
     int rc = ensure_occupancy(b, s);
     if (rc) return rc;
-    if (!b->d_feat) {
-        if ((rc = b->mem.alloc(&b->d_feat, (size_t)b->N * gal::kMlpIn)) ||
-            (rc = b->mem.alloc(&b->d_flags, (size_t)b->N)) || (rc = b->mem.alloc(&b->d_sur_stats, 4)))
+    if (!b->d_flags) {
+        if ((rc = b->mem.alloc(&b->d_flags, (size_t)b->N)) || (rc = b->mem.alloc(&b->d_sur_stats, 4)))
             return rc;
-        HIP_TRY(hipMemset(b->d_feat, 0, sizeof(uint16_t) * (size_t)b->N * gal::kMlpIn));
         HIP_TRY(hipMemset(b->d_sur_stats, 0, sizeof(unsigned long long) * 4));
     }
     b->sur = m;
@@ -1200,6 +1209,14 @@ int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t au
     b->sur_audit = audit_period;
     b->tune_gen += 1;   // the captured graph changes
     return GAL_OK;
+}
+
+int gal_surrogate_logits(gal_batch *b, const float *actions_dev, float *logits_dev, void *stream)
+{
+    if (!b || !actions_dev || !logits_dev) return fail(GAL_EINVAL, "null argument");
+    if (!b->sur) return fail(GAL_EINVAL, "no surrogate is attached to the batch");
+    const gal::SurInferArgs src = batch_features(b, actions_dev);
+    return gal::mlp_infer_rows(b->sur, nullptr, &src, b->N, logits_dev, nullptr, (hipStream_t)stream);
 }
 
 int gal_surrogate_detach(gal_batch *b)

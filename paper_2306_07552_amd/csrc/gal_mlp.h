@@ -6,6 +6,8 @@
 
 #include "gal_internal.h"
 
+struct gal_mlp;
+
 namespace gal {
 
 constexpr int kMlpIn = 2112;       // 44 scalars, 20 zeros, 16 x 16 x 8 occupancy patch
@@ -90,12 +92,37 @@ struct MlpTail {
     const uint16_t *w[4];
     const float *b[4];
 };
-// Logits of rows inputs x (BF16 [rows][2112]) into z [rows]; with route, also
-// the routing flags and counts of envs route->base .. route->base + rows - 1.
-// part: FP32 workspace of mlp_infer_workspace_floats() values.
-size_t mlp_infer_workspace_floats();
-hipError_t mlp_infer(const uint16_t *x, int rows, const MlpTail &t, float *part, float *z,
-                     const RouteArgs *route, hipStream_t s);
+// Inference (inputs -> logits -> routing; one launch for large batches, two
+// otherwise).  The inputs are x (BF16 [rows][2112]) or, with x null,
+// computed on the fly for envs 0 .. rows - 1 of the batch (rp, sb, og,
+// actions) exactly as k_features would write them.  Scratch: part
+// (sur_infer_part_floats(rows) FP32 values, the first layer's partial sums);
+// launches that share it must not overlap.
+struct SurInferArgs {
+    MlpTail t;
+    const uint16_t *x;
+    RobotParams rp;
+    SimBuffers sb;
+    OccGrid og;
+    const float *actions;
+    int rows;
+    int splits;            // chosen by sur_infer
+    float *part;
+    float *z;              // [rows] logits, or null
+    RouteArgs ra;
+    int route;             // 1 = write routing flags and counts (ra)
+};
+int sur_infer_splits(int rows);
+size_t sur_infer_part_floats(int rows);
+// The scratch that covers every row count up to max_rows (splits are chosen
+// so that tiles x splits <= 512 whenever partial sums are used, so never more
+// than 512 slabs of 32 x 256 FP32 values = 16 MiB).
+size_t sur_infer_part_floats_max(int max_rows);
+hipError_t sur_infer(const SurInferArgs &args, hipStream_t s);
+
+// Inference of the MLP m (gal_mlp_api.cpp); part null = the MLP's own scratch.
+int mlp_infer_rows(gal_mlp *m, const uint16_t *x, const SurInferArgs *src, int rows, float *z,
+                   const RouteArgs *route, hipStream_t s, float *part = nullptr);
 
 
 }  // namespace gal

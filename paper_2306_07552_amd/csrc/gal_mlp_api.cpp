@@ -40,7 +40,7 @@ struct gal_mlp {
     uint16_t *h[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // h[1..4]
     uint16_t *dp[2] = {nullptr, nullptr};
     float *z = nullptr, *dz = nullptr, *loss = nullptr;
-    float *part = nullptr;   // split-K partial sums of inference
+    float *part = nullptr;      // inference: the first layer's partial sums
     float *dw_part = nullptr;   // split-K partial sums of the weight gradients
     size_t dw_part_floats = 0;
     int64_t t = 0;
@@ -92,7 +92,7 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out)
         (rc = m->alloc(&m->dp[0], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->dp[1], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->z, max_rows)) || (rc = m->alloc(&m->dz, max_rows)) ||
-        (rc = m->alloc(&m->part, gal::mlp_infer_workspace_floats())) ||
+        (rc = m->alloc(&m->part, gal::sur_infer_part_floats_max(max_rows))) ||
         (rc = m->alloc(&m->dw_part, (m->dw_part_floats = (size_t)gal::kMaxDwSplits * kDims[1] * kDims[0]))) ||
         (rc = m->alloc(&m->loss, 1))) {
         delete m;
@@ -162,18 +162,26 @@ int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s)
     return GAL_OK;
 }
 
-// inference: split-K first layer, then the fused layers 2..4, head and
-// (optional) routing; logits into m->z
-int mlp_infer_rows(gal_mlp *m, const uint16_t *x, int rows, const RouteArgs *route, hipStream_t s)
+// inference: the inputs x, or (x null) the features of the batch envs
+// described by `src` computed on the fly; logits into z (may be null),
+// routing flags and counts with route
+int mlp_infer_rows(gal_mlp *m, const uint16_t *x, const SurInferArgs *src, int rows, float *z,
+                   const RouteArgs *route, hipStream_t s, float *part)
 {
-    MlpTail t;
-    t.w0 = m->wb + m->off_w[0];
-    t.b0 = m->w + m->off_b[0];
+    SurInferArgs a = src ? *src : SurInferArgs{};
+    a.t.w0 = m->wb + m->off_w[0];
+    a.t.b0 = m->w + m->off_b[0];
     for (int l = 0; l < 4; ++l) {
-        t.w[l] = m->wb + m->off_w[l + 1];
-        t.b[l] = m->w + m->off_b[l + 1];
+        a.t.w[l] = m->wb + m->off_w[l + 1];
+        a.t.b[l] = m->w + m->off_b[l + 1];
     }
-    MLP_TRY(mlp_infer(x, rows, t, m->part, m->z, route, s));
+    a.x = x;
+    a.rows = rows;
+    a.part = part ? part : m->part;
+    a.z = z;
+    a.route = route ? 1 : 0;
+    if (route) a.ra = *route;
+    MLP_TRY(sur_infer(a, s));
     return GAL_OK;
 }
 
@@ -213,11 +221,7 @@ int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logi
     if (!m || !x_dev || rows < 0 || rows > m->max_rows) return gal::api_fail(GAL_EINVAL, "bad arguments");
     if ((uintptr_t)x_dev % 16) return gal::api_fail(GAL_EINVAL, "x_dev must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    int rc = gal::mlp_infer_rows(m, x_dev, rows, nullptr, s);
-    if (rc) return rc;
-    if (logits_dev && rows > 0)
-        MLP_TRY(hipMemcpyAsync(logits_dev, m->z, sizeof(float) * rows, hipMemcpyDeviceToDevice, s));
-    return GAL_OK;
+    return gal::mlp_infer_rows(m, x_dev, nullptr, rows, logits_dev ? logits_dev : m->z, nullptr, s);
 }
 
 int gal_mlp_gradients(gal_mlp *m, const uint16_t *x_dev, const float *labels_dev, int32_t rows,

@@ -248,193 +248,6 @@ __global__ void k_to_bf16(const float *__restrict__ a, int64_t n, uint16_t *__re
     if (i < n) out[i] = f2bf(a[i]);
 }
 
-// Inference.  Layer 1 (K = 2112) runs split-K: workgroup (n tile, m tile,
-// split) computes a 64 x 64 FP32 partial product over 6 K steps of 32, each
-// wave 16 rows x 64 columns from fragments loaded straight from memory into
-// registers (all 30 of them before the first MFMA, so the loads overlap);
-// 704 workgroups for 1024 rows keep every CU busy where a 64 x 64 tiling
-// over the whole K would launch 64.
-constexpr int kL0Splits = 11;      // 2112 = 11 x 192
-constexpr int kL0SplitK = 192;
-constexpr int kInferChunk = 2048;  // rows per split-K pass (bounds the partial buffer)
-
-__global__ __launch_bounds__(256) void k_l0_part(const uint16_t *__restrict__ x, int rows,
-                                                 const uint16_t *__restrict__ w0, float *__restrict__ part)
-{
-    constexpr int K = kMlpIn, D = kMlpHidden, kSteps = kL0SplitK / 32;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64 + wave * 16, sp = blockIdx.z;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    const int m = m0 + r16;
-    const int kb = sp * kL0SplitK + kq;
-    bf16x8 af[kSteps], bfr[kSteps][4];
-#pragma unroll
-    for (int st = 0; st < kSteps; ++st) {
-        if (m < rows) af[st] = *reinterpret_cast<const bf16x8 *>(x + (size_t)m * K + kb + 32 * st);
-        else af[st] = bf16x8{};
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bfr[st][j] = *reinterpret_cast<const bf16x8 *>(w0 + (size_t)(n0 + 16 * j + r16) * K + kb + 32 * st);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    floatx4 acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int st = 0; st < kSteps; ++st)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[st], bfr[st][j], acc[j], 0, 0, 0);
-    float *out = part + (size_t)sp * rows * D;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int mm = m0 + (lane >> 4) * 4 + r;
-            if (mm < rows) out[(size_t)mm * D + n0 + 16 * j + r16] = acc[j][r];
-        }
-}
-
-// Hidden layers 2..4 + head (+ routing) for 16 rows per workgroup, starting
-// from layer 1's split-K partials.  The rows' activations stay in LDS between
-// layers; each of the 8 waves owns 32 output columns (2 MFMA 16x16 tiles) and
-// issues all of its weight-fragment loads for the layer (K = 256: 8 steps x 2
-// tiles of 16 bytes per lane) before the first MFMA, so that a CU has twice
-// the loads in flight of a 4-wave layout.  The head sums in k_head_fwd's
-// order.
-constexpr int kTailRows = 16;
-constexpr int kTailThreads = 512;
-constexpr int kTailWaves = kTailThreads / 64;
-constexpr int kTailCols = kMlpHidden / kTailWaves;   // output columns per wave
-constexpr int kTailTiles = kTailCols / 16;
-constexpr int kActPad = 8;
-
-__global__ __launch_bounds__(kTailThreads, 1) void k_mlp_tail(const float *__restrict__ part, int rows,
-                                                              MlpTail t, float *__restrict__ z,
-                                                              RouteArgs ra, int route)
-{
-    constexpr int D = kMlpHidden;
-    __shared__ __attribute__((aligned(16))) uint16_t act[2][kTailRows][D + kActPad];
-    __shared__ float zs[kTailRows];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * kTailRows;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    // a layer's weight fragments for this wave: K = 256 in 8 steps x kTailTiles tiles
-    auto load_w = [&](const uint16_t *W, bf16x8 (&f)[D / 32][kTailTiles]) {
-#pragma unroll
-        for (int st = 0; st < D / 32; ++st)
-#pragma unroll
-            for (int j = 0; j < kTailTiles; ++j)
-                f[st][j] = *reinterpret_cast<const bf16x8 *>(
-                    W + (size_t)(kTailCols * wave + 16 * j + r16) * D + 32 * st + kq);
-    };
-    // every weight, bias and head load is issued one stage ahead of its use,
-    // so the memory latencies of the layers overlap instead of adding up
-    bf16x8 fa[D / 32][kTailTiles], fb[D / 32][kTailTiles];
-    load_w(t.w[0], fa);
-    float bias[3][kTailTiles];
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int j = 0; j < kTailTiles; ++j) bias[l][j] = t.b[l][kTailCols * wave + 16 * j + r16];
-    uint16_t hw[D / 64];
-#pragma unroll
-    for (int k = 0; k < D / 64; ++k) hw[k] = t.w[3][lane + 64 * k];
-    // first hidden layer: the split-K partial sums in split order, + bias,
-    // ReLU, BF16; a thread takes 4 adjacent columns of 2 rows, all 2 x 11
-    // partial loads in flight at once
-    {
-        constexpr int kRowsPerPass = kTailThreads / (D / 4);   // 8
-        const int c = (threadIdx.x % (D / 4)) * 4, rq = threadIdx.x / (D / 4);
-        const float4 bb = *reinterpret_cast<const float4 *>(t.b0 + c);
-        float4 pv[kTailRows / kRowsPerPass][kL0Splits];
-#pragma unroll
-        for (int k = 0; k < kTailRows / kRowsPerPass; ++k) {
-            const int r = rq + kRowsPerPass * k;
-            const bool live = row0 + r < rows;
-#pragma unroll
-            for (int sp = 0; sp < kL0Splits; ++sp)
-                pv[k][sp] = live ? *reinterpret_cast<const float4 *>(part + ((size_t)sp * rows + row0 + r) * D + c)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int k = 0; k < kTailRows / kRowsPerPass; ++k) {
-            const int r = rq + kRowsPerPass * k;
-            float4 v = pv[k][0];
-#pragma unroll
-            for (int sp = 1; sp < kL0Splits; ++sp) {
-                v.x += pv[k][sp].x;
-                v.y += pv[k][sp].y;
-                v.z += pv[k][sp].z;
-                v.w += pv[k][sp].w;
-            }
-            const bool live = row0 + r < rows;
-            act[0][r][c + 0] = f2bf(live ? relu(v.x + bb.x) : 0.f);
-            act[0][r][c + 1] = f2bf(live ? relu(v.y + bb.y) : 0.f);
-            act[0][r][c + 2] = f2bf(live ? relu(v.z + bb.z) : 0.f);
-            act[0][r][c + 3] = f2bf(live ? relu(v.w + bb.w) : 0.f);
-        }
-    }
-    __syncthreads();
-    // one hidden layer from act[cur] into act[cur ^ 1] with weights f
-    auto layer = [&](const bf16x8 (&f)[D / 32][kTailTiles], const float (&bl)[kTailTiles], int cur) {
-        floatx4 acc[kTailTiles];
-#pragma unroll
-        for (int j = 0; j < kTailTiles; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int st = 0; st < D / 32; ++st) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[cur][r16][32 * st + kq]);
-#pragma unroll
-            for (int j = 0; j < kTailTiles; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, f[st][j], acc[j], 0, 0, 0);
-        }
-        // lane holds column n = kTailCols w + 16 j + lane % 16 of rows 4 (lane / 16) + 0..3
-#pragma unroll
-        for (int j = 0; j < kTailTiles; ++j) {
-            const int n = kTailCols * wave + 16 * j + r16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) act[cur ^ 1][(lane >> 4) * 4 + r][n] = f2bf(relu(acc[j][r] + bl[j]));
-        }
-        __syncthreads();
-    };
-    load_w(t.w[1], fb);
-    layer(fa, bias[0], 0);
-    load_w(t.w[2], fa);
-    layer(fb, bias[1], 1);
-    layer(fa, bias[2], 0);
-    const int cur = 1;
-    // head: wave w takes rows kTailRows / kTailWaves * w + 0..
-#pragma unroll
-    for (int rr = 0; rr < kTailRows / kTailWaves; ++rr) {
-        const int r = (kTailRows / kTailWaves) * wave + rr;
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < D / 64; ++k) acc += bf2f(act[cur][r][lane + 64 * k]) * bf2f(hw[k]);
-        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (lane == 0) zs[r] = acc + t.b[3][0];
-    }
-    __syncthreads();
-    if (wave == 0) {
-        const int e = row0 + lane;
-        const bool live = lane < kTailRows && e < rows;
-        int flag = 0;
-        if (live) {
-            z[e] = zs[lane];
-            if (route) {
-                flag = route_flag(ra, ra.base + e, zs[lane]);
-                ra.flags[ra.base + e] = (uint8_t)flag;
-            }
-        }
-        if (route) {
-            const uint64_t mq = __ballot(live), ms = __ballot(flag != 0), ma = __ballot(flag == 2);
-            if (lane == 0) {
-                atomicAdd(&ra.stats[0], (unsigned long long)__popcll(mq));
-                if (ms) atomicAdd(&ra.stats[1], (unsigned long long)__popcll(ms));
-                if (ma) atomicAdd(&ra.stats[2], (unsigned long long)__popcll(ma));
-            }
-        }
-    }
-}
-
 // out[i] = sum over splits of part[sp][i], in split order (deterministic)
 __global__ void k_sum_splits(const float *__restrict__ part, int splits, int64_t n, float *__restrict__ out)
 {
@@ -502,26 +315,6 @@ hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, in
     default:
         return hipErrorInvalidValue;
     }
-}
-
-size_t mlp_infer_workspace_floats() { return (size_t)kL0Splits * kInferChunk * kMlpHidden; }
-
-hipError_t mlp_infer(const uint16_t *x, int rows, const MlpTail &t, float *part, float *z,
-                     const RouteArgs *route, hipStream_t s)
-{
-    static_assert(kL0Splits * kL0SplitK == kMlpIn && kMlpHidden % 64 == 0, "layer-1 split-K tiling");
-    for (int r0 = 0; r0 < rows; r0 += kInferChunk) {
-        const int n = rows - r0 < kInferChunk ? rows - r0 : kInferChunk;
-        hipLaunchKernelGGL(k_l0_part, dim3(kMlpHidden / 64, (n + 63) / 64, kL0Splits), dim3(256), 0, s,
-                           x + (size_t)r0 * kMlpIn, n, t.w0, part);
-        RouteArgs ra = route ? *route : RouteArgs{nullptr, 0.f, 0u, nullptr, nullptr, 0};
-        ra.base += r0;
-        hipLaunchKernelGGL(k_mlp_tail, dim3((n + kTailRows - 1) / kTailRows), dim3(kTailThreads), 0, s, part, n, t,
-                           z + r0, ra, route ? 1 : 0);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 hipError_t mlp_head_fwd(const uint16_t *h, const uint16_t *w, const float *b, int rows, int D,

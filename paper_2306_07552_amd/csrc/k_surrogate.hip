@@ -15,31 +15,11 @@
 // centred on the base, so it covers the arm's reach); a patch cell is
 // blocked when any column under its rotated footprint's bounding box is, or
 // when that box leaves the grid.
-#include "gal_fk.h"
-#include "gal_math.h"
-#include "gal_mlp.h"
+#include "gal_features.h"
 
 namespace gal {
 
 namespace {
-
-__device__ __forceinline__ float clampf(float v, float lo, float hi)
-{
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
-__device__ __forceinline__ float sanitize(float a, float lim)
-{
-    if (a != a) a = 0.0f;
-    return clampf(a, -lim, lim);
-}
-
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
 
 // free-space test of one column of an env's class-0 grid at height z
 __device__ __forceinline__ bool column_free(const SimBuffers &sb, const GridMeta &gm, size_t ek,
@@ -91,85 +71,13 @@ __global__ __launch_bounds__(256) void k_features(RobotParams rp, SimBuffers sb,
     const float *a = actions + (size_t)env * 9;
     uint16_t *row = x + (size_t)env * kMlpIn;
     const GridMeta gm = sb.grid_meta[env];
-    const float a0 = sanitize(a[0], rp.act_lim[0]), a1 = sanitize(a[1], rp.act_lim[1]);
     if (t < 64) {
-        float v = 0.f;
-        if (t < 7)
-            v = clampf(st[3 + t] + sanitize(a[2 + t], rp.act_lim[2]), rp.qlim[t][0], rp.qlim[t][1]);
-        else if (t < 14) v = sanitize(a[2 + t - 7], rp.act_lim[2]) / rp.act_lim[2];
-        else if (t == 14) v = a0 / rp.act_lim[0];
-        else if (t == 15) v = a1 / rp.act_lim[1];
-        else if (t == 16) v = (st[0] - gm.x0) / ((float)gm.nx * sb.cell);
-        else if (t == 17) v = (st[1] - gm.y0) / ((float)gm.ny * sb.cell);
-        else if (t == 18) v = st[2] * 0.31830988618f;
-        else if (t == 19) v = sb.held[env] ? 1.0f : 0.0f;
-        else {
-            // arm frames of the candidate joint angles with the base at the origin:
-            // t = 20..40 origin of frame 1 + (t - 20) / 3, t = 41..43 z axis of frame 7
-            float q[10] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int j = 0; j < 7; ++j)
-                q[3 + j] = clampf(st[3 + j] + sanitize(a[2 + j], rp.act_lim[2]), rp.qlim[j][0],
-                                  rp.qlim[j][1]);
-            Fk fk;
-            forward_kinematics(rp, q, fk);
-#pragma unroll
-            for (int j = 1; j < 8; ++j)
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    if (t == 20 + 3 * (j - 1) + r) v = fk.f[j].m[4 * r + 3];
-                    if (j == 7 && t == 41 + r) v = fk.f[7].m[4 * r + 2];
-                }
-        }
-        row[t] = f2bf(v);
+        float arm[24];
+        if (t >= 20 && t < 44) arm_frame_features(rp, st, a, arm);
+        row[t] = feat_bf16(scalar_feature(rp, sb, gm, env, st, a, t, arm));
     }
-    // candidate base pose, in the robot step's own operation order
-    const float pi_f = 0x1.921fb6p+1f, two_pi_f = 0x1.921fb6p+2f;
-    float yaw = st[2] + a1;
-    if (yaw > pi_f) yaw = yaw - two_pi_f;
-    else if (yaw < -pi_f) yaw = yaw + two_pi_f;
-    float sy, cy;
-    dsincos(yaw, sy, cy);
-    const float bx = st[0] + a0 * cy, by = st[1] + a0 * sy;
-    const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
-    const uint8_t *occ = og.occ + og.occ_off[env];
-    // patch column c = t: cell (a, b), 8 layers
-    const float hx = 0.05f * (fabsf(cy) + fabsf(sy));   // half-extent of a rotated cell's box
-    const int pa = t / kPatch, pb = t % kPatch;
-    const float px = ((float)pa - 7.5f) * 0.1f, py = ((float)pb - 7.5f) * 0.1f;
-    const float wx = bx + (cy * px - sy * py), wy = by + (sy * px + cy * py);
-    const float fi0 = floorf(((wx - hx) - gm.x0) / og.occ_cell);
-    const float fi1 = floorf(((wx + hx) - gm.x0) / og.occ_cell);
-    const float fj0 = floorf(((wy - hx) - gm.y0) / og.occ_cell);
-    const float fj1 = floorf(((wy + hx) - gm.y0) / og.occ_cell);
-    uint32_t bits = 0xFFu;   // box leaves the grid: every layer blocked
-    // the box is under 3 cells wide, so at most 4 x 4 columns: a fixed 4 x 4
-    // block of loads (indices clamped into the lattice) issued together, the
-    // columns past the box masked out
-    if (fi0 >= 0.0f && fj0 >= 0.0f && fi1 < (float)ox && fj1 < (float)oy && fi1 - fi0 < 4.0f &&
-        fj1 - fj0 < 4.0f) {
-        const int i0 = (int)fi0, i1 = (int)fi1, j0 = (int)fj0, j1 = (int)fj1;
-        uint32_t v[4][4];
-#pragma unroll
-        for (int dj = 0; dj < 4; ++dj)
-#pragma unroll
-            for (int di = 0; di < 4; ++di) {
-                const int i = min(i0 + di, ox - 1), j = min(j0 + dj, oy - 1);
-                v[dj][di] = occ[(size_t)j * ox + i];
-            }
-        bits = 0;
-#pragma unroll
-        for (int dj = 0; dj < 4; ++dj)
-#pragma unroll
-            for (int di = 0; di < 4; ++di)
-                if (i0 + di <= i1 && j0 + dj <= j1) bits |= v[dj][di];
-    }
-    // layers 2k and 2k + 1 as BF16 ones or zeros in one word
-    uint32_t w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        w[k] = (((bits >> (2 * k)) & 1u) ? 0x3F80u : 0u) | ((((bits >> (2 * k + 1)) & 1u) ? 0x3F80u : 0u) << 16);
-    *reinterpret_cast<uint4 *>(row + kFeatPatchBase + t * kPatchZ) = make_uint4(w[0], w[1], w[2], w[3]);
+    const CandBase cb = cand_base(rp, st, a);
+    *reinterpret_cast<uint4 *>(row + kFeatPatchBase + t * kPatchZ) = patch_words(patch_bits(og, gm, env, cb, t));
 }
 
 }  // namespace

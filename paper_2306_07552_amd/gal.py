@@ -114,6 +114,7 @@ def load_library():
         L.gal_mlp_destroy.restype = None
         L.gal_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gal_surrogate_attach.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_uint32, C.c_void_p]
+        L.gal_surrogate_logits.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gal_surrogate_detach.argtypes = [C.c_void_p]
         L.gal_surrogate_stats.argtypes = [C.c_void_p, _i64p, C.c_int]
         L.gal_set_tuning.argtypes = [C.c_void_p, C.POINTER(GalTuning)]
@@ -342,6 +343,11 @@ class Batch:
         _check(load_library().gal_surrogate_attach(self._h, mlp._h, float(skip_below),
                                                    int(audit_period), _stream_handle(stream)))
         self._mlp = mlp   # keep it alive while attached
+
+    def surrogate_logits(self, actions, logits, stream=None):
+        """Logits (torch float32 [N]) of the attached surrogate for the next move."""
+        _check(load_library().gal_surrogate_logits(self._h, actions.data_ptr(), logits.data_ptr(),
+                                                   _stream_handle(stream)))
 
     def detach_surrogate(self):
         _check(load_library().gal_surrogate_detach(self._h))

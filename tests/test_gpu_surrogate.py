@@ -156,6 +156,46 @@ def test_features_match_cpu(torch_cuda):
     assert 0 < blocked_total < 6 * 2048, "the patches are all free or all blocked"
 
 
+@pytest.mark.parametrize("n", [6, 100, 1024])
+def test_step_inference_features_match_feature_kernel(torch_cuda, n):
+    """The step's inference launch builds the surrogate inputs of every env
+    itself (no input rows in memory).  Its logits equal, bit for bit, those of
+    the same network on the rows gal_features writes (one launch shape per
+    row count), and they lie within the derived bound of the FP64 oracle.
+    Sizes: one ragged tile, four tiles with a ragged end, and 32 tiles (the
+    headline batch, eight workgroups per tile)."""
+    torch = torch_cuda
+    print(f"case: step inference features, {n} envs", flush=True)
+    from paper_2306_07552_amd import gal
+    cfg = sg.scaled_config(1, n, tri_target=None)
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    b = gal.Batch(robot, scenes, sg.config_constants(cfg))
+    out = {k: v for k, v in b.alloc_outputs().items() if k != "depth"}
+    for k in range(3):
+        b.step(torch.from_numpy(sg.actions(cfg, k, num_envs=n) * 4).cuda(), out)
+    mlp = gal.Mlp(max_rows=max(n, 64), seed=3)
+    X = torch.empty((n, 2112), dtype=torch.int16, device="cuda")
+    a = torch.from_numpy(sg.actions(cfg, 9, num_envs=n)).cuda()
+    b.features(a, X)
+    y = torch.from_numpy((np.random.default_rng(2).uniform(size=n) < 0.3).astype(np.float32)).cuda()
+    for _ in range(2):
+        mlp.train_step(X, y, 4.0, 1e-3)
+    b.attach_surrogate(mlp, 0.01, audit_period=1)
+    z_step = torch.full((n,), np.nan, dtype=torch.float32, device="cuda")
+    z_rows = torch.full((n,), np.nan, dtype=torch.float32, device="cuda")
+    b.surrogate_logits(a, z_step)
+    mlp.forward(X, z_rows)
+    torch.cuda.synchronize()
+    assert torch.equal(z_step, z_rows)
+    w = mlp.get_weights()
+    x64 = bits_to_f64(X.cpu().numpy().view(np.uint16))
+    zo = oracle_net(w).forward(x64, round_bf16=True)
+    check_logits_elementwise(z_step.cpu().numpy().astype(np.float64), zo, w, x64,
+                             f"step inference, {n} envs")
+    b.detach_surrogate()
+
+
 def oracle_net(w):
     from oracle.oracle_mlp import OracleMLP, bf16_round_f32
     from paper_2306_07552_amd.gal import Mlp
