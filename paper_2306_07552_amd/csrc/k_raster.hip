@@ -392,14 +392,17 @@ __device__ __forceinline__ int wave_incl_max(int v, int lane)
     return max(v, row == 0 ? kMin : row == 1 ? r0 : row == 2 ? r1 : r2);
 }
 
-// Load-balanced rasterisation of every lane's triangle at once: the pixels of
-// all bboxes are numbered by a wave prefix sum and lane l takes pixels
-// l, l + 64, ...  For each window of 64 pixels, every triangle starting inside
-// it writes (first pixel, lane) at its start position in the wave's 64 LDS
-// words `own`, and a wave maximum-scan over the positions gives every pixel
-// its triangle (the last start at or before it; position 0 inherits the
-// previous window's last owner).  The triangle's record is then fetched from
-// its lane.
+// Load-balanced rasterisation of every lane's triangle at once.  Each bbox row
+// is cut into spans of 4 pixels; the spans of all bboxes are numbered by a
+// wave prefix sum and lane l takes spans l, l + 64, ...  For each window of
+// 64 spans, every triangle starting inside it writes (first span, lane) at its
+// start position in the wave's 64 LDS words `own`, and a wave maximum-scan
+// over the positions gives every span its triangle (the last start at or
+// before it; position 0 inherits the previous window's last owner).  The
+// triangle's record is then fetched from its lane once for the span's 4
+// pixels, whose edge functions step by the exact integer increments.
+constexpr int kSpan = 4;
+
 template <class Sink>
 __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, bool mine, int lane,
                                                 int rx0, int ry0, int P, int *own_generic,
@@ -410,7 +413,8 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
     lds_int *own = (lds_int *)own_generic;
     const int w = mine ? S.px1 - S.px0 + 1 : 0;
     const int h = mine ? S.py1 - S.py0 + 1 : 0;
-    const int cnt = w * h;
+    const int ns = (w + kSpan - 1) / kSpan;   // spans per bbox row
+    const int cnt = ns * h;
     const int incl = wave_incl_sum(cnt, lane);
     const int excl = incl - cnt;
     const int total = __builtin_amdgcn_readlane(incl, 63);
@@ -419,9 +423,9 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
     const int xy0 = (S.x0 & 0xFFFF) | (S.y0 << 16);
     const int xy1 = (S.x1 & 0xFFFF) | (S.y1 << 16);
     const int xy2 = (S.x2 & 0xFFFF) | (S.y2 << 16);
-    const int meta = S.px0 | (S.py0 << 9) | ((w - 1) << 18) | (S.bias << 27);
-    const float invw = 1.0f / (float)(w > 0 ? w : 1);
-    // (first pixel << 6 | lane): increasing along the lanes with pixels
+    const int meta = S.px0 | (S.py0 << 9) | ((ns > 0 ? ns - 1 : 0) << 18) | (S.bias << 27);
+    const float invns = 1.0f / (float)(ns > 0 ? ns : 1);
+    // (first span << 6 | lane): increasing along the lanes with spans
     const int start = (excl << 6) | lane;
     int carry = 0;
     for (int base = 0; base < total; base += 64) {
@@ -436,25 +440,41 @@ __device__ __forceinline__ void raster_balanced(const Setup &S, uint32_t myid, b
         const int local = g - (packed >> 6);
         const int txy0 = __shfl(xy0, t, 64), txy1 = __shfl(xy1, t, 64), txy2 = __shfl(xy2, t, 64);
         const int tmeta = __shfl(meta, t, 64);
+        const int tpx1 = __shfl(S.px1, t, 64);
         const float tq0 = __shfl(S.q0, t, 64), tq1 = __shfl(S.q1, t, 64), tq2 = __shfl(S.q2, t, 64);
-        const float tinvw = __shfl(invw, t, 64);
+        const float tinvns = __shfl(invns, t, 64);
         const uint32_t tid = (uint32_t)__shfl((int)myid, t, 64);
         if (g >= total) continue;
-        const int tw = ((tmeta >> 18) & 0x1FF) + 1;
-        const int oy = (int)(((float)local + 0.5f) * tinvw);
-        const int ox = local - mul24(oy, tw);
-        const int px = (tmeta & 0x1FF) + ox, py = ((tmeta >> 9) & 0x1FF) + oy;
+        const int tns = ((tmeta >> 18) & 0x1FF) + 1;
+        // span (row oy, span ox) of the triangle's bbox; the float quotient is
+        // within 0.002 of (local + 0.5) / tns, whose fraction is at least
+        // 0.5 / 64 from an integer, and the step below settles any doubt
+        int oy = (int)(((float)local + 0.5f) * tinvns);
+        int ox = local - mul24(oy, tns);
+        if (ox < 0) { oy -= 1; ox += tns; }
+        else if (ox >= tns) { oy += 1; ox -= tns; }
+        const int px = (tmeta & 0x1FF) + kSpan * ox, py = ((tmeta >> 9) & 0x1FF) + oy;
         const int x0 = (int)(short)(txy0 & 0xFFFF), y0 = txy0 >> 16;
         const int x1 = (int)(short)(txy1 & 0xFFFF), y1 = txy1 >> 16;
         const int x2 = (int)(short)(txy2 & 0xFFFF), y2 = txy2 >> 16;
         const int tb = tmeta >> 27;
+        const int b0 = tb & 1, b1 = (tb >> 1) & 1, b2 = (tb >> 2) & 1;
         const int Px = 16 * px + 8, Py = 16 * py + 8;
-        const int e0 = mul24(x2 - x1, Py - y1) - mul24(y2 - y1, Px - x1);
-        const int e1 = mul24(x0 - x2, Py - y2) - mul24(y0 - y2, Px - x2);
-        const int e2 = mul24(x1 - x0, Py - y0) - mul24(y1 - y0, Px - x0);
-        if (e0 >= (tb & 1) && e1 >= ((tb >> 1) & 1) && e2 >= ((tb >> 2) & 1)) {
-            const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
-            if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, tid);
+        int e0 = mul24(x2 - x1, Py - y1) - mul24(y2 - y1, Px - x1);
+        int e1 = mul24(x0 - x2, Py - y2) - mul24(y0 - y2, Px - x2);
+        int e2 = mul24(x1 - x0, Py - y0) - mul24(y1 - y0, Px - x0);
+        // one pixel to the right: E decreases by 16 (y_j - y_i)
+        const int d0 = 16 * (y2 - y1), d1 = 16 * (y0 - y2), d2 = 16 * (y1 - y0);
+        const int zrow = mul24(py - ry0, P) - rx0;
+#pragma unroll
+        for (int k = 0; k < kSpan; ++k) {
+            if (px + k <= tpx1 && e0 >= b0 && e1 >= b1 && e2 >= b2) {
+                const uint32_t D = frag_depth(e0, e1, e2, tq0, tq1, tq2);
+                if (D < kFar) zb.put(zrow + px + k, D, tid);
+            }
+            e0 -= d0;
+            e1 -= d1;
+            e2 -= d2;
         }
     }
 }
