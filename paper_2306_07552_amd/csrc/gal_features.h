@@ -96,45 +96,63 @@ __device__ __forceinline__ float scalar_feature(const RobotParams &rp, const Sim
     return 0.0f;
 }
 
-// Occupancy bits (bit k = layer k blocked) of patch column c = a * 16 + b of
-// env `env` around the candidate base pose: the OR of the lattice bytes under
-// the bounding box of the rotated 0.1 m cell, every layer blocked when that
-// box leaves the grid.  The box is under 3 columns wide, so at most 4 x 4
-// columns: a fixed 4 x 4 block of loads (indices clamped into the lattice)
-// issued together, the columns past the box masked out.
-__device__ __forceinline__ uint32_t patch_bits(const OccGrid &og, const GridMeta &gm, int env,
-                                               const CandBase &cb, int c)
+// Lattice box of patch column c = a * 16 + b around the candidate base pose:
+// the columns i0..i1 x j0..j1 under the bounding box of the rotated 0.1 m
+// cell.  False when the box leaves the grid (every layer blocked).  The box
+// is under 3 columns wide, so at most 4 x 4 columns.
+__device__ __forceinline__ bool patch_box(const CandBase &cb, float x0, float y0, float cell, int ox,
+                                          int oy, int c, int &i0, int &i1, int &j0, int &j1)
 {
-    const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
-    const uint8_t *occ = og.occ + og.occ_off[env];
     const float hx = 0.05f * (fabsf(cb.cy) + fabsf(cb.sy));   // half-extent of a rotated cell's box
     const int pa = c / kPatch, pb = c % kPatch;
     const float px = ((float)pa - 7.5f) * 0.1f, py = ((float)pb - 7.5f) * 0.1f;
     const float wx = cb.bx + (cb.cy * px - cb.sy * py), wy = cb.by + (cb.sy * px + cb.cy * py);
-    const float fi0 = floorf(((wx - hx) - gm.x0) / og.occ_cell);
-    const float fi1 = floorf(((wx + hx) - gm.x0) / og.occ_cell);
-    const float fj0 = floorf(((wy - hx) - gm.y0) / og.occ_cell);
-    const float fj1 = floorf(((wy + hx) - gm.y0) / og.occ_cell);
-    uint32_t bits = 0xFFu;
-    if (fi0 >= 0.0f && fj0 >= 0.0f && fi1 < (float)ox && fj1 < (float)oy && fi1 - fi0 < 4.0f &&
-        fj1 - fj0 < 4.0f) {
-        const int i0 = (int)fi0, i1 = (int)fi1, j0 = (int)fj0, j1 = (int)fj1;
-        uint32_t v[4][4];
+    const float fi0 = floorf(((wx - hx) - x0) / cell);
+    const float fi1 = floorf(((wx + hx) - x0) / cell);
+    const float fj0 = floorf(((wy - hx) - y0) / cell);
+    const float fj1 = floorf(((wy + hx) - y0) / cell);
+    if (!(fi0 >= 0.0f && fj0 >= 0.0f && fi1 < (float)ox && fj1 < (float)oy && fi1 - fi0 < 4.0f &&
+          fj1 - fj0 < 4.0f))
+        return false;
+    i0 = (int)fi0;
+    i1 = (int)fi1;
+    j0 = (int)fj0;
+    j1 = (int)fj1;
+    return true;
+}
+
+// Occupancy bits (bit k = layer k blocked) of a patch column: the OR of the
+// lattice bytes of its box, all 0xFF outside the grid.  A fixed 4 x 4 block
+// of loads (indices clamped into the lattice; box 0..0 when outside) issued
+// without a branch, so that the loads of several columns can be in flight
+// together; the columns past the box are masked out.
+__device__ __forceinline__ uint32_t patch_or(const uint8_t *occ, int ox, int oy, bool inside, int i0,
+                                             int i1, int j0, int j1)
+{
+    uint32_t v[4][4];
 #pragma unroll
-        for (int dj = 0; dj < 4; ++dj)
+    for (int dj = 0; dj < 4; ++dj)
 #pragma unroll
-            for (int di = 0; di < 4; ++di) {
-                const int i = min(i0 + di, ox - 1), j = min(j0 + dj, oy - 1);
-                v[dj][di] = occ[(size_t)j * ox + i];
-            }
-        bits = 0;
+        for (int di = 0; di < 4; ++di) {
+            const int i = min(i0 + di, ox - 1), j = min(j0 + dj, oy - 1);
+            v[dj][di] = occ[(size_t)j * ox + i];
+        }
+    uint32_t bits = 0;
 #pragma unroll
-        for (int dj = 0; dj < 4; ++dj)
+    for (int dj = 0; dj < 4; ++dj)
 #pragma unroll
-            for (int di = 0; di < 4; ++di)
-                if (i0 + di <= i1 && j0 + dj <= j1) bits |= v[dj][di];
-    }
-    return bits;
+        for (int di = 0; di < 4; ++di)
+            if (i0 + di <= i1 && j0 + dj <= j1) bits |= v[dj][di];
+    return inside ? bits : 0xFFu;
+}
+
+__device__ __forceinline__ uint32_t patch_bits(const OccGrid &og, const GridMeta &gm, int env,
+                                               const CandBase &cb, int c)
+{
+    const int ox = og.occ_dims[2 * env], oy = og.occ_dims[2 * env + 1];
+    int i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+    const bool in = patch_box(cb, gm.x0, gm.y0, og.occ_cell, ox, oy, c, i0, i1, j0, j1);
+    return patch_or(og.occ + og.occ_off[env], ox, oy, in, i0, i1, j0, j1);
 }
 
 // The 8 layers of a patch column as BF16 ones and zeros, two per word.

@@ -45,7 +45,7 @@ namespace {
 
 constexpr uint32_t kFar = 0xFFFFFFu;
 constexpr uint32_t kClipBits = 0x1Fu;
-constexpr int kVisCap = 4096;   // clusters per visibility window (u16 list in LDS)
+constexpr int kVisCap = 3072;   // clusters per visibility window (u16 list in LDS)
 
 // Products of edge-function terms: snapped coordinates lie in the guard band
 // (|x| < 3 * 16 * 256 / 2 < 2^13 at the largest resolution, 256), so every
@@ -275,30 +275,32 @@ __device__ __forceinline__ float rlf(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// The whole wave rasterises lane L's triangle, one 8x8 tile at a time (lane =
-// pixel).  The bbox's tiles (at most 16 per row in a 128-pixel region) are
-// first tested lane-parallel, four tile rows at a time: a tile is skipped when
-// some edge function is below its threshold even at the tile's pixel centre
-// where that edge is largest (the functions are linear), so only tiles that
-// can hold a covered pixel are visited.  Within a tile the edge values are the
-// tile origin's plus a per-lane offset (the same integers as evaluating them
-// per pixel).
+// One triangle's record, uniform over the wave.
+struct TriRec {
+    int x0, y0, x1, y1, x2, y2;
+    int bias;
+    float q0, q1, q2;
+    int px0, px1, py0, py1;
+    uint32_t id;
+};
+
+// The whole wave rasterises one triangle over 8x8 tile rows ty_first ..
+// ty_last (lane = pixel).  The tiles of its bbox in those rows (at most 16 per
+// row in a 128-pixel region) are first tested lane-parallel, four tile rows at
+// a time: a tile is skipped when some edge function is below its threshold
+// even at the tile's pixel centre where that edge is largest (the functions
+// are linear), so only tiles that can hold a covered pixel are visited.
+// Within a tile the edge values are the tile origin's plus a per-lane offset
+// (the same integers as evaluating them per pixel).
 template <class Sink>
-__device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L, int lane, int rx0,
-                                           int ry0, int P, const Sink &zb)
+__device__ __forceinline__ void raster_tiles(const TriRec &t, int ty_first, int ty_last, int lane,
+                                             int ry0, int rx0, int P, const Sink &zb)
 {
-    const uint32_t id = (uint32_t)rl((int)myid, L);
-    const int x0 = rl(S.x0, L), y0 = rl(S.y0, L);
-    const int x1 = rl(S.x1, L), y1 = rl(S.y1, L);
-    const int x2 = rl(S.x2, L), y2 = rl(S.y2, L);
-    const int bias = rl(S.bias, L);
-    const float q0 = rlf(S.q0, L), q1 = rlf(S.q1, L), q2 = rlf(S.q2, L);
-    const int px0 = rl(S.px0, L), px1 = rl(S.px1, L);
-    const int py0 = rl(S.py0, L), py1 = rl(S.py1, L);
+    const int x0 = t.x0, y0 = t.y0, x1 = t.x1, y1 = t.y1, x2 = t.x2, y2 = t.y2;
     const int ex0 = x2 - x1, ey0 = y2 - y1;
     const int ex1 = x0 - x2, ey1 = y0 - y2;
     const int ex2 = x1 - x0, ey2 = y1 - y0;
-    const int b0 = bias & 1, b1 = (bias >> 1) & 1, b2 = (bias >> 2) & 1;
+    const int b0 = t.bias & 1, b1 = (t.bias >> 1) & 1, b2 = (t.bias >> 2) & 1;
     const int lx = lane & 7, ly = lane >> 3;
     // offset of pixel (lx, ly) from its tile's origin pixel, per edge
     const int o0 = mul24(16 * ex0, ly) - mul24(16 * ey0, lx);
@@ -308,12 +310,12 @@ __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L,
     const int c0x = ey0 < 0 ? 112 : 0, c0y = ex0 > 0 ? 112 : 0;
     const int c1x = ey1 < 0 ? 112 : 0, c1y = ex1 > 0 ? 112 : 0;
     const int c2x = ey2 < 0 ? 112 : 0, c2y = ex2 > 0 ? 112 : 0;
-    const int tx0 = px0 >> 3, tx1 = px1 >> 3, ty0 = py0 >> 3, ty1 = py1 >> 3;
-    for (int tyb = ty0; tyb <= ty1; tyb += 4) {
+    const int tx0 = t.px0 >> 3, tx1 = t.px1 >> 3;
+    for (int tyb = ty_first; tyb <= ty_last; tyb += 4) {
         bool live = false;
         {
             const int tx = tx0 + (lane & 15), ty = tyb + (lane >> 4);
-            if (tx <= tx1 && ty <= ty1) {
+            if (tx <= tx1 && ty <= ty_last) {
                 const int Pxb = 128 * tx + 8, Pyb = 128 * ty + 8;
                 const int m0 = mul24(ex0, Pyb + c0y - y1) - mul24(ey0, Pxb + c0x - x1);
                 const int m1 = mul24(ex1, Pyb + c1y - y2) - mul24(ey1, Pxb + c1x - x2);
@@ -331,12 +333,64 @@ __device__ __forceinline__ void raster_big(const Setup &S, uint32_t myid, int L,
             const int e1 = mul24(ex1, Pyb - y2) - mul24(ey1, Pxb - x2) + o1;
             const int e2 = mul24(ex2, Pyb - y0) - mul24(ey2, Pxb - x0) + o2;
             const int px = tx * 8 + lx, py = ty * 8 + ly;
-            if (px >= px0 && px <= px1 && py >= py0 && py <= py1 && e0 >= b0 && e1 >= b1 && e2 >= b2) {
-                const uint32_t D = frag_depth(e0, e1, e2, q0, q1, q2);
-                if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, id);
+            if (px >= t.px0 && px <= t.px1 && py >= t.py0 && py <= t.py1 && e0 >= b0 && e1 >= b1 &&
+                e2 >= b2) {
+                const uint32_t D = frag_depth(e0, e1, e2, t.q0, t.q1, t.q2);
+                if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, t.id);
             }
         }
     }
+}
+
+// Lane L's triangle record, read into every lane.
+__device__ __forceinline__ TriRec lane_record(const Setup &S, uint32_t myid, int L)
+{
+    TriRec t;
+    t.id = (uint32_t)rl((int)myid, L);
+    t.x0 = rl(S.x0, L); t.y0 = rl(S.y0, L);
+    t.x1 = rl(S.x1, L); t.y1 = rl(S.y1, L);
+    t.x2 = rl(S.x2, L); t.y2 = rl(S.y2, L);
+    t.bias = rl(S.bias, L);
+    t.q0 = rlf(S.q0, L); t.q1 = rlf(S.q1, L); t.q2 = rlf(S.q2, L);
+    t.px0 = rl(S.px0, L); t.px1 = rl(S.px1, L);
+    t.py0 = rl(S.py0, L); t.py1 = rl(S.py1, L);
+    return t;
+}
+
+// Large triangles (bbox above small_max pixels) are not drawn by the wave that
+// sets them up: their records go to a list in LDS and, at the end of each
+// drawing round, every wave of the workgroup takes groups of four tile rows
+// of them in turn, so that a floor or wall triangle covering half the region
+// does not keep one wave busy while the others wait at the round's barrier.
+// A full list falls back to drawing by the wave itself.
+constexpr int kBigCap = 32;
+struct BigRec {
+    int xy0, xy1, xy2;   // snapped x | y << 16
+    int box;             // px0 | px1 << 8 | py0 << 16 | py1 << 24
+    int bias;
+    float q0, q1, q2;
+    uint32_t id;
+};
+
+// (the record is the same for every lane: kept in scalar registers)
+__device__ __forceinline__ TriRec unpack_big(const BigRec &b)
+{
+    const int xy0 = __builtin_amdgcn_readfirstlane(b.xy0);
+    const int xy1 = __builtin_amdgcn_readfirstlane(b.xy1);
+    const int xy2 = __builtin_amdgcn_readfirstlane(b.xy2);
+    const int box = __builtin_amdgcn_readfirstlane(b.box);
+    TriRec t;
+    t.x0 = (int)(short)(xy0 & 0xFFFF); t.y0 = xy0 >> 16;
+    t.x1 = (int)(short)(xy1 & 0xFFFF); t.y1 = xy1 >> 16;
+    t.x2 = (int)(short)(xy2 & 0xFFFF); t.y2 = xy2 >> 16;
+    t.bias = __builtin_amdgcn_readfirstlane(b.bias);
+    t.q0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(b.q0)));
+    t.q1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(b.q1)));
+    t.q2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(b.q2)));
+    t.px0 = box & 0xFF; t.px1 = (box >> 8) & 0xFF;
+    t.py0 = (box >> 16) & 0xFF; t.py1 = (box >> 24) & 0xFF;
+    t.id = (uint32_t)__builtin_amdgcn_readfirstlane((int)b.id);
+    return t;
 }
 
 // Row-shifted copy of v (DPP, no LDS traffic); lanes whose source lies
@@ -615,6 +669,8 @@ struct Ctx {
     const uint32_t *planefront;   // bit per env face plane: camera strictly in front
     int small_max;   // bbox pixels: <= lane_max per lane, <= small_max balanced, else tiles
     int lane_max;
+    BigRec *big;     // the workgroup's list of deferred large triangles
+    int *nbig;
 };
 
 // One cluster's per-lane inputs: lane l holds vertex l and triangle l.
@@ -760,13 +816,65 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
             stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
         }
         if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.P, c.own, zb);
-        uint64_t bmask = __ballot(big);
+        bool spill = false;
+        if (big) {
+            const int slot = atomicAdd(c.nbig, 1);
+            if (slot < kBigCap) {
+                BigRec &r = c.big[slot];
+                r.xy0 = (S.x0 & 0xFFFF) | (S.y0 << 16);
+                r.xy1 = (S.x1 & 0xFFFF) | (S.y1 << 16);
+                r.xy2 = (S.x2 & 0xFFFF) | (S.y2 << 16);
+                r.box = S.px0 | (S.px1 << 8) | (S.py0 << 16) | (S.py1 << 24);
+                r.bias = S.bias;
+                r.q0 = S.q0;
+                r.q1 = S.q1;
+                r.q2 = S.q2;
+                r.id = myid;
+            } else {
+                spill = true;
+            }
+        }
+        uint64_t bmask = __ballot(spill);
         while (bmask) {
             const int L = __ffsll((unsigned long long)bmask) - 1;
             bmask &= bmask - 1;
-            raster_big(S, myid, L, lane, c.rx0, c.ry0, c.P, zb);
+            const TriRec t = lane_record(S, myid, L);
+            raster_tiles(t, t.py0 >> 3, t.py1 >> 3, lane, c.ry0, c.rx0, c.P, zb);
         }
     }
+}
+
+// Every wave of the workgroup draws the deferred large triangles, groups of
+// four tile rows at a time, then the list is emptied (called by the whole
+// workgroup right after a barrier).
+template <class Sink>
+__device__ __forceinline__ void drain_big(BigRec *big, int *nbig, int *gofs, int wave, int nwaves,
+                                          int lane, int rx0, int ry0, int P, const Sink &zb)
+{
+    const int n = min(*nbig, kBigCap);
+    if (n == 0) return;
+    if (wave == 0) {
+        int ng = 0;
+        if (lane < n) {
+            const int box = big[lane].box;
+            ng = ((((box >> 24) & 0xFF) >> 3) - (((box >> 16) & 0xFF) >> 3) + 4) >> 2;
+        }
+        const int incl = wave_incl_sum(ng, lane);
+        if (lane < n) gofs[lane + 1] = incl;
+        if (lane == 0) gofs[0] = 0;
+    }
+    __syncthreads();
+    const int G = gofs[n];
+    for (int g = wave; g < G; g += nwaves) {
+        int k = 0;
+        while (gofs[k + 1] <= g) ++k;
+        const TriRec t = unpack_big(big[k]);
+        const int ty = (t.py0 >> 3) + 4 * (g - gofs[k]);
+        raster_tiles(t, ty, min(ty + 3, t.py1 >> 3), lane, ry0, rx0, P, zb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *nbig = 0;
+    __syncthreads();
 }
 
 // LDS of one workgroup besides the z-buffer.
@@ -778,6 +886,9 @@ struct ItemShared {
     int wave_cnt[kBlock / 64];
     int own[kBlock];   // 64 words per wave, balanced raster
     uint32_t planefront[kMaxPlanes / 32];   // camera strictly in front of face plane p
+    BigRec big[kBigCap];
+    int big_gofs[kBigCap + 1];
+    int nbig;
     int next;
     int queue_item;
 };
@@ -812,6 +923,9 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     c.ry0 = (reg / nr) * c.R;
     c.P = zpitch(c.R);
     c.own = sh.own + (threadIdx.x & ~63);
+    c.big = sh.big;
+    c.nbig = &sh.nbig;
+    if (threadIdx.x == 0) sh.nbig = 0;
     c.planefront = sh.planefront;
     c.small_max = rp.small_max;
     c.lane_max = rp.lane_max;
@@ -960,6 +1074,7 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                 cd = nd;
             }
             __syncthreads();
+            drain_big(sh.big, &sh.nbig, sh.big_gofs, wave, kWaves, lane, c.rx0, c.ry0, c.P, zb);
             pos = end;
             if (pos >= V) break;
             refresh_bounds(zb, oc, R, wave, kWaves, lane);

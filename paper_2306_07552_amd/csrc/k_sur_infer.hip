@@ -55,22 +55,18 @@ __device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
 
 
 // Layers 2..4, the head and the routing of the tile's 32 rows, from the first
-// hidden layer in H[0]; fa holds this wave's fragments of layer 2.
+// hidden layer in H[0]; f2, f3, f4 hold this wave's fragments of the three
+// layers, all loaded before the first of them runs (a chain of per-layer loads
+// waits on memory three times over).
 __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
                                             uint16_t (*H)[kR][kHPitch], float *zs,
-                                            bf16x8 (&fa)[kMlpHidden / 32][2])
+                                            const bf16x8 (&f2)[kMlpHidden / 32][2],
+                                            const bf16x8 (&f3)[kMlpHidden / 32][2],
+                                            const bf16x8 (&f4)[kMlpHidden / 32][2])
 {
     constexpr int D = kMlpHidden;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    auto load_w = [&](const uint16_t *W, bf16x8(&f)[D / 32][2]) {
-#pragma unroll
-        for (int st = 0; st < D / 32; ++st)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                f[st][j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(kColsW * wave + 16 * j + r16) * D + 32 * st + kq);
-    };
-    bf16x8 fb[D / 32][2];
     float bias[3][2];
 #pragma unroll
     for (int l = 0; l < 3; ++l)
@@ -105,11 +101,9 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
         }
         __syncthreads();
     };
-    load_w(p.t.w[1], fb);
-    layer(fa, bias[0], 0);
-    load_w(p.t.w[2], fa);
-    layer(fb, bias[1], 1);
-    layer(fa, bias[2], 0);
+    layer(f2, bias[0], 0);
+    layer(f3, bias[1], 1);
+    layer(f4, bias[2], 0);
     // head (summed in the training head's order): wave w takes rows 4w .. 4w + 3
 #pragma unroll
     for (int rr = 0; rr < kR / kWaves; ++rr) {
@@ -156,11 +150,21 @@ __device__ __forceinline__ void load_layer(const uint16_t *W, bf16x8 (&f)[kMlpHi
                                                         32 * st + kq);
 }
 
+// What the patch columns of one row need: the candidate base pose and where
+// the env's lattice lies.
+struct RowInfo {
+    CandBase cb;
+    float x0, y0;
+    int ox, oy;
+    uint64_t occ_off;
+    bool live;
+};
+
 template <int FEAT>
 __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kR * kHPitch];
-    __shared__ float arm[kR][24];
+    __shared__ RowInfo rows[kR];
     __shared__ float zs[kR];
     static_assert(kR * kAPitch <= 2 * kR * kHPitch, "chunk fits the activation buffer");
     uint16_t(*A)[kAPitch] = reinterpret_cast<uint16_t(*)[kAPitch]>(lds);
@@ -179,12 +183,14 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
     for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    for (int c = cbeg; c < cbeg + cpb; ++c) {
+    // this wave's weight fragments of chunk c: column 32 wave + 16 j + r16,
+    // K = 32 (first step + st) + kq; the first chunk's are issued before
+    // anything else, each later chunk's as soon as the previous one's MFMAs
+    // have been issued
+    bf16x8 w[kChunk0][2];
+    auto load_chunk = [&](int c) {
         const int s0 = c == 0 ? 0 : kChunk0 + kChunkN * (c - 1);
         const int ns = c == 0 ? kChunk0 : kChunkN;
-        // this wave's weight fragments: column 32 wave + 16 j + r16, K = 32 (s0 + st) + kq
-        bf16x8 w[kChunk0][2];
 #pragma unroll
         for (int st = 0; st < kChunk0; ++st)
 #pragma unroll
@@ -193,6 +199,31 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
                                          p.t.w0 + (size_t)(kColsW * wave + 16 * j + r16) * kMlpIn +
                                          32 * (s0 + st) + kq)
                                    : bf16x8{};
+    };
+    load_chunk(cbeg);
+    if (FEAT) {
+        // per row: the candidate base pose and the lattice placement, once
+        if (tid < kR) {
+            RowInfo ri{};
+            const int e = row0 + tid;
+            ri.live = e < p.rows;
+            if (ri.live) {
+                ri.cb = cand_base(p.rp, p.sb.state + (size_t)e * 10, p.actions + (size_t)e * 9);
+                const GridMeta gm = p.sb.grid_meta[e];
+                ri.x0 = gm.x0;
+                ri.y0 = gm.y0;
+                ri.ox = p.og.occ_dims[2 * e];
+                ri.oy = p.og.occ_dims[2 * e + 1];
+                ri.occ_off = p.og.occ_off[e];
+            }
+            rows[tid] = ri;
+        }
+        __syncthreads();
+    }
+
+    for (int c = cbeg; c < cbeg + cpb; ++c) {
+        const int s0 = c == 0 ? 0 : kChunk0 + kChunkN * (c - 1);
+        const int ns = c == 0 ? kChunk0 : kChunkN;
         if (FEAT == 0) {
             // the chunk's columns of the input rows, 16 bytes per thread and pass
             const int per_row = ns * 4;
@@ -204,46 +235,69 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
                 *reinterpret_cast<uint4 *>(&A[r][8 * q]) = v;
             }
         } else {
-            // chunk 0: wave 1 evaluates the arm frames of the 32 rows (one lane
-            // each) while the other waves build the patch columns
+            // chunk 0: wave 1 builds the 64 scalars of the 32 rows (one lane
+            // each, with the arm frames) while the other waves build the patch
+            // columns
             const bool fk_wave = c == 0 && wave == 1;
             if (fk_wave && lane < kR) {
                 const int e = row0 + lane;
-                float f[24];
-                if (e < p.rows)
-                    arm_frame_features(p.rp, p.sb.state + (size_t)e * 10, p.actions + (size_t)e * 9, f);
-                else
+                if (e < p.rows) {
+                    float st[10], a[9];
 #pragma unroll
-                    for (int k = 0; k < 24; ++k) f[k] = 0.f;
+                    for (int k = 0; k < 10; ++k) st[k] = p.sb.state[(size_t)e * 10 + k];
 #pragma unroll
-                for (int k = 0; k < 24; ++k) arm[lane][k] = f[k];
+                    for (int k = 0; k < 9; ++k) a[k] = p.actions[(size_t)e * 9 + k];
+                    const GridMeta gm = p.sb.grid_meta[e];
+                    float arm[24];
+                    arm_frame_features(p.rp, st, a, arm);
+#pragma unroll
+                    for (int t = 0; t < 64; ++t)
+                        A[lane][t] = feat_bf16(scalar_feature(p.rp, p.sb, gm, e, st, a, t, arm));
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 64; ++t) A[lane][t] = 0;
+                }
             }
-            // patch columns 32c .. 32c + 31 of every row
+            // patch columns 32c .. 32c + 31 of every row: two per thread (three
+            // in chunk 0, where wave 1 is busy), every lattice load of a
+            // thread's columns in flight together
             const int pbase = c == 0 ? kFeatPatchBase : 0;
             const int t0 = c == 0 ? (tid < 64 ? tid : tid - 64) : tid;
             const int nt = c == 0 ? kThreads - 64 : kThreads;
-            if (!fk_wave)
-                for (int i = t0; i < kR * 32; i += nt) {
-                    const int r = i >> 5, pc = i & 31;
-                    const int e = row0 + r;
-                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                    if (e < p.rows) {
-                        const CandBase cb = cand_base(p.rp, p.sb.state + (size_t)e * 10, p.actions + (size_t)e * 9);
-                        v = patch_words(patch_bits(p.og, p.sb.grid_meta[e], e, cb, 32 * c + pc));
+            constexpr int kTasks = 3;
+            if (!fk_wave) {
+                int ti[kTasks], i0[kTasks], i1[kTasks], j0[kTasks], j1[kTasks], oxs[kTasks], oys[kTasks];
+                bool in[kTasks];
+                const uint8_t *occ[kTasks];
+#pragma unroll
+                for (int k = 0; k < kTasks; ++k) {
+                    ti[k] = t0 + k * nt;
+                    in[k] = false;
+                    occ[k] = p.og.occ;
+                    oxs[k] = oys[k] = 1;
+                    i0[k] = i1[k] = j0[k] = j1[k] = 0;
+                    if (ti[k] < kR * 32) {
+                        const RowInfo &ri = rows[ti[k] >> 5];
+                        if (ri.live) {
+                            oxs[k] = ri.ox;
+                            oys[k] = ri.oy;
+                            occ[k] = p.og.occ + ri.occ_off;
+                            in[k] = patch_box(ri.cb, ri.x0, ri.y0, p.og.occ_cell, ri.ox, ri.oy,
+                                              32 * c + (ti[k] & 31), i0[k], i1[k], j0[k], j1[k]);
+                        }
                     }
-                    *reinterpret_cast<uint4 *>(&A[r][pbase + 8 * pc]) = v;
                 }
-            if (c == 0) {
-                __syncthreads();
-                for (int i = tid; i < kR * 64; i += kThreads) {
-                    const int r = i >> 6, t = i & 63;
-                    const int e = row0 + r;
-                    float v = 0.f;
-                    if (e < p.rows)
-                        v = scalar_feature(p.rp, p.sb, p.sb.grid_meta[e], e, p.sb.state + (size_t)e * 10,
-                                           p.actions + (size_t)e * 9, t, arm[r]);
-                    A[r][t] = feat_bf16(v);
-                }
+                uint32_t bits[kTasks];
+#pragma unroll
+                for (int k = 0; k < kTasks; ++k)
+                    bits[k] = patch_or(occ[k], oxs[k], oys[k], in[k], i0[k], i1[k], j0[k], j1[k]);
+#pragma unroll
+                for (int k = 0; k < kTasks; ++k)
+                    if (ti[k] < kR * 32) {
+                        const int r = ti[k] >> 5, pc = ti[k] & 31;
+                        *reinterpret_cast<uint4 *>(&A[r][pbase + 8 * pc]) =
+                            rows[r].live ? patch_words(bits[k]) : make_uint4(0u, 0u, 0u, 0u);
+                    }
             }
         }
         __syncthreads();
@@ -259,6 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
                 }
             }
         }
+        if (c + 1 < cbeg + cpb) load_chunk(c + 1);
         __syncthreads();
     }
 
@@ -275,8 +330,10 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
         return;
     }
     // one split: the first hidden layer (bias, ReLU, BF16), then the rest
-    bf16x8 fa[kMlpHidden / 32][2];
-    load_layer(p.t.w[0], fa);
+    bf16x8 f2[kMlpHidden / 32][2], f3[kMlpHidden / 32][2], f4[kMlpHidden / 32][2];
+    load_layer(p.t.w[0], f2);
+    load_layer(p.t.w[1], f3);
+    load_layer(p.t.w[2], f4);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int n = kColsW * wave + 16 * j + r16;
@@ -287,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
             for (int i = 0; i < 4; ++i) H[0][16 * m + 4 * (lane >> 4) + i][n] = to_bf16(relu(acc[m][j][i] + bn));
     }
     __syncthreads();
-    tail_layers(p, row0, H, zs, fa);
+    tail_layers(p, row0, H, zs, f2, f3, f4);
 }
 
 // Second launch with several splits: one workgroup per tile adds the tile's
@@ -299,41 +356,56 @@ __global__ __launch_bounds__(kThreads) void k_sur_tail(SurInferArgs p)
     uint16_t(*H)[kR][kHPitch] = reinterpret_cast<uint16_t(*)[kR][kHPitch]>(lds);
     const int S = p.splits;
     const int tile = blockIdx.x, row0 = tile * kR;
-    bf16x8 fa[kMlpHidden / 32][2];
-    load_layer(p.t.w[0], fa);
-    // thread: 4 adjacent columns of rows r, r + 8, r + 16, r + 24
+    // thread: 4 adjacent columns of rows r, r + 8, r + 16, r + 24; every
+    // split's partial sums of two of them in flight at once (the splits are
+    // added in split order afterwards)
+    constexpr int kMaxSplits = 8;
     const int c = (threadIdx.x % (kMlpHidden / 4)) * 4, r0 = threadIdx.x / (kMlpHidden / 4);
     constexpr int kRowStep = kThreads / (kMlpHidden / 4);   // 8
-    const float4 bb = *reinterpret_cast<const float4 *>(p.t.b0 + c);
     const float *tp = p.part + (size_t)tile * S * kR * kMlpHidden;
-#pragma unroll
-    for (int h = 0; h < kR / kRowStep; h += 2) {
-        float4 v[2];
+    auto load_rows = [&](int h, float4 (&v)[2][kMaxSplits]) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const int r = r0 + kRowStep * (h + k);
-            const float *q = tp + (size_t)r * kMlpHidden + c;
-            float4 a = *reinterpret_cast<const float4 *>(q);
-            for (int sp = 1; sp < S; ++sp) {
-                const float4 b = *reinterpret_cast<const float4 *>(q + (size_t)sp * kR * kMlpHidden);
-                a.x += b.x;
-                a.y += b.y;
-                a.z += b.z;
-                a.w += b.w;
-            }
-            v[k] = a;
+            const float *q = tp + (size_t)(r0 + kRowStep * (h + k)) * kMlpHidden + c;
+#pragma unroll
+            for (int sp = 0; sp < kMaxSplits; ++sp)
+                v[k][sp] = sp < S ? *reinterpret_cast<const float4 *>(q + (size_t)sp * kR * kMlpHidden)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+    };
+    auto store_rows = [&](int h, const float4 (&v)[2][kMaxSplits]) {
+        const float4 bb = *reinterpret_cast<const float4 *>(p.t.b0 + c);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
+            float4 a = v[k][0];
+#pragma unroll
+            for (int sp = 1; sp < kMaxSplits; ++sp)
+                if (sp < S) {
+                    a.x += v[k][sp].x;
+                    a.y += v[k][sp].y;
+                    a.z += v[k][sp].z;
+                    a.w += v[k][sp].w;
+                }
             const int r = r0 + kRowStep * (h + k);
-            H[0][r][c + 0] = to_bf16(relu(v[k].x + bb.x));
-            H[0][r][c + 1] = to_bf16(relu(v[k].y + bb.y));
-            H[0][r][c + 2] = to_bf16(relu(v[k].z + bb.z));
-            H[0][r][c + 3] = to_bf16(relu(v[k].w + bb.w));
+            H[0][r][c + 0] = to_bf16(relu(a.x + bb.x));
+            H[0][r][c + 1] = to_bf16(relu(a.y + bb.y));
+            H[0][r][c + 2] = to_bf16(relu(a.z + bb.z));
+            H[0][r][c + 3] = to_bf16(relu(a.w + bb.w));
         }
+    };
+    bf16x8 f2[kMlpHidden / 32][2], f3[kMlpHidden / 32][2], f4[kMlpHidden / 32][2];
+    load_layer(p.t.w[0], f2);
+    {
+        float4 v[2][kMaxSplits];
+        load_rows(0, v);
+        load_layer(p.t.w[1], f3);
+        store_rows(0, v);
+        load_rows(2, v);
+        store_rows(2, v);
     }
+    load_layer(p.t.w[2], f4);
     __syncthreads();
-    tail_layers(p, row0, H, zs, fa);
+    tail_layers(p, row0, H, zs, f2, f3, f4);
 }
 
 }  // namespace
