@@ -405,6 +405,19 @@ int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count);
  * pass in the last bits; they are reproducible for a given row count.  The
  * partial sums live in the MLP object: calls on one MLP must not overlap. */
 int gal_mlp_forward(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gal_mlp_forward with its scratch -- the first layer's partial sums, at most
+ * 16 MiB -- in a fixed device array of the library instead of the MLP
+ * object.  Allocates nothing; each GPU the library runs
+ * on holds one such array until the process ends.  Same logits, bit for
+ * bit, as gal_mlp_forward for the same rows.  logits_dev must not be NULL;
+ * rows above GAL_MLP_STATIC_MAX_ROWS are rejected (GAL_EINVAL).  Every call
+ * on one GPU shares that GPU's array (whatever the MLP or the stream):
+ * calls that overlap on one GPU race. */
+#define GAL_MLP_STATIC_MAX_ROWS (1 << 22)
+int gal_mlp_forward_static(gal_mlp *m, const uint16_t *x_dev, int32_t rows, float *logits_dev,
+                           void *stream);
 /* Surrogate of the Section 3.2 static-scene test (not in the paper).
  * Gradients of the weighted logistic loss (1/rows) sum_i w_i l(z_i, y_i),
  * w_i = pos_weight for labels 1, into grads_dev (device f32, parameter

@@ -103,6 +103,8 @@ def load_library():
         L.gal_mlp_set_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
         L.gal_mlp_get_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
         L.gal_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.gal_mlp_forward_static.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                             C.c_void_p]
         L.gal_mlp_gradients.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                         C.c_void_p, C.c_void_p, C.c_void_p]
         L.gal_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
@@ -446,6 +448,12 @@ class Mlp:
         rows = x.shape[0] if rows is None else rows
         _check(load_library().gal_mlp_forward(self._h, x.data_ptr(), int(rows), logits.data_ptr(),
                                               _stream_handle(stream)))
+
+    def forward_static(self, x, logits, rows=None, stream=None):
+        """gal_mlp_forward_static: the same logits, scratch in the library's fixed array."""
+        rows = x.shape[0] if rows is None else rows
+        _check(load_library().gal_mlp_forward_static(self._h, x.data_ptr(), int(rows),
+                                                     logits.data_ptr(), _stream_handle(stream)))
 
     def gradients(self, x, y, pos_weight, grads=None, loss=None, stream=None):
         _check(load_library().gal_mlp_gradients(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
