@@ -89,6 +89,8 @@ int plane_index(const float *pl, std::vector<float> &table, std::unordered_map<s
     return idx;
 }
 
+constexpr int kFaceSplitMin = 24;
+
 void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris, int64_t ntris,
                         const float *tri_plane, EnvClusters &out)
 {
@@ -144,8 +146,12 @@ void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris,
             for (int k = 0; k < ncpl; ++k)
                 if (cpl[k] == pidx) pslot = k;
         }
+        // a new face plane also starts a new cluster once the current one holds
+        // kFaceSplitMin triangles, so that most clusters lie on one face and are
+        // culled whole when it faces away
         if (nt == gal::kClusterTris || nv + fresh > gal::kClusterVerts ||
-            (tri_plane && pslot < 0 && ncpl == gal::kClusterPlanes)) {
+            (tri_plane && pslot < 0 && ncpl == gal::kClusterPlanes) ||
+            (tri_plane && pslot < 0 && ncpl > 0 && nt >= kFaceSplitMin)) {
             close();
             pslot = -1;
         }

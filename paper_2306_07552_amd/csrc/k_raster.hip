@@ -284,14 +284,16 @@ struct TriRec {
     uint32_t id;
 };
 
-// The whole wave rasterises one triangle over 8x8 tile rows ty_first ..
-// ty_last (lane = pixel).  The tiles of its bbox in those rows (at most 16 per
-// row in a 128-pixel region) are first tested lane-parallel, four tile rows at
-// a time: a tile is skipped when some edge function is below its threshold
-// even at the tile's pixel centre where that edge is largest (the functions
-// are linear), so only tiles that can hold a covered pixel are visited.
-// Within a tile the edge values are the tile origin's plus a per-lane offset
-// (the same integers as evaluating them per pixel).
+// The whole wave rasterises one triangle over 8-pixel tile rows ty_first ..
+// ty_last, in 16 x 8 double tiles (lane = pixel pair (lx, ly), (lx + 8, ly)).
+// The double tiles of its bbox in those rows (at most 8 per row in a
+// 128-pixel region) are first tested lane-parallel, four tile rows at a time:
+// a tile is skipped when some edge function is below its threshold even at
+// the tile's pixel centre where that edge is largest (the functions are
+// linear), so only tiles that can hold a covered pixel are visited.  Within a
+// tile the edge values are the tile origin's plus a per-lane offset, and the
+// right half's are the left half's minus 8 pixel steps (the same integers as
+// evaluating them per pixel).
 template <class Sink>
 __device__ __forceinline__ void raster_tiles(const TriRec &t, int ty_first, int ty_last, int lane,
                                              int ry0, int rx0, int P, const Sink &zb)
@@ -306,17 +308,17 @@ __device__ __forceinline__ void raster_tiles(const TriRec &t, int ty_first, int 
     const int o0 = mul24(16 * ex0, ly) - mul24(16 * ey0, lx);
     const int o1 = mul24(16 * ex1, ly) - mul24(16 * ey1, lx);
     const int o2 = mul24(16 * ex2, ly) - mul24(16 * ey2, lx);
-    // corner offsets (in pixel-centre units) where each edge is largest
-    const int c0x = ey0 < 0 ? 112 : 0, c0y = ex0 > 0 ? 112 : 0;
-    const int c1x = ey1 < 0 ? 112 : 0, c1y = ex1 > 0 ? 112 : 0;
-    const int c2x = ey2 < 0 ? 112 : 0, c2y = ex2 > 0 ? 112 : 0;
-    const int tx0 = t.px0 >> 3, tx1 = t.px1 >> 3;
+    // corner offsets of a 16 x 8 tile (pixel-centre units) where each edge is largest
+    const int c0x = ey0 < 0 ? 240 : 0, c0y = ex0 > 0 ? 112 : 0;
+    const int c1x = ey1 < 0 ? 240 : 0, c1y = ex1 > 0 ? 112 : 0;
+    const int c2x = ey2 < 0 ? 240 : 0, c2y = ex2 > 0 ? 112 : 0;
+    const int tx0 = t.px0 >> 4, tx1 = t.px1 >> 4;
     for (int tyb = ty_first; tyb <= ty_last; tyb += 4) {
         bool live = false;
         {
             const int tx = tx0 + (lane & 15), ty = tyb + (lane >> 4);
             if (tx <= tx1 && ty <= ty_last) {
-                const int Pxb = 128 * tx + 8, Pyb = 128 * ty + 8;
+                const int Pxb = 256 * tx + 8, Pyb = 128 * ty + 8;
                 const int m0 = mul24(ex0, Pyb + c0y - y1) - mul24(ey0, Pxb + c0x - x1);
                 const int m1 = mul24(ex1, Pyb + c1y - y2) - mul24(ey1, Pxb + c1x - x2);
                 const int m2 = mul24(ex2, Pyb + c2y - y0) - mul24(ey2, Pxb + c2x - x0);
@@ -328,15 +330,23 @@ __device__ __forceinline__ void raster_tiles(const TriRec &t, int ty_first, int 
             const int k = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
             const int tx = tx0 + (k & 15), ty = tyb + (k >> 4);
-            const int Pxb = 128 * tx + 8, Pyb = 128 * ty + 8;
-            const int e0 = mul24(ex0, Pyb - y1) - mul24(ey0, Pxb - x1) + o0;
-            const int e1 = mul24(ex1, Pyb - y2) - mul24(ey1, Pxb - x2) + o1;
-            const int e2 = mul24(ex2, Pyb - y0) - mul24(ey2, Pxb - x0) + o2;
-            const int px = tx * 8 + lx, py = ty * 8 + ly;
-            if (px >= t.px0 && px <= t.px1 && py >= t.py0 && py <= t.py1 && e0 >= b0 && e1 >= b1 &&
-                e2 >= b2) {
-                const uint32_t D = frag_depth(e0, e1, e2, t.q0, t.q1, t.q2);
-                if (D < kFar) zb.put(mul24(py - ry0, P) + (px - rx0), D, t.id);
+            const int Pxb = 256 * tx + 8, Pyb = 128 * ty + 8;
+            int e0 = mul24(ex0, Pyb - y1) - mul24(ey0, Pxb - x1) + o0;
+            int e1 = mul24(ex1, Pyb - y2) - mul24(ey1, Pxb - x2) + o1;
+            int e2 = mul24(ex2, Pyb - y0) - mul24(ey2, Pxb - x0) + o2;
+            const int py = ty * 8 + ly;
+            const int zrow = mul24(py - ry0, P) - rx0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int px = tx * 16 + 8 * h + lx;
+                if (px >= t.px0 && px <= t.px1 && py >= t.py0 && py <= t.py1 && e0 >= b0 && e1 >= b1 &&
+                    e2 >= b2) {
+                    const uint32_t D = frag_depth(e0, e1, e2, t.q0, t.q1, t.q2);
+                    if (D < kFar) zb.put(zrow + px, D, t.id);
+                }
+                e0 -= 128 * ey0;
+                e1 -= 128 * ey1;
+                e2 -= 128 * ey2;
             }
         }
     }
