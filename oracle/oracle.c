@@ -394,6 +394,386 @@ O_EXPORT void o_robot_step(const o_robot *rb, const o_params *pr, const o_env *e
     o_camera(rb, state, cam);
 }
 
+/* ------------------------------------------------------------------------ */
+/* manipulation (Section 3.2: suction grasp with a small sphere at the end-   */
+/* effector tip, the grasped object fixed to the end effector, snap-to-       */
+/* surface on release; Appendix I: sliding and object-placing heuristics)     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t slide;             /* resolve a collision by sliding the base       */
+    float grasp_tip[3];        /* end-effector-frame point of the grasp sphere  */
+    float grasp_radius;
+    int32_t held_class;        /* radius class of the held object's spheres     */
+    float slide_step;          /* base jitter per sliding try (m)               */
+    float place_step;          /* object jitter per placing try (m)             */
+    uint64_t seed;             /* counter-based jitter randomness               */
+} o_manip;
+
+/* dynamic state of one environment's movable objects */
+typedef struct {
+    float *objects;            /* [O][8] resting records; the held object keeps
+                                  its record from before the grasp              */
+    const float *objects0;     /* [O][8] records at episode start               */
+    int32_t *held;             /* held object index, -1 = none                   */
+    float *rel;                /* [12] held object's frame in the EE frame       */
+} o_dyn;
+
+enum { O_SLIDE_TRIES = 3, O_PLACE_TRIES = 6, O_HELD_SPHERES = 8 };
+
+/* frame of a resting object: Rz(yaw) about its centre */
+static void object_frame(const float *o, float *F)
+{
+    float c = o[6], s = o[7];
+    F[0] = c;    F[1] = -s;   F[2] = 0.0f;  F[3] = o[0];
+    F[4] = s;    F[5] = c;    F[6] = 0.0f;  F[7] = o[1];
+    F[8] = 0.0f; F[9] = 0.0f; F[10] = 1.0f; F[11] = o[2];
+}
+
+/* inverse of a rigid frame: R^T | -R^T t */
+static void frame_inverse(const float *F, float *G)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i * 4 + j] = F[j * 4 + i];
+    for (int i = 0; i < 3; ++i)
+        G[i * 4 + 3] = -((F[0 * 4 + i] * F[3] + F[1 * 4 + i] * F[7]) + F[2 * 4 + i] * F[11]);
+}
+
+/* octant k of a box of half extents e: (+-e0/2, +-e1/2, +-e2/2), bit 0 = x */
+static void octant(const float *e, int k, float *p)
+{
+    p[0] = (k & 1) ? 0.5f * e[0] : -(0.5f * e[0]);
+    p[1] = (k & 2) ? 0.5f * e[1] : -(0.5f * e[1]);
+    p[2] = (k & 4) ? 0.5f * e[2] : -(0.5f * e[2]);
+}
+
+/* squared distance from p to an oriented box (the test of obb_contact) */
+static float obb_dist2(const float *o, const float *p)
+{
+    float dx = p[0] - o[0], dy = p[1] - o[1], dz = p[2] - o[2];
+    float cps = o[6], sps = o[7];
+    float l[3];
+    l[0] = cps * dx + sps * dy;
+    l[1] = cps * dy - sps * dx;
+    l[2] = dz;
+    float d[3];
+    for (int k = 0; k < 3; ++k) {
+        float e = o[3 + k];
+        float q = l[k] < -e ? -e : (l[k] > e ? e : l[k]);
+        d[k] = l[k] - q;
+    }
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+/* SplitMix64 (Steele, Lea & Flood 2014) of a counter; uniform in [0, 1) with
+   24 bits */
+static float o_hash01(uint64_t seed, uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+{
+    uint64_t x = seed + 0x9E3779B97F4A7C15ull * (((a << 40) ^ (b << 24) ^ (c << 8) ^ d) + 1ull);
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x = x ^ (x >> 31);
+    return (float)(x >> 40) * 0x1p-24f;
+}
+
+/* Overlap test of a candidate pose (robot spheres, and with a held object its
+   8 spheres at the octant centres of its box) against the column grids and
+   the resting objects.  Masks: bit s = robot sphere s, bits S..S+7 = the held
+   object's spheres.  With sum != NULL, the x, y of every overlapping sphere's
+   centre is summed in sphere order (robot spheres, then held) and counted. */
+static int pose_contacts(const o_robot *rb, const o_params *pr, const o_env *env,
+                         const o_manip *mp, const o_dyn *dy, const float *cand,
+                         uint32_t *mask_static, uint32_t *mask_object, float *sum, int *count)
+{
+    float fr[8 * 12];
+    o_fk(rb, cand, fr);
+    int S = rb->num_spheres;
+    int words = (S + O_HELD_SPHERES + 31) / 32;
+    for (int w = 0; w < words; ++w) { mask_static[w] = 0; mask_object[w] = 0; }
+    int any = 0;
+    float sx = 0.0f, sy = 0.0f;
+    int n = 0;
+    int held = *dy->held;
+    for (int s = 0; s < S + O_HELD_SPHERES; ++s) {
+        float c[3];
+        int cls;
+        if (s < S) {
+            if (rb->sphere_held_only && rb->sphere_held_only[s]) continue;   /* replaced by the object */
+            frame_point(fr + 12 * rb->sphere_link[s], rb->sphere_pos + 3 * s, c);
+            cls = rb->sphere_class[s];
+        } else {
+            if (held < 0) continue;
+            float F[12], p[3];
+            frame_mul(fr + 12 * 7, dy->rel, F);
+            octant(dy->objects + 8 * held + 3, s - S, p);
+            frame_point(F, p, c);
+            cls = mp->held_class;
+        }
+        float r = pr->class_radius[cls];
+        int hit = 0;
+        if (grid_contact(env, cls, c)) { mask_static[s >> 5] |= 1u << (s & 31); hit = 1; }
+        for (int o = 0; o < env->num_objects; ++o) {
+            if (o == held) continue;
+            if (obb_contact(dy->objects + 8 * o, c, r)) {
+                mask_object[s >> 5] |= 1u << (s & 31);
+                hit = 1;
+                break;
+            }
+        }
+        if (hit) {
+            any = 1;
+            sx = sx + c[0];
+            sy = sy + c[1];
+            ++n;
+        }
+    }
+    if (sum) { sum[0] = sx; sum[1] = sy; *count = n; }
+    return any;
+}
+
+/* Snap-to-surface of object h released at frame F (Section 3.2), then the
+   placing heuristic (Appendix I): the object lands upright with the yaw of
+   its x axis; four spheres of the held class touching its bottom face from
+   inside (octant x, y; z = -e2 + r) are cast straight down through the
+   column grid: each drops to the bottom of the free layer holding its centre,
+   the object by the smallest of those drops.  The cast fails when a sphere
+   centre is outside the grid or in no free layer; the landed object fails
+   when one of its 8 octant spheres overlaps another resting object.  On a
+   failure the drop point moves by place_step along a jitter direction -- away
+   from the overlapped object, turned by a random angle in [-pi/4, pi/4), or
+   a random direction when the grid refused the cast -- and the cast is
+   repeated, up to O_PLACE_TRIES jitters.  If every try fails the object goes
+   back to its resting record from before the grasp. */
+static void place_object(const o_params *pr, const o_env *env, const o_manip *mp, const o_dyn *dy,
+                         int h, const float *F, uint64_t env_id, int32_t episode, int32_t t)
+{
+    float *ob = dy->objects + 8 * h;
+    const float *e = ob + 3;
+    float cx = F[0], sx = F[4];
+    float n2 = cx * cx + sx * sx;
+    float c = 1.0f, s = 0.0f;
+    if (n2 > 1e-12f) {
+        float len = sqrtf(n2);
+        c = cx / len;
+        s = sx / len;
+    }
+    float px = F[3], py = F[7], z0 = F[11];
+    float r = pr->class_radius[mp->held_class];
+    int cls = mp->held_class;
+    for (int k = 0; k <= O_PLACE_TRIES; ++k) {
+        int fail_static = 0, fail_obj = -1;
+        float drop = INFINITY;
+        for (int q = 0; q < 4; ++q) {
+            float p[3];
+            octant(e, q, p);
+            float w[3];
+            w[0] = px + (c * p[0] - s * p[1]);
+            w[1] = py + (s * p[0] + c * p[1]);
+            w[2] = z0 + (r - e[2]);
+            float inv_h = 1.0f / env->grid_cell;
+            float fx = (w[0] - env->grid_x0) * inv_h;
+            float fy = (w[1] - env->grid_y0) * inv_h;
+            if (!(fx >= 0.0f && fx < (float)env->nx && fy >= 0.0f && fy < (float)env->ny)) {
+                fail_static = 1;
+                break;
+            }
+            int i = (int)floorf(fx), j = (int)floorf(fy);
+            int64_t col = (int64_t)j * env->nx + i;
+            const uint32_t *off = env->grid_offsets[cls];
+            const float *lay = env->grid_layers[cls];
+            int found = 0;
+            for (uint32_t l = off[col]; l < off[col + 1]; ++l)
+                if (lay[2 * l] <= w[2] && w[2] <= lay[2 * l + 1]) {
+                    float d = w[2] - lay[2 * l];
+                    if (d < drop) drop = d;
+                    found = 1;
+                    break;
+                }
+            if (!found) { fail_static = 1; break; }
+        }
+        float rec[8] = {px, py, 0.0f, e[0], e[1], e[2], c, s};
+        if (!fail_static) {
+            rec[2] = z0 - drop;
+            float Fo[12];
+            object_frame(rec, Fo);
+            for (int q = 0; q < O_HELD_SPHERES && fail_obj < 0; ++q) {
+                float p[3], w[3];
+                octant(e, q, p);
+                frame_point(Fo, p, w);
+                for (int o = 0; o < env->num_objects; ++o) {
+                    if (o == h) continue;
+                    if (obb_contact(dy->objects + 8 * o, w, r)) { fail_obj = o; break; }
+                }
+            }
+            if (fail_obj < 0) {
+                memcpy(ob, rec, sizeof(rec));
+                return;
+            }
+        }
+        if (k == O_PLACE_TRIES) break;
+        float u = o_hash01(mp->seed, env_id, (uint64_t)(uint32_t)episode, (uint64_t)(uint32_t)t,
+                           (uint64_t)(16 + k));
+        float dx, dy2;
+        if (fail_obj >= 0) {
+            const float *oo = dy->objects + 8 * fail_obj;
+            float vx = px - oo[0], vy = py - oo[1];
+            float vn = sqrtf(vx * vx + vy * vy);
+            float bx = 1.0f, by = 0.0f;
+            if (vn > 1e-6f) { bx = vx / vn; by = vy / vn; }
+            float sphi, cphi;
+            o_sincos((u - 0.5f) * 0x1.921fb6p+0f, &sphi, &cphi);   /* [-pi/4, pi/4) */
+            dx = cphi * bx - sphi * by;
+            dy2 = sphi * bx + cphi * by;
+        } else {
+            float sphi, cphi;
+            o_sincos(u * K_TWO_PI - K_PI, &sphi, &cphi);
+            dx = cphi;
+            dy2 = sphi;
+        }
+        px = px + mp->place_step * dx;
+        py = py + mp->place_step * dy2;
+    }
+    /* every try failed: the object keeps its record from before the grasp */
+}
+
+/* One step with manipulation.  action: 11 floats, the 9 of o_robot_step, then
+   grasp/release (>= 0.5: grasp when nothing is held; otherwise a held object
+   is released; NaN counts as 0) and stop (>= 0.5 ends the episode).
+   accepted: 0 = no movement, 1 = the candidate, 2 = a slid candidate.
+   obj_frames [O][12]: every object's frame after the step (held: carried by
+   the end effector). */
+O_EXPORT void o_robot_step_manip(const o_robot *rb, const o_params *pr, const o_env *env,
+                                 const o_manip *mp, const o_dyn *dy, int32_t env_id,
+                                 float *state, int32_t *counters, const float *action,
+                                 uint32_t *mask_static, uint32_t *mask_object,
+                                 uint8_t *accepted, uint8_t *done, float *frames, float *cam,
+                                 float *obj_frames)
+{
+    float a0 = sanitize(action[0], pr->act_lim[0]);
+    float a1 = sanitize(action[1], pr->act_lim[1]);
+    float ag = action[9], as = action[10];
+    int grasp = ag == ag && ag >= 0.5f;
+    int stop = as == as && as >= 0.5f;
+    float cand[10];
+    float yaw = state[2] + a1;
+    if (yaw > K_PI) yaw = yaw - K_TWO_PI;
+    else if (yaw < -K_PI) yaw = yaw + K_TWO_PI;
+    float sy, cy;
+    o_sincos(yaw, &sy, &cy);
+    cand[0] = state[0] + a0 * cy;
+    cand[1] = state[1] + a0 * sy;
+    cand[2] = yaw;
+    for (int j = 0; j < 7; ++j) {
+        float aj = sanitize(action[2 + j], pr->act_lim[2]);
+        cand[3 + j] = clampf(state[3 + j] + aj, rb->qlim[j][0], rb->qlim[j][1]);
+    }
+
+    float sum[2];
+    int cnt = 0;
+    int any = pose_contacts(rb, pr, env, mp, dy, cand, mask_static, mask_object, sum, &cnt);
+    if (!any) {
+        memcpy(state, cand, sizeof(cand));
+        *accepted = 1;
+    } else {
+        *accepted = 0;
+        if (mp->slide) {
+            /* sliding (Appendix I): push the base away from the mean of the
+               overlapping spheres' centres, up to O_SLIDE_TRIES jitters */
+            int words = (rb->num_spheres + O_HELD_SPHERES + 31) / 32;
+            uint32_t ms[16], mo[16];
+            for (int k = 0; k < O_SLIDE_TRIES && words <= 16; ++k) {
+                float mx = sum[0] / (float)cnt, my = sum[1] / (float)cnt;
+                float vx = cand[0] - mx, vy = cand[1] - my;
+                float vn = sqrtf(vx * vx + vy * vy);
+                if (!(vn > 1e-6f)) break;
+                cand[0] = cand[0] + mp->slide_step * (vx / vn);
+                cand[1] = cand[1] + mp->slide_step * (vy / vn);
+                if (!pose_contacts(rb, pr, env, mp, dy, cand, ms, mo, sum, &cnt)) {
+                    memcpy(state, cand, sizeof(cand));
+                    *accepted = 2;
+                    break;
+                }
+            }
+        }
+    }
+
+    /* grasp / release at the resolved pose */
+    {
+        float fr[8 * 12];
+        o_fk(rb, state, fr);
+        const float *Fee = fr + 12 * 7;
+        int held = *dy->held;
+        if (grasp && held < 0) {
+            float tip[3];
+            frame_point(Fee, mp->grasp_tip, tip);
+            float r2 = mp->grasp_radius * mp->grasp_radius;
+            int best = -1;
+            float bd = 0.0f;
+            for (int o = 0; o < env->num_objects; ++o) {
+                float d2 = obb_dist2(dy->objects + 8 * o, tip);
+                if (d2 < r2 && (best < 0 || d2 < bd)) { best = o; bd = d2; }
+            }
+            if (best >= 0) {
+                float Fo[12], G[12];
+                object_frame(dy->objects + 8 * best, Fo);
+                frame_inverse(Fee, G);
+                frame_mul(G, Fo, dy->rel);
+                *dy->held = best;
+            }
+        } else if (!grasp && held >= 0) {
+            float F[12];
+            frame_mul(Fee, dy->rel, F);
+            place_object(pr, env, mp, dy, held, F, (uint64_t)(uint32_t)env_id, counters[1], counters[0]);
+            *dy->held = -1;
+        }
+    }
+
+    /* episode bookkeeping: horizon or stop action, auto-reset */
+    *done = 0;
+    counters[0] += 1;
+    if (stop || (pr->episode_len > 0 && counters[0] >= pr->episode_len)) {
+        counters[1] += 1;
+        int p = counters[1] % env->num_starts;
+        state[0] = env->starts[3 * p + 0];
+        state[1] = env->starts[3 * p + 1];
+        state[2] = env->starts[3 * p + 2];
+        for (int j = 0; j < 7; ++j) state[3 + j] = rb->q_home[j];
+        counters[0] = 0;
+        memcpy(dy->objects, dy->objects0, sizeof(float) * 8 * (size_t)env->num_objects);
+        *dy->held = -1;
+        *done = 1;
+    }
+    o_fk(rb, state, frames);
+    o_camera(rb, state, cam);
+    for (int o = 0; o < env->num_objects; ++o) {
+        if (o == *dy->held) frame_mul(frames + 12 * 7, dy->rel, obj_frames + 12 * o);
+        else object_frame(dy->objects + 8 * o, obj_frames + 12 * o);
+    }
+}
+
+/* The movable objects as render triangles: box corner k of object o =
+   F_o (+-e0, +-e1, +-e2) (bit 0 of k: x, bit 1: y, bit 2: z) at vertex 8 o + k;
+   12 triangles per object, wound counter-clockwise around the outward
+   normals, vertex indices offset by vbase.  verts [8 O][3], tris [12 O][3]. */
+O_EXPORT void o_object_mesh(const float *obj_frames, const float *objects, int O, int32_t vbase,
+                            float *verts, int32_t *tris)
+{
+    static const int faces[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4},
+                                    {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+    for (int o = 0; o < O; ++o) {
+        const float *e = objects + 8 * o + 3;
+        for (int k = 0; k < 8; ++k) {
+            float p[3] = {(k & 1) ? e[0] : -e[0], (k & 2) ? e[1] : -e[1], (k & 4) ? e[2] : -e[2]};
+            frame_point(obj_frames + 12 * o, p, verts + 3 * (8 * o + k));
+        }
+        for (int f = 0; f < 6; ++f) {
+            const int *q = faces[f];
+            int32_t *t0 = tris + 3 * (12 * o + 2 * f), *t1 = t0 + 3;
+            t0[0] = vbase + 8 * o + q[0]; t0[1] = vbase + 8 * o + q[1]; t0[2] = vbase + 8 * o + q[2];
+            t1[0] = vbase + 8 * o + q[0]; t1[1] = vbase + 8 * o + q[2]; t1[2] = vbase + 8 * o + q[3];
+        }
+    }
+}
+
 /* reset one environment to the start pose of its (incremented) episode */
 O_EXPORT void o_reset_env(const o_robot *rb, const o_env *env, float *state, int32_t *counters,
                           int new_episode)

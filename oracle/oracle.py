@@ -78,6 +78,16 @@ class OEnv(C.Structure):
                 ("num_starts", C.c_int32), ("starts", _fp), ("held", C.c_int32)]
 
 
+class OManip(C.Structure):
+    _fields_ = [("slide", C.c_int32), ("grasp_tip", C.c_float * 3), ("grasp_radius", C.c_float),
+                ("held_class", C.c_int32), ("slide_step", C.c_float), ("place_step", C.c_float),
+                ("seed", C.c_uint64)]
+
+
+class ODyn(C.Structure):
+    _fields_ = [("objects", _fp), ("objects0", _fp), ("held", _i32p), ("rel", _fp)]
+
+
 class ORStats(C.Structure):
     _fields_ = [("tris_in", C.c_int64), ("tris_front", C.c_int64), ("cand_px", C.c_int64),
                 ("frags", C.c_int64), ("clipped", C.c_int64)]
@@ -97,6 +107,10 @@ def _declare(L):
     L.o_robot_step.argtypes = [C.POINTER(ORobot), C.POINTER(OParams), C.POINTER(OEnv), _fp, _i32p,
                                _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp]
     L.o_reset_env.argtypes = [C.POINTER(ORobot), C.POINTER(OEnv), _fp, _i32p, C.c_int]
+    L.o_robot_step_manip.argtypes = [C.POINTER(ORobot), C.POINTER(OParams), C.POINTER(OEnv),
+                                     C.POINTER(OManip), C.POINTER(ODyn), C.c_int32, _fp, _i32p,
+                                     _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp, _fp]
+    L.o_object_mesh.argtypes = [_fp, _fp, C.c_int, C.c_int32, _fp, _i32p]
     L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
                            _u32p, _u32p, _u8p, C.POINTER(ORStats)]
 
@@ -220,7 +234,32 @@ class OracleBatch:
         n = len(self.envs)
         self.state = np.zeros((n, 10), np.float32)
         self.counters = np.zeros((n, 2), np.int32)
-        self.words = (robot.num_spheres + 31) // 32
+        self.manip = bool(cc.get("manip", False))
+        self.words = (robot.num_spheres + (8 if self.manip else 0) + 31) // 32
+        if self.manip:
+            m = OManip()
+            m.slide = 1 if cc.get("slide", False) else 0
+            m.grasp_tip[:] = [float(v) for v in np.asarray(cc["grasp_tip"], np.float32)]
+            m.grasp_radius = float(np.float32(cc["grasp_radius"]))
+            m.held_class = int(cc["held_class"])
+            m.slide_step = float(np.float32(cc["slide_step"]))
+            m.place_step = float(np.float32(cc["place_step"]))
+            m.seed = int(cc["seed"])
+            self.mparams = m
+            O = scenes.num_objects
+            self.objects = np.ascontiguousarray(scenes.objects[self.envs], np.float32).copy()
+            self.objects0 = self.objects.copy()
+            self.held = np.full(n, -1, np.int32)
+            self.rel = np.zeros((n, 12), np.float32)
+            self._dyn = []
+            for i in range(n):
+                d = ODyn()
+                d.objects = ptr(self.objects[i], _fp)
+                d.objects0 = ptr(self.objects0[i], _fp)
+                d.held = ptr(self.held[i:i + 1], _i32p)
+                d.rel = ptr(self.rel[i], _fp)
+                self._dyn.append(d)
+            self.obj_frames = np.zeros((n, O, 12), np.float32)
         self._env_structs = []
         self._env_keep = []
         for e in self.envs:
@@ -268,22 +307,58 @@ class OracleBatch:
                 L.o_reset_env(C.byref(self.robot), C.byref(self._env_structs[i]),
                               ptr(self.state[i], _fp), ptr(self.counters[i], _i32p), 1)
 
-    def set_state(self, state: np.ndarray, counters: np.ndarray):
+    def set_state(self, state: np.ndarray, counters: np.ndarray, objects=None, held=None, rel=None):
         self.state[...] = state
         self.counters[...] = counters
+        if objects is not None:
+            self.objects[...] = objects
+        if held is not None:
+            self.held[...] = held
+        if rel is not None:
+            self.rel[...] = rel
+
+    def env_render_mesh(self, i):
+        """Render triangles of env i: its static mesh and, in the manipulation
+        workload, a box for every movable object where it is now (ids after the
+        static triangles, no face plane)."""
+        e = self.envs[i]
+        v, t, rgb = self.scenes.env_mesh(e)
+        planes = self.scenes.env_planes(e)
+        if not self.manip:
+            return v, t, rgb, planes
+        O = self.scenes.num_objects
+        ov = np.zeros((8 * O, 3), np.float32)
+        ot = np.zeros((12 * O, 3), np.int32)
+        lib().o_object_mesh(ptr(self.obj_frames[i], _fp), ptr(self.objects[i], _fp), O, v.shape[0],
+                            ptr(ov, _fp), ptr(ot, _i32p))
+        nop = np.tile(np.array([0.0, 0.0, 0.0, -1.0], np.float32), (12 * O, 1))
+        orgb = np.repeat(self.scenes.obj_rgb[e], 12, axis=0)
+        return (np.concatenate([v, ov]), np.concatenate([t, ot]), np.concatenate([rgb, orgb]),
+                None if planes is None else np.concatenate([planes, nop]))
 
     def _step_env(self, i, act, out):
         L = lib()
         e = self.envs[i]
-        L.o_robot_step(C.byref(self.robot), C.byref(self.params), C.byref(self._env_structs[i]),
-                       ptr(self.state[i], _fp), ptr(self.counters[i], _i32p), ptr(act, _fp),
-                       ptr(out["contact_static"][i], _u32p), ptr(out["contact_object"][i], _u32p),
-                       ptr(out["accepted"][i:i + 1], _u8p), ptr(out["done"][i:i + 1], _u8p),
-                       ptr(out["frames"][i], _fp), ptr(out["cam"][i], _fp))
+        if self.manip:
+            L.o_robot_step_manip(C.byref(self.robot), C.byref(self.params),
+                                 C.byref(self._env_structs[i]), C.byref(self.mparams),
+                                 C.byref(self._dyn[i]), e, ptr(self.state[i], _fp),
+                                 ptr(self.counters[i], _i32p), ptr(act, _fp),
+                                 ptr(out["contact_static"][i], _u32p),
+                                 ptr(out["contact_object"][i], _u32p),
+                                 ptr(out["accepted"][i:i + 1], _u8p), ptr(out["done"][i:i + 1], _u8p),
+                                 ptr(out["frames"][i], _fp), ptr(out["cam"][i], _fp),
+                                 ptr(self.obj_frames[i], _fp))
+        else:
+            L.o_robot_step(C.byref(self.robot), C.byref(self.params), C.byref(self._env_structs[i]),
+                           ptr(self.state[i], _fp), ptr(self.counters[i], _i32p), ptr(act, _fp),
+                           ptr(out["contact_static"][i], _u32p), ptr(out["contact_object"][i], _u32p),
+                           ptr(out["accepted"][i:i + 1], _u8p), ptr(out["done"][i:i + 1], _u8p),
+                           ptr(out["frames"][i], _fp), ptr(out["cam"][i], _fp))
         res = int(self.scenes.res[e])
-        v, t, _rgb = self.scenes.env_mesh(e)
+        v, t, _rgb, planes = self.env_render_mesh(i)
         depth, win, _cov, stats = render(v, t, out["cam"][i], res, res, self.near, self.far,
-                                         want_id=self.color, planes=self.scenes.env_planes(e))
+                                         want_id=self.color, planes=planes)
         out["depth"][i] = depth
         if self.color:
             rgb = np.zeros((res, res, 3), np.uint8)
@@ -308,6 +383,11 @@ class OracleBatch:
                 list(ex.map(lambda i: self._step_env(i, actions[i], out), range(n)))
         out["state"] = self.state.copy()
         out["counters"] = self.counters.copy()
+        if self.manip:
+            out["objects"] = self.objects.copy()
+            out["held"] = self.held.copy()
+            out["rel"] = self.rel.copy()
+            out["obj_frames"] = self.obj_frames.copy()
         return out
 
 

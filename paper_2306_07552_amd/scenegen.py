@@ -38,6 +38,10 @@ import numpy as np
 # (Appendix G); the configs draw radii in [0.04, 0.12] m, which snap *up* to
 # the next class (conservative).
 RADIUS_CLASSES = (0.06, 0.08, 0.10, 0.12)
+# The paper's own working set (Appendix G: 1.5, 5 and 12 cm), used by the
+# manipulation workload, whose held objects need a radius that fits inside a
+# 5 cm box.
+RADIUS_CLASSES_PAPER = (0.015, 0.05, 0.12)
 
 ROOM_X = 4.0
 ROOM_Y = 6.0
@@ -88,6 +92,9 @@ class SceneSet:
     res: np.ndarray           # i32 [N] square depth resolution per env
     tri_plane: Optional[np.ndarray] = None   # f32 [T][4] outward unit normal, offset of each
                                              # triangle's face (n . p = w on the face)
+    obj_rgb: Optional[np.ndarray] = None     # u8 [N][O][3] flat colour of each movable object
+                                             # (manipulation workload: objects are not in the
+                                             # static mesh but drawn where they are)
 
     def env_mesh(self, e: int):
         v0, v1 = int(self.vert_offset[e]), int(self.vert_offset[e + 1])
@@ -129,6 +136,8 @@ class Config:
     far: float = 10.0
     act_lim: Sequence[float] = (0.1, 0.1, 0.05)
     color: bool = False
+    manip: bool = False              # grasp / release / place / slide, 11-float actions
+    radius_set: Sequence[float] = RADIUS_CLASSES
 
 
 # The five workloads (sizes and distributions of the paper-scale step).
@@ -141,7 +150,21 @@ CONFIGS = {
               (2000.0, 200000.0), tri_target_log=True, res_choices=(64, 128, 256)),
     4: Config("mixed-8192env-2k-200k-tris-128px-rgb", 5, 8192, 128, 8, True, 8, (2, 6),
               (2000.0, 200000.0), tri_target_log=True, color=True),
+    # the rest of the kinematic sim of Section 3.2 / Appendix I on the
+    # paper-scale step: grasp, carry, release with snap-to-surface and the
+    # placing heuristic, sliding; the paper's radius working set
+    5: Config("manip-1024env-128px-20k-80k-tris", 6, 1024, 128, 8, False, 8, (2, 6),
+              (20000.0, 80000.0), steps=1000, episode_len=500, manip=True,
+              radius_set=RADIUS_CLASSES_PAPER),
 }
+
+# Manipulation constants (Section 3.2: a small sphere at the end-effector tip,
+# read as 3 cm across; the jitter steps of Appendix I's heuristics are this
+# build's choice).
+GRASP_TIP = (0.0, 0.0, 0.10)
+GRASP_RADIUS = 0.015
+SLIDE_STEP = 0.05
+PLACE_STEP = 0.10
 
 
 def scaled_config(base: int, num_envs: int, **kw) -> Config:
@@ -153,7 +176,8 @@ def scaled_config(base: int, num_envs: int, **kw) -> Config:
 # --------------------------------------------------------------------------
 # robot
 # --------------------------------------------------------------------------
-def make_robot(seed: int, spheres_per_link: int, held_proxy: bool) -> Robot:
+def make_robot(seed: int, spheres_per_link: int, held_proxy: bool,
+               classes: Sequence[float] = RADIUS_CLASSES) -> Robot:
     rng = np.random.default_rng([seed, 0xB0B])
     dh = np.zeros((7, 4), np.float32)
     alpha_choices = [(0.0, -1.0), (1.0, 0.0), (0.0, 1.0)]  # -pi/2, 0, +pi/2 (exact)
@@ -178,7 +202,7 @@ def make_robot(seed: int, spheres_per_link: int, held_proxy: bool) -> Robot:
             links.append(link)
             pos.append(p)
             radius.append(rng.uniform(0.04, 0.12))
-    cls = [snap_class(r) for r in radius]
+    cls = [snap_class(r, classes) for r in radius]
     held_only = [0] * len(links)
     if held_proxy:
         # one sphere for the held object, on the end-effector frame
@@ -194,11 +218,11 @@ def make_robot(seed: int, spheres_per_link: int, held_proxy: bool) -> Robot:
                  sphere_held_only=np.asarray(held_only, np.uint8))
 
 
-def snap_class(r: float) -> int:
-    for k, rk in enumerate(RADIUS_CLASSES):
+def snap_class(r: float, classes: Sequence[float] = RADIUS_CLASSES) -> int:
+    for k, rk in enumerate(classes):
         if rk >= r:
             return k
-    return len(RADIUS_CLASSES) - 1
+    return len(classes) - 1
 
 
 # --------------------------------------------------------------------------
@@ -425,8 +449,9 @@ def make_scene(cfg: Config, env: int):
     if furniture:
         fb = np.asarray(furniture, np.float64)
         add(*boxes_mesh(fb[:, :3], fb[:, 3:], n_sub), boxes_planes(fb[:, :3], fb[:, 3:], n_sub))
-    for o in objs:
-        add(*obb_mesh(o[:3], o[3:6], o[6], o[7]), obb_planes(o[:3], o[3:6], o[6], o[7]))
+    if not cfg.manip:
+        for o in objs:
+            add(*obb_mesh(o[:3], o[3:6], o[6], o[7]), obb_planes(o[:3], o[3:6], o[6], o[7]))
 
     verts, tris, base = [], [], 0
     for v, t in zip(parts_v, parts_t):
@@ -448,6 +473,8 @@ def make_scene(cfg: Config, env: int):
     if cfg.res_choices:
         res = int(cfg.res_choices[int(rng.integers(0, len(cfg.res_choices)))])
     held = int(rng.uniform() < 0.5) if cfg.held_proxy else 0
+    # drawn last, so that the other workloads' scenes are unchanged
+    obj_rgb = rng.integers(0, 256, size=(len(objs), 3), dtype=np.uint8) if cfg.manip else None
     nx = int(round(W / CELL))
     ny = int(round(H / CELL))
     return dict(verts=verts, tris=tris, rgb=rgb, planes=planes,
@@ -455,7 +482,7 @@ def make_scene(cfg: Config, env: int):
                 objects=np.asarray(objs, np.float32).reshape(-1, 8),
                 grid_origin=np.array([0.0, 0.0], np.float32),
                 grid_dims=np.array([nx, ny], np.int32),
-                starts=starts, held=held, res=res)
+                starts=starts, held=held, res=res, obj_rgb=obj_rgb)
 
 
 def make_scene_set(cfg: Config, envs: Optional[Sequence[int]] = None) -> SceneSet:
@@ -489,11 +516,13 @@ def make_scene_set(cfg: Config, envs: Optional[Sequence[int]] = None) -> SceneSe
         held=np.asarray([s["held"] for s in scenes], np.uint8),
         res=np.asarray([s["res"] for s in scenes], np.int32),
         tri_plane=np.ascontiguousarray(np.concatenate([s["planes"] for s in scenes])),
+        obj_rgb=(np.ascontiguousarray(np.stack([s["obj_rgb"] for s in scenes]))
+                 if cfg.manip else None),
     )
 
 
 def make_robot_for(cfg: Config) -> Robot:
-    return make_robot(cfg.seed, cfg.num_spheres_per_link, cfg.held_proxy)
+    return make_robot(cfg.seed, cfg.num_spheres_per_link, cfg.held_proxy, tuple(cfg.radius_set))
 
 
 # --------------------------------------------------------------------------
@@ -509,9 +538,21 @@ def actions(cfg: Config, step: int, num_envs: Optional[int] = None,
     lim = np.array([cfg.act_lim[0], cfg.act_lim[1]] + [cfg.act_lim[2]] * 7, np.float64)
     full_n = int(ids.max()) + 1 if ids.size else 0
     u = rng.uniform(-1.0, 1.0, size=(max(full_n, 1), 9))
-    return (u[ids] * lim).astype(np.float32)
+    a = (u[ids] * lim).astype(np.float32)
+    if cfg.manip:
+        # grasp / release as a 0/1 value (grasp intent 60 % of steps, so that
+        # objects are both picked and dropped), stop rarely
+        d = rng.uniform(0.0, 1.0, size=(max(full_n, 1), 2))[ids]
+        extra = np.stack([(d[:, 0] < 0.6), (d[:, 1] < 0.002)], axis=1).astype(np.float32)
+        a = np.concatenate([a, extra], axis=1)
+    return a
 
 
 def config_constants(cfg: Config) -> dict:
-    return dict(near=cfg.near, far=cfg.far, cell=CELL, radius_classes=RADIUS_CLASSES,
-                act_lim=tuple(cfg.act_lim), episode_len=cfg.episode_len, res0=cfg.res0)
+    c = dict(near=cfg.near, far=cfg.far, cell=CELL, radius_classes=tuple(cfg.radius_set),
+             act_lim=tuple(cfg.act_lim), episode_len=cfg.episode_len, res0=cfg.res0)
+    if cfg.manip:
+        c.update(manip=True, slide=True, grasp_tip=GRASP_TIP, grasp_radius=GRASP_RADIUS,
+                 held_class=0, slide_step=SLIDE_STEP, place_step=PLACE_STEP,
+                 seed=cfg.seed * 1000003 + 17)
+    return c
