@@ -52,6 +52,11 @@ extern "C" {
 
 /* flags of gal_config.flags */
 #define GAL_COLOR 0x1u      /* also produce flat-shaded RGB8 per pixel         */
+#define GAL_MANIP 0x2u      /* grasp / carry / release of the movable objects
+                               (Section 3.2, Appendix I): 11-float actions,
+                               objects move and are drawn where they are     */
+#define GAL_SLIDE 0x4u      /* with GAL_MANIP: a collision slides the base
+                               instead of stopping it (Appendix I.1)         */
 
 /*
  * Robot (Section 3.2 / Appendix G): a planar base (x, y, yaw) and a 7-DoF
@@ -75,6 +80,14 @@ typedef struct gal_robot {
     const float *sphere_pos;    /* [S][3] centre in the link frame           */
     const int32_t *sphere_class;/* [S] radius class index                    */
     const uint8_t *sphere_held_only; /* [S] or NULL (none held-only)         */
+    /* GAL_MANIP (Section 3.2 suction grasp): the grasp sphere at grasp_tip in
+       the end-effector frame (link 7), its radius, and the radius class of a
+       held object's 8 octant spheres.  Ignored without GAL_MANIP.  With
+       GAL_MANIP the held-only spheres above are not used (the held object's
+       own spheres replace them). */
+    float grasp_tip[3];
+    float grasp_radius;
+    int32_t held_class;
 } gal_robot;
 
 /*
@@ -119,6 +132,13 @@ typedef struct gal_scene_set {
                                    lets the renderer skip whole groups of them.
                                    At most GAL_MAX_PLANES distinct planes per
                                    env (GAL_EINVAL otherwise).               */
+    const uint8_t *obj_rgb;     /* [N][O][3] flat colour of each movable
+                                   object (GAL_MANIP with GAL_COLOR), or NULL.
+                                   With GAL_MANIP the render mesh holds only
+                                   the static scene: every object is drawn as
+                                   its box where it is, 12 triangles numbered
+                                   after the env's mesh triangles, culled by
+                                   their winding only.                       */
 } gal_scene_set;
 
 typedef struct gal_config {
@@ -129,7 +149,12 @@ typedef struct gal_config {
     float class_radius[GAL_MAX_CLASSES];
     float act_lim[3];           /* |forward| m, |yaw| rad, |joint delta| rad */
     int32_t episode_len;        /* steps per episode; 0 = never auto-reset   */
-    uint32_t flags;             /* GAL_COLOR                                 */
+    uint32_t flags;             /* GAL_COLOR | GAL_MANIP | GAL_SLIDE         */
+    /* GAL_MANIP (Appendix I): base jitter per sliding try and object jitter
+       per placing try (m), and the seed of the placing jitter's counter-based
+       randomness */
+    float slide_step, place_step;
+    uint64_t manip_seed;
 } gal_config;
 
 /*
@@ -154,6 +179,10 @@ typedef struct gal_outputs {
     float *frames;              /* [N][8][12] link frames (3x4 row-major)    */
     int32_t *counters;          /* [N][2] step in episode, episode index     */
     uint8_t *done;              /* [N] 1 = the episode ended at this step    */
+    float *object_frames;       /* [N][O][12] GAL_MANIP: every object's frame
+                                   after the step (3x4 row-major; a held one
+                                   is carried by the end effector)           */
+    int32_t *held;              /* [N] GAL_MANIP: held object, -1 = none     */
 } gal_outputs;
 
 typedef struct gal_batch gal_batch;   /* opaque, owned by the library */
@@ -199,6 +228,21 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
  *     (gal_reset semantics) and `done` is set;
  *  5. frames and the depth (and colour) image are produced for the final
  *     state.  With out->depth NULL only the physics runs (no image).
+ * With GAL_MANIP (Section 3.2 grasping and snap-to-surface, Appendix I):
+ * actions are [N][11], the 9 above then grasp/release (>= 0.5: grasp when
+ * nothing is held -- the nearest object overlapping the grasp sphere is
+ * fixed to the end effector -- otherwise a held object is released; NaN
+ * counts as 0) and stop (>= 0.5 ends the episode like the horizon).  A held
+ * object's 8 octant spheres join the overlap test; resting objects are
+ * tested as boxes.  With GAL_SLIDE a rejected move is retried up to 3 times
+ * with the base moved slide_step away from the mean centre of the
+ * overlapping spheres (accepted = 2 when one of those is taken).  A release
+ * sets the object upright (yaw of its x axis), casts 4 spheres of its bottom
+ * face down the held class's column grid, lands it on the highest surface
+ * they meet, and retries up to 6 times, jittered by place_step, while the
+ * cast fails or the landed box overlaps another object; then it returns to
+ * where it was grasped.  Contact words then cover S + 8 spheres (bits S..S+7
+ * = the held object's).  An episode start restores every object.
  * Errors: GAL_EINVAL (NULL batch/actions/outputs, rgb without GAL_COLOR or
  * without depth),
  * GAL_EDEVICE (launch failure).
@@ -302,7 +346,10 @@ int gal_depth_offsets(const gal_batch *b, int64_t *offsets_host, size_t count);
  * base pose and joint angles; objects and scene are static in this step) and
  * the episode counters of Section 4.1 (synchronises `stream`):
  * host buffer of N * (10 floats + 2 int32) bytes, laid out as f32 state
- * [N][10] followed by i32 counters [N][2].  GAL_ESTATE when `bytes` differs.
+ * [N][10] followed by i32 counters [N][2]; with GAL_MANIP followed by f32
+ * objects [N][O][8] (resting records; a held object's from before its
+ * grasp), i32 held [N] and f32 rel [N][12] (the held object's frame in the
+ * end-effector frame).  GAL_ESTATE when `bytes` differs.
  */
 int gal_get_state(gal_batch *b, void *host, size_t bytes, void *stream);
 int gal_set_state(gal_batch *b, const void *host, size_t bytes, void *stream);

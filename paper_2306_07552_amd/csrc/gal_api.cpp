@@ -254,6 +254,9 @@ struct gal_batch {
     // autotuner scratch (allocated on the first gal_autotune, reused after)
     float *tune_st0 = nullptr;
     int32_t *tune_cnt0 = nullptr;
+    float *tune_obj0 = nullptr;      // manipulation: objects, held, rel
+    int32_t *tune_held0 = nullptr;
+    float *tune_rel0 = nullptr;
     unsigned long long *tune_hash = nullptr;
     // captured step graph and what it was captured for
     hipStream_t cap_stream = nullptr;
@@ -444,11 +447,21 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
         ((rc = b->mem.alloc(&b->tune_st0, (size_t)b->N * 10)) ||
          (rc = b->mem.alloc(&b->tune_cnt0, (size_t)b->N * 2)) || (rc = b->mem.alloc(&b->tune_hash, 1))))
         return rc;
+    const size_t nobj = (size_t)b->N * b->O * 8;
+    if (b->rp.manip && !b->tune_obj0 &&
+        ((rc = b->mem.alloc(&b->tune_obj0, std::max<size_t>(nobj, 1))) ||
+         (rc = b->mem.alloc(&b->tune_held0, (size_t)b->N)) || (rc = b->mem.alloc(&b->tune_rel0, (size_t)b->N * 12))))
+        return rc;
     float *st0 = b->tune_st0;
     int32_t *cnt0 = b->tune_cnt0;
     unsigned long long *hash = b->tune_hash;
     HIP_TRY(hipMemcpyAsync(st0, b->sb.state, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(cnt0, b->sb.counters, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
+    if (b->rp.manip) {
+        HIP_TRY(hipMemcpyAsync(b->tune_obj0, b->sb.obj_dyn, sizeof(float) * nobj, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->tune_held0, b->sb.held_obj, sizeof(int32_t) * b->N, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->tune_rel0, b->sb.rel, sizeof(float) * b->N * 12, hipMemcpyDeviceToDevice, s));
+    }
     // the surrogate's query counters are not the tuner's to change: saved here,
     // restored at the end
     unsigned long long sur_stats0[4] = {0, 0, 0, 0};
@@ -462,6 +475,11 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     auto restore = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(b->sb.state, st0, sizeof(float) * b->N * 10, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(b->sb.counters, cnt0, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToDevice, s));
+        if (b->rp.manip) {
+            HIP_TRY(hipMemcpyAsync(b->sb.obj_dyn, b->tune_obj0, sizeof(float) * nobj, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(b->sb.held_obj, b->tune_held0, sizeof(int32_t) * b->N, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(b->sb.rel, b->tune_rel0, sizeof(float) * b->N * 12, hipMemcpyDeviceToDevice, s));
+        }
         return GAL_OK;
     };
     std::vector<gal_tuning> cands;
@@ -634,6 +652,17 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     }
     for (int k = 0; k < cfg->num_classes; ++k)
         if (!(cfg->class_radius[k] > 0.0f)) return fail(GAL_EINVAL, "class radius must be > 0");
+    const bool manip = (cfg->flags & GAL_MANIP) != 0;
+    if ((cfg->flags & GAL_SLIDE) && !manip) return fail(GAL_EINVAL, "GAL_SLIDE needs GAL_MANIP");
+    if (manip) {
+        if (robot->held_class < 0 || robot->held_class >= cfg->num_classes)
+            return fail(GAL_EINVAL, "held_class out of range");
+        if (!(robot->grasp_radius > 0.0f)) return fail(GAL_EINVAL, "grasp_radius must be > 0");
+        if (!(cfg->slide_step >= 0.0f) || !(cfg->place_step >= 0.0f))
+            return fail(GAL_EINVAL, "slide_step and place_step must be >= 0");
+        if ((cfg->flags & GAL_COLOR) && sc->num_objects > 0 && !sc->obj_rgb)
+            return fail(GAL_EINVAL, "GAL_MANIP with GAL_COLOR needs obj_rgb");
+    }
 
     gal_batch *b = new gal_batch();
     auto cleanup = [&](int code) {
@@ -645,7 +674,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     b->K = cfg->num_classes;
     b->O = sc->num_objects;
     b->P = sc->num_starts;
-    b->words = (b->S + 31) / 32;
+    b->words = (b->S + (manip ? gal::kHeldSpheres : 0) + 31) / 32;
     b->flags = cfg->flags;
 
     // ---- per-env resolution, depth offsets
@@ -695,6 +724,16 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     rp.num_starts = b->P;
     rp.episode_len = cfg->episode_len;
     rp.contact_words = b->words;
+    rp.manip = manip ? 1 : 0;
+    rp.slide = (cfg->flags & GAL_SLIDE) ? 1 : 0;
+    if (manip) {
+        memcpy(rp.grasp_tip, robot->grasp_tip, sizeof(rp.grasp_tip));
+        rp.grasp_radius = robot->grasp_radius;
+        rp.held_class = robot->held_class;
+        rp.slide_step = cfg->slide_step;
+        rp.place_step = cfg->place_step;
+        rp.manip_seed = cfg->manip_seed;
+    }
 
     int rc;
     // ---- spheres, per-env tables
@@ -751,6 +790,19 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     sb.cell = cfg->cell_m;
     sb.inv_cell = 1.0f / cfg->cell_m;
     sb.num_envs = N;
+    if (manip) {
+        // movable objects: resting records (a copy of those at episode start),
+        // the held object and its pose in the end-effector frame, the frames
+        const size_t no = (size_t)N * std::max(b->O, 1);
+        if ((rc = b->mem.alloc(&sb.obj_dyn, no * 8)) || (rc = b->mem.alloc(&sb.held_obj, (size_t)N)) ||
+            (rc = b->mem.alloc(&sb.rel, (size_t)N * 12)) || (rc = b->mem.alloc(&sb.obj_frames, no * 12)))
+            return cleanup(rc);
+        if (b->O > 0)
+            HIP_TRY(hipMemcpy(sb.obj_dyn, d_obj, sizeof(float) * (size_t)N * b->O * 8, hipMemcpyDeviceToDevice));
+        HIP_TRY(hipMemset(sb.held_obj, 0xFF, sizeof(int32_t) * N));
+        HIP_TRY(hipMemset(sb.rel, 0, sizeof(float) * N * 12));
+        HIP_TRY(hipMemset(sb.obj_frames, 0, sizeof(float) * no * 12));
+    }
 
     // ---- column grids: count, scan, fill (on the device)
     {
@@ -910,6 +962,17 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
             HIP_TRY(hipMemcpy(d_rgb, sc->tri_rgb, nt_tot * 3, hipMemcpyHostToDevice));
             b->mesh.tri_rgb = d_rgb;
         }
+        if (manip && b->O > 0) {
+            b->mesh.obj_frames = b->sb.obj_frames;
+            b->mesh.obj_rec = b->sb.objects;
+            b->mesh.num_objects = b->O;
+            if ((cfg->flags & GAL_COLOR) && sc->obj_rgb) {
+                uint8_t *d_orgb;
+                if ((rc = b->mem.alloc(&d_orgb, (size_t)N * b->O * 3))) return cleanup(rc);
+                HIP_TRY(hipMemcpy(d_orgb, sc->obj_rgb, (size_t)N * b->O * 3, hipMemcpyHostToDevice));
+                b->mesh.obj_rgb = d_orgb;
+            }
+        }
     }
 
     // ---- raster parameters and the (env, region) work list
@@ -1030,6 +1093,8 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     so.frames = out->frames;
     so.counters = out->counters;
     so.done = out->done;
+    so.object_frames = out->object_frames;
+    so.held = out->held;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     gal::SimBuffers sb = b->sb;
     if (b->sur) {
@@ -1063,7 +1128,8 @@ bool same_outputs(const gal_outputs &a, const gal_outputs &c)
 {
     return a.depth == c.depth && a.rgb == c.rgb && a.contact_static == c.contact_static &&
            a.contact_object == c.contact_object && a.accepted == c.accepted && a.state == c.state &&
-           a.frames == c.frames && a.counters == c.counters && a.done == c.done;
+           a.frames == c.frames && a.counters == c.counters && a.done == c.done &&
+           a.object_frames == c.object_frames && a.held == c.held;
 }
 
 // Replay the step graph, capturing it first if the pointers or tuning changed.
@@ -1101,6 +1167,8 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
     if (!b || !actions_dev || !out)
         return fail(GAL_EINVAL, "gal_step needs a batch, actions and outputs");
     if (out->rgb && !out->depth) return fail(GAL_EINVAL, "rgb output needs the depth output");
+    if (!b->rp.manip && (out->object_frames || out->held))
+        return fail(GAL_EINVAL, "object frames and held outputs need GAL_MANIP");
     if (out->rgb && !(b->flags & GAL_COLOR))
         return fail(GAL_EINVAL, "rgb output requested but the batch was created without GAL_COLOR");
     hipStream_t s = (hipStream_t)stream;
@@ -1199,6 +1267,7 @@ int gal_surrogate_attach(gal_batch *b, gal_mlp *m, float skip_below, uint32_t au
 {
     if (!b || !m) return fail(GAL_EINVAL, "null argument");
     if (!(skip_below >= 0.0f && skip_below < 1.0f)) return fail(GAL_EINVAL, "skip_below must be in [0, 1)");
+    if (b->rp.manip) return fail(GAL_EINVAL, "the surrogate pre-filter is not available with GAL_MANIP");
     if (gal::mlp_max_rows(m) < b->N)
         return fail(GAL_EINVAL, "the MLP was created for %d rows, the batch has %d envs", gal::mlp_max_rows(m), b->N);
     hipStream_t s = (hipStream_t)stream;
@@ -1274,31 +1343,61 @@ int gal_depth_offsets(const gal_batch *b, int64_t *offsets_host, size_t count)
     return GAL_OK;
 }
 
+namespace {
+// bytes of the manipulation part of the state (0 without GAL_MANIP)
+size_t manip_state_bytes(const gal_batch *b)
+{
+    if (!b->rp.manip) return 0;
+    return (size_t)b->N * (sizeof(float) * 8 * b->O + sizeof(int32_t) + sizeof(float) * 12);
+}
+}  // namespace
+
 int gal_get_state(gal_batch *b, void *host, size_t bytes, void *stream)
 {
     if (!b || !host) return fail(GAL_EINVAL, "null argument");
-    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t));
+    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t)) + manip_state_bytes(b);
     if (bytes != need) return fail(GAL_ESTATE, "state buffer must be %zu bytes", need);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     char *h = static_cast<char *>(host);
     HIP_TRY(hipMemcpy(h, b->sb.state, sizeof(float) * b->N * 10, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(h + sizeof(float) * b->N * 10, b->sb.counters, sizeof(int32_t) * b->N * 2,
-                      hipMemcpyDeviceToHost));
+    h += sizeof(float) * b->N * 10;
+    HIP_TRY(hipMemcpy(h, b->sb.counters, sizeof(int32_t) * b->N * 2, hipMemcpyDeviceToHost));
+    h += sizeof(int32_t) * b->N * 2;
+    if (b->rp.manip) {
+        HIP_TRY(hipMemcpy(h, b->sb.obj_dyn, sizeof(float) * b->N * b->O * 8, hipMemcpyDeviceToHost));
+        h += sizeof(float) * b->N * b->O * 8;
+        HIP_TRY(hipMemcpy(h, b->sb.held_obj, sizeof(int32_t) * b->N, hipMemcpyDeviceToHost));
+        h += sizeof(int32_t) * b->N;
+        HIP_TRY(hipMemcpy(h, b->sb.rel, sizeof(float) * b->N * 12, hipMemcpyDeviceToHost));
+    }
     return GAL_OK;
 }
 
 int gal_set_state(gal_batch *b, const void *host, size_t bytes, void *stream)
 {
     if (!b || !host) return fail(GAL_EINVAL, "null argument");
-    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t));
+    const size_t need = (size_t)b->N * (10 * sizeof(float) + 2 * sizeof(int32_t)) + manip_state_bytes(b);
     if (bytes != need) return fail(GAL_ESTATE, "state buffer must be %zu bytes", need);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     const char *h = static_cast<const char *>(host);
     HIP_TRY(hipMemcpy(b->sb.state, h, sizeof(float) * b->N * 10, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->sb.counters, h + sizeof(float) * b->N * 10, sizeof(int32_t) * b->N * 2,
-                      hipMemcpyHostToDevice));
+    h += sizeof(float) * b->N * 10;
+    HIP_TRY(hipMemcpy(b->sb.counters, h, sizeof(int32_t) * b->N * 2, hipMemcpyHostToDevice));
+    h += sizeof(int32_t) * b->N * 2;
+    if (b->rp.manip) {
+        const int32_t *held = reinterpret_cast<const int32_t *>(h + sizeof(float) * b->N * b->O * 8);
+        for (int e = 0; e < b->N; ++e)
+            if (held[e] < -1 || held[e] >= b->O) return fail(GAL_ESTATE, "env %d: held object %d out of range", e, held[e]);
+        HIP_TRY(hipMemcpy(b->sb.obj_dyn, h, sizeof(float) * b->N * b->O * 8, hipMemcpyHostToDevice));
+        h += sizeof(float) * b->N * b->O * 8;
+        HIP_TRY(hipMemcpy(b->sb.held_obj, h, sizeof(int32_t) * b->N, hipMemcpyHostToDevice));
+        h += sizeof(int32_t) * b->N;
+        HIP_TRY(hipMemcpy(b->sb.rel, h, sizeof(float) * b->N * 12, hipMemcpyHostToDevice));
+        HIP_TRY(gal::launch_object_frames(b->rp, b->sb, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return GAL_OK;
 }
 

@@ -34,7 +34,18 @@ struct RobotParams {
     int32_t num_starts;
     int32_t episode_len;
     int32_t contact_words;
+    // manipulation (grasp / release / place / slide); manip = 0 elsewhere
+    int32_t manip;              // 1: 11-float actions, movable objects
+    int32_t slide;              // 1: a collision slides the base
+    float grasp_tip[3];         // end-effector-frame point of the grasp sphere
+    float grasp_radius;
+    int32_t held_class;         // radius class of a held object's spheres
+    float slide_step, place_step;
+    uint64_t manip_seed;
 };
+
+// Spheres of a held object (one per octant of its box).
+constexpr int kHeldSpheres = 8;
 
 struct ClassRadii {
     float r[kMaxClasses];
@@ -74,6 +85,12 @@ struct SimBuffers {
     const uint8_t *skip_flags;       // [N] surrogate routing (null = exact check for all):
                                      // 1 = skip the static check, 2 = skipped but audited
     unsigned long long *sur_stats;   // [4] queries, skipped, audited, audit mismatches
+    // manipulation state (null unless RobotParams::manip); `objects` above
+    // then holds every object's record at episode start
+    float *obj_dyn;                  // [N][O][8] resting records (the held one: before the grasp)
+    int32_t *held_obj;               // [N] held object, -1 = none
+    float *rel;                      // [N][12] held object's frame in the end-effector frame
+    float *obj_frames;               // [N][O][12] object frames after the step (for the raster)
 };
 
 // Step outputs (device, caller-owned).
@@ -85,6 +102,8 @@ struct StepOutputs {
     float *frames;
     int32_t *counters;
     uint8_t *done;
+    float *object_frames;   // [N][O][12] (manipulation)
+    int32_t *held;          // [N] (manipulation)
 };
 
 // Render cluster: up to 64 consecutive triangles of one env, the unique
@@ -107,6 +126,12 @@ struct RenderMesh {
     const uint32_t *ctris;           // [C][64] packed i0 | i1<<8 | i2<<16 | plane slot<<24
     const uint8_t *tri_rgb;          // [T][3] in original order per env, or null
     const uint64_t *env_tri_off;     // [N+1] for colour lookup
+    // movable objects drawn where they are (manipulation; null elsewhere):
+    // a box per object, its 12 triangles numbered after the env's mesh
+    const float *obj_frames;         // [N][O][12]
+    const float *obj_rec;            // [N][O][8] (half extents at [3..5])
+    const uint8_t *obj_rgb;          // [N][O][3] or null
+    int32_t num_objects;
 };
 
 struct RasterParams {
@@ -133,6 +158,9 @@ hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const 
                              hipStream_t s);
 hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8_t *mask,
                         hipStream_t s);
+// Object frames of the current state (manipulation; after create, reset and
+// state restore, so that the raster draws the objects where they are).
+hipError_t launch_object_frames(const RobotParams &rp, const SimBuffers &sb, hipStream_t s);
 hipError_t raster_prepare();   // raises the dynamic-LDS limit of the raster kernels
 // Workgroups of the persistent raster kernel that fit on the device at once.
 int raster_persistent_grid(const RasterParams &rp, int max_region, bool color);

@@ -710,6 +710,51 @@ __device__ __forceinline__ void fetch_cluster(const RenderMesh &m, uint64_t ci, 
     d.p23 = cf.w;
 }
 
+// Movable objects drawn where they are: a box per object, its 8 corners
+// F_o (+-e0, +-e1, +-e2) (bit 0 of the corner index = x, 1 = y, 2 = z) and 12
+// triangles wound counter-clockwise around the outward normals, numbered
+// after the env's mesh triangles (12 per object, in object order), with no
+// face plane.  Four objects (32 vertices, 48 triangles) make one cluster.
+__device__ __forceinline__ void object_cluster(const RenderMesh &m, int env, int cidx, int lane,
+                                               uint32_t first_id, ClusterData &d)
+{
+    const int O = m.num_objects;
+    const int nobj = min(4, O - 4 * cidx);
+    d.nv = 8 * nobj;
+    d.nt = 12 * nobj;
+    d.first = first_id + 48u * (uint32_t)cidx;
+    d.p01 = kNoPlane | (kNoPlane << 16);
+    d.p23 = d.p01;
+    d.vx = d.vy = d.vz = 0.0f;
+    d.packed = 0u;
+    if (lane < d.nv) {
+        const int o = 4 * cidx + (lane >> 3), k = lane & 7;
+        const float *e = m.obj_rec + ((size_t)env * O + o) * 8 + 3;
+        const float *F = m.obj_frames + ((size_t)env * O + o) * 12;
+        const float px = (k & 1) ? e[0] : -e[0];
+        const float py = (k & 2) ? e[1] : -e[1];
+        const float pz = (k & 4) ? e[2] : -e[2];
+        d.vx = ((F[0] * px + F[1] * py) + F[2] * pz) + F[3];
+        d.vy = ((F[4] * px + F[5] * py) + F[6] * pz) + F[7];
+        d.vz = ((F[8] * px + F[9] * py) + F[10] * pz) + F[11];
+    }
+    if (lane < d.nt) {
+        // faces -x, +x, -y, +y, -z, +z as corner quads, two triangles each
+        const int ol = lane / 12, f2 = lane - 12 * ol;
+        const int face = f2 >> 1;
+        // corner quads (a, b, c, d) of the six faces
+        const int q[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+        int a = q[0][0], b = q[0][1], c = q[0][2], dd = q[0][3];
+#pragma unroll
+        for (int f = 1; f < 6; ++f)
+            if (face == f) { a = q[f][0]; b = q[f][1]; c = q[f][2]; dd = q[f][3]; }
+        const int i0 = 8 * ol + a;
+        const int i1 = 8 * ol + ((f2 & 1) ? c : b);
+        const int i2 = 8 * ol + ((f2 & 1) ? dd : c);
+        d.packed = (uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16);
+    }
+}
+
 // Work counters (debug / roofline accounting), summed per wave.
 enum {
     kStatBatchClusters = 0,  // clusters tested against the frustum
@@ -1015,6 +1060,16 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
 
     const uint64_t c0 = m.env_cluster_off[env], c1 = m.env_cluster_off[env + 1];
     unsigned long long *stats = rp.stats;
+    // ---- the movable objects first (one wave per four objects)
+    if (m.obj_frames) {
+        const int nc = (m.num_objects + 3) / 4;
+        const uint32_t first_id = (uint32_t)(m.env_tri_off[env + 1] - m.env_tri_off[env]);
+        for (int cidx = wave; cidx < nc; cidx += kWaves) {
+            ClusterData cd;
+            object_cluster(m, env, cidx, lane, first_id, cd);
+            draw_cluster(c, cd, lane, zb, stats);
+        }
+    }
     // Clusters are processed in windows of up to kVisCap: the workgroup tests
     // a window against the region frustum and compacts the visible ones, in
     // mesh order, into an LDS list; waves then pull list entries one at a
@@ -1138,7 +1193,10 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
             if (rgb) {
                 uint8_t r = 0, g = 0, bch = 0;
                 if (D < kFar) {
-                    const uint8_t *cc = m.tri_rgb + (m.env_tri_off[env] + (key & 0xFFFFFFFFull)) * 3;
+                    const uint64_t id = key & 0xFFFFFFFFull;
+                    const uint64_t ntri = m.env_tri_off[env + 1] - m.env_tri_off[env];
+                    const uint8_t *cc = id < ntri ? m.tri_rgb + (m.env_tri_off[env] + id) * 3
+                                                  : m.obj_rgb + ((size_t)env * m.num_objects + (id - ntri) / 12) * 3;
                     r = cc[0];
                     g = cc[1];
                     bch = cc[2];

@@ -397,6 +397,477 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
     }
 }
 
+// ---- manipulation: grasp / carry / release with snap-to-surface and
+// placing, sliding (Section 3.2 grasping paragraphs, Appendix I) ----------
+
+__device__ __forceinline__ float rlf(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Frame of a resting object: Rz(yaw) about its centre.
+__device__ __forceinline__ Frame object_frame(const float *o)
+{
+    Frame F;
+    F.m[0] = o[6];  F.m[1] = -o[7]; F.m[2] = 0.0f;  F.m[3] = o[0];
+    F.m[4] = o[7];  F.m[5] = o[6];  F.m[6] = 0.0f;  F.m[7] = o[1];
+    F.m[8] = 0.0f;  F.m[9] = 0.0f;  F.m[10] = 1.0f; F.m[11] = o[2];
+    return F;
+}
+
+// R^T | -R^T t
+__device__ __forceinline__ Frame frame_inverse(const Frame &F)
+{
+    Frame G;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G.m[i * 4 + j] = F.m[j * 4 + i];
+        G.m[i * 4 + 3] = -((F.m[0 * 4 + i] * F.m[3] + F.m[1 * 4 + i] * F.m[7]) + F.m[2 * 4 + i] * F.m[11]);
+    }
+    return G;
+}
+
+// Octant k of a box of half extents e (bit 0 = x, 1 = y, 2 = z).
+__device__ __forceinline__ void octant(const float *e, int k, float &x, float &y, float &z)
+{
+    x = (k & 1) ? 0.5f * e[0] : -(0.5f * e[0]);
+    y = (k & 2) ? 0.5f * e[1] : -(0.5f * e[1]);
+    z = (k & 4) ? 0.5f * e[2] : -(0.5f * e[2]);
+}
+
+__device__ __forceinline__ float obb_dist2(const float *o, float x, float y, float z)
+{
+    float dx = x - o[0], dy = y - o[1], dz = z - o[2];
+    float cps = o[6], sps = o[7];
+    float l0 = cps * dx + sps * dy;
+    float l1 = cps * dy - sps * dx;
+    float l2 = dz;
+    float q0 = clampf(l0, -o[3], o[3]);
+    float q1 = clampf(l1, -o[4], o[4]);
+    float q2 = clampf(l2, -o[5], o[5]);
+    float d0 = l0 - q0, d1 = l1 - q1, d2 = l2 - q2;
+    return (d0 * d0 + d1 * d1) + d2 * d2;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) of a counter, as a uniform in [0, 1)
+// with 24 bits.
+__device__ __forceinline__ float hash01(uint64_t seed, uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+{
+    uint64_t x = seed + 0x9E3779B97F4A7C15ull * (((a << 40) ^ (b << 24) ^ (c << 8) ^ d) + 1ull);
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x = x ^ (x >> 31);
+    return (float)(x >> 40) * 0x1p-24f;
+}
+
+// Full column-grid test of one point for class k of env e.
+__device__ __forceinline__ bool grid_point_contact(const RobotParams &rp, const SimBuffers &sb,
+                                                   const GridMeta &gm, int env, int cls, float x,
+                                                   float y, float z)
+{
+    const size_t gk = (size_t)env * rp.num_classes + cls;
+    GridProbe g;
+    grid_probe_column(sb, gm, sb.grid_off_base[gk], x, y, z, g);
+    if (!g.outside) grid_probe_layers(sb, sb.grid_layer_base[gk], g);
+    return grid_probe_contact(sb, sb.grid_layer_base[gk], g);
+}
+
+// Overlap test of a pose (frames fk) of one env, one wave: lane l takes
+// spheres l + 64 p of the robot's S spheres followed, with an object held,
+// by the held object's 8 octant spheres.  Returns whether any sphere
+// overlaps the grid or a resting object; with masks, writes the contact
+// words; the x, y of every overlapping sphere centre are summed in sphere
+// order (the same in every lane).
+__device__ __forceinline__ bool manip_pose_contacts(const RobotParams &rp, const SimBuffers &sb,
+                                                    const GridMeta &gm, int env, const Fk &fk,
+                                                    int held, const Frame &rel, const float *objs,
+                                                    int lane, uint32_t *ms_out, uint32_t *mo_out,
+                                                    float &sx, float &sy, int &n)
+{
+    const int S = rp.num_spheres;
+    const int total = S + (held >= 0 ? kHeldSpheres : 0);
+    Frame Fh;
+    const float *eh = nullptr;
+    if (held >= 0) {
+        Fh = fmul(fk.f[7], rel);
+        eh = objs + 8 * held + 3;
+    }
+    bool any = false;
+    sx = 0.0f;
+    sy = 0.0f;
+    n = 0;
+    for (int base = 0; base < S + kHeldSpheres; base += 64) {
+        const int s = base + lane;
+        bool live = false;
+        float cx = 0.f, cy = 0.f, cz = 0.f;
+        int cls = 0;
+        if (s < S) {
+            const Sphere sp = sb.spheres[s];
+            if (!sp.held_only) {
+                live = true;
+                const Frame F = pick(fk, sp.link);
+                fpoint(F, sp.px, sp.py, sp.pz, cx, cy, cz);
+                cls = sp.cls;
+            }
+        } else if (s < total) {
+            live = true;
+            float px, py, pz;
+            octant(eh, s - S, px, py, pz);
+            fpoint(Fh, px, py, pz, cx, cy, cz);
+            cls = rp.held_class;
+        }
+        bool hs = false, ho = false;
+        if (live) {
+            hs = grid_point_contact(rp, sb, gm, env, cls, cx, cy, cz);
+            const float r = rp.class_radius[cls];
+            for (int o = 0; o < rp.num_objects; ++o) {
+                if (o == held) continue;
+                if (obb_contact(objs + 8 * o, cx, cy, cz, r)) {
+                    ho = true;
+                    break;
+                }
+            }
+        }
+        const uint64_t ms = __ballot(hs), mo = __ballot(ho);
+        if (lane == 0) {
+            const int w = base >> 5;
+            if (ms_out && w < rp.contact_words) ms_out[w] = (uint32_t)ms;
+            if (ms_out && w + 1 < rp.contact_words) ms_out[w + 1] = (uint32_t)(ms >> 32);
+            if (mo_out && w < rp.contact_words) mo_out[w] = (uint32_t)mo;
+            if (mo_out && w + 1 < rp.contact_words) mo_out[w + 1] = (uint32_t)(mo >> 32);
+        }
+        uint64_t hm = ms | mo;
+        any = any || hm != 0;
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            sx = sx + rlf(cx, l);
+            sy = sy + rlf(cy, l);
+            ++n;
+        }
+    }
+    return any;
+}
+
+// Release of held object h at frame F: snap-to-surface and the placing
+// heuristic.  The object lands upright with the yaw of its x axis; four
+// spheres of the held class touching its bottom face from inside are cast
+// down the column grid (each drops to the bottom of the free layer holding
+// its centre; the object drops by the least of those); the landed object
+// must not overlap another resting object with its octant spheres.  A failed
+// try moves the drop point by place_step: away from the blocking object,
+// turned by a hashed angle in [-pi/4, pi/4), or in a hashed direction when
+// the grid refused the cast; after kPlaceTries jitters the object keeps its
+// record from before the grasp.  Uniform over the wave; lanes share the
+// sphere tests.
+constexpr int kPlaceTries = 6;
+constexpr int kSlideTries = 3;
+
+__device__ __forceinline__ void place_object(const RobotParams &rp, const SimBuffers &sb,
+                                             const GridMeta &gm, int env, int h, const Frame &F,
+                                             float *objs, int episode, int t, int lane)
+{
+    float e[3] = {objs[8 * h + 3], objs[8 * h + 4], objs[8 * h + 5]};
+    const float cx0 = F.m[0], sx0 = F.m[4];
+    const float n2 = cx0 * cx0 + sx0 * sx0;
+    float c = 1.0f, s = 0.0f;
+    if (n2 > 1e-12f) {
+        const float len = sqrtf(n2);
+        c = cx0 / len;
+        s = sx0 / len;
+    }
+    float px = F.m[3], py = F.m[7];
+    const float z0 = F.m[11];
+    const int cls = rp.held_class;
+    const float r = rp.class_radius[cls];
+    const size_t gk = (size_t)env * rp.num_classes + cls;
+    for (int k = 0; k <= kPlaceTries; ++k) {
+        // the bottom-face cast: lanes 0..3
+        bool fail = false;
+        float d = INFINITY;
+        if (lane < 4) {
+            float ox, oy, oz;
+            octant(e, lane, ox, oy, oz);
+            const float wx = px + (c * ox - s * oy);
+            const float wy = py + (s * ox + c * oy);
+            const float wz = z0 + (r - e[2]);
+            const float fx = (wx - gm.x0) * sb.inv_cell;
+            const float fy = (wy - gm.y0) * sb.inv_cell;
+            if (!(fx >= 0.0f && fx < (float)gm.nx && fy >= 0.0f && fy < (float)gm.ny)) {
+                fail = true;
+            } else {
+                const int i = (int)floorf(fx), j = (int)floorf(fy);
+                const uint64_t col = (uint64_t)j * (uint64_t)gm.nx + (uint64_t)i;
+                const uint32_t *off = sb.grid_offsets + sb.grid_off_base[gk] + col;
+                const float2 *lay = sb.grid_layers + sb.grid_layer_base[gk];
+                bool found = false;
+                for (uint32_t l = off[0]; l < off[1]; ++l) {
+                    const float2 L = lay[l];
+                    if (L.x <= wz && wz <= L.y) {
+                        d = wz - L.x;
+                        found = true;
+                        break;
+                    }
+                }
+                fail = !found;
+            }
+        }
+        const bool fail_static = __ballot(fail) != 0;
+        int fail_obj = -1;
+        if (!fail_static) {
+            float drop = d;
+            drop = fminf(drop, rlf(d, 1));
+            drop = fminf(drop, rlf(d, 2));
+            drop = fminf(drop, rlf(d, 3));
+            drop = fminf(rlf(d, 0), drop);
+            float rec[8] = {px, py, z0 - drop, e[0], e[1], e[2], c, s};
+            const Frame Fo = object_frame(rec);
+            int hit = -1;
+            if (lane < kHeldSpheres) {
+                float ox, oy, oz, wx, wy, wz;
+                octant(e, lane, ox, oy, oz);
+                fpoint(Fo, ox, oy, oz, wx, wy, wz);
+                for (int o = 0; o < rp.num_objects; ++o) {
+                    if (o == h) continue;
+                    if (obb_contact(objs + 8 * o, wx, wy, wz, r)) {
+                        hit = o;
+                        break;
+                    }
+                }
+            }
+            const uint64_t hm = __ballot(hit >= 0);
+            if (hm) {
+                fail_obj = __builtin_amdgcn_readlane(hit, __ffsll((unsigned long long)hm) - 1);
+            } else {
+                if (lane < 8) objs[8 * h + lane] = rec[lane];
+                return;
+            }
+        }
+        if (k == kPlaceTries) break;
+        const float u = hash01(rp.manip_seed, (uint64_t)(uint32_t)env, (uint64_t)(uint32_t)episode,
+                               (uint64_t)(uint32_t)t, (uint64_t)(16 + k));
+        float dx, dy;
+        if (fail_obj >= 0) {
+            const float *oo = objs + 8 * fail_obj;
+            const float vx = px - oo[0], vy = py - oo[1];
+            const float vn = sqrtf(vx * vx + vy * vy);
+            float bx = 1.0f, by = 0.0f;
+            if (vn > 1e-6f) {
+                bx = vx / vn;
+                by = vy / vn;
+            }
+            float sphi, cphi;
+            dsincos((u - 0.5f) * 0x1.921fb6p+0f, sphi, cphi);
+            dx = cphi * bx - sphi * by;
+            dy = sphi * bx + cphi * by;
+        } else {
+            float sphi, cphi;
+            dsincos(u * 0x1.921fb6p+2f - 0x1.921fb6p+1f, sphi, cphi);
+            dx = cphi;
+            dy = sphi;
+        }
+        px = px + rp.place_step * dx;
+        py = py + rp.place_step * dy;
+    }
+}
+
+// One manipulation step per wave (4 envs per 256-thread workgroup).
+__global__ __launch_bounds__(256) void k_robot_step_manip(RobotParams rp, SimBuffers sb,
+                                                          const float *__restrict__ actions,
+                                                          StepOutputs out, uint32_t *queue_reset,
+                                                          ItemOrder ord)
+{
+    if (ord.n > 0 && blockIdx.x == gridDim.x - 1) {
+        order_items_block(ord);
+        return;
+    }
+    if (queue_reset && blockIdx.x == 0 && threadIdx.x == 0) *queue_reset = 0u;
+    const int lane = threadIdx.x & 63;
+    const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)threadIdx.x / 64);
+    if (env >= sb.num_envs) return;
+    const int O = rp.num_objects;
+    float st[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) st[k] = sb.state[(size_t)env * 10 + k];
+    int t = sb.counters[(size_t)env * 2 + 0];
+    int episode = sb.counters[(size_t)env * 2 + 1];
+    const float *act = actions + (size_t)env * 11;
+    float *objs = sb.obj_dyn + (size_t)env * O * 8;
+    int held = sb.held_obj[env];
+    Frame rel;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rel.m[k] = sb.rel[(size_t)env * 12 + k];
+    const float ag = act[9], as = act[10];
+    const bool grasp = ag == ag && ag >= 0.5f;
+    const bool stop = as == as && as >= 0.5f;
+
+    // 1. kinematic update
+    float cand[10];
+    {
+        float a0 = sanitize(act[0], rp.act_lim[0]);
+        float a1 = sanitize(act[1], rp.act_lim[1]);
+        const float pi_f = 0x1.921fb6p+1f, two_pi_f = 0x1.921fb6p+2f;
+        float yaw = st[2] + a1;
+        if (yaw > pi_f) yaw = yaw - two_pi_f;
+        else if (yaw < -pi_f) yaw = yaw + two_pi_f;
+        float sy, cy;
+        dsincos(yaw, sy, cy);
+        cand[0] = st[0] + a0 * cy;
+        cand[1] = st[1] + a0 * sy;
+        cand[2] = yaw;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            float aj = sanitize(act[2 + j], rp.act_lim[2]);
+            cand[3 + j] = clampf(st[3 + j] + aj, rp.qlim[j][0], rp.qlim[j][1]);
+        }
+    }
+    // 2. overlap test of the candidate (its masks are reported)
+    const GridMeta gm = sb.grid_meta[env];
+    Fk fk;
+    forward_kinematics(rp, cand, fk);
+    float sx, sy;
+    int n;
+    uint32_t *ms_out = out.contact_static ? out.contact_static + (size_t)env * rp.contact_words : nullptr;
+    uint32_t *mo_out = out.contact_object ? out.contact_object + (size_t)env * rp.contact_words : nullptr;
+    const bool any = manip_pose_contacts(rp, sb, gm, env, fk, held, rel, objs, lane, ms_out, mo_out,
+                                         sx, sy, n);
+    // 3. resolve: commit, or slide the base (up to kSlideTries jitters away
+    // from the mean overlapping sphere centre), or keep the old state
+    int accepted = 0;
+    if (!any) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) st[k] = cand[k];
+        accepted = 1;
+    } else if (rp.slide) {
+        for (int k = 0; k < kSlideTries; ++k) {
+            const float mx = sx / (float)n, my = sy / (float)n;
+            const float vx = cand[0] - mx, vy = cand[1] - my;
+            const float vn = sqrtf(vx * vx + vy * vy);
+            if (!(vn > 1e-6f)) break;
+            cand[0] = cand[0] + rp.slide_step * (vx / vn);
+            cand[1] = cand[1] + rp.slide_step * (vy / vn);
+            forward_kinematics(rp, cand, fk);
+            if (!manip_pose_contacts(rp, sb, gm, env, fk, held, rel, objs, lane, nullptr, nullptr, sx,
+                                     sy, n)) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) st[q] = cand[q];
+                accepted = 2;
+                break;
+            }
+        }
+    }
+    // 4. grasp / release at the resolved pose
+    forward_kinematics(rp, st, fk);
+    if (grasp && held < 0) {
+        float tx, ty, tz;
+        fpoint(fk.f[7], rp.grasp_tip[0], rp.grasp_tip[1], rp.grasp_tip[2], tx, ty, tz);
+        const float r2 = rp.grasp_radius * rp.grasp_radius;
+        unsigned long long key = ~0ull;
+        if (lane < O) {
+            const float d2 = obb_dist2(objs + 8 * lane, tx, ty, tz);
+            if (d2 < r2) key = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned long long)lane;
+        }
+        // the nearest overlapping object (d2 >= 0, so its bits order like the
+        // values), the smallest index among equals
+        uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint32_t h2 = (uint32_t)__shfl_xor((int)hi, off, 64);
+            const uint32_t l2 = (uint32_t)__shfl_xor((int)lo, off, 64);
+            if (h2 < hi || (h2 == hi && l2 < lo)) { hi = h2; lo = l2; }
+        }
+        if (hi != 0xFFFFFFFFu || lo != 0xFFFFFFFFu) {
+            const int best = __builtin_amdgcn_readfirstlane((int)lo);
+            rel = fmul(frame_inverse(fk.f[7]), object_frame(objs + 8 * best));
+            held = best;
+        }
+    } else if (!grasp && held >= 0) {
+        const Frame F = fmul(fk.f[7], rel);
+        place_object(rp, sb, gm, env, held, F, objs, episode, t, lane);
+        held = -1;
+    }
+    // 5. episode bookkeeping: horizon or stop, auto-reset (objects back too)
+    bool done = false;
+    t += 1;
+    if (stop || (rp.episode_len > 0 && t >= rp.episode_len)) {
+        episode += 1;
+        load_start(rp, sb, env, episode, st);
+        t = 0;
+        done = true;
+        held = -1;
+        const float *o0 = sb.objects + (size_t)env * O * 8;
+        for (int i = lane; i < O * 8; i += 64) objs[i] = o0[i];
+        forward_kinematics(rp, st, fk);
+    }
+    // 6. outputs
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sb.state[(size_t)env * 10 + k] = st[k];
+        sb.counters[(size_t)env * 2 + 0] = t;
+        sb.counters[(size_t)env * 2 + 1] = episode;
+        sb.held_obj[env] = held;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sb.rel[(size_t)env * 12 + k] = rel.m[k];
+        float cam[12];
+        write_camera(rp, fk.f[0], cam);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sb.camera[(size_t)env * 12 + k] = cam[k];
+        if (out.state)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) out.state[(size_t)env * 10 + k] = st[k];
+        if (out.counters) {
+            out.counters[(size_t)env * 2 + 0] = t;
+            out.counters[(size_t)env * 2 + 1] = episode;
+        }
+        if (out.accepted) out.accepted[env] = (uint8_t)accepted;
+        if (out.done) out.done[env] = done ? 1 : 0;
+        if (out.held) out.held[env] = held;
+    }
+    if (out.frames && lane < 8) {
+        Frame F = pick(fk, lane);
+        float *dst = out.frames + ((size_t)env * 8 + lane) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+    }
+    if (lane < O) {
+        const Frame Fo = lane == held ? fmul(fk.f[7], rel) : object_frame(objs + 8 * lane);
+        float *dst = sb.obj_frames + ((size_t)env * O + lane) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[k] = Fo.m[k];
+        if (out.object_frames) {
+            float *d2 = out.object_frames + ((size_t)env * O + lane) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) d2[k] = Fo.m[k];
+        }
+    }
+}
+
+// Object frames of the current state (one wave per env).
+__global__ __launch_bounds__(256) void k_object_frames(RobotParams rp, SimBuffers sb)
+{
+    const int lane = threadIdx.x & 63;
+    const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)threadIdx.x / 64);
+    if (env >= sb.num_envs) return;
+    const int O = rp.num_objects;
+    float st[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) st[k] = sb.state[(size_t)env * 10 + k];
+    const int held = sb.held_obj[env];
+    Fk fk;
+    forward_kinematics(rp, st, fk);
+    Frame rel;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rel.m[k] = sb.rel[(size_t)env * 12 + k];
+    if (lane < O) {
+        const Frame Fo = lane == held ? fmul(fk.f[7], rel)
+                                      : object_frame(sb.obj_dyn + ((size_t)env * O + lane) * 8);
+        float *dst = sb.obj_frames + ((size_t)env * O + lane) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[k] = Fo.m[k];
+    }
+}
+
 // New episode for the selected envs (mask null = all): episode += 1, start
 // pose of that episode, arm at home, step counter 0; camera refreshed.
 __global__ void k_reset(RobotParams rp, SimBuffers sb, const uint8_t *__restrict__ mask)
@@ -410,6 +881,12 @@ __global__ void k_reset(RobotParams rp, SimBuffers sb, const uint8_t *__restrict
     for (int k = 0; k < 10; ++k) sb.state[(size_t)env * 10 + k] = st[k];
     sb.counters[(size_t)env * 2 + 0] = 0;
     sb.counters[(size_t)env * 2 + 1] = episode;
+    if (rp.manip) {
+        // the movable objects return to their places, nothing is held
+        const int O = rp.num_objects;
+        for (int i = 0; i < O * 8; ++i) sb.obj_dyn[(size_t)env * O * 8 + i] = sb.objects[(size_t)env * O * 8 + i];
+        sb.held_obj[env] = -1;
+    }
     float s, c;
     dsincos(st[2], s, c);
     Frame F0;
@@ -430,6 +907,12 @@ hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const 
     if (ord.n < 0 || ord.n > kOrderCap || (ord.n > 0 && (!ord.cost || !ord.order)))
         return hipErrorInvalidValue;
     const int extra = ord.n > 0 ? 1 : 0;
+    if (rp.manip) {
+        const int blocks = (sb.num_envs + 3) / 4 + extra;
+        hipLaunchKernelGGL(k_robot_step_manip, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
+                           queue_reset, ord);
+        return hipGetLastError();
+    }
     if (lanes_per_env == 32) {
         const int blocks = (sb.num_envs + 7) / 8 + extra;
         hipLaunchKernelGGL(k_robot_step<32>, dim3(blocks), dim3(256), 0, s, rp, sb, actions, out,
@@ -455,6 +938,15 @@ hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8
 {
     const int blocks = (sb.num_envs + 255) / 256;
     hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, rp, sb, mask);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !rp.manip) return e;
+    return launch_object_frames(rp, sb, s);
+}
+
+hipError_t launch_object_frames(const RobotParams &rp, const SimBuffers &sb, hipStream_t s)
+{
+    if (!rp.manip || sb.num_envs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_object_frames, dim3((sb.num_envs + 3) / 4), dim3(256), 0, s, rp, sb);
     return hipGetLastError();
 }
 

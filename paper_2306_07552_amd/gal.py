@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "libgal.so")
 
 GAL_OK = 0
 GAL_COLOR = 0x1
+GAL_MANIP = 0x2
+GAL_SLIDE = 0x4
 ERRORS = {-1: "GAL_EINVAL", -2: "GAL_ENOMEM", -3: "GAL_EDEVICE", -4: "GAL_ESTATE",
           -5: "GAL_EOVERFLOW"}
 
@@ -33,7 +35,8 @@ class GalRobot(C.Structure):
                 ("mount", C.c_float * 3), ("cam_offset", C.c_float * 3),
                 ("cam_pitch_cs", C.c_float * 2), ("num_spheres", C.c_int32),
                 ("sphere_link", _i32p), ("sphere_pos", _fp), ("sphere_class", _i32p),
-                ("sphere_held_only", _u8p)]
+                ("sphere_held_only", _u8p), ("grasp_tip", C.c_float * 3),
+                ("grasp_radius", C.c_float), ("held_class", C.c_int32)]
 
 
 class GalSceneSet(C.Structure):
@@ -42,14 +45,15 @@ class GalSceneSet(C.Structure):
                 ("box_offset", _i64p), ("boxes", _fp), ("num_objects", C.c_int32),
                 ("objects", _fp), ("grid_origin", _fp), ("grid_dims", _i32p),
                 ("num_starts", C.c_int32), ("starts", _fp), ("held", _u8p), ("res", _i32p),
-                ("tri_plane", _fp)]
+                ("tri_plane", _fp), ("obj_rgb", _u8p)]
 
 
 class GalConfig(C.Structure):
     _fields_ = [("res0", C.c_int32), ("near_m", C.c_float), ("far_m", C.c_float),
                 ("cell_m", C.c_float), ("num_classes", C.c_int32),
                 ("class_radius", C.c_float * 8), ("act_lim", C.c_float * 3),
-                ("episode_len", C.c_int32), ("flags", C.c_uint32)]
+                ("episode_len", C.c_int32), ("flags", C.c_uint32),
+                ("slide_step", C.c_float), ("place_step", C.c_float), ("manip_seed", C.c_uint64)]
 
 
 class GalTuning(C.Structure):
@@ -63,7 +67,8 @@ class GalTuning(C.Structure):
 class GalOutputs(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("rgb", C.c_void_p), ("contact_static", C.c_void_p),
                 ("contact_object", C.c_void_p), ("accepted", C.c_void_p), ("state", C.c_void_p),
-                ("frames", C.c_void_p), ("counters", C.c_void_p), ("done", C.c_void_p)]
+                ("frames", C.c_void_p), ("counters", C.c_void_p), ("done", C.c_void_p),
+                ("object_frames", C.c_void_p), ("held", C.c_void_p)]
 
 
 _lib = None
@@ -184,6 +189,12 @@ class Batch:
         cfg.act_lim[:] = [float(np.float32(v)) for v in consts["act_lim"]]
         cfg.episode_len = int(consts["episode_len"])
         cfg.flags = GAL_COLOR if color else 0
+        self.manip = bool(consts.get("manip", False))
+        if self.manip:
+            cfg.flags |= GAL_MANIP | (GAL_SLIDE if consts.get("slide", False) else 0)
+            cfg.slide_step = float(np.float32(consts["slide_step"]))
+            cfg.place_step = float(np.float32(consts["place_step"]))
+            cfg.manip_seed = int(consts["seed"])
 
         r = GalRobot()
         r.dh[:] = [float(v) for v in np.asarray(robot.dh, np.float32).ravel()]
@@ -197,6 +208,10 @@ class Batch:
         r.sphere_pos = _p(arr(robot.sphere_pos, np.float32), _fp)
         r.sphere_class = _p(arr(robot.sphere_class, np.int32), _i32p)
         r.sphere_held_only = _p(arr(robot.sphere_held_only, np.uint8), _u8p)
+        if self.manip:
+            r.grasp_tip[:] = [float(v) for v in np.asarray(consts["grasp_tip"], np.float32)]
+            r.grasp_radius = float(np.float32(consts["grasp_radius"]))
+            r.held_class = int(consts["held_class"])
 
         s = GalSceneSet()
         S = scenes
@@ -237,6 +252,11 @@ class Batch:
         s.res = _p(arr(S.res, np.int32), _i32p)
         tp = getattr(S, "tri_plane", None)
         s.tri_plane = _p(arr(tp, np.float32), _fp) if tp is not None else None
+        orgb = getattr(S, "obj_rgb", None)
+        if orgb is not None:
+            _need(orgb, (N, int(S.num_objects), 3), "obj_rgb")
+        s.obj_rgb = _p(arr(orgb, np.uint8), _u8p) if orgb is not None else None
+        self.num_objects = int(S.num_objects)
 
         h = C.c_void_p()
         _check(L.gal_create_batch(C.byref(cfg), C.byref(r), C.byref(s),
@@ -279,13 +299,17 @@ class Batch:
         )
         if self.color:
             out["rgb"] = torch.empty((self.depth_pixels, 3), dtype=torch.uint8, device=device)
+        if self.manip:
+            out["object_frames"] = torch.empty((N, self.num_objects, 12), dtype=torch.float32,
+                                               device=device)
+            out["held"] = torch.empty(N, dtype=torch.int32, device=device)
         return out
 
     @staticmethod
     def _outputs(out) -> GalOutputs:
         o = GalOutputs()
         for k in ("depth", "rgb", "contact_static", "contact_object", "accepted", "state",
-                  "frames", "counters", "done"):
+                  "frames", "counters", "done", "object_frames", "held"):
             setattr(o, k, _ptr(out.get(k)))
         return o
 
@@ -308,18 +332,42 @@ class Batch:
     def reset(self, mask=None, stream=None):
         _check(load_library().gal_reset(self._h, _ptr(mask), _stream_handle(stream)))
 
-    def get_state(self, stream=None):
-        N = self.num_envs
-        buf = np.zeros(N * 12, np.float32)
+    def _state_words(self):
+        N, O = self.num_envs, self.num_objects
+        return N * 12 + (N * (8 * O + 1 + 12) if self.manip else 0)
+
+    def get_state(self, stream=None, manip: bool = False):
+        """(state [N][10], counters [N][2]); with manip=True (GAL_MANIP batches)
+        also objects [N][O][8], held [N], rel [N][12]."""
+        N, O = self.num_envs, self.num_objects
+        buf = np.zeros(self._state_words(), np.float32)
         _check(load_library().gal_get_state(self._h, buf.ctypes.data, buf.nbytes,
                                             _stream_handle(stream)))
-        return buf[:N * 10].reshape(N, 10).copy(), buf[N * 10:].view(np.int32).reshape(N, 2).copy()
+        st = buf[:N * 10].reshape(N, 10).copy()
+        cnt = buf[N * 10:N * 12].view(np.int32).reshape(N, 2).copy()
+        if not manip:
+            return st, cnt
+        k = N * 12
+        objs = buf[k:k + N * O * 8].reshape(N, O, 8).copy()
+        k += N * O * 8
+        held = buf[k:k + N].view(np.int32).copy()
+        k += N
+        rel = buf[k:k + N * 12].reshape(N, 12).copy()
+        return st, cnt, objs, held, rel
 
-    def set_state(self, state: np.ndarray, counters: np.ndarray, stream=None):
+    def set_state(self, state: np.ndarray, counters: np.ndarray, objects=None, held=None, rel=None,
+                  stream=None):
         N = self.num_envs
-        buf = np.concatenate([np.ascontiguousarray(state, np.float32).ravel(),
-                              np.ascontiguousarray(counters, np.int32).ravel().view(np.float32)])
-        assert buf.size == N * 12
+        parts = [np.ascontiguousarray(state, np.float32).ravel(),
+                 np.ascontiguousarray(counters, np.int32).ravel().view(np.float32)]
+        if self.manip:
+            if objects is None:
+                _, _, objects, held, rel = self.get_state(stream, manip=True)
+            parts += [np.ascontiguousarray(objects, np.float32).ravel(),
+                      np.ascontiguousarray(held, np.int32).ravel().view(np.float32),
+                      np.ascontiguousarray(rel, np.float32).ravel()]
+        buf = np.concatenate(parts)
+        assert buf.size == self._state_words()
         _check(load_library().gal_set_state(self._h, buf.ctypes.data, buf.nbytes,
                                             _stream_handle(stream)))
 

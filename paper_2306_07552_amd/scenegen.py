@@ -158,10 +158,11 @@ CONFIGS = {
               radius_set=RADIUS_CLASSES_PAPER),
 }
 
-# Manipulation constants (Section 3.2: a small sphere at the end-effector tip,
-# read as 3 cm across; the jitter steps of Appendix I's heuristics are this
-# build's choice).
-GRASP_TIP = (0.0, 0.0, 0.10)
+# Manipulation constants.  Section 3.2 queries a small (3 cm) sphere at the
+# end-effector tip: read as 3 cm across, placed 0.25 m out along the last
+# link's z axis (a suction tool clear of the arm's own spheres).  The jitter
+# steps of Appendix I's heuristics are this build's choice.
+GRASP_TIP = (0.0, 0.0, 0.25)
 GRASP_RADIUS = 0.015
 SLIDE_STEP = 0.05
 PLACE_STEP = 0.10

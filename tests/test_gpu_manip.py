@@ -1,0 +1,164 @@
+"""GPU parity of the manipulation step (Section 3.2 grasping and
+snap-to-surface, Appendix I sliding and placing) against the CPU oracle,
+through the C ABI: state, counters, accepted (incl. slid moves), contact
+masks (incl. the held object's spheres), held object, object records and
+frames, depth and colour with the moving objects drawn, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2306_07552_amd import scenegen as sg
+from parity_util import compare_step, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def compare_manip(b, ob, out, oout, label):
+    compare_step(b, ob, out, oout, label)
+    envs = ob.envs
+    assert np.array_equal(out["held"].cpu().numpy()[envs], oout["held"]), f"{label} held"
+    of = out["object_frames"].cpu().numpy()[envs]
+    assert np.array_equal(of.view(np.uint32), oout["obj_frames"].view(np.uint32)), f"{label} object frames"
+    _, _, objs, held, rel = b.get_state(manip=True)
+    assert np.array_equal(objs[envs].view(np.uint32), oout["objects"].view(np.uint32)), f"{label} objects"
+    assert np.array_equal(held[envs], oout["held"]), f"{label} held state"
+    live = oout["held"] >= 0
+    assert np.array_equal(rel[envs][live].view(np.uint32), oout["rel"][live].view(np.uint32)), f"{label} rel"
+
+
+def objects_at_tips(O, robot, scenes, consts, envs):
+    """Move object 0 of every env so that it overlaps the grasp sphere at the
+    end-effector tip of the env's first start pose (computed with the oracle's
+    kinematics), hanging 2 cm below the tip."""
+    for e in envs:
+        st = np.zeros(10, np.float32)
+        st[:3] = scenes.starts[e, 0]
+        st[3:] = robot.q_home
+        F = O.fk(robot, st)[7].astype(np.float64).reshape(3, 4)
+        tip = F[:, :3] @ np.asarray(consts["grasp_tip"], np.float64) + F[:, 3]
+        scenes.objects[e, 0, :3] = tip - np.array([0.0, 0.0, 0.02])
+        scenes.objects[e, 0, 3:6] = (0.03, 0.025, 0.02)
+
+
+def run_pair(torch, cfg, actions_fn, steps, color=False, tweak=None, label="manip"):
+    from oracle import oracle as O
+    from paper_2306_07552_amd import gal
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    if tweak:
+        tweak(O, robot, scenes, consts)
+    b = gal.Batch(robot, scenes, consts, color=color)
+    ob = O.OracleBatch(robot, scenes, consts, color=color)
+    out = b.alloc_outputs()
+    events = dict(grasps=0, releases=0, slides=0, done=0)
+    prev_held = np.full(cfg.num_envs, -1)
+    for k in range(steps):
+        a = actions_fn(k)
+        b.step(torch.from_numpy(a).cuda(), out)
+        torch.cuda.synchronize()
+        oout = ob.step(a)
+        compare_manip(b, ob, out, oout, f"{label} step {k}")
+        h = oout["held"]
+        events["grasps"] += int(np.sum((prev_held < 0) & (h >= 0)))
+        events["releases"] += int(np.sum((prev_held >= 0) & (h < 0)))
+        events["slides"] += int(np.sum(oout["accepted"] == 2))
+        events["done"] += int(np.sum(oout["done"]))
+        prev_held = h
+    print(f"{label}: {events}", flush=True)
+    return events, b, ob
+
+
+def test_manip_random_rollout(torch_cuda):
+    """12 envs of the manipulation workload (small scenes), 60 steps of random
+    actions (grasp intent 60 %): every output bit-exact; slides happen."""
+    torch = torch_cuda
+    print("case: manip random rollout", flush=True)
+    cfg = sg.scaled_config(5, 12, tri_target=None)
+    ev, _, _ = run_pair(torch, cfg, lambda k: sg.actions(cfg, k), 60)
+    assert ev["slides"] > 0
+
+
+def scripted(cfg, n):
+    """Grasp and lift (arm moves with grasp intent), carry with base motion,
+    release, then a second grasp attempt and a stop action."""
+    def fn(k):
+        a = sg.actions(cfg, 1000 + k, num_envs=n) * 0.5
+        a[:, 9] = 1.0 if (k % 24) < 14 else 0.0
+        a[:, 10] = 1.0 if k == 40 else 0.0
+        if k % 24 < 3:
+            a[:, :9] = 0.0
+        return a
+    return fn
+
+
+@pytest.mark.parametrize("color", [False, True])
+def test_manip_scripted_grasp_carry_release(torch_cuda, color):
+    """Objects placed at the grasp sphere, then grasp, carry (the object's 8
+    spheres in the overlap test, the box drawn where it is), release with
+    snap-to-surface and placing, re-grasp, stop: every output bit-exact, with
+    grasps and releases actually happening."""
+    torch = torch_cuda
+    print(f"case: manip scripted, color={color}", flush=True)
+    n = 10
+    cfg = sg.scaled_config(5, n, tri_target=None)
+    ev, _, _ = run_pair(torch, cfg, scripted(cfg, n), 50, color=color,
+                        tweak=lambda O, r, s, c: objects_at_tips(O, r, s, c, range(n)),
+                        label=f"scripted color={color}")
+    assert ev["grasps"] >= n // 2 and ev["releases"] >= n // 2
+    assert ev["done"] >= n
+
+
+def test_manip_state_roundtrip_and_graph(torch_cuda):
+    """Mid-episode (objects held): the state round-trips through
+    gal_get_state / gal_set_state, and the persistent queue replayed as a
+    graph gives the same bits as the oracle from there on."""
+    torch = torch_cuda
+    print("case: manip state round trip + graph", flush=True)
+    from oracle import oracle as O
+    from paper_2306_07552_amd import gal
+    n = 8
+    cfg = sg.scaled_config(5, n, tri_target=None)
+    scenes = sg.make_scene_set(cfg)
+    robot = sg.make_robot_for(cfg)
+    consts = sg.config_constants(cfg)
+    objects_at_tips(O, robot, scenes, consts, range(n))
+    b = gal.Batch(robot, scenes, consts)
+    out = b.alloc_outputs()
+    fn = scripted(cfg, n)
+    for k in range(8):
+        b.step(torch.from_numpy(fn(k)).cuda(), out)
+    torch.cuda.synchronize()
+    st, cnt, objs, held, rel = b.get_state(manip=True)
+    assert (held >= 0).sum() >= n // 2
+    b.set_state(st, cnt, objs, held, rel)
+    st2, cnt2, objs2, held2, rel2 = b.get_state(manip=True)
+    for x, y in ((st, st2), (objs, objs2), (rel, rel2)):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.array_equal(cnt, cnt2) and np.array_equal(held, held2)
+    ob = O.OracleBatch(robot, scenes, consts)
+    ob.set_state(st, cnt, objects=objs, held=held, rel=rel)
+    b.set_tuning(persistent=1, order=1, graph=1)
+    act = torch.empty((n, 11), dtype=torch.float32, device="cuda")
+    for k in range(8, 30):
+        a = fn(k)
+        act.copy_(torch.from_numpy(a))
+        b.step(act, out)
+        torch.cuda.synchronize()
+        oout = ob.step(a)
+        compare_manip(b, ob, out, oout, f"graph step {k}")
+
+
+def test_manip_paper_scale_scenes(torch_cuda):
+    """The manipulation workload at its real scene sizes (20k-80k triangles,
+    128x128) on 6 envs, random actions: bit-exact."""
+    torch = torch_cuda
+    print("case: manip paper-scale scenes", flush=True)
+    cfg = sg.scaled_config(5, 6)
+    run_pair(torch, cfg, lambda k: sg.actions(cfg, k), 12, label="paper-scale")
