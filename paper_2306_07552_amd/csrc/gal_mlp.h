@@ -84,8 +84,9 @@ __device__ __forceinline__ int route_flag(const RouteArgs &ra, int e, float z)
     return audit ? 2 : 1;
 }
 
-// Weights of inference: layer 1 (w0 BF16 [256][2112], b0), layers 2..4
-// (w[0..2] BF16 [256][256], b[0..2]) and the head (w[3] BF16 [256], b[3]).
+// Weights of inference: layer 1 (w0, b0), layers 2..4 (w[0..2], b[0..2]),
+// all four matrices in the fragment order sur_infer_layout writes, and the
+// head (w[3] BF16 [256], b[3]).
 struct MlpTail {
     const uint16_t *w0;
     const float *b0;
@@ -119,7 +120,16 @@ size_t sur_infer_part_floats(int rows);
 // than 512 slabs of 32 x 256 FP32 values = 16 MiB).
 size_t sur_infer_part_floats_max(int max_rows);
 hipError_t sur_infer(const SurInferArgs &args, hipStream_t s);
+// The copy of the four matrix layers that inference reads (BF16,
+// sur_infer_layout_elems() values: layer 1 then layers 2..4), rewritten from
+// the row-major BF16 matrices w0 [256][2112] and w1..w3 [256][256] whenever
+// they change.
+size_t sur_infer_layout_elems();
+hipError_t sur_infer_layout(const uint16_t *w0, const uint16_t *w1, const uint16_t *w2, const uint16_t *w3,
+                            uint16_t *wi, hipStream_t s);
 
+// Rewrites m's inference copy of the weights (call after they change).
+hipError_t mlp_refresh_inference(gal_mlp *m, hipStream_t s);
 // Inference of the MLP m (gal_mlp_api.cpp); part null = the MLP's own scratch.
 int mlp_infer_rows(gal_mlp *m, const uint16_t *x, const SurInferArgs *src, int rows, float *z,
                    const RouteArgs *route, hipStream_t s, float *part = nullptr);

@@ -37,6 +37,7 @@ struct gal_mlp {
     int64_t off_w[5], off_b[5], n_params = 0;
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     uint16_t *wb = nullptr;
+    uint16_t *wi = nullptr;     // inference copy of the matrix layers (fragment order)
     uint16_t *h[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // h[1..4]
     uint16_t *dp[2] = {nullptr, nullptr};
     float *z = nullptr, *dz = nullptr, *loss = nullptr;
@@ -89,6 +90,7 @@ int gal_mlp_create(int32_t max_rows, uint64_t seed, gal_mlp **out)
     int rc;
     if ((rc = m->alloc(&m->w, off)) || (rc = m->alloc(&m->m, off)) || (rc = m->alloc(&m->v, off)) ||
         (rc = m->alloc(&m->g, off)) || (rc = m->alloc(&m->wb, off)) ||
+        (rc = m->alloc(&m->wi, gal::sur_infer_layout_elems())) ||
         (rc = m->alloc(&m->dp[0], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->dp[1], (size_t)max_rows * gal::kMlpHidden)) ||
         (rc = m->alloc(&m->z, max_rows)) || (rc = m->alloc(&m->dz, max_rows)) ||
@@ -128,6 +130,7 @@ int gal_mlp_set_weights(gal_mlp *m, const float *host, size_t count)
     MLP_TRY(hipMemset(m->m, 0, sizeof(float) * count));
     MLP_TRY(hipMemset(m->v, 0, sizeof(float) * count));
     MLP_TRY(gal::mlp_to_bf16(m->w, (int64_t)count, m->wb, nullptr));
+    MLP_TRY(gal::mlp_refresh_inference(m, nullptr));
     MLP_TRY(hipDeviceSynchronize());
     m->t = 0;
     return GAL_OK;
@@ -147,6 +150,13 @@ int gal_mlp_get_weights(gal_mlp *m, float *host, size_t count)
 namespace gal {
 
 int mlp_max_rows(const gal_mlp *m) { return m->max_rows; }
+
+// the inference copy of the matrix layers, after the BF16 weights changed
+hipError_t mlp_refresh_inference(gal_mlp *m, hipStream_t s)
+{
+    return sur_infer_layout(m->wb + m->off_w[0], m->wb + m->off_w[1], m->wb + m->off_w[2],
+                            m->wb + m->off_w[3], m->wi, s);
+}
 
 // forward pass of rows inputs (BF16 [rows][2112]) into m->h[1..4] and m->z
 int mlp_forward_rows(gal_mlp *m, const uint16_t *x, int rows, hipStream_t s)
@@ -169,10 +179,11 @@ int mlp_infer_rows(gal_mlp *m, const uint16_t *x, const SurInferArgs *src, int r
                    const RouteArgs *route, hipStream_t s, float *part)
 {
     SurInferArgs a = src ? *src : SurInferArgs{};
-    a.t.w0 = m->wb + m->off_w[0];
+    a.t.w0 = m->wi;
     a.t.b0 = m->w + m->off_b[0];
     for (int l = 0; l < 4; ++l) {
-        a.t.w[l] = m->wb + m->off_w[l + 1];
+        a.t.w[l] = l < 3 ? m->wi + (size_t)kMlpIn * kMlpHidden + (size_t)l * kMlpHidden * kMlpHidden
+                         : m->wb + m->off_w[4];
         a.t.b[l] = m->w + m->off_b[l + 1];
     }
     a.x = x;
@@ -248,6 +259,7 @@ int gal_mlp_train_step(gal_mlp *m, const uint16_t *x_dev, const float *labels_de
     if (rc) return rc;
     m->t += 1;
     MLP_TRY(gal::mlp_adam(m->w, m->m, m->v, m->g, m->n_params, lr, 0.9f, 0.999f, 1e-8f, m->t, m->wb, s));
+    MLP_TRY(gal::mlp_refresh_inference(m, s));
     if (loss_dev) MLP_TRY(hipMemcpyAsync(loss_dev, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return GAL_OK;
 }

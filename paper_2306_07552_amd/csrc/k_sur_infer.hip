@@ -20,6 +20,14 @@
 // slower here.)  Layers 2..4 keep the activations in LDS and load the next
 // layer's weights while the current one runs; then the head and the routing.
 // No input rows are written to memory.
+//
+// The weights of the four matrix layers are read from a copy in fragment
+// order (sur_infer_layout): the 16 bytes a lane needs for one MFMA operand
+// sit at lane * 16 within a 1 KiB block per (wave, K-step, column tile), so
+// every weight load of a wave reads whole cache lines once, where the
+// row-major matrix would have it gather 16 half-lines 4 KiB apart.  Weight
+// streaming into each workgroup is what bounds both launches at small
+// batches.
 #include "gal_features.h"
 
 namespace gal {
@@ -137,17 +145,24 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
     }
 }
 
-// this wave's fragments of a 256 x 256 layer: column 32 wave + 16 j + r16
+// Element offset, in the fragment-ordered copy of a layer, of the block that
+// holds K-steps s0 .. s0 + ns - 1: fragment (wave, st, j) of that block is
+// 64 lanes x 8 BF16 values, lane = 16 (K group) + (column within the tile).
+__device__ __forceinline__ size_t frag_offset(int s0, int ns, int wave, int st, int j, int lane)
+{
+    return (size_t)32 * s0 * kMlpHidden + ((size_t)((wave * ns + st) * 2 + j) * 64 + lane) * 8;
+}
+
+// this wave's fragments of a 256 x 256 layer (fragment order): column
+// 32 wave + 16 j + r16, K = 32 st + kq
 __device__ __forceinline__ void load_layer(const uint16_t *W, bf16x8 (&f)[kMlpHidden / 32][2])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
     for (int st = 0; st < kMlpHidden / 32; ++st)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            f[st][j] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(kColsW * wave + 16 * j + r16) * kMlpHidden +
-                                                        32 * st + kq);
+            f[st][j] = *reinterpret_cast<const bf16x8 *>(W + frag_offset(0, kMlpHidden / 32, wave, st, j, lane));
 }
 
 // What the patch columns of one row need: the candidate base pose and where
@@ -172,7 +187,20 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int S = p.splits;
-    const int tile = blockIdx.x / S, split = blockIdx.x - tile * S;
+    // Workgroups are handed to the 8 XCDs in turn (blockIdx mod 8).  When the
+    // tile count allows, all splits of tile t go to XCD t mod 8, where the
+    // second launch's workgroup t runs: its partial sums are then read from
+    // the same L2 they were written to.
+    const int tiles_all = gridDim.x / S;
+    int tile, split;
+    if (S > 1 && tiles_all % 8 == 0) {
+        const int slot = blockIdx.x >> 3;
+        tile = (blockIdx.x & 7) + 8 * (slot / S);
+        split = slot - (slot / S) * S;
+    } else {
+        tile = blockIdx.x / S;
+        split = blockIdx.x - tile * S;
+    }
     const int row0 = tile * kR;
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     const int cpb = kChunks / S;
@@ -195,9 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
         for (int st = 0; st < kChunk0; ++st)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                w[st][j] = st < ns ? *reinterpret_cast<const bf16x8 *>(
-                                         p.t.w0 + (size_t)(kColsW * wave + 16 * j + r16) * kMlpIn +
-                                         32 * (s0 + st) + kq)
+                w[st][j] = st < ns ? *reinterpret_cast<const bf16x8 *>(p.t.w0 + frag_offset(s0, ns, wave, st, j, lane))
                                    : bf16x8{};
     };
     load_chunk(cbeg);
@@ -319,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
 
     // lane holds rows 16 m + 4 (lane / 16) + i, column 32 wave + 16 j + r16
     if (S > 1) {
-        float *mine = p.part + (size_t)blockIdx.x * kR * kMlpHidden;
+        float *mine = p.part + (size_t)(tile * S + split) * kR * kMlpHidden;
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -408,7 +434,52 @@ __global__ __launch_bounds__(kThreads) void k_sur_tail(SurInferArgs p)
     tail_layers(p, row0, H, zs, f2, f3, f4);
 }
 
+// One thread per 8 consecutive K values of one output column of one layer:
+// copies them from the row-major BF16 matrix to their fragment-order slot.
+__global__ void k_infer_layout(const uint16_t *w0, const uint16_t *w1, const uint16_t *w2,
+                               const uint16_t *w3, uint16_t *wi)
+{
+    constexpr int g0 = kMlpHidden * (kMlpIn / 8), gh = kMlpHidden * (kMlpHidden / 8);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g0 + 3 * gh) return;
+    int layer, g;
+    if (i < g0) {
+        layer = 0;
+        g = i;
+    } else {
+        layer = 1 + (i - g0) / gh;
+        g = (i - g0) % gh;
+    }
+    const int K = layer == 0 ? kMlpIn : kMlpHidden;
+    const int n = g / (K / 8), k = (g % (K / 8)) * 8;
+    const uint16_t *src = layer == 0 ? w0 : layer == 1 ? w1 : layer == 2 ? w2 : w3;
+    const int S = k / 32, kq = (k % 32) / 8;
+    int s0 = 0, ns = kMlpHidden / 32;
+    if (layer == 0) {
+        if (S < kChunk0) {
+            ns = kChunk0;
+        } else {
+            s0 = kChunk0 + kChunkN * ((S - kChunk0) / kChunkN);
+            ns = kChunkN;
+        }
+    }
+    const size_t base = layer == 0 ? 0 : (size_t)kMlpIn * kMlpHidden + (size_t)(layer - 1) * kMlpHidden * kMlpHidden;
+    const int lane = kq * 16 + (n & 15);
+    *reinterpret_cast<uint4 *>(wi + base + frag_offset(s0, ns, n / 32, S - s0, (n / 16) & 1, lane)) =
+        *reinterpret_cast<const uint4 *>(src + (size_t)n * K + k);
+}
+
 }  // namespace
+
+size_t sur_infer_layout_elems() { return (size_t)kMlpIn * kMlpHidden + 3 * (size_t)kMlpHidden * kMlpHidden; }
+
+hipError_t sur_infer_layout(const uint16_t *w0, const uint16_t *w1, const uint16_t *w2, const uint16_t *w3,
+                            uint16_t *wi, hipStream_t s)
+{
+    const int n = kMlpHidden * (kMlpIn / 8) + 3 * kMlpHidden * (kMlpHidden / 8);
+    hipLaunchKernelGGL(k_infer_layout, dim3((n + 255) / 256), dim3(256), 0, s, w0, w1, w2, w3, wi);
+    return hipGetLastError();
+}
 
 int sur_infer_splits(int rows)
 {
