@@ -33,9 +33,12 @@ def log(msg):
 # Tuning keys that change what the raster kernel reads and writes (the others
 # only change how the same pixels are rasterised, or other kernels).
 TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split")
+# the instruction count also depends on how pixels are spread over lanes and
+# waves (the queue order changes neither bytes nor instructions)
+VALU_KEYS = TRAFFIC_KEYS + ("block", "lane_max", "small_max")
 
 
-def counter_record(kernel_sources, record, tuning, field):
+def counter_record(kernel_sources, record, tuning, field, keys=None):
     """One per-launch figure (HBM bytes from FETCH_SIZE / WRITE_SIZE, VALU
     instructions from SQ_INSTS_VALU) from a committed rocprofv3 counter
     record of the launch configuration being timed, or None when the kernel
@@ -51,7 +54,7 @@ def counter_record(kernel_sources, record, tuning, field):
     if rec.get("source_sha256") != h:
         return None
     for r in rec["records"]:
-        if field in r and all(r["tuning"].get(k) == tuning.get(k) for k in TRAFFIC_KEYS):
+        if field in r and all(r["tuning"].get(k) == tuning.get(k) for k in (keys or TRAFFIC_KEYS)):
             return r[field]
     return None
 
@@ -309,7 +312,7 @@ def main():
         traffic = counter_record(srcs, "k_raster_1024env_128px_traffic.json", tuning,
                                  "traffic_bytes_per_launch")
         valu = counter_record(srcs, "k_raster_1024env_128px_sq.json", tuning,
-                              "sq_insts_valu_per_launch")
+                              "sq_insts_valu_per_launch", VALU_KEYS)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel, "algorithmic_bytes_per_launch": int(raster_bytes),

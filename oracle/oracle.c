@@ -774,6 +774,36 @@ O_EXPORT void o_object_mesh(const float *obj_frames, const float *objects, int O
     }
 }
 
+/* The robot's links as render triangles (the head camera sees the robot's own
+   body and arm): link l (frame l of the step's kinematics, 0 = base) is the box
+   centred at c_l with half extents h_l in its own frame (link_box [8][6] =
+   c xyz, h xyz).  Corner k of link l = F_l (c_l + (+-h_l)) (bit 0 of k: x,
+   bit 1: y, bit 2: z; the sum in FP32 before the frame product) at vertex
+   8 l + k; 12 triangles per link in the object boxes' face order, vertex
+   indices offset by vbase.  verts [64][3], tris [96][3]. */
+O_EXPORT void o_link_mesh(const float *frames, const float *link_box, int32_t vbase, float *verts,
+                          int32_t *tris)
+{
+    static const int faces[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4},
+                                    {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+    for (int l = 0; l < 8; ++l) {
+        const float *c = link_box + 6 * l, *h = c + 3;
+        for (int k = 0; k < 8; ++k) {
+            float p[3];
+            p[0] = c[0] + ((k & 1) ? h[0] : -h[0]);
+            p[1] = c[1] + ((k & 2) ? h[1] : -h[1]);
+            p[2] = c[2] + ((k & 4) ? h[2] : -h[2]);
+            frame_point(frames + 12 * l, p, verts + 3 * (8 * l + k));
+        }
+        for (int f = 0; f < 6; ++f) {
+            const int *q = faces[f];
+            int32_t *t0 = tris + 3 * (12 * l + 2 * f), *t1 = t0 + 3;
+            t0[0] = vbase + 8 * l + q[0]; t0[1] = vbase + 8 * l + q[1]; t0[2] = vbase + 8 * l + q[2];
+            t1[0] = vbase + 8 * l + q[0]; t1[1] = vbase + 8 * l + q[2]; t1[2] = vbase + 8 * l + q[3];
+        }
+    }
+}
+
 /* reset one environment to the start pose of its (incremented) episode */
 O_EXPORT void o_reset_env(const o_robot *rb, const o_env *env, float *state, int32_t *counters,
                           int new_episode)

@@ -111,6 +111,7 @@ def _declare(L):
                                      C.POINTER(OManip), C.POINTER(ODyn), C.c_int32, _fp, _i32p,
                                      _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp, _fp]
     L.o_object_mesh.argtypes = [_fp, _fp, C.c_int, C.c_int32, _fp, _i32p]
+    L.o_link_mesh.argtypes = [_fp, _fp, C.c_int32, _fp, _i32p]
     L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
                            _u32p, _u32p, _u8p, C.POINTER(ORStats)]
 
@@ -235,6 +236,10 @@ class OracleBatch:
         self.state = np.zeros((n, 10), np.float32)
         self.counters = np.zeros((n, 2), np.int32)
         self.manip = bool(cc.get("manip", False))
+        self.links = bool(cc.get("links", False))
+        if self.links:
+            self.link_box = np.ascontiguousarray(robot.link_box, np.float32)
+            self.link_rgb = np.ascontiguousarray(robot.link_rgb, np.uint8)
         self.words = (robot.num_spheres + (8 if self.manip else 0) + 31) // 32
         if self.manip:
             m = OManip()
@@ -317,24 +322,41 @@ class OracleBatch:
         if rel is not None:
             self.rel[...] = rel
 
-    def env_render_mesh(self, i):
-        """Render triangles of env i: its static mesh and, in the manipulation
-        workload, a box for every movable object where it is now (ids after the
-        static triangles, no face plane)."""
+    def env_render_mesh(self, i, frames=None):
+        """Render triangles of env i: its static mesh; in the manipulation
+        workload a box for every movable object where it is now; with links, a
+        box per robot link at the link frames `frames` [8][12] (ids in that
+        order: static, objects, links; the boxes have no face plane)."""
         e = self.envs[i]
         v, t, rgb = self.scenes.env_mesh(e)
         planes = self.scenes.env_planes(e)
-        if not self.manip:
+        vs, ts, rgbs, pls = [v], [t], [rgb], [planes]
+        nv = v.shape[0]
+        nop = np.array([0.0, 0.0, 0.0, -1.0], np.float32)
+        if self.manip:
+            O = self.scenes.num_objects
+            ov = np.zeros((8 * O, 3), np.float32)
+            ot = np.zeros((12 * O, 3), np.int32)
+            lib().o_object_mesh(ptr(self.obj_frames[i], _fp), ptr(self.objects[i], _fp), O, nv,
+                                ptr(ov, _fp), ptr(ot, _i32p))
+            vs.append(ov)
+            ts.append(ot)
+            rgbs.append(np.repeat(self.scenes.obj_rgb[e], 12, axis=0))
+            pls.append(np.tile(nop, (12 * O, 1)))
+            nv += 8 * O
+        if self.links:
+            fr = np.ascontiguousarray(frames, np.float32).reshape(8, 12)
+            lv = np.zeros((64, 3), np.float32)
+            lt = np.zeros((96, 3), np.int32)
+            lib().o_link_mesh(ptr(fr, _fp), ptr(self.link_box, _fp), nv, ptr(lv, _fp), ptr(lt, _i32p))
+            vs.append(lv)
+            ts.append(lt)
+            rgbs.append(np.repeat(self.link_rgb, 12, axis=0))
+            pls.append(np.tile(nop, (96, 1)))
+        if len(vs) == 1:
             return v, t, rgb, planes
-        O = self.scenes.num_objects
-        ov = np.zeros((8 * O, 3), np.float32)
-        ot = np.zeros((12 * O, 3), np.int32)
-        lib().o_object_mesh(ptr(self.obj_frames[i], _fp), ptr(self.objects[i], _fp), O, v.shape[0],
-                            ptr(ov, _fp), ptr(ot, _i32p))
-        nop = np.tile(np.array([0.0, 0.0, 0.0, -1.0], np.float32), (12 * O, 1))
-        orgb = np.repeat(self.scenes.obj_rgb[e], 12, axis=0)
-        return (np.concatenate([v, ov]), np.concatenate([t, ot]), np.concatenate([rgb, orgb]),
-                None if planes is None else np.concatenate([planes, nop]))
+        return (np.concatenate(vs), np.concatenate(ts), np.concatenate(rgbs),
+                None if planes is None else np.concatenate(pls))
 
     def _step_env(self, i, act, out):
         L = lib()
@@ -356,7 +378,7 @@ class OracleBatch:
                            ptr(out["accepted"][i:i + 1], _u8p), ptr(out["done"][i:i + 1], _u8p),
                            ptr(out["frames"][i], _fp), ptr(out["cam"][i], _fp))
         res = int(self.scenes.res[e])
-        v, t, _rgb, planes = self.env_render_mesh(i)
+        v, t, _rgb, planes = self.env_render_mesh(i, out["frames"][i])
         depth, win, _cov, stats = render(v, t, out["cam"][i], res, res, self.near, self.far,
                                          want_id=self.color, planes=planes)
         out["depth"][i] = depth

@@ -65,6 +65,9 @@ class Robot:
     sphere_pos: np.ndarray    # f32 [S][3] link-local centre
     sphere_class: np.ndarray  # i32 [S] index into the radius classes
     sphere_held_only: np.ndarray  # u8 [S] 1 = active only while holding
+    link_box: Optional[np.ndarray] = None   # f32 [8][6] per link frame: box centre xyz, half
+                                            # extents xyz (drawn when links are rendered)
+    link_rgb: Optional[np.ndarray] = None   # u8 [8][3] flat colour of each link's box
 
     @property
     def num_spheres(self) -> int:
@@ -138,6 +141,7 @@ class Config:
     color: bool = False
     manip: bool = False              # grasp / release / place / slide, 11-float actions
     radius_set: Sequence[float] = RADIUS_CLASSES
+    links: bool = False              # the head camera also sees the robot's own links
 
 
 # The five workloads (sizes and distributions of the paper-scale step).
@@ -211,12 +215,23 @@ def make_robot(seed: int, spheres_per_link: int, held_proxy: bool,
         pos.append((0.0, 0.0, 0.10))
         cls.append(1)
         held_only.append(1)
+    # render boxes of the links (no random draws): the base body below the
+    # camera, and each arm link along its frame's -x over its DH length a
+    # (where its spheres lie), 6 cm thick
+    box = np.zeros((8, 6), np.float32)
+    box[0] = (0.0, 0.0, 0.45, 0.25, 0.25, 0.45)
+    for link in range(1, 8):
+        a = float(dh[link - 1, 0])
+        box[link] = (-0.5 * a, 0.0, 0.0, 0.5 * a + 0.02, 0.03, 0.03)
+    rgb = np.array([(90, 90, 100)] + [(200, 200, 205) if k % 2 else (60, 60, 70) for k in range(1, 7)]
+                   + [(180, 40, 40)], np.uint8)
     return Robot(dh=dh, qlim=qlim, q_home=q_home, mount=mount, cam_offset=cam_offset,
                  cam_pitch_cs=cam_pitch_cs,
                  sphere_link=np.asarray(links, np.int32),
                  sphere_pos=np.asarray(pos, np.float32).reshape(-1, 3),
                  sphere_class=np.asarray(cls, np.int32),
-                 sphere_held_only=np.asarray(held_only, np.uint8))
+                 sphere_held_only=np.asarray(held_only, np.uint8),
+                 link_box=box, link_rgb=rgb)
 
 
 def snap_class(r: float, classes: Sequence[float] = RADIUS_CLASSES) -> int:
@@ -552,6 +567,8 @@ def actions(cfg: Config, step: int, num_envs: Optional[int] = None,
 def config_constants(cfg: Config) -> dict:
     c = dict(near=cfg.near, far=cfg.far, cell=CELL, radius_classes=tuple(cfg.radius_set),
              act_lim=tuple(cfg.act_lim), episode_len=cfg.episode_len, res0=cfg.res0)
+    if cfg.links:
+        c.update(links=True)
     if cfg.manip:
         c.update(manip=True, slide=True, grasp_tip=GRASP_TIP, grasp_radius=GRASP_RADIUS,
                  held_class=0, slide_step=SLIDE_STEP, place_step=PLACE_STEP,

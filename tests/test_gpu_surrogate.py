@@ -468,7 +468,11 @@ def test_routing_full_audit_is_exact(torch_cuda, trained):
 def test_surrogate_gain_zero_mismatches(torch_cuda, trained):
     """On fresh scenes and motions, with a full audit: no skipped query had a
     contact (mismatches 0), and the fraction of exact static checks the
-    surrogate removes is reported (the gain)."""
+    surrogate removes is reported (the gain).  Then the price: the step with
+    depth, at one launch configuration, timed with the surrogate (1-in-16
+    audit) and without it.  At 1024 envs the exact checks the network removes
+    cost less than its inference, so the step is slower with it; the test
+    prints both times and the per-stage split, and bounds the overhead."""
     torch = torch_cuda
     print("case: surrogate gain", flush=True)
     mlp, skip_below, info = trained
@@ -489,6 +493,41 @@ def test_surrogate_gain_zero_mismatches(torch_cuda, trained):
           flush=True)
     assert st["mismatches"] == 0
     assert frac > 0.0
+
+    # step time with and without the surrogate, same launch configuration
+    b.set_tuning(block=512, region=128, lane_max=8, small_max=256, refresh=1, occlusion=1,
+                 prologue=128, persistent=1, robot_lanes=64, graph=1, split=0, order=1)
+    full = b.alloc_outputs()
+    acts = ((torch.rand((32, 1024, 9), generator=g, device="cuda") * 2 - 1) * lim).contiguous()
+
+    def timed(n=96):
+        for k in range(8):
+            b.step(acts[k % 32], full)
+        torch.cuda.synchronize()
+        b.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(n):
+            b.step(acts[k % 32], full)
+        e1.record()
+        torch.cuda.synchronize()
+        b.profile(False)
+        sur_ms, robot_ms, raster_ms, steps = b.profile_read_stages()
+        return (e0.elapsed_time(e1) / n,
+                dict(surrogate=sur_ms / steps, robot=robot_ms / steps, raster=raster_ms / steps))
+
+    b.attach_surrogate(mlp, skip_below, audit_period=16)
+    b.surrogate_stats(reset=True)
+    t_sur, st_sur = timed()
+    st16 = b.surrogate_stats()
+    b.detach_surrogate()
+    t_plain, st_plain = timed()
+    print(f"step time: {t_sur:.4f} ms with the surrogate, {t_plain:.4f} ms without "
+          f"({(t_sur / t_plain - 1) * 100:+.1f} %); stages with {st_sur}, without {st_plain}; "
+          f"timed-region skipped fraction {st16['skipped'] / st16['queries']:.3f}, "
+          f"mismatches {st16['mismatches']}", flush=True)
+    assert st16["mismatches"] == 0
+    assert 0.0 < t_plain and 0.0 < t_sur < 1.15 * t_plain
 
 
 def test_benchmarked_configuration_matches_oracle(torch_cuda, trained):
