@@ -57,6 +57,9 @@ extern "C" {
                                objects move and are drawn where they are     */
 #define GAL_SLIDE 0x4u      /* with GAL_MANIP: a collision slides the base
                                instead of stopping it (Appendix I.1)         */
+#define GAL_LINKS 0x8u      /* the head camera also sees the robot itself
+                               (Section 4.1's observation): each link drawn
+                               as its box (gal_robot.link_box)               */
 
 /*
  * Robot (Section 3.2 / Appendix G): a planar base (x, y, yaw) and a 7-DoF
@@ -88,6 +91,16 @@ typedef struct gal_robot {
     float grasp_tip[3];
     float grasp_radius;
     int32_t held_class;
+    /* GAL_LINKS: the render box of each link in its own frame (link 0 = the
+       base): centre xyz, half extents xyz (> 0).  Corner k of link l is
+       F_l (c + (+-h)) (bit 0 of k: x, bit 1: y, bit 2: z) with F_l the link's
+       frame after the step; 12 triangles per link, wound counter-clockwise
+       around the outward normals, numbered after the env's mesh triangles
+       and (GAL_MANIP) its objects' 12 O, culled by their winding only.
+       link_rgb: the flat colour of each link (needed with GAL_COLOR).
+       Ignored without GAL_LINKS. */
+    const float *link_box;      /* [8][6]                                    */
+    const uint8_t *link_rgb;    /* [8][3] or NULL                            */
 } gal_robot;
 
 /*
@@ -149,7 +162,8 @@ typedef struct gal_config {
     float class_radius[GAL_MAX_CLASSES];
     float act_lim[3];           /* |forward| m, |yaw| rad, |joint delta| rad */
     int32_t episode_len;        /* steps per episode; 0 = never auto-reset   */
-    uint32_t flags;             /* GAL_COLOR | GAL_MANIP | GAL_SLIDE         */
+    uint32_t flags;             /* GAL_COLOR | GAL_MANIP | GAL_SLIDE |
+                                   GAL_LINKS                                 */
     /* GAL_MANIP (Appendix I): base jitter per sliding try and object jitter
        per placing try (m), and the seed of the placing jitter's counter-based
        randomness */

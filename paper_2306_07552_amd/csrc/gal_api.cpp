@@ -653,7 +653,17 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     for (int k = 0; k < cfg->num_classes; ++k)
         if (!(cfg->class_radius[k] > 0.0f)) return fail(GAL_EINVAL, "class radius must be > 0");
     const bool manip = (cfg->flags & GAL_MANIP) != 0;
+    const bool links = (cfg->flags & GAL_LINKS) != 0;
     if ((cfg->flags & GAL_SLIDE) && !manip) return fail(GAL_EINVAL, "GAL_SLIDE needs GAL_MANIP");
+    if (links) {
+        if (!robot->link_box) return fail(GAL_EINVAL, "GAL_LINKS needs link_box");
+        for (int l = 0; l < 8; ++l)
+            for (int k = 3; k < 6; ++k)
+                if (!(robot->link_box[6 * l + k] > 0.0f) || !std::isfinite(robot->link_box[6 * l + k]))
+                    return fail(GAL_EINVAL, "link %d: half extents must be finite and > 0", l);
+        if ((cfg->flags & GAL_COLOR) && !robot->link_rgb)
+            return fail(GAL_EINVAL, "GAL_LINKS with GAL_COLOR needs link_rgb");
+    }
     if (manip) {
         if (robot->held_class < 0 || robot->held_class >= cfg->num_classes)
             return fail(GAL_EINVAL, "held_class out of range");
@@ -726,6 +736,7 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
     rp.contact_words = b->words;
     rp.manip = manip ? 1 : 0;
     rp.slide = (cfg->flags & GAL_SLIDE) ? 1 : 0;
+    rp.links = links ? 1 : 0;
     if (manip) {
         memcpy(rp.grasp_tip, robot->grasp_tip, sizeof(rp.grasp_tip));
         rp.grasp_radius = robot->grasp_radius;
@@ -802,6 +813,11 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         HIP_TRY(hipMemset(sb.held_obj, 0xFF, sizeof(int32_t) * N));
         HIP_TRY(hipMemset(sb.rel, 0, sizeof(float) * N * 12));
         HIP_TRY(hipMemset(sb.obj_frames, 0, sizeof(float) * no * 12));
+    }
+    if (links) {
+        // link frames after each step (written by the robot step, read by the raster)
+        if ((rc = b->mem.alloc(&sb.link_frames, (size_t)N * 8 * 12))) return cleanup(rc);
+        HIP_TRY(hipMemset(sb.link_frames, 0, sizeof(float) * N * 8 * 12));
     }
 
     // ---- column grids: count, scan, fill (on the device)
@@ -961,6 +977,19 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
             if ((rc = b->mem.alloc(&d_rgb, (size_t)std::max<uint64_t>(nt_tot, 1) * 3))) return cleanup(rc);
             HIP_TRY(hipMemcpy(d_rgb, sc->tri_rgb, nt_tot * 3, hipMemcpyHostToDevice));
             b->mesh.tri_rgb = d_rgb;
+        }
+        if (links) {
+            float *d_box;
+            if ((rc = b->mem.alloc(&d_box, (size_t)8 * 6))) return cleanup(rc);
+            HIP_TRY(hipMemcpy(d_box, robot->link_box, sizeof(float) * 8 * 6, hipMemcpyHostToDevice));
+            b->mesh.link_box = d_box;
+            b->mesh.link_frames = b->sb.link_frames;
+            if ((cfg->flags & GAL_COLOR) && robot->link_rgb) {
+                uint8_t *d_lrgb;
+                if ((rc = b->mem.alloc(&d_lrgb, (size_t)8 * 3))) return cleanup(rc);
+                HIP_TRY(hipMemcpy(d_lrgb, robot->link_rgb, 8 * 3, hipMemcpyHostToDevice));
+                b->mesh.link_rgb = d_lrgb;
+            }
         }
         if (manip && b->O > 0) {
             b->mesh.obj_frames = b->sb.obj_frames;

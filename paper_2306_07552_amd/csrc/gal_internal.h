@@ -42,6 +42,7 @@ struct RobotParams {
     int32_t held_class;         // radius class of a held object's spheres
     float slide_step, place_step;
     uint64_t manip_seed;
+    int32_t links;              // 1: write every link's frame for the raster (sb.link_frames)
 };
 
 // Spheres of a held object (one per octant of its box).
@@ -91,6 +92,7 @@ struct SimBuffers {
     int32_t *held_obj;               // [N] held object, -1 = none
     float *rel;                      // [N][12] held object's frame in the end-effector frame
     float *obj_frames;               // [N][O][12] object frames after the step (for the raster)
+    float *link_frames;              // [N][8][12] link frames after the step (links drawn)
 };
 
 // Step outputs (device, caller-owned).
@@ -132,6 +134,10 @@ struct RenderMesh {
     const float *obj_rec;            // [N][O][8] (half extents at [3..5])
     const uint8_t *obj_rgb;          // [N][O][3] or null
     int32_t num_objects;
+    // the robot's links drawn as boxes (null link_frames: not drawn)
+    const float *link_frames;        // [N][8][12]
+    const float *link_box;           // [8][6] centre, half extents in the link frame
+    const uint8_t *link_rgb;         // [8][3] or null
 };
 
 struct RasterParams {

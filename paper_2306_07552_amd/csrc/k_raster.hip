@@ -755,6 +755,48 @@ __device__ __forceinline__ void object_cluster(const RenderMesh &m, int env, int
     }
 }
 
+// The robot's links drawn where they are: link l's box has centre c_l and
+// half extents h_l in link frame l, corner k = F_l (c_l + (+-h_l)) (bit 0 of
+// k = x, 1 = y, 2 = z; the sum in FP32 before the frame product), the same
+// 12 triangles per box as the objects, numbered from first_id in link order,
+// with no face plane.  Four links (32 vertices, 48 triangles) make one
+// cluster, two clusters per env.
+__device__ __forceinline__ void link_cluster(const RenderMesh &m, int env, int cidx, int lane,
+                                             uint32_t first_id, ClusterData &d)
+{
+    d.nv = 32;
+    d.nt = 48;
+    d.first = first_id + 48u * (uint32_t)cidx;
+    d.p01 = kNoPlane | (kNoPlane << 16);
+    d.p23 = d.p01;
+    d.vx = d.vy = d.vz = 0.0f;
+    d.packed = 0u;
+    if (lane < 32) {
+        const int l = 4 * cidx + (lane >> 3), k = lane & 7;
+        const float *c = m.link_box + 6 * l, *h = c + 3;
+        const float *F = m.link_frames + ((size_t)env * 8 + l) * 12;
+        const float px = c[0] + ((k & 1) ? h[0] : -h[0]);
+        const float py = c[1] + ((k & 2) ? h[1] : -h[1]);
+        const float pz = c[2] + ((k & 4) ? h[2] : -h[2]);
+        d.vx = ((F[0] * px + F[1] * py) + F[2] * pz) + F[3];
+        d.vy = ((F[4] * px + F[5] * py) + F[6] * pz) + F[7];
+        d.vz = ((F[8] * px + F[9] * py) + F[10] * pz) + F[11];
+    }
+    if (lane < 48) {
+        const int ol = lane / 12, f2 = lane - 12 * ol;
+        const int face = f2 >> 1;
+        const int q[6][4] = {{0, 4, 6, 2}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 6, 7, 3}, {0, 2, 3, 1}, {4, 5, 7, 6}};
+        int a = q[0][0], b = q[0][1], c = q[0][2], dd = q[0][3];
+#pragma unroll
+        for (int f = 1; f < 6; ++f)
+            if (face == f) { a = q[f][0]; b = q[f][1]; c = q[f][2]; dd = q[f][3]; }
+        const int i0 = 8 * ol + a;
+        const int i1 = 8 * ol + ((f2 & 1) ? c : b);
+        const int i2 = 8 * ol + ((f2 & 1) ? dd : c);
+        d.packed = (uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16);
+    }
+}
+
 // Work counters (debug / roofline accounting), summed per wave.
 enum {
     kStatBatchClusters = 0,  // clusters tested against the frustum
@@ -1070,6 +1112,14 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
             draw_cluster(c, cd, lane, zb, stats);
         }
     }
+    // ---- the robot's links (four links per cluster, on the last two waves)
+    if (m.link_frames && wave >= kWaves - 2) {
+        const uint32_t first_id = (uint32_t)(m.env_tri_off[env + 1] - m.env_tri_off[env]) +
+                                  (m.obj_frames ? 12u * (uint32_t)m.num_objects : 0u);
+        ClusterData cd;
+        link_cluster(m, env, kWaves - 1 - wave, lane, first_id, cd);
+        draw_cluster(c, cd, lane, zb, stats);
+    }
     // Clusters are processed in windows of up to kVisCap: the workgroup tests
     // a window against the region frustum and compacts the visible ones, in
     // mesh order, into an LDS list; waves then pull list entries one at a
@@ -1195,8 +1245,10 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                 if (D < kFar) {
                     const uint64_t id = key & 0xFFFFFFFFull;
                     const uint64_t ntri = m.env_tri_off[env + 1] - m.env_tri_off[env];
-                    const uint8_t *cc = id < ntri ? m.tri_rgb + (m.env_tri_off[env] + id) * 3
-                                                  : m.obj_rgb + ((size_t)env * m.num_objects + (id - ntri) / 12) * 3;
+                    const uint64_t nobj = m.obj_frames ? 12ull * (uint64_t)m.num_objects : 0ull;
+                    const uint8_t *cc = id < ntri          ? m.tri_rgb + (m.env_tri_off[env] + id) * 3
+                                        : id < ntri + nobj ? m.obj_rgb + ((size_t)env * m.num_objects + (id - ntri) / 12) * 3
+                                                           : m.link_rgb + ((id - ntri - nobj) / 12) * 3;
                     r = cc[0];
                     g = cc[1];
                     bch = cc[2];

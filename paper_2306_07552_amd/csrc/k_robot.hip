@@ -389,11 +389,18 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         if (out.accepted) out.accepted[env] = accepted ? 1 : 0;
         if (out.done) out.done[env] = done ? 1 : 0;
     }
-    if (out.frames && sub < 8) {
+    if ((out.frames || rp.links) && sub < 8) {
         Frame F = pick(fk, sub);
-        float *dst = out.frames + ((size_t)env * 8 + sub) * 12;
+        if (out.frames) {
+            float *dst = out.frames + ((size_t)env * 8 + sub) * 12;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+            for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+        }
+        if (rp.links) {
+            float *dst = sb.link_frames + ((size_t)env * 8 + sub) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+        }
     }
 }
 
@@ -824,11 +831,18 @@ __global__ __launch_bounds__(256) void k_robot_step_manip(RobotParams rp, SimBuf
         if (out.done) out.done[env] = done ? 1 : 0;
         if (out.held) out.held[env] = held;
     }
-    if (out.frames && lane < 8) {
+    if ((out.frames || rp.links) && lane < 8) {
         Frame F = pick(fk, lane);
-        float *dst = out.frames + ((size_t)env * 8 + lane) * 12;
+        if (out.frames) {
+            float *dst = out.frames + ((size_t)env * 8 + lane) * 12;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+            for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+        }
+        if (rp.links) {
+            float *dst = sb.link_frames + ((size_t)env * 8 + lane) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) dst[k] = F.m[k];
+        }
     }
     if (lane < O) {
         const Frame Fo = lane == held ? fmul(fk.f[7], rel) : object_frame(objs + 8 * lane);

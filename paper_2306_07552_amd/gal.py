@@ -20,6 +20,7 @@ GAL_OK = 0
 GAL_COLOR = 0x1
 GAL_MANIP = 0x2
 GAL_SLIDE = 0x4
+GAL_LINKS = 0x8
 ERRORS = {-1: "GAL_EINVAL", -2: "GAL_ENOMEM", -3: "GAL_EDEVICE", -4: "GAL_ESTATE",
           -5: "GAL_EOVERFLOW"}
 
@@ -36,7 +37,8 @@ class GalRobot(C.Structure):
                 ("cam_pitch_cs", C.c_float * 2), ("num_spheres", C.c_int32),
                 ("sphere_link", _i32p), ("sphere_pos", _fp), ("sphere_class", _i32p),
                 ("sphere_held_only", _u8p), ("grasp_tip", C.c_float * 3),
-                ("grasp_radius", C.c_float), ("held_class", C.c_int32)]
+                ("grasp_radius", C.c_float), ("held_class", C.c_int32),
+                ("link_box", _fp), ("link_rgb", _u8p)]
 
 
 class GalSceneSet(C.Structure):
@@ -208,6 +210,14 @@ class Batch:
         r.sphere_pos = _p(arr(robot.sphere_pos, np.float32), _fp)
         r.sphere_class = _p(arr(robot.sphere_class, np.int32), _i32p)
         r.sphere_held_only = _p(arr(robot.sphere_held_only, np.uint8), _u8p)
+        self.links = bool(consts.get("links", False))
+        if self.links:
+            cfg.flags |= GAL_LINKS
+            _need(robot.link_box, (8, 6), "link_box")
+            r.link_box = _p(arr(robot.link_box, np.float32), _fp)
+            if robot.link_rgb is not None:
+                _need(robot.link_rgb, (8, 3), "link_rgb")
+                r.link_rgb = _p(arr(robot.link_rgb, np.uint8), _u8p)
         if self.manip:
             r.grasp_tip[:] = [float(v) for v in np.asarray(consts["grasp_tip"], np.float32)]
             r.grasp_radius = float(np.float32(consts["grasp_radius"]))

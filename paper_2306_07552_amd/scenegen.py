@@ -159,7 +159,7 @@ CONFIGS = {
     # placing heuristic, sliding; the paper's radius working set
     5: Config("manip-1024env-128px-20k-80k-tris", 6, 1024, 128, 8, False, 8, (2, 6),
               (20000.0, 80000.0), steps=1000, episode_len=500, manip=True,
-              radius_set=RADIUS_CLASSES_PAPER),
+              radius_set=RADIUS_CLASSES_PAPER, links=True),
 }
 
 # Manipulation constants.  Section 3.2 queries a small (3 cm) sphere at the
