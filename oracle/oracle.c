@@ -1052,3 +1052,84 @@ O_EXPORT void o_render(const float *verts, const int32_t *tris, int64_t ntri, co
     }
     if (stats) *stats = local;
 }
+
+/* ------------------------------------------------------------------------ */
+/* lit, textured colour                                                       */
+/* ------------------------------------------------------------------------ */
+/* The RGB half of the RGBD observation (Section 4.1) with lighting and a
+   texture: the paper's scenes carry baked textures and lighting, which are not
+   available, so a procedural stand-in is computed per pixel from what the
+   depth pass leaves (the winning triangle and its D24 depth):
+     - the pixel's camera-space depth from its D24 value, 1/Z = 1/n - D / K
+       (K the depth scale of the rasteriser), and its world position
+       P = c + Z ((f + u r) + v d) along the pixel-centre ray, u = (x + 1/2 -
+       W/2) / (W/2), v likewise in y;
+     - Lambert lighting from one directional light L = (0.36, 0.48, 0.8) (a
+       unit vector) with an ambient term: s = 0.35 + 0.65 max(0, n . L), n the
+       winning triangle's outward unit normal;
+     - a world-space checker texture of 0.25 m squares on the plane the face
+       most nearly lies in (the two world axes other than n's largest
+       component: z first, then x), dark squares at 0.8 of the colour:
+       t = 0.8 when floor(4 a) + floor(4 b) is odd, else 1;
+     - each channel min(255, floor(c s t + 1/2)) of the triangle's flat
+       colour c; background (0, 0, 0).
+   FP32 throughout in the order written.  depth and win as o_render leaves
+   them (win = winning triangle id); tri_n [T][3] the outward unit normals;
+   rgb [H][W][3] out. */
+O_EXPORT void o_shade(const uint32_t *depth, const uint32_t *win, int W, int H, const float *cam,
+                      float near_m, float far_m, const float *tri_n, const uint8_t *tri_rgb,
+                      uint8_t *rgb)
+{
+    const float invn = 1.0f / near_m, invf = 1.0f / far_m;
+    const float kd = 16777215.0f / (invn - invf);
+    const float invk = 1.0f / kd;
+    const float hw = (float)W * 0.5f, hh = (float)H * 0.5f;
+    const float L0 = 0.36f, L1 = 0.48f, L2 = 0.8f;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int64_t p = (int64_t)y * W + x;
+            uint8_t *out = rgb + 3 * p;
+            const uint32_t D = depth[p];
+            if (D >= 16777215u) {
+                out[0] = out[1] = out[2] = 0;
+                continue;
+            }
+            const uint32_t id = win[p];
+            const float invz = invn - (float)D * invk;
+            const float z = 1.0f / invz;
+            const float u = (((float)x + 0.5f) - hw) / hw;
+            const float v = (((float)y + 0.5f) - hh) / hh;
+            float P[3];
+            for (int i = 0; i < 3; ++i) P[i] = cam[i] + z * ((cam[9 + i] + u * cam[3 + i]) + v * cam[6 + i]);
+            const float *n = tri_n + 3 * (int64_t)id;
+            const float ndl = (n[0] * L0 + n[1] * L1) + n[2] * L2;
+            const float s = 0.35f + 0.65f * (ndl > 0.0f ? ndl : 0.0f);
+            const float a0 = fabsf(n[0]), a1 = fabsf(n[1]), a2 = fabsf(n[2]);
+            float ta, tb;
+            if (a2 >= a0 && a2 >= a1) { ta = P[0]; tb = P[1]; }
+            else if (a0 >= a1) { ta = P[1]; tb = P[2]; }
+            else { ta = P[0]; tb = P[2]; }
+            const int ia = (int)floorf(ta * 4.0f), ib = (int)floorf(tb * 4.0f);
+            const float t = ((ia + ib) & 1) ? 0.8f : 1.0f;
+            const float f = s * t;
+            for (int c = 0; c < 3; ++c) {
+                const float val = floorf((float)tri_rgb[3 * (int64_t)id + c] * f + 0.5f);
+                out[c] = (uint8_t)(val >= 255.0f ? 255.0f : val);
+            }
+        }
+}
+
+/* Outward unit normals of the 12 triangles of each of nbox boxes in the order
+   of o_object_mesh / o_link_mesh (faces -x, +x, -y, +y, -z, +z, two triangles
+   each): the box frame's axis column, negated for the minus faces.
+   frames [nbox][12], tri_n [12 nbox][3]. */
+O_EXPORT void o_box_normals(const float *frames, int nbox, float *tri_n)
+{
+    for (int b = 0; b < nbox; ++b)
+        for (int j = 0; j < 12; ++j) {
+            const int face = j >> 1, axis = face >> 1;
+            const float *F = frames + 12 * b;
+            float *n = tri_n + 3 * (12 * b + j);
+            for (int i = 0; i < 3; ++i) n[i] = (face & 1) ? F[4 * i + axis] : -F[4 * i + axis];
+        }
+}

@@ -112,6 +112,8 @@ def _declare(L):
                                      _fp, _u32p, _u32p, _u8p, _u8p, _fp, _fp, _fp]
     L.o_object_mesh.argtypes = [_fp, _fp, C.c_int, C.c_int32, _fp, _i32p]
     L.o_link_mesh.argtypes = [_fp, _fp, C.c_int32, _fp, _i32p]
+    L.o_shade.argtypes = [_u32p, _u32p, C.c_int, C.c_int, _fp, C.c_float, C.c_float, _fp, _u8p, _u8p]
+    L.o_box_normals.argtypes = [_fp, C.c_int, _fp]
     L.o_render.argtypes = [_fp, _i32p, C.c_int64, _fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
                            _u32p, _u32p, _u8p, C.POINTER(ORStats)]
 
@@ -209,6 +211,20 @@ def render(verts, tris, cam, W, H, near, far, want_id=False, want_cover=False, p
     return depth, win, cov, stats
 
 
+def shade(depth, win, cam, near, far, tri_n, tri_rgb):
+    """Lit, textured RGB8 [H][W][3] of one rendered image (o_shade)."""
+    H, W = depth.shape
+    depth = np.ascontiguousarray(depth, np.uint32)
+    win = np.ascontiguousarray(win, np.uint32)
+    cam = np.ascontiguousarray(cam, np.float32)
+    tri_n = np.ascontiguousarray(tri_n, np.float32)
+    tri_rgb = np.ascontiguousarray(tri_rgb, np.uint8)
+    rgb = np.zeros((H, W, 3), np.uint8)
+    lib().o_shade(ptr(depth, _u32p), ptr(win, _u32p), W, H, ptr(cam, _fp), float(np.float32(near)),
+                  float(np.float32(far)), ptr(tri_n, _fp), ptr(tri_rgb, _u8p), ptr(rgb, _u8p))
+    return rgb
+
+
 # --------------------------------------------------------------------------
 # the whole step over a batch of environments
 # --------------------------------------------------------------------------
@@ -237,6 +253,7 @@ class OracleBatch:
         self.counters = np.zeros((n, 2), np.int32)
         self.manip = bool(cc.get("manip", False))
         self.links = bool(cc.get("links", False))
+        self.shade = bool(cc.get("shade", False)) and color
         if self.links:
             self.link_box = np.ascontiguousarray(robot.link_box, np.float32)
             self.link_rgb = np.ascontiguousarray(robot.link_rgb, np.uint8)
@@ -358,6 +375,26 @@ class OracleBatch:
         return (np.concatenate(vs), np.concatenate(ts), np.concatenate(rgbs),
                 None if planes is None else np.concatenate(pls))
 
+    def env_normals(self, i, frames):
+        """Outward unit normals [T][3] of env i's render triangles, in
+        env_render_mesh's order: the static faces' plane normals, then the
+        object boxes' and the link boxes' face normals."""
+        e = self.envs[i]
+        planes = self.scenes.env_planes(e)
+        assert planes is not None, "shading needs the face planes"
+        ns = [np.ascontiguousarray(planes[:, :3], np.float32)]
+        if self.manip:
+            O = self.scenes.num_objects
+            n = np.zeros((12 * O, 3), np.float32)
+            lib().o_box_normals(ptr(np.ascontiguousarray(self.obj_frames[i]), _fp), O, ptr(n, _fp))
+            ns.append(n)
+        if self.links:
+            n = np.zeros((96, 3), np.float32)
+            lib().o_box_normals(ptr(np.ascontiguousarray(frames, np.float32).reshape(8, 12), _fp), 8,
+                                ptr(n, _fp))
+            ns.append(n)
+        return np.concatenate(ns)
+
     def _step_env(self, i, act, out):
         L = lib()
         e = self.envs[i]
@@ -382,7 +419,10 @@ class OracleBatch:
         depth, win, _cov, stats = render(v, t, out["cam"][i], res, res, self.near, self.far,
                                          want_id=self.color, planes=planes)
         out["depth"][i] = depth
-        if self.color:
+        if self.shade:
+            out["rgb"][i] = shade(depth, win, out["cam"][i], self.near, self.far,
+                                  self.env_normals(i, out["frames"][i]), _rgb)
+        elif self.color:
             rgb = np.zeros((res, res, 3), np.uint8)
             hit = win != 0xFFFFFFFF
             rgb[hit] = _rgb[win[hit]]
