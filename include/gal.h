@@ -60,6 +60,9 @@ extern "C" {
 #define GAL_LINKS 0x8u      /* the head camera also sees the robot itself
                                (Section 4.1's observation): each link drawn
                                as its box (gal_robot.link_box)               */
+#define GAL_SHADE 0x10u     /* with GAL_COLOR: lit, textured colour instead of
+                               flat colour (Section 4.1's RGB; see gal_step);
+                               needs scenes->tri_plane (the faces' normals) */
 
 /*
  * Robot (Section 3.2 / Appendix G): a planar base (x, y, yaw) and a 7-DoF
@@ -163,7 +166,7 @@ typedef struct gal_config {
     float act_lim[3];           /* |forward| m, |yaw| rad, |joint delta| rad */
     int32_t episode_len;        /* steps per episode; 0 = never auto-reset   */
     uint32_t flags;             /* GAL_COLOR | GAL_MANIP | GAL_SLIDE |
-                                   GAL_LINKS                                 */
+                                   GAL_LINKS | GAL_SHADE                     */
     /* GAL_MANIP (Appendix I): base jitter per sliding try and object jitter
        per placing try (m), and the seed of the placing jitter's counter-based
        randomness */
@@ -257,6 +260,15 @@ int gal_reset(gal_batch *b, const uint8_t *env_mask_dev, void *stream);
  * cast fails or the landed box overlaps another object; then it returns to
  * where it was grasped.  Contact words then cover S + 8 spheres (bits S..S+7
  * = the held object's).  An episode start restores every object.
+ * With GAL_SHADE the colour is lit and textured (a stand-in for the paper's
+ * baked textures and lighting), per pixel from the winning triangle's outward
+ * unit normal n (its face plane; a box face's frame axis) and colour c and the
+ * pixel's D24 depth D: 1/Z = 1/near - D / K (K the depth scale), world point
+ * P = cam + Z ((fwd + u right) + v down) at the pixel centre (u, v in
+ * [-1, 1]); s = 0.35 + 0.65 max(0, n . (0.36, 0.48, 0.8)); a checker of
+ * 0.25 m squares on the two world axes other than n's largest component
+ * (z first, then x) darkens odd squares to t = 0.8; each channel
+ * min(255, floor(c s t + 1/2)); FP32 in that order.
  * Errors: GAL_EINVAL (NULL batch/actions/outputs, rgb without GAL_COLOR or
  * without depth),
  * GAL_EDEVICE (launch failure).

@@ -72,6 +72,7 @@ struct EnvClusters {
     std::vector<float> verts;     // [Vc][3]
     std::vector<uint32_t> tris;   // [T]
     std::vector<float> planes;    // [P][4] distinct face planes of the env (bit patterns)
+    std::vector<uint16_t> pidx;   // [T] each triangle's index in `planes` (with face planes)
     int bad = 0;                  // 1 = triangle index out of range, 2 = too many planes
 };
 
@@ -159,6 +160,7 @@ void build_env_clusters(const float *verts, int64_t nverts, const int32_t *tris,
             pslot = ncpl;
             cpl[ncpl++] = pidx;
         }
+        if (tri_plane) out.pidx.push_back((uint16_t)pidx);
         uint32_t packed = tri_plane ? (uint32_t)pslot << 24 : 0u;
         for (int k = 0; k < 3; ++k) {
             if (mark[v[k]] != cid) {
@@ -654,6 +656,9 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         if (!(cfg->class_radius[k] > 0.0f)) return fail(GAL_EINVAL, "class radius must be > 0");
     const bool manip = (cfg->flags & GAL_MANIP) != 0;
     const bool links = (cfg->flags & GAL_LINKS) != 0;
+    const bool shade = (cfg->flags & GAL_SHADE) != 0;
+    if (shade && (!(cfg->flags & GAL_COLOR) || !sc->tri_plane))
+        return fail(GAL_EINVAL, "GAL_SHADE needs GAL_COLOR and tri_plane (the faces' normals)");
     if ((cfg->flags & GAL_SLIDE) && !manip) return fail(GAL_EINVAL, "GAL_SLIDE needs GAL_MANIP");
     if (links) {
         if (!robot->link_box) return fail(GAL_EINVAL, "GAL_LINKS needs link_box");
@@ -926,6 +931,18 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
                 std::copy(ec[e].planes.begin(), ec[e].planes.end(), pl_all.begin() + pl_off[e] * 4);
             HIP_TRY(hipMemcpy(d_pl, pl_all.data(), sizeof(float) * pl_all.size(), hipMemcpyHostToDevice));
             HIP_TRY(hipMemcpy(d_pl_off, pl_off.data(), sizeof(uint64_t) * (N + 1), hipMemcpyHostToDevice));
+        }
+        if (shade) {
+            // each triangle's face-plane index (its normal), in the caller's order
+            uint16_t *d_pidx;
+            if ((rc = b->mem.alloc(&d_pidx, (size_t)std::max<uint64_t>(tri_off[N], 1)))) return cleanup(rc);
+            std::vector<uint16_t> all((size_t)std::max<uint64_t>(tri_off[N], 1), 0);
+            for (int e = 0; e < N; ++e) {
+                std::copy(ec[e].pidx.begin(), ec[e].pidx.end(), all.begin() + tri_off[e]);
+                std::vector<uint16_t>().swap(ec[e].pidx);
+            }
+            HIP_TRY(hipMemcpy(d_pidx, all.data(), sizeof(uint16_t) * all.size(), hipMemcpyHostToDevice));
+            b->mesh.tri_pidx = d_pidx;
         }
         std::vector<float> cl_all((size_t)cl_off[N] * 12);
         std::vector<float> cv_all(slots * 3, 0.0f);

@@ -138,6 +138,9 @@ struct RenderMesh {
     const float *link_frames;        // [N][8][12]
     const float *link_box;           // [8][6] centre, half extents in the link frame
     const uint8_t *link_rgb;         // [8][3] or null
+    // lit, textured colour (null: flat colour): each triangle's index into
+    // its env's face planes, whose normals light it
+    const uint16_t *tri_pidx;        // [T] in the caller's order per env
 };
 
 struct RasterParams {

@@ -21,6 +21,7 @@ GAL_COLOR = 0x1
 GAL_MANIP = 0x2
 GAL_SLIDE = 0x4
 GAL_LINKS = 0x8
+GAL_SHADE = 0x10
 ERRORS = {-1: "GAL_EINVAL", -2: "GAL_ENOMEM", -3: "GAL_EDEVICE", -4: "GAL_ESTATE",
           -5: "GAL_EOVERFLOW"}
 
@@ -210,6 +211,8 @@ class Batch:
         r.sphere_pos = _p(arr(robot.sphere_pos, np.float32), _fp)
         r.sphere_class = _p(arr(robot.sphere_class, np.int32), _i32p)
         r.sphere_held_only = _p(arr(robot.sphere_held_only, np.uint8), _u8p)
+        if color and consts.get("shade", False):
+            cfg.flags |= GAL_SHADE
         self.links = bool(consts.get("links", False))
         if self.links:
             cfg.flags |= GAL_LINKS
