@@ -308,7 +308,7 @@ def main():
     kernel = "k_raster_persistent" if tuning["persistent"] else "k_raster"
     traffic = valu = None
     if args.config == 1 and not cfg.color:
-        srcs = ["paper_2306_07552_amd/csrc/k_raster.hip", "paper_2306_07552_amd/csrc/gal_internal.h"]
+        srcs = ["paper_2306_07552_amd/csrc/k_raster.hip", "paper_2306_07552_amd/csrc/gal_raster.h"]
         traffic = counter_record(srcs, "k_raster_1024env_128px_traffic.json", tuning,
                                  "traffic_bytes_per_launch")
         valu = counter_record(srcs, "k_raster_1024env_128px_sq.json", tuning,

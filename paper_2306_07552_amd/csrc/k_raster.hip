@@ -35,7 +35,7 @@
 // own lane, mid-sized ones by the whole wave with the pixels spread over the
 // lanes, large ones one 8x8 tile (lane = pixel) at a time.  Every extra
 // rejection only removes triangles that cannot change a pixel of the region.
-#include "gal_internal.h"
+#include "gal_raster.h"
 
 #include <type_traits>
 
