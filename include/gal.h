@@ -312,9 +312,15 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             the order of their times in the previous step, longest first
  *             (measured on the device; up to 32768 items, the static order
  *             beyond), 0 = the static order by cluster count
+ *  objgrid    1 = a sphere's resting-object candidates come from four offset
+ *             regular grids of 0.5 m cells (Appendix G: any sphere of
+ *             radius <= 12.5 cm lies wholly inside a cell of one of them;
+ *             a cell lists the objects whose footprint meets it), 0 = every
+ *             object is tested; the contacts are the same either way
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
- * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0.
+ * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0,
+ * objgrid 1 with 16 or more objects per env (else 0).
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -329,6 +335,7 @@ typedef struct gal_tuning {
     int32_t graph;
     int32_t split;
     int32_t order;
+    int32_t objgrid;
 } gal_tuning;
 
 /* Read / replace the launch configuration above (Section 3.1 batching

@@ -389,6 +389,7 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->graph = b->use_graph;
     t->split = b->split;
     t->order = b->rast.order;
+    t->objgrid = b->rp.objgrid;
     return GAL_OK;
 }
 
@@ -409,6 +410,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->robot_lanes != 32 && t->robot_lanes != 64) return fail(GAL_EINVAL, "robot_lanes must be 32 or 64");
     if (t->split < 0 || t->split > b->N) return fail(GAL_EINVAL, "split must be in 0..num_envs");
     if (t->order != 0 && t->order != 1) return fail(GAL_EINVAL, "order must be 0 or 1");
+    if (t->objgrid != 0 && t->objgrid != 1) return fail(GAL_EINVAL, "objgrid must be 0 or 1");
     const bool rebuild = t->region != b->rast.region || t->split != b->split;
     b->rast.block = t->block;
     b->rast.region = t->region;
@@ -422,6 +424,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->use_graph = t->graph ? 1 : 0;
     b->split = t->split;
     b->rast.order = t->order;
+    b->rp.objgrid = t->objgrid;
     b->tune_gen += 1;
     b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
     if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");
@@ -481,6 +484,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
             HIP_TRY(hipMemcpyAsync(b->sb.obj_dyn, b->tune_obj0, sizeof(float) * nobj, hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(b->sb.held_obj, b->tune_held0, sizeof(int32_t) * b->N, hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(b->sb.rel, b->tune_rel0, sizeof(float) * b->N * 12, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(gal::launch_object_frames(b->rp, b->sb, s));
         }
         return GAL_OK;
     };
@@ -823,6 +827,30 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         // link frames after each step (written by the robot step, read by the raster)
         if ((rc = b->mem.alloc(&sb.link_frames, (size_t)N * 8 * 12))) return cleanup(rc);
         HIP_TRY(hipMemset(sb.link_frames, 0, sizeof(float) * N * 8 * 12));
+    }
+    if (b->O > 0) {
+        // the resting objects' four offset grids per env, over the column
+        // grid's rectangle with a cell of margin on every side
+        std::vector<gal::ObjGridMeta> og(N);
+        uint64_t words = 0;
+        for (int e = 0; e < N; ++e) {
+            const gal::GridMeta &gm = b->meta_host[e];
+            og[e].x0 = gm.x0 - gal::kObjCell;
+            og[e].y0 = gm.y0 - gal::kObjCell;
+            og[e].nx = (int32_t)std::ceil((double)gm.nx * cfg->cell_m / gal::kObjCell) + 3;
+            og[e].ny = (int32_t)std::ceil((double)gm.ny * cfg->cell_m / gal::kObjCell) + 3;
+            og[e].base = words;
+            words += 4ull * (uint64_t)og[e].nx * (uint64_t)og[e].ny;
+        }
+        gal::ObjGridMeta *d_og;
+        unsigned long long *d_mask;
+        if ((rc = b->mem.alloc(&d_og, (size_t)N)) || (rc = b->mem.alloc(&d_mask, (size_t)words)))
+            return cleanup(rc);
+        HIP_TRY(hipMemcpy(d_og, og.data(), sizeof(gal::ObjGridMeta) * N, hipMemcpyHostToDevice));
+        sb.objgrid_meta = d_og;
+        sb.objgrid_mask = d_mask;
+        rp.objgrid = b->O >= 16 ? 1 : 0;
+        HIP_TRY(gal::launch_objgrid_build(rp, sb, nullptr));
     }
 
     // ---- column grids: count, scan, fill (on the device)

@@ -39,6 +39,7 @@ struct RobotParams {
     float slide_step, place_step;
     uint64_t manip_seed;
     int32_t links;              // 1: write every link's frame for the raster (sb.link_frames)
+    int32_t objgrid;            // 1: resting objects found through the object grids
 };
 
 // Spheres of a held object (one per octant of its box).
@@ -54,6 +55,20 @@ struct Sphere {
     int32_t link;
     int32_t cls;
     int32_t held_only;
+};
+
+// Regular grids of the resting objects (Appendix G): four grids of
+// kObjCell squares per env, grid g shifted by (g & 1, g >> 1) x kObjCell / 2
+// from (x0, y0), nx x ny cells each; a cell's word holds one bit per object
+// whose footprint box (grown by kObjMargin) meets the cell.  A sphere of
+// radius <= kObjCell / 4 lies wholly inside a cell of at least one grid, so
+// that cell's word lists every object the sphere can touch.
+constexpr float kObjCell = 0.5f;
+constexpr float kObjMargin = 1e-3f;
+struct ObjGridMeta {
+    float x0, y0;
+    int32_t nx, ny;
+    uint64_t base;                   // first word of the env's 4 grids in objgrid_mask
 };
 
 // Per-env grid placement (device table [N]).
@@ -89,6 +104,9 @@ struct SimBuffers {
     float *rel;                      // [N][12] held object's frame in the end-effector frame
     float *obj_frames;               // [N][O][12] object frames after the step (for the raster)
     float *link_frames;              // [N][8][12] link frames after the step (links drawn)
+    // the resting objects' regular grids (null: every object is tested)
+    const ObjGridMeta *objgrid_meta; // [N]
+    unsigned long long *objgrid_mask;// per env 4 x ny x nx words
 };
 
 // Step outputs (device, caller-owned).
@@ -113,6 +131,9 @@ hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8
 // Object frames of the current state (manipulation; after create, reset and
 // state restore, so that the raster draws the objects where they are).
 hipError_t launch_object_frames(const RobotParams &rp, const SimBuffers &sb, hipStream_t s);
+// The resting objects' grids of every env, from the current object records
+// (after create; with manipulation also after reset and state restore).
+hipError_t launch_objgrid_build(const RobotParams &rp, const SimBuffers &sb, hipStream_t s);
 hipError_t launch_hash_u32(const uint32_t *a, uint64_t n, unsigned long long *out, hipStream_t s);
 // Work items the raster queue order handles (the static order beyond).
 constexpr int kOrderCap = 32768;

@@ -113,6 +113,65 @@ __device__ __forceinline__ bool obb_contact(const float *o, float x, float y, fl
     return dd < r * r;
 }
 
+// Objects a sphere (x, y, radius r) may touch: the word of the first object
+// grid cell that holds the sphere's whole disk (x +- r, y +- r inside the
+// cell), or every object when no cell does (a sphere wider than a quarter
+// cell, or outside the grids) or the grids are not in use.  Every object whose
+// box the sphere meets has its footprint in that cell, so testing the word's
+// objects finds exactly the contacts of testing them all.
+__device__ __forceinline__ uint64_t objgrid_candidates(const RobotParams &rp, const SimBuffers &sb, int env,
+                                                        float x, float y, float r)
+{
+    const int O = rp.num_objects;
+    const uint64_t all = O >= 64 ? ~0ull : ((1ull << O) - 1ull);
+    if (!rp.objgrid || !sb.objgrid_mask) return all;
+    const ObjGridMeta gm = sb.objgrid_meta[env];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float ox = gm.x0 + (float)(g & 1) * (0.5f * kObjCell);
+        const float oy = gm.y0 + (float)(g >> 1) * (0.5f * kObjCell);
+        const float fx = (x - ox) * (1.0f / kObjCell), fy = (y - oy) * (1.0f / kObjCell);
+        if (!(fx >= 0.0f && fx < (float)gm.nx && fy >= 0.0f && fy < (float)gm.ny)) continue;
+        const float i = floorf(fx), j = floorf(fy);
+        const float lx = x - (ox + i * kObjCell), ly = y - (oy + j * kObjCell);
+        if (lx >= r && kObjCell - lx >= r && ly >= r && kObjCell - ly >= r)
+            return sb.objgrid_mask[gm.base + ((uint64_t)g * (uint64_t)gm.ny + (uint64_t)j) * (uint64_t)gm.nx +
+                                   (uint64_t)i];
+    }
+    return all;
+}
+
+// The object grids of one env from its object records (one wave): clear the
+// words, then set object o's bit in every cell, of every grid, that its
+// footprint box (grown by kObjMargin) meets.  Objects wholly outside a grid,
+// or with non-finite records (which no sphere can touch), set no bit there.
+__device__ void objgrid_rebuild(const RobotParams &rp, const SimBuffers &sb, int env, const float *objs, int lane)
+{
+    const ObjGridMeta gm = sb.objgrid_meta[env];
+    unsigned long long *w = sb.objgrid_mask + gm.base;
+    const int per = gm.nx * gm.ny;
+    for (int i = lane; i < 4 * per; i += 64) w[i] = 0ull;
+    __threadfence_block();
+    for (int p = lane; p < 4 * rp.num_objects; p += 64) {
+        const int o = p >> 2, g = p & 3;
+        const float *ob = objs + 8 * o;
+        const float c = fabsf(ob[6]), sn = fabsf(ob[7]);
+        const float ax = (c * ob[3] + sn * ob[4]) + kObjMargin;
+        const float ay = (sn * ob[3] + c * ob[4]) + kObjMargin;
+        const float ox = gm.x0 + (float)(g & 1) * (0.5f * kObjCell);
+        const float oy = gm.y0 + (float)(g >> 1) * (0.5f * kObjCell);
+        const float fi0 = floorf(((ob[0] - ax) - ox) * (1.0f / kObjCell));
+        const float fi1 = floorf(((ob[0] + ax) - ox) * (1.0f / kObjCell));
+        const float fj0 = floorf(((ob[1] - ay) - oy) * (1.0f / kObjCell));
+        const float fj1 = floorf(((ob[1] + ay) - oy) * (1.0f / kObjCell));
+        if (!(fi1 >= 0.0f && fj1 >= 0.0f && fi0 < (float)gm.nx && fj0 < (float)gm.ny)) continue;
+        const int i0 = (int)fmaxf(fi0, 0.0f), i1 = (int)fminf(fi1, (float)(gm.nx - 1));
+        const int j0 = (int)fmaxf(fj0, 0.0f), j1 = (int)fminf(fj1, (float)(gm.ny - 1));
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) atomicOr(&w[(size_t)g * per + (size_t)j * gm.nx + i], 1ull << o);
+    }
+}
+
 __device__ __forceinline__ void load_start(const RobotParams &rp, const SimBuffers &sb, int env,
                                            int episode, float *st)
 {
@@ -281,15 +340,18 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         GridProbe g[kSlots];
         float cx[kSlots], cy[kSlots], cz[kSlots];
         const bool grid = route != 1;
+        uint64_t cm[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             g[k].outside = false;
             g[k].l0 = g[k].l1 = 0;
             cx[k] = cy[k] = cz[k] = 0.0f;
+            cm[k] = 0ull;
             if (sl.live[k]) {
                 const Frame F = pick(fk, sl.sp[k].link);
                 fpoint(F, sl.sp[k].px, sl.sp[k].py, sl.sp[k].pz, cx[k], cy[k], cz[k]);
                 if (grid) grid_probe_column(sb, gm, sl.off_base[k], cx[k], cy[k], cz[k], g[k]);
+                cm[k] = objgrid_candidates(rp, sb, env, cx[k], cy[k], rp.class_radius[sl.sp[k].cls]);
             }
         }
 #pragma unroll
@@ -303,7 +365,8 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
             if (sl.live[k]) {
                 if (grid) hit_static[k] = grid_probe_contact(sb, sl.layer_base[k], g[k]);
                 const float r = rp.class_radius[sl.sp[k].cls];
-                for (int o = 0; o < rp.num_objects; ++o) {
+                for (uint64_t m = cm[k]; m; m &= m - 1) {
+                    const int o = __ffsll((unsigned long long)m) - 1;
                     if (obb_contact(objs + 8 * o, cx[k], cy[k], cz[k], r)) {
                         hit_object[k] = true;
                         break;
@@ -528,8 +591,10 @@ __device__ __forceinline__ bool manip_pose_contacts(const RobotParams &rp, const
         if (live) {
             hs = grid_point_contact(rp, sb, gm, env, cls, cx, cy, cz);
             const float r = rp.class_radius[cls];
-            for (int o = 0; o < rp.num_objects; ++o) {
-                if (o == held) continue;
+            uint64_t m = objgrid_candidates(rp, sb, env, cx, cy, r);
+            if (held >= 0) m &= ~(1ull << held);
+            for (; m; m &= m - 1) {
+                const int o = __ffsll((unsigned long long)m) - 1;
                 if (obb_contact(objs + 8 * o, cx, cy, cz, r)) {
                     ho = true;
                     break;
@@ -635,8 +700,10 @@ __device__ __forceinline__ void place_object(const RobotParams &rp, const SimBuf
                 float ox, oy, oz, wx, wy, wz;
                 octant(e, lane, ox, oy, oz);
                 fpoint(Fo, ox, oy, oz, wx, wy, wz);
-                for (int o = 0; o < rp.num_objects; ++o) {
-                    if (o == h) continue;
+                // candidates in ascending order: the first hit is the lowest
+                // index of the objects the sphere touches
+                for (uint64_t m = objgrid_candidates(rp, sb, env, wx, wy, r) & ~(1ull << h); m; m &= m - 1) {
+                    const int o = __ffsll((unsigned long long)m) - 1;
                     if (obb_contact(objs + 8 * o, wx, wy, wz, r)) {
                         hit = o;
                         break;
@@ -706,6 +773,7 @@ __global__ __launch_bounds__(256) void k_robot_step_manip(RobotParams rp, SimBuf
 #pragma unroll
     for (int k = 0; k < 12; ++k) rel.m[k] = sb.rel[(size_t)env * 12 + k];
     const float ag = act[9], as = act[10];
+    bool moved = false;   // a resting object changed place (its grids are rebuilt)
     const bool grasp = ag == ag && ag >= 0.5f;
     const bool stop = as == as && as >= 0.5f;
 
@@ -793,6 +861,7 @@ __global__ __launch_bounds__(256) void k_robot_step_manip(RobotParams rp, SimBuf
         const Frame F = fmul(fk.f[7], rel);
         place_object(rp, sb, gm, env, held, F, objs, episode, t, lane);
         held = -1;
+        moved = true;
     }
     // 5. episode bookkeeping: horizon or stop, auto-reset (objects back too)
     bool done = false;
@@ -806,6 +875,12 @@ __global__ __launch_bounds__(256) void k_robot_step_manip(RobotParams rp, SimBuf
         const float *o0 = sb.objects + (size_t)env * O * 8;
         for (int i = lane; i < O * 8; i += 64) objs[i] = o0[i];
         forward_kinematics(rp, st, fk);
+        moved = true;
+    }
+    if (moved) {
+        // the records other lanes wrote are read below: fence the wave
+        __threadfence_block();
+        if (sb.objgrid_mask) objgrid_rebuild(rp, sb, env, objs, lane);
     }
     // 6. outputs
     if (lane == 0) {
@@ -880,6 +955,17 @@ __global__ __launch_bounds__(256) void k_object_frames(RobotParams rp, SimBuffer
 #pragma unroll
         for (int k = 0; k < 12; ++k) dst[k] = Fo.m[k];
     }
+    if (sb.objgrid_mask) objgrid_rebuild(rp, sb, env, sb.obj_dyn + (size_t)env * O * 8, lane);
+}
+
+// The object grids of every env (one wave per env) from the resting records.
+__global__ __launch_bounds__(256) void k_objgrid_build(RobotParams rp, SimBuffers sb)
+{
+    const int lane = threadIdx.x & 63;
+    const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)threadIdx.x / 64);
+    if (env >= sb.num_envs) return;
+    const float *objs = (rp.manip ? sb.obj_dyn : sb.objects) + (size_t)env * rp.num_objects * 8;
+    objgrid_rebuild(rp, sb, env, objs, lane);
 }
 
 // New episode for the selected envs (mask null = all): episode += 1, start
@@ -955,6 +1041,13 @@ hipError_t launch_reset(const RobotParams &rp, const SimBuffers &sb, const uint8
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !rp.manip) return e;
     return launch_object_frames(rp, sb, s);
+}
+
+hipError_t launch_objgrid_build(const RobotParams &rp, const SimBuffers &sb, hipStream_t s)
+{
+    if (!sb.objgrid_mask || sb.num_envs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_objgrid_build, dim3((sb.num_envs + 3) / 4), dim3(256), 0, s, rp, sb);
+    return hipGetLastError();
 }
 
 hipError_t launch_object_frames(const RobotParams &rp, const SimBuffers &sb, hipStream_t s)

@@ -156,8 +156,9 @@ CONFIGS = {
               (2000.0, 200000.0), tri_target_log=True, color=True),
     # the rest of the kinematic sim of Section 3.2 / Appendix I on the
     # paper-scale step: grasp, carry, release with snap-to-surface and the
-    # placing heuristic, sliding; the paper's radius working set
-    5: Config("manip-1024env-128px-20k-80k-tris", 6, 1024, 128, 8, False, 8, (2, 6),
+    # placing heuristic, sliding; the paper's radius working set and its 30
+    # resting objects per episode (1 target + 29 distractors, Section 4.1)
+    5: Config("manip-1024env-128px-20k-80k-tris", 6, 1024, 128, 8, False, 30, (2, 6),
               (20000.0, 80000.0), steps=1000, episode_len=500, manip=True,
               radius_set=RADIUS_CLASSES_PAPER, links=True),
 }
