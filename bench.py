@@ -186,7 +186,11 @@ def main():
                        dtype=torch.float32, device="cuda")
     total = args.warmup + args.steps
     acts = (torch.rand((total, N, 9), generator=g, device="cuda") * 2 - 1) * lim
-    act_buf = torch.empty((N, 9), dtype=torch.float32, device="cuda")
+    if cfg.manip:
+        # grasp / release intent on 60 % of steps, a stop action on 0.2 %
+        u = torch.rand((total, N, 2), generator=g, device="cuda")
+        acts = torch.cat([acts, torch.stack([(u[..., 0] < 0.6), (u[..., 1] < 0.002)], -1).float()], -1)
+    act_buf = torch.empty((N, acts.shape[-1]), dtype=torch.float32, device="cuda")
 
     def run(k0, n):
         for k in range(k0, k0 + n):
@@ -278,7 +282,7 @@ def main():
     launch = (("persistent queue" if batched["tuning"]["persistent"] else "one workgroup per item")
               + (f", {batched['tuning']['split']} envs split" if batched["tuning"].get("split") else ""))
     path = f"batched (autotuned: {launch}, hipGraph)"
-    if not args.no_surrogate:
+    if not args.no_surrogate and not cfg.manip:
         mlp, skip_below, info = train_surrogate(cfg, robot, consts)
         log(f"surrogate: {info}")
         b.attach_surrogate(mlp, skip_below, audit_period=16)
