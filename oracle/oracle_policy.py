@@ -1,0 +1,118 @@
+"""CPU oracle of the batched policy network -- TEST INFRASTRUCTURE ONLY.
+
+The policy that consumes the depth stack (Section 4.2 "Approach: End-to-End
+RL"; the SimpleCNN visual encoder of the appendix on model sizes): three
+convolutions without padding or dilation, 8x8 stride 4, 4x4 stride 2, 3x3
+stride 1 (32, 64 and 32 channels), each followed by ReLU, then a fully
+connected layer to 512 with ReLU; the actor's Gaussian mean and the critic's
+value are linear in [the 512 features, the 7 joint angles].  Written in FP64
+with numpy, as definitions: a convolution is the sum over its window of
+weight x input (cross-correlation, as the encoder is usually written), a fully
+connected layer a matrix product.  Where the device keeps BF16 activations
+(every ReLU output) the oracle rounds the same values to BF16, so that each
+layer can be checked from the device's own input to it.
+
+Parameter vector (FP32, in this order): conv1 W [32][8][8][1], b [32];
+conv2 W [64][4][4][32], b [64]; conv3 W [32][3][3][64], b [32]; fc W [512][4608]
+(input index (y * 12 + x) * 32 + c), b [512]; actor W [A][519], b [A];
+critic W [519], b [1]; log_std [A].  Input: depth D24 of a 128 x 128 image,
+x = D / (2^24 - 1) (no hit: 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+from .oracle_mlp import bf16_round_f32
+
+CONV = ((32, 8, 4, 1), (64, 4, 2, 32), (32, 3, 1, 64))   # out, kernel, stride, in
+FEAT = 512
+PROPRIO = 7
+RES = 128
+
+
+def out_size(n: int, k: int, s: int) -> int:
+    return (n - k) // s + 1
+
+
+def layout(act_dim: int):
+    """[(name, shape)] of the parameter vector."""
+    shapes = []
+    for i, (o, k, s, c) in enumerate(CONV):
+        shapes += [(f"conv{i + 1}.w", (o, k, k, c)), (f"conv{i + 1}.b", (o,))]
+    n = RES
+    for (o, k, s, c) in CONV:
+        n = out_size(n, k, s)
+    flat = n * n * CONV[-1][0]
+    shapes += [("fc.w", (FEAT, flat)), ("fc.b", (FEAT,)),
+               ("actor.w", (act_dim, FEAT + PROPRIO)), ("actor.b", (act_dim,)),
+               ("critic.w", (FEAT + PROPRIO,)), ("critic.b", (1,)), ("log_std", (act_dim,))]
+    return shapes
+
+
+def unpack(theta: np.ndarray, act_dim: int) -> dict:
+    out, i = {}, 0
+    for name, shp in layout(act_dim):
+        n = int(np.prod(shp))
+        out[name] = np.asarray(theta[i:i + n], np.float32).reshape(shp)
+        i += n
+    assert i == theta.size, (i, theta.size)
+    return out
+
+
+def bf16(a) -> np.ndarray:
+    return bf16_round_f32(np.asarray(a, np.float32)).astype(np.float64)
+
+
+def depth_input(depth: np.ndarray) -> np.ndarray:
+    """[N][128][128][1] BF16 values of x = D / (2^24 - 1), D in FP32 as the device divides."""
+    d = np.minimum(np.asarray(depth, np.uint64), 16777215).astype(np.float32)
+    x = (d / np.float32(16777215.0)).astype(np.float32)
+    return bf16(x)[..., None]
+
+
+def conv2d(x: np.ndarray, w: np.ndarray, b: np.ndarray, stride: int) -> np.ndarray:
+    """Valid cross-correlation, NHWC input, w [O][k][k][C]: FP64 sums over the window."""
+    k = w.shape[1]
+    win = sliding_window_view(x, (k, k), axis=(1, 2))[:, ::stride, ::stride]   # N, OH, OW, C, k, k
+    return np.einsum("nhwcij,oijc->nhwo", win, np.asarray(w, np.float64), optimize=True) + b
+
+
+def relu_bf16(v: np.ndarray) -> np.ndarray:
+    return bf16(np.maximum(v, 0.0).astype(np.float32))
+
+
+def encoder_layer(i: int, x: np.ndarray, P: dict) -> np.ndarray:
+    """Layer i (0..2 conv, 3 fc) from its BF16 input; BF16 output."""
+    if i < 3:
+        o, k, s, c = CONV[i]
+        return relu_bf16(conv2d(x, bf16(P[f"conv{i + 1}.w"]), P[f"conv{i + 1}.b"].astype(np.float64), s))
+    flat = x.reshape(x.shape[0], -1)
+    return relu_bf16(flat @ bf16(P["fc.w"]).T + P["fc.b"].astype(np.float64))
+
+
+def heads(h: np.ndarray, q: np.ndarray, P: dict):
+    """(mean [N][A], value [N]) in FP64 from the 512 BF16 features and the joint angles."""
+    f = np.concatenate([np.asarray(h, np.float64), np.asarray(q, np.float32).astype(np.float64)], axis=1)
+    mean = f @ P["actor.w"].astype(np.float64).T + P["actor.b"].astype(np.float64)
+    value = f @ P["critic.w"].astype(np.float64) + float(P["critic.b"][0])
+    return mean, value
+
+
+def forward(depth: np.ndarray, state: np.ndarray, theta: np.ndarray, act_dim: int) -> dict:
+    """Every layer of the policy on N images (the oracle's own chain)."""
+    P = unpack(theta, act_dim)
+    acts = [depth_input(depth)]
+    for i in range(4):
+        acts.append(encoder_layer(i, acts[-1], P))
+    mean, value = heads(acts[4], np.asarray(state)[:, 3:10], P)
+    return dict(x=acts[0], h1=acts[1], h2=acts[2], h3=acts[3], h4=acts[4], mean=mean, value=value)
+
+
+def sample(mean: np.ndarray, log_std: np.ndarray, noise: np.ndarray):
+    """Gaussian action a = mean + exp(log_std) noise and its log-density (FP64)."""
+    ls = np.asarray(log_std, np.float64)
+    n = np.asarray(noise, np.float64)
+    a = mean + np.exp(ls) * n
+    logp = np.sum(-0.5 * n * n - ls, axis=1) - 0.5 * np.log(2 * np.pi) * n.shape[1]
+    return a, logp
