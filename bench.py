@@ -59,6 +59,54 @@ def counter_record(kernel_sources, record, tuning, field, keys=None):
     return None
 
 
+# multiply-adds per env of the policy encoder and heads (128x128 depth):
+# conv 8x8/4 -> 31x31x32, conv 4x4/2 -> 14x14x64, conv 3x3/1 -> 12x12x32,
+# fc 4608 -> 512, heads 519 -> 9 + 1
+POLICY_MAC_PER_ENV = 961 * 32 * 64 + 196 * 64 * 512 + 144 * 32 * 576 + 4608 * 512 + 519 * 10
+
+
+def policy_record(gal, torch, b, out, act_buf, N, steps, stream):
+    """Policy inference on the step's depth output (in place): mean time of
+    one call for all envs, and the rollout loop (inference then step, the
+    policy writing the actions the step reads) in env-steps/s."""
+    pol = gal.Policy(N, act_dim=9, seed=1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    reps = 50
+    noise = torch.randn((max(reps, steps), N, 9), generator=g, device="cuda")
+    val = torch.empty(N, device="cuda")
+    lp = torch.empty(N, device="cuda")
+    for k in range(5):
+        pol.act(out["depth"], out["state"], act_buf, noise=noise[k], value=val, logp=lp)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(reps):
+        pol.act(out["depth"], out["state"], act_buf, noise=noise[k], value=val, logp=lp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    flop = 2.0 * N * POLICY_MAC_PER_ENV
+    for k in range(5):
+        pol.act(out["depth"], out["state"], act_buf, noise=noise[k])
+        b.step(act_buf, out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        pol.act(out["depth"], out["state"], act_buf, noise=noise[k])
+        b.step(act_buf, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    return {"params": pol.num_params, "envs": N, "forward_ms": round(fwd_ms, 4),
+            "flop_per_call": int(flop), "achieved_tflops": round(flop / (fwd_ms / 1e3) / 1e12, 1),
+            "mfma_peak_tflops": BF16_PEAK_TFLOPS,
+            "mfma_frac": round(flop / (fwd_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+            "rollout_env_steps_per_s": round(N * steps / (loop_ms / 1e3), 1),
+            "rollout_ms_per_step": round(loop_ms / steps, 4),
+            "rollout": "policy inference + step (the step's tuning as timed above)"}
+
+
 def host_threads():
     """Threads the CPU baseline may use: the cores this process may run on,
     at most 16 (the host share of one GPU on a shared box)."""
@@ -123,6 +171,8 @@ def main():
                     help="timed passes of --steps steps per path; the median is reported")
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-policy", action="store_true",
+                    help="skip the policy-inference and rollout-loop measurement")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
@@ -348,6 +398,13 @@ def main():
             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(flop / (sur["surrogate_ms"] / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 5)}
 
+    # ---- the policy that consumes the depth stack in place, and the rollout
+    # loop it drives (policy inference + step)
+    policy = None
+    if not args.no_policy and not cfg.manip and int(max(scenes.res)) == int(min(scenes.res)) == 128:
+        policy = policy_record(gal, torch, b, out, act_buf, N, args.steps, stream)
+        log(f"policy: {policy}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -364,7 +421,7 @@ def main():
                       "objects": cfg.num_objects, "episode_len": cfg.episode_len,
                       "path": path},
            "roofline": roofline, "cpu_baseline": cpu,
-           "plain": plain, "batched": batched, "batched_surrogate": sur,
+           "plain": plain, "batched": batched, "batched_surrogate": sur, "policy": policy,
            "timing": {"repeats": args.repeats, "reported": "median pass",
                       "pass_ms": pass_ms}}
     print(json.dumps(res), flush=True)

@@ -552,6 +552,53 @@ int gal_surrogate_detach(gal_batch *b);
  * reset (synchronises the device; reset != 0 clears them). */
 int gal_surrogate_stats(gal_batch *b, int64_t *stats_host, int reset);
 
+/*
+ * The policy that consumes the depth stack (Section 4.2 "Approach: End-to-End
+ * RL": the simulator's stacked observation feeds batched DNN inference in
+ * place; the SimpleCNN encoder of the appendix on model sizes): 128x128 D24
+ * depth, x = D / (2^24 - 1) in BF16 -> conv 8x8 stride 4 (32 channels) ->
+ * conv 4x4 stride 2 (64) -> conv 3x3 stride 1 (32), no padding, each with
+ * ReLU -> fully connected 4608 -> 512 with ReLU (BF16 weights and
+ * activations, FP32 accumulation) -> a Gaussian actor (mean linear in the 512
+ * features and the 7 joint angles, a learned log_std per action) and a critic
+ * (linear in the same), in FP32.  No recurrent core (a reading: the joint
+ * angles carry the state the paper's LSTM would).  Parameter vector (FP32):
+ * conv1 W [32][8][8][1], b [32]; conv2 W [64][4][4][32], b [64]; conv3 W
+ * [32][3][3][64], b [32]; fc W [512][4608] (input (y * 12 + x) * 32 + c), b
+ * [512]; actor W [A][519], b [A]; critic W [519], b [1]; log_std [A].
+ * Create: room for max_envs images, act_dim A (1..32), seeded He-uniform
+ * encoder weights, small heads, log_std -0.5.  Errors: GAL_EINVAL,
+ * GAL_ENOMEM.
+ */
+typedef struct gal_policy gal_policy;
+int gal_policy_create(int32_t max_envs, int32_t act_dim, uint64_t seed, gal_policy **out);
+/* The policy of Section 4.2: number of FP32 parameters. */
+int gal_policy_num_params(const gal_policy *p, int64_t *n);
+/* The policy of Section 4.2: replace / read the parameter vector (host FP32,
+ * the layout above; synchronous). */
+int gal_policy_set_weights(gal_policy *p, const float *host, size_t count);
+int gal_policy_get_weights(gal_policy *p, float *host, size_t count);
+/*
+ * The policy of Section 4.2 on n_envs envs, asynchronous on `stream`:
+ * depth_dev = the batch's depth output of 128x128 images (device u32
+ * [n_envs][128][128], 16-byte aligned, read in place), state_dev = its state
+ * output (device f32 [n_envs][10], joint angles at 3..9).  actions_dev (f32
+ * [n_envs][A]) = mean + exp(log_std) * noise with noise_dev (f32 [n_envs][A],
+ * the caller's standard normal draws), or the mean when noise_dev is NULL;
+ * value_dev (f32 [n_envs], or NULL) = the critic; logp_dev (f32 [n_envs], or
+ * NULL; needs noise) = sum_a (-noise_a^2 / 2 - log_std_a) - A log(2 pi) / 2.
+ * Calls that overlap on one policy race on its activation buffers.
+ */
+int gal_policy_act(gal_policy *p, const uint32_t *depth_dev, const float *state_dev, int32_t n_envs,
+                   const float *noise_dev, float *actions_dev, float *value_dev, float *logp_dev,
+                   void *stream);
+/* The policy of Section 4.2: the BF16 activations of layer 1..4 (conv1..3
+ * NHWC, fc) of the last gal_policy_act into host memory, count values
+ * (synchronous; for checking the encoder layer by layer). */
+int gal_policy_activations(gal_policy *p, int32_t layer, uint16_t *host, size_t count);
+/* The policy of Section 4.2: frees it. */
+void gal_policy_destroy(gal_policy *p);
+
 /* Frees a batch created by gal_create_batch (Section 3.1 batch object). */
 void gal_destroy(gal_batch *b);
 

@@ -91,6 +91,22 @@ def encoder_layer(i: int, x: np.ndarray, P: dict) -> np.ndarray:
     return relu_bf16(flat @ bf16(P["fc.w"]).T + P["fc.b"].astype(np.float64))
 
 
+def encoder_layer_pre(i: int, x: np.ndarray, P: dict) -> np.ndarray:
+    """Layer i's FP64 pre-activation (before ReLU and rounding) from its BF16 input."""
+    if i < 3:
+        o, k, s, c = CONV[i]
+        return conv2d(x, bf16(P[f"conv{i + 1}.w"]), P[f"conv{i + 1}.b"].astype(np.float64), s)
+    return x.reshape(x.shape[0], -1) @ bf16(P["fc.w"]).T + P["fc.b"].astype(np.float64)
+
+
+def encoder_layer_abs(i: int, x: np.ndarray, P: dict) -> np.ndarray:
+    """Sum of |terms| of layer i's pre-activation (the scale of its rounding error)."""
+    if i < 3:
+        o, k, s, c = CONV[i]
+        return conv2d(np.abs(x), np.abs(bf16(P[f"conv{i + 1}.w"])), np.abs(P[f"conv{i + 1}.b"].astype(np.float64)), s)
+    return np.abs(x.reshape(x.shape[0], -1)) @ np.abs(bf16(P["fc.w"])).T + np.abs(P["fc.b"].astype(np.float64))
+
+
 def heads(h: np.ndarray, q: np.ndarray, P: dict):
     """(mean [N][A], value [N]) in FP64 from the 512 BF16 features and the joint angles."""
     f = np.concatenate([np.asarray(h, np.float64), np.asarray(q, np.float32).astype(np.float64)], axis=1)

@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libgal.so")
 
 SOURCES = ["gal_api.cpp", "gal_mlp_api.cpp", "k_robot.hip", "k_grid.hip", "k_raster.hip",
            "k_util.hip", "k_mlp.hip", "k_surrogate.hip", "k_sur_infer.hip",
-           "gal_noalloc.cpp"]
+           "gal_noalloc.cpp", "k_policy.hip", "gal_policy_api.cpp"]
 
 # Exact binary32 semantics on the device: no contraction into FMA, correctly
 # rounded division and square root, denormals kept; packed-FP32 instructions

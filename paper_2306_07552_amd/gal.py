@@ -122,6 +122,15 @@ def load_library():
                                         C.c_void_p]
         L.gal_mlp_destroy.argtypes = [C.c_void_p]
         L.gal_mlp_destroy.restype = None
+        L.gal_policy_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]
+        L.gal_policy_num_params.argtypes = [C.c_void_p, _i64p]
+        L.gal_policy_set_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
+        L.gal_policy_get_weights.argtypes = [C.c_void_p, _fp, C.c_size_t]
+        L.gal_policy_act.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gal_policy_activations.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_uint16), C.c_size_t]
+        L.gal_policy_destroy.argtypes = [C.c_void_p]
+        L.gal_policy_destroy.restype = None
         L.gal_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gal_surrogate_attach.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_uint32, C.c_void_p]
         L.gal_surrogate_logits.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -543,3 +552,58 @@ class Mlp:
 def gemm_test(variant, a, b, M, N, K, lda, ldb, c, ldc, stream=None):
     _check(load_library().gal_mlp_gemm_test(variant, a.data_ptr(), b.data_ptr(), M, N, K, lda, ldb,
                                             c.data_ptr(), ldc, _stream_handle(stream)))
+
+
+class Policy:
+    """The policy network that consumes the depth stack (see include/gal.h)."""
+
+    def __init__(self, max_envs: int, act_dim: int = 9, seed: int = 0):
+        L = load_library()
+        h = C.c_void_p()
+        _check(L.gal_policy_create(int(max_envs), int(act_dim), int(seed), C.byref(h)))
+        self._h = h
+        self.max_envs = int(max_envs)
+        self.act_dim = int(act_dim)
+        n = C.c_int64()
+        _check(L.gal_policy_num_params(h, C.byref(n)))
+        self.num_params = n.value
+        self._last = 0
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gal_policy_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.num_params, np.float32)
+        _check(load_library().gal_policy_get_weights(self._h, _p(w, _fp), w.size))
+        return w
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(load_library().gal_policy_set_weights(self._h, _p(w, _fp), w.size))
+
+    def act(self, depth, state, actions, noise=None, value=None, logp=None, n_envs=None, stream=None):
+        """depth: the batch's depth output (128x128 images, read in place)."""
+        n = int(state.shape[0]) if n_envs is None else int(n_envs)
+        _check(load_library().gal_policy_act(self._h, depth.data_ptr(), state.data_ptr(), n, _ptr(noise),
+                                             actions.data_ptr(), _ptr(value), _ptr(logp),
+                                             _stream_handle(stream)))
+        self._last = n
+
+    SHAPES = {1: (31, 31, 32), 2: (14, 14, 64), 3: (12, 12, 32), 4: (512,)}
+
+    def activations(self, layer: int) -> np.ndarray:
+        """Layer 1..4 activations of the last act (BF16 bit patterns)."""
+        shp = (self._last,) + self.SHAPES[layer]
+        out = np.zeros(shp, np.uint16)
+        _check(load_library().gal_policy_activations(self._h, int(layer),
+                                                     out.ctypes.data_as(C.POINTER(C.c_uint16)), out.size))
+        return out
