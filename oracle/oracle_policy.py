@@ -60,7 +60,14 @@ def unpack(theta: np.ndarray, act_dim: int) -> dict:
     return out
 
 
+# BF16 rounding at the device's rounding points (off only in the pins that
+# differentiate the FP64 definition numerically)
+ROUND = True
+
+
 def bf16(a) -> np.ndarray:
+    if not ROUND:
+        return np.asarray(a, np.float64)
     return bf16_round_f32(np.asarray(a, np.float32)).astype(np.float64)
 
 
@@ -79,7 +86,7 @@ def conv2d(x: np.ndarray, w: np.ndarray, b: np.ndarray, stride: int) -> np.ndarr
 
 
 def relu_bf16(v: np.ndarray) -> np.ndarray:
-    return bf16(np.maximum(v, 0.0).astype(np.float32))
+    return bf16(np.maximum(v, 0.0))
 
 
 def encoder_layer(i: int, x: np.ndarray, P: dict) -> np.ndarray:
@@ -132,3 +139,105 @@ def sample(mean: np.ndarray, log_std: np.ndarray, noise: np.ndarray):
     a = mean + np.exp(ls) * n
     logp = np.sum(-0.5 * n * n - ls, axis=1) - 0.5 * np.log(2 * np.pi) * n.shape[1]
     return a, logp
+
+
+# ----------------------------------------------------------------------------
+# PPO update (the learning half of Section 4.2's training: DD-PPO, i.e. PPO on
+# each GPU with the gradients all-reduced; one GPU here)
+# ----------------------------------------------------------------------------
+def gae(rewards, values, dones, last_value, gamma, lam):
+    """Generalised advantage estimation over a rollout [T][N] (FP64, by the
+    recursion's definition): delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t,
+    A_t = delta_t + gamma lam (1 - d_t) A_{t+1}; returns = A + V.  d_t = 1
+    when step t ended its episode (its successor is a new episode)."""
+    r = np.asarray(rewards, np.float64)
+    v = np.asarray(values, np.float64)
+    d = np.asarray(dones, np.float64)
+    T = r.shape[0]
+    adv = np.zeros_like(r)
+    nxt_v = np.asarray(last_value, np.float64)
+    nxt_a = np.zeros(r.shape[1])
+    for t in range(T - 1, -1, -1):
+        live = 1.0 - d[t]
+        delta = r[t] + gamma * nxt_v * live - v[t]
+        nxt_a = delta + gamma * lam * live * nxt_a
+        adv[t] = nxt_a
+        nxt_v = v[t]
+    return adv, adv + v
+
+
+def conv_dw(x, dy, k, s):
+    """dW[o][i][j][c] = sum over (n, y, x) of dy[n, y, x, o] x[n, s y + i, s x + j, c]."""
+    win = sliding_window_view(x, (k, k), axis=(1, 2))[:, ::s, ::s]        # N, OH, OW, C, k, k
+    return np.einsum("nhwcij,nhwo->oijc", win, dy, optimize=True)
+
+
+def conv_dx(dy, w, s, in_shape):
+    """The adjoint of the convolution: dx[n, s y + i, s x + j, c] += sum_o dy[n, y, x, o] w[o, i, j, c]."""
+    dx = np.zeros(in_shape)
+    k = w.shape[1]
+    oh, ow = dy.shape[1], dy.shape[2]
+    for i in range(k):
+        for j in range(k):
+            dx[:, i:i + s * (oh - 1) + 1:s, j:j + s * (ow - 1) + 1:s, :] += np.einsum(
+                "nhwo,oc->nhwc", dy, w[:, i, j, :], optimize=True)
+    return dx
+
+
+def ppo_loss_and_grads(depth, state, actions, old_logp, adv, ret, theta, act_dim, clip, vcoef, ecoef):
+    """Loss and parameter gradient of one PPO step over S samples (the mean
+    over samples), FP64, with the device's BF16 rounding points: the
+    activations (ReLU outputs) and the gradients of the pre-activations of the
+    encoder layers are BF16.
+      r = exp(logp - old_logp); L = -mean(min(r A, clip(r, 1 - eps, 1 + eps) A))
+          + vcoef mean((V - R)^2) - ecoef H,  H = sum_a (log_std_a + (1 + ln 2 pi) / 2)."""
+    P = unpack(theta, act_dim)
+    fw = forward(depth, state, theta, act_dim)
+    S = depth.shape[0]
+    ls = P["log_std"].astype(np.float64)
+    std = np.exp(ls)
+    a = np.asarray(actions, np.float64)
+    mean, V = fw["mean"], fw["value"]
+    z = (a - mean) / std
+    logp = np.sum(-0.5 * z * z - ls, axis=1) - 0.5 * np.log(2 * np.pi) * act_dim
+    r = np.exp(logp - np.asarray(old_logp, np.float64))
+    A_ = np.asarray(adv, np.float64)
+    s1 = r * A_
+    s2 = np.clip(r, 1.0 - clip, 1.0 + clip) * A_
+    use1 = s1 <= s2
+    R = np.asarray(ret, np.float64)
+    H = float(np.sum(ls + 0.5 * (1.0 + np.log(2 * np.pi))))
+    loss_pi = -np.mean(np.where(use1, s1, s2))
+    loss_v = np.mean((V - R) ** 2)
+    loss = loss_pi + vcoef * loss_v - ecoef * H
+    # gradients
+    dlogp = np.where(use1, -A_ * r, 0.0) / S                  # dL / dlogp per sample
+    g_mean = dlogp[:, None] * (z / std)                       # dlogp/dmean = (a - mean) / std^2
+    g_ls = np.sum(dlogp[:, None] * (z * z - 1.0), axis=0) - ecoef * np.ones(act_dim)
+    g_v = vcoef * 2.0 * (V - R) / S
+    q = np.asarray(state, np.float32)[:, 3:10].astype(np.float64)
+    f = np.concatenate([fw["h4"], q], axis=1)
+    G = {}
+    G["actor.w"] = g_mean.T @ f
+    G["actor.b"] = g_mean.sum(axis=0)
+    G["critic.w"] = g_v @ f
+    G["critic.b"] = np.array([g_v.sum()])
+    G["log_std"] = g_ls
+    df = g_mean @ P["actor.w"].astype(np.float64) + np.outer(g_v, P["critic.w"].astype(np.float64))
+    # fc (ReLU mask on its output h4); the device keeps dpre in BF16
+    d4 = bf16(df[:, :FEAT] * (fw["h4"] > 0))
+    h3 = fw["h3"].reshape(S, -1)
+    G["fc.w"] = d4.T @ h3
+    G["fc.b"] = d4.sum(axis=0)
+    d3 = bf16((d4 @ bf16(P["fc.w"])) * (h3 > 0)).reshape(fw["h3"].shape)
+    ins = [fw["x"], fw["h1"], fw["h2"]]
+    dpre = d3
+    for i in (2, 1, 0):
+        o, k, s, c = CONV[i]
+        G[f"conv{i + 1}.w"] = conv_dw(ins[i], dpre, k, s)
+        G[f"conv{i + 1}.b"] = dpre.sum(axis=(0, 1, 2))
+        if i > 0:
+            dx = conv_dx(dpre, bf16(P[f"conv{i + 1}.w"]), s, ins[i].shape)
+            dpre = bf16(dx * (ins[i] > 0))
+    grad = np.concatenate([np.asarray(G[name], np.float64).reshape(-1) for name, _ in layout(act_dim)])
+    return dict(loss=loss, loss_pi=loss_pi, loss_v=loss_v, entropy=H, grad=grad, ratio=r, logp=logp)

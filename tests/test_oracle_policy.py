@@ -105,3 +105,119 @@ def test_heads_linear_and_gaussian_logp():
     std = np.exp(P["log_std"].astype(np.float64))
     ref = stats.norm.logpdf(act, loc=mean, scale=std).sum(axis=1)
     assert np.allclose(logp, ref, rtol=1e-12, atol=1e-10)
+
+
+def test_gae_closed_form_and_done_cut():
+    """GAE with lam = 1 is the discounted return minus V; with lam = 0 the
+    one-step TD error; an episode end cuts both."""
+    rng = np.random.default_rng(8)
+    T, N = 6, 3
+    r = rng.normal(size=(T, N))
+    v = rng.normal(size=(T, N))
+    last = rng.normal(size=N)
+    d = np.zeros((T, N))
+    g = 0.9
+    adv, ret = OP.gae(r, v, d, last, g, 1.0)
+    for n in range(N):
+        for t in range(T):
+            disc = sum(g ** (k - t) * r[k, n] for k in range(t, T)) + g ** (T - t) * last[n]
+            assert abs(ret[t, n] - disc) < 1e-12
+    adv0, _ = OP.gae(r, v, d, last, g, 0.0)
+    nxt = np.vstack([v[1:], last[None]])
+    assert np.allclose(adv0, r + g * nxt - v)
+    d[2, 1] = 1.0
+    adv1, ret1 = OP.gae(r, v, d, last, g, 1.0)
+    assert abs(ret1[2, 1] - r[2, 1]) < 1e-12          # nothing flows back across the episode end
+    assert abs(ret1[1, 1] - (r[1, 1] + g * r[2, 1])) < 1e-12
+
+
+def test_conv_backward_is_the_adjoint():
+    """<conv(x), dy> = <x, conv_dx(dy)> and the weight gradient is the
+    derivative of <conv(x; w), dy> in w (checked by central differences)."""
+    rng = np.random.default_rng(9)
+    for k, s in ((8, 4), (4, 2), (3, 1)):
+        x = rng.normal(size=(2, 20, 20, 3))
+        w = rng.normal(size=(4, k, k, 3))
+        y = OP.conv2d(x, w, np.zeros(4), s)
+        dy = rng.normal(size=y.shape)
+        dx = OP.conv_dx(dy, w, s, x.shape)
+        assert abs(np.sum(y * dy) - np.sum(x * dx)) < 1e-9 * (1 + abs(np.sum(y * dy)))
+        dw = OP.conv_dw(x, dy, k, s)
+        idx = (1, k - 1, 0, 2)
+        e = np.zeros_like(w)
+        e[idx] = 1e-6
+        num = (np.sum(OP.conv2d(x, w + e, np.zeros(4), s) * dy) - np.sum(OP.conv2d(x, w - e, np.zeros(4), s) * dy)) / 2e-6
+        assert abs(num - dw[idx]) < 1e-5 * (1 + abs(num))
+
+
+def test_ppo_gradient_vs_central_differences():
+    """The PPO loss's gradient for the heads and log_std against central
+    differences of the same loss (the encoder's BF16 rounding points make
+    its own gradients step-wise; they are checked by the device parity)."""
+    rng = np.random.default_rng(10)
+    A, S = 4, 5
+    theta = (rng.normal(size=sum(int(np.prod(s)) for _, s in OP.layout(A))) * 0.05).astype(np.float32)
+    depth = rng.integers(0, 2 ** 24, size=(S, 128, 128)).astype(np.uint32)
+    state = rng.normal(size=(S, 10)).astype(np.float32)
+    acts = rng.normal(size=(S, A))
+    old = rng.normal(size=S) - 4.0
+    adv = rng.normal(size=S)
+    ret = rng.normal(size=S)
+    args = (depth, state, acts, old, adv, ret)
+    res = OP.ppo_loss_and_grads(*args, theta, A, 0.2, 0.5, 0.01)
+    off = {}
+    o = 0
+    for name, shp in OP.layout(A):
+        off[name] = o
+        o += int(np.prod(shp))
+    for name, k in (("actor.w", 7), ("actor.b", 1), ("critic.w", 515), ("critic.b", 0), ("log_std", 2)):
+        i = off[name] + k
+        t1, t2 = theta.astype(np.float64).copy(), theta.astype(np.float64).copy()
+        h = 1e-3
+        t1[i] += h
+        t2[i] -= h
+        l1 = OP.ppo_loss_and_grads(*args, t1.astype(np.float32), A, 0.2, 0.5, 0.01)["loss"]
+        l2 = OP.ppo_loss_and_grads(*args, t2.astype(np.float32), A, 0.2, 0.5, 0.01)["loss"]
+        # theta is stored in FP32: use the actually-applied step
+        step = float(np.float32(t1[i])) - float(np.float32(t2[i]))
+        num = (l1 - l2) / step
+        assert abs(num - res["grad"][i]) < 2e-3 * (1 + abs(num)), (name, num, res["grad"][i])
+
+
+def test_ppo_encoder_gradient_vs_central_differences():
+    """With the BF16 rounding points switched off (the plain FP64 definition),
+    the whole gradient chain through the fully connected layer and the three
+    convolutions (their ReLU masks included) against central differences."""
+    rng = np.random.default_rng(12)
+    A, S = 3, 3
+    theta = (rng.normal(size=sum(int(np.prod(s)) for _, s in OP.layout(A))) * 0.05).astype(np.float64)
+    depth = rng.integers(0, 2 ** 24, size=(S, 128, 128)).astype(np.uint32)
+    state = rng.normal(size=(S, 10)).astype(np.float32)
+    acts = rng.normal(size=(S, A))
+    old = rng.normal(size=S) - 6.0
+    adv = rng.normal(size=S)
+    ret = rng.normal(size=S)
+    off, o = {}, 0
+    for name, shp in OP.layout(A):
+        off[name] = o
+        o += int(np.prod(shp))
+    OP.ROUND = False
+    try:
+        def run(t):
+            return OP.ppo_loss_and_grads(depth, state, acts, old, adv, ret, t, A, 0.2, 0.5, 0.01)
+        # unpack keeps float32 parameters: differentiate in the FP32-representable
+        # neighbourhood with a step that survives the cast
+        res = run(theta.astype(np.float32))
+        for name, k in (("conv1.w", 37), ("conv2.w", 1000), ("conv3.w", 77), ("conv2.b", 5), ("fc.w", 12345)):
+            i = off[name] + k
+            base = theta.astype(np.float32).astype(np.float64)
+            h = 1e-2 * max(abs(base[i]), 1e-2)
+            t1, t2 = base.copy(), base.copy()
+            t1[i] += h
+            t2[i] -= h
+            step = float(np.float32(t1[i])) - float(np.float32(t2[i]))
+            num = (run(t1.astype(np.float32))["loss"] - run(t2.astype(np.float32))["loss"]) / step
+            g = res["grad"][i]
+            assert abs(num - g) < 5e-3 * (abs(num) + abs(g)) + 1e-9, (name, num, g)
+    finally:
+        OP.ROUND = True
