@@ -98,13 +98,74 @@ def policy_record(gal, torch, b, out, act_buf, N, steps, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     loop_ms = e0.elapsed_time(e1)
+    train = ppo_record(gal, torch, b, out, act_buf, N, stream)
     return {"params": pol.num_params, "envs": N, "forward_ms": round(fwd_ms, 4),
             "flop_per_call": int(flop), "achieved_tflops": round(flop / (fwd_ms / 1e3) / 1e12, 1),
             "mfma_peak_tflops": BF16_PEAK_TFLOPS,
             "mfma_frac": round(flop / (fwd_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 4),
             "rollout_env_steps_per_s": round(N * steps / (loop_ms / 1e3), 1),
             "rollout_ms_per_step": round(loop_ms / steps, 4),
-            "rollout": "policy inference + step (the step's tuning as timed above)"}
+            "rollout": "policy inference + step (the step's tuning as timed above)",
+            "train": train}
+
+
+def ppo_record(gal, torch, b, out, act_buf, N, stream, T=64, minibatches=2, iters=2):
+    """The paper's training loop on one GPU (Section 4.2: rollouts of 64
+    steps, 2 minibatches, 1 epoch per update): the policy drives the step for
+    T steps, its observations kept on the device; GAE; one PPO gradient and
+    Adam step per minibatch (half of the rollout each).  Reward: +0.01 per
+    accepted move, -0.1 per rejected one (a stand-in; the task reward is not
+    built).  Env-steps/s over whole iterations."""
+    mb = T * N // minibatches
+    pol = gal.Policy(mb, act_dim=9, seed=2)
+    R = 128 * 128
+    obs = torch.empty((T, N * R), dtype=torch.int32, device="cuda")
+    st = torch.empty((T, N, 10), device="cuda")
+    acts = torch.empty((T, N, 9), device="cuda")
+    logp = torch.empty((T, N), device="cuda")
+    val = torch.empty((T, N), device="cuda")
+    rew = torch.empty((T, N), device="cuda")
+    done = torch.empty((T, N), dtype=torch.uint8, device="cuda")
+    last = torch.empty(N, device="cuda")
+    adv = torch.empty((T, N), device="cuda")
+    ret = torch.empty((T, N), device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9)
+    noise = torch.randn((T, N, 9), generator=g, device="cuda")
+    stats = torch.empty(4, device="cuda")
+
+    def iteration():
+        for t in range(T):
+            obs[t].copy_(out["depth"])
+            st[t].copy_(out["state"])
+            pol.act(out["depth"], out["state"], acts[t], noise=noise[t], value=val[t], logp=logp[t])
+            act_buf.copy_(acts[t])
+            b.step(act_buf, out)
+            rew[t] = out["accepted"].float() * 0.11 - 0.1
+            done[t] = out["done"]
+        pol.act(out["depth"], out["state"], act_buf, value=last)
+        gal.gae(rew, val, done, last, 0.99, 0.95, adv, ret)
+        per = T // minibatches
+        for k in range(minibatches):
+            sl = slice(k * per, (k + 1) * per)
+            pol.ppo_gradients(obs[sl], st[sl].reshape(-1, 10), acts[sl].reshape(-1, 9), logp[sl].reshape(-1),
+                              adv[sl].reshape(-1), ret[sl].reshape(-1), stats=stats, samples=mb)
+            pol.adam_step(2.5e-4)
+
+    iteration()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(iters):
+        iteration()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    s = stats.cpu().numpy()
+    return {"rollout_len": T, "envs": N, "minibatches": minibatches, "epochs": 1, "minibatch_samples": mb,
+            "ms_per_iteration": round(ms, 3), "env_steps_per_s": round(T * N / (ms / 1e3), 1),
+            "last_stats": {"policy_loss": float(s[0]), "value_mse": float(s[1]), "entropy": float(s[2]),
+                           "mean_ratio": float(s[3])}}
 
 
 def host_threads():

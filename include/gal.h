@@ -592,6 +592,46 @@ int gal_policy_get_weights(gal_policy *p, float *host, size_t count);
 int gal_policy_act(gal_policy *p, const uint32_t *depth_dev, const float *state_dev, int32_t n_envs,
                    const float *noise_dev, float *actions_dev, float *value_dev, float *logp_dev,
                    void *stream);
+/* Coefficients of the PPO loss below. */
+typedef struct gal_ppo_params {
+    float clip;                 /* the ratio's clip range, e.g. 0.2          */
+    float value_coef;           /* e.g. 0.5                                  */
+    float entropy_coef;         /* e.g. 0.01                                 */
+} gal_ppo_params;
+/*
+ * The policy's update (Section 4.2 trains the policy with DD-PPO: PPO with
+ * the gradients all-reduced over GPUs; this is one GPU's step).  One
+ * gradient of the PPO loss over `samples` (<= max_envs) rollout samples:
+ * depth_dev (u32 [S][128][128]) and state_dev (f32 [S][10]) the observations,
+ * actions_dev (f32 [S][A]) the actions taken, old_logp_dev (f32 [S]) their
+ * log-density under the policy that took them, adv_dev and ret_dev (f32 [S])
+ * the advantages and returns (gal_gae).  With r = exp(logp - old_logp):
+ *   L = -mean(min(r A, clip(r, 1 - clip, 1 + clip) A))
+ *       + value_coef mean((V - R)^2) - entropy_coef H,
+ *   H = sum_a (log_std_a + (1 + ln 2 pi) / 2).
+ * The gradient (FP32, the parameter layout above) stays in the policy for
+ * gal_policy_adam_step and is copied to grads_dev (f32 [n_params]) when not
+ * NULL; stats_dev (f32 [4], or NULL) = mean policy loss, mean (V - R)^2, H,
+ * mean ratio.  BF16 activations and pre-activation gradients, FP32 weight
+ * gradients.  Asynchronous on `stream`.
+ */
+int gal_policy_ppo_gradients(gal_policy *p, const uint32_t *depth_dev, const float *state_dev,
+                             const float *actions_dev, const float *old_logp_dev, const float *adv_dev,
+                             const float *ret_dev, int32_t samples, const gal_ppo_params *hp,
+                             float *grads_dev, float *stats_dev, void *stream);
+/* The policy's update of Section 4.2: one Adam step (beta 0.9 / 0.999, eps
+ * 1e-5) of the parameters with the last gradient, learning rate lr; the BF16
+ * copy follows.  GAL_ESTATE before any gradient. */
+int gal_policy_adam_step(gal_policy *p, float lr, void *stream);
+/* Advantages for the update of Section 4.2 (generalised advantage
+ * estimation): over a rollout of T steps x N envs (f32 [T][N], dones u8
+ * [T][N] = the step ended its episode), last_value_dev (f32 [N]) the critic
+ * after the last step:  delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t,
+ * A_t = delta_t + gamma lam (1 - d_t) A_{t+1}, returns = A + V (FP32, one
+ * thread per env, backwards in time). */
+int gal_gae(const float *rewards_dev, const float *values_dev, const uint8_t *dones_dev,
+            const float *last_value_dev, int32_t T, int32_t N, float gamma, float lam, float *adv_dev,
+            float *ret_dev, void *stream);
 /* The policy of Section 4.2: the BF16 activations of layer 1..4 (conv1..3
  * NHWC, fc) of the last gal_policy_act into host memory, count values
  * (synchronous; for checking the encoder layer by layer). */

@@ -10,6 +10,7 @@ namespace gal {
 constexpr int kPolicyRes = 128;      // depth image edge the encoder takes
 constexpr int kPolicyFeat = 512;     // encoder features
 constexpr int kPolicyProprio = 7;    // joint angles fed to the heads beside the features
+constexpr int kPolicyMaxAct = 32;    // action dimensions
 
 // One convolution as an implicit GEMM over NHWC input: `rows` = envs x oh x
 // ow output pixels, `k` = kw x kw x in_c, `out_c` output channels.
@@ -24,5 +25,26 @@ hipError_t conv_gemm(bool depth_input, const void *in, const uint16_t *W, const 
 hipError_t policy_heads(const uint16_t *h, const float *state, const float *aw, const float *ab, const float *vw,
                         const float *vb, const float *log_std, int A, int n_envs, const float *noise,
                         float *actions, float *value, float *logp, hipStream_t s);
+
+// Backward: weight gradient of a convolution into out [out_c][k] (FP32,
+// split over the output pixels into `part`, then summed in split order);
+// the input gradient (adjoint) masked by the ReLU of h (the layer's input
+// activation), through Wt [in_c][taps x out_c] (scratch, rebuilt here).
+hipError_t conv_dw(bool depth_input, const void *in, const uint16_t *dy, const ConvGeom &g, float *part,
+                   size_t part_floats, float *out, hipStream_t s);
+// Column sums of a BF16 [rows][D] matrix (bias gradients), chunked through
+// part and summed in chunk order (deterministic).
+hipError_t colsum(const uint16_t *g, int rows, int D, float *part, size_t part_floats, float *out, hipStream_t s);
+hipError_t conv_dx(const uint16_t *dy, const uint16_t *W, uint16_t *Wt, const uint16_t *h, const ConvGeom &g,
+                   uint16_t *dx, hipStream_t s);
+hipError_t ppo_heads(const uint16_t *h, const float *state, const float *aw, const float *ab, const float *vw,
+                     const float *vb, const float *log_std, int A, int S, const float *actions, const float *old_logp,
+                     const float *adv, const float *ret, float clip, float vcoef, float *gm, float *gls, float *gv,
+                     float *terms, uint16_t *d4, hipStream_t s);
+hipError_t ppo_head_grads(const uint16_t *h, const float *state, const float *gm, const float *gls, const float *gv,
+                          const float *terms, const float *log_std, int A, int S, float ecoef, float *g_aw,
+                          float *g_ab, float *g_vw, float *g_vb, float *g_ls, float *stats, hipStream_t s);
+hipError_t gae(const float *rew, const float *val, const uint8_t *done, const float *last, int T, int N, float gamma,
+               float lam, float *adv, float *ret, hipStream_t s);
 
 }  // namespace gal

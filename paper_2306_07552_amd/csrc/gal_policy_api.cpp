@@ -42,6 +42,14 @@ struct gal_policy {
     uint16_t *wb = nullptr;    // BF16 copy (the convolutions' and the fc layer's weights are read from it)
     uint16_t *h[4] = {nullptr, nullptr, nullptr, nullptr};   // activations of conv1..3, fc
     int32_t last_envs = 0;
+    // training (allocated on the first update)
+    float *g = nullptr, *m = nullptr, *v = nullptr;          // gradient, Adam moments
+    uint16_t *d[4] = {nullptr, nullptr, nullptr, nullptr};   // gradients of the pre-activations of conv1..3, fc
+    uint16_t *wt = nullptr;                                  // adjoint weights
+    float *gm = nullptr, *gls = nullptr, *gv = nullptr, *terms = nullptr;
+    float *part = nullptr;
+    size_t part_floats = 0;
+    int64_t t = 0;
     ~gal_policy()
     {
         for (void *p : allocs) (void)hipFree(p);
@@ -164,6 +172,63 @@ int gal_policy_get_weights(gal_policy *p, float *host, size_t count)
     return GAL_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+gal::ConvGeom geom(const gal_policy *p, int l, int n)
+{
+    gal::ConvGeom g;
+    g.ih = g.iw = p->side[l];
+    g.in_c = kConv[l][3];
+    g.kw = kConv[l][1];
+    g.stride = kConv[l][2];
+    g.oh = g.ow = p->side[l + 1];
+    g.out_c = kConv[l][0];
+    g.k = g.kw * g.kw * g.in_c;
+    g.rows = n * g.oh * g.ow;
+    return g;
+}
+
+// the encoder on n images: h[0..3]
+int encode(gal_policy *p, const uint32_t *depth_dev, int n, hipStream_t s)
+{
+    const void *in = depth_dev;
+    for (int l = 0; l < 3; ++l) {
+        POL_TRY(gal::conv_gemm(l == 0, in, p->wb + p->off_w[l], p->w + p->off_b[l], geom(p, l, n), p->h[l], s));
+        in = p->h[l];
+    }
+    const int flat = p->side[3] * p->side[3] * kConv[2][0];
+    POL_TRY(gal::mlp_gemm(gal::kGemmFwd, p->h[2], p->wb + p->off_w[3], n, gal::kPolicyFeat, flat, flat, flat,
+                          p->w + p->off_b[3], nullptr, 0, nullptr, p->h[3], gal::kPolicyFeat, s));
+    return GAL_OK;
+}
+
+int train_buffers(gal_policy *p)
+{
+    if (p->g) return GAL_OK;
+    const int n = p->max_envs, A = p->A;
+    const int flat = p->side[3] * p->side[3] * kConv[2][0];
+    // split-K workspace: the fc weight gradient's (<= 16 splits) or a convolution's (<= 256 splits)
+    p->part_floats = std::max<size_t>((size_t)16 * gal::kPolicyFeat * flat, (size_t)256 * 64 * 16 * 32);
+    int rc;
+    if ((rc = p->alloc(&p->g, p->n_params)) || (rc = p->alloc(&p->m, p->n_params)) ||
+        (rc = p->alloc(&p->v, p->n_params)) || (rc = p->alloc(&p->wt, (size_t)64 * 16 * 32)) ||
+        (rc = p->alloc(&p->gm, (size_t)n * A)) || (rc = p->alloc(&p->gls, (size_t)n * A)) ||
+        (rc = p->alloc(&p->gv, (size_t)n)) || (rc = p->alloc(&p->terms, (size_t)n * 3)) ||
+        (rc = p->alloc(&p->part, p->part_floats)))
+        return rc;
+    for (int l = 0; l < 4; ++l)
+        if ((rc = p->alloc(&p->d[l], p->act_count(l, n)))) return rc;
+    POL_TRY(hipMemset(p->m, 0, sizeof(float) * p->n_params));
+    POL_TRY(hipMemset(p->v, 0, sizeof(float) * p->n_params));
+    return GAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gal_policy_act(gal_policy *p, const uint32_t *depth_dev, const float *state_dev, int32_t n_envs,
                    const float *noise_dev, float *actions_dev, float *value_dev, float *logp_dev, void *stream)
 {
@@ -172,27 +237,81 @@ int gal_policy_act(gal_policy *p, const uint32_t *depth_dev, const float *state_
     if ((uintptr_t)depth_dev % 16) return gal::api_fail(GAL_EINVAL, "depth_dev must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (n_envs == 0) return GAL_OK;
-    const void *in = depth_dev;
-    for (int l = 0; l < 3; ++l) {
-        gal::ConvGeom g;
-        g.ih = g.iw = p->side[l];
-        g.in_c = kConv[l][3];
-        g.kw = kConv[l][1];
-        g.stride = kConv[l][2];
-        g.oh = g.ow = p->side[l + 1];
-        g.out_c = kConv[l][0];
-        g.k = g.kw * g.kw * g.in_c;
-        g.rows = n_envs * g.oh * g.ow;
-        POL_TRY(gal::conv_gemm(l == 0, in, p->wb + p->off_w[l], p->w + p->off_b[l], g, p->h[l], s));
-        in = p->h[l];
-    }
-    const int flat = p->side[3] * p->side[3] * kConv[2][0];
-    POL_TRY(gal::mlp_gemm(gal::kGemmFwd, p->h[2], p->wb + p->off_w[3], n_envs, gal::kPolicyFeat, flat, flat, flat,
-                          p->w + p->off_b[3], nullptr, 0, nullptr, p->h[3], gal::kPolicyFeat, s));
+    int rc = encode(p, depth_dev, n_envs, s);
+    if (rc) return rc;
     POL_TRY(gal::policy_heads(p->h[3], state_dev, p->w + p->off_aw, p->w + p->off_ab, p->w + p->off_vw,
                               p->w + p->off_vb, p->w + p->off_ls, p->A, n_envs, noise_dev, actions_dev, value_dev,
                               logp_dev, s));
     p->last_envs = n_envs;
+    return GAL_OK;
+}
+
+int gal_policy_ppo_gradients(gal_policy *p, const uint32_t *depth_dev, const float *state_dev,
+                             const float *actions_dev, const float *old_logp_dev, const float *adv_dev,
+                             const float *ret_dev, int32_t samples, const gal_ppo_params *hp, float *grads_dev,
+                             float *stats_dev, void *stream)
+{
+    if (!p || !depth_dev || !state_dev || !actions_dev || !old_logp_dev || !adv_dev || !ret_dev || !hp ||
+        samples < 1 || samples > p->max_envs)
+        return gal::api_fail(GAL_EINVAL, "bad arguments");
+    if ((uintptr_t)depth_dev % 16) return gal::api_fail(GAL_EINVAL, "depth_dev must be 16-byte aligned");
+    if (!(hp->clip >= 0.0f) || !(hp->value_coef >= 0.0f) || !(hp->entropy_coef >= 0.0f))
+        return gal::api_fail(GAL_EINVAL, "clip and coefficients must be >= 0");
+    int rc = train_buffers(p);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int S = samples, A = p->A;
+    if ((rc = encode(p, depth_dev, S, s))) return rc;
+    p->last_envs = S;
+    const int F = gal::kPolicyFeat + gal::kPolicyProprio;
+    (void)F;
+    float *g = p->g;
+    // heads: per-sample loss gradients, the features' gradient, then the
+    // heads' own parameter gradients and the statistics
+    POL_TRY(gal::ppo_heads(p->h[3], state_dev, p->w + p->off_aw, p->w + p->off_ab, p->w + p->off_vw,
+                           p->w + p->off_vb, p->w + p->off_ls, A, S, actions_dev, old_logp_dev, adv_dev, ret_dev,
+                           hp->clip, hp->value_coef, p->gm, p->gls, p->gv, p->terms, p->d[3], s));
+    POL_TRY(gal::ppo_head_grads(p->h[3], state_dev, p->gm, p->gls, p->gv, p->terms, p->w + p->off_ls, A, S,
+                                hp->entropy_coef, g + p->off_aw, g + p->off_ab, g + p->off_vw, g + p->off_vb,
+                                g + p->off_ls, stats_dev, s));
+    // fully connected layer
+    const int flat = p->side[3] * p->side[3] * kConv[2][0];
+    POL_TRY(gal::mlp_gemm(gal::kGemmDw, p->d[3], p->h[2], gal::kPolicyFeat, flat, S, gal::kPolicyFeat, flat, nullptr,
+                          nullptr, 0, g + p->off_w[3], nullptr, flat, s, p->part, p->part_floats));
+    POL_TRY(gal::colsum(p->d[3], S, gal::kPolicyFeat, p->part, p->part_floats, g + p->off_b[3], s));
+    POL_TRY(gal::mlp_gemm(gal::kGemmDx, p->d[3], p->wb + p->off_w[3], S, flat, gal::kPolicyFeat, gal::kPolicyFeat,
+                          flat, nullptr, p->h[2], flat, nullptr, p->d[2], flat, s));
+    // convolutions 3, 2, 1
+    for (int l = 2; l >= 0; --l) {
+        const gal::ConvGeom gg = geom(p, l, S);
+        const void *in = l == 0 ? (const void *)depth_dev : (const void *)p->h[l - 1];
+        POL_TRY(gal::conv_dw(l == 0, in, p->d[l], gg, p->part, p->part_floats, g + p->off_w[l], s));
+        POL_TRY(gal::colsum(p->d[l], gg.rows, kConv[l][0], p->part, p->part_floats, g + p->off_b[l], s));
+        if (l > 0)
+            POL_TRY(gal::conv_dx(p->d[l], p->wb + p->off_w[l], p->wt, p->h[l - 1], gg, p->d[l - 1], s));
+    }
+    if (grads_dev)
+        POL_TRY(hipMemcpyAsync(grads_dev, g, sizeof(float) * p->n_params, hipMemcpyDeviceToDevice, s));
+    return GAL_OK;
+}
+
+int gal_policy_adam_step(gal_policy *p, float lr, void *stream)
+{
+    if (!p || !(lr >= 0.0f)) return gal::api_fail(GAL_EINVAL, "bad arguments");
+    if (!p->g) return gal::api_fail(GAL_ESTATE, "no gradient computed yet");
+    p->t += 1;
+    POL_TRY(gal::mlp_adam(p->w, p->m, p->v, p->g, p->n_params, lr, 0.9f, 0.999f, 1e-5f, p->t, p->wb,
+                          (hipStream_t)stream));
+    return GAL_OK;
+}
+
+int gal_gae(const float *rewards_dev, const float *values_dev, const uint8_t *dones_dev, const float *last_value_dev,
+            int32_t T, int32_t N, float gamma, float lam, float *adv_dev, float *ret_dev, void *stream)
+{
+    if (!rewards_dev || !values_dev || !dones_dev || !last_value_dev || !adv_dev || !ret_dev || T < 0 || N < 0)
+        return gal::api_fail(GAL_EINVAL, "bad arguments");
+    POL_TRY(gal::gae(rewards_dev, values_dev, dones_dev, last_value_dev, T, N, gamma, lam, adv_dev, ret_dev,
+                     (hipStream_t)stream));
     return GAL_OK;
 }
 

@@ -16,6 +16,8 @@
 #include "gal_internal.h"
 #include "gal_policy.h"
 
+#include <algorithm>
+
 namespace gal {
 
 namespace {
@@ -191,7 +193,469 @@ __global__ __launch_bounds__(256) void k_policy_heads(const uint16_t *__restrict
     if (lane == 0 && noise && logp) logp[e] = lp - 0.9189385332046727f * (float)A;
 }
 
+// ---------------------------------------------------------------- backward
+
+// The gathered input operand of a convolution (8 consecutive k of row m), as
+// in the forward: the depth image for the first layer, NHWC BF16 otherwise.
+template <bool DEPTH>
+__device__ __forceinline__ void gather8(const void *in, const ConvGeom &g, int m, int k, uint16_t (&v)[8])
+{
+    if (m >= g.rows || k >= g.k) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = 0;
+        return;
+    }
+    const int per = g.oh * g.ow;
+    const int e = m / per, rem = m - e * per;
+    const int oy = rem / g.ow, ox = rem - oy * g.ow;
+    const size_t base = (((size_t)e * g.ih + (size_t)(g.stride * oy)) * g.iw + (size_t)(g.stride * ox)) * g.in_c;
+    if (DEPTH) {
+        const int ky = k / g.kw, kx = k - ky * g.kw;
+        const uint32_t *p = static_cast<const uint32_t *>(in) + base + (size_t)ky * g.iw + kx;
+        const uint4 q0 = *reinterpret_cast<const uint4 *>(p);
+        const uint4 q1 = *reinterpret_cast<const uint4 *>(p + 4);
+        v[0] = depth_bf16(q0.x); v[1] = depth_bf16(q0.y); v[2] = depth_bf16(q0.z); v[3] = depth_bf16(q0.w);
+        v[4] = depth_bf16(q1.x); v[5] = depth_bf16(q1.y); v[6] = depth_bf16(q1.z); v[7] = depth_bf16(q1.w);
+    } else {
+        const int tap = k / g.in_c, c = k - tap * g.in_c;
+        const int ky = tap / g.kw, kx = tap - ky * g.kw;
+        const uint16_t *p = static_cast<const uint16_t *>(in) + base + ((size_t)ky * g.iw + (size_t)kx) * g.in_c + c;
+        const uint4 q = *reinterpret_cast<const uint4 *>(p);
+        memcpy(v, &q, 16);
+    }
+}
+
+// Weight gradient of a convolution, split over the output pixels:
+// part[z][o][k] = sum over rows m of split z of dY[m][o] A(m, k), A gathered
+// as in the forward, dY BF16 [rows][out_c].  Workgroup (64 o x 64 k tile, one
+// split): the K dimension of the matrix cores runs over 32 rows at a time.
+template <bool DEPTH>
+__global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, const uint16_t *__restrict__ dy,
+                                                 ConvGeom g, int rows_per_split, float *__restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];   // [o][row]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];   // [k][row]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int O = g.out_c, K = g.k;
+    const int k0 = blockIdx.x * kBN;
+    const int rbeg = blockIdx.y * rows_per_split, rend = min(g.rows, rbeg + rows_per_split);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int rr = t >> 3, c8 = (t & 7) * 8;   // row of the step, 8-wide column group
+    for (int r0 = rbeg; r0 < rend; r0 += kBK) {
+        const int m = r0 + rr;
+        {
+            // dY[m][c8 .. c8 + 7] -> As[o][rr]
+            uint16_t v[8];
+            if (m < rend && c8 < O) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(dy + (size_t)m * O + c8);
+                memcpy(v, &q, 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[c8 + j][rr] = v[j];
+        }
+        {
+            // A(m, k0 + c8 .. + 7) -> Bs[k][rr]
+            uint16_t v[8];
+            gather8<DEPTH>(in, g, m < rend ? m : g.rows, k0 + c8, v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[c8 + j][rr] = v[j];
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + r16][kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + r16][kq]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    float *dst = part + (size_t)blockIdx.y * O * K;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int o = wm + i * 16 + (lane >> 4) * 4 + q;
+                const int k = k0 + wn + j * 16 + (lane & 15);
+                if (o < O && k < K) dst[(size_t)o * K + k] = acc[i][j][q];
+            }
+}
+
+// out[i] = sum over splits of part[z][i], in split order
+__global__ void k_sum_parts(const float *__restrict__ part, int splits, int64_t n, float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = part[i];
+    for (int z = 1; z < splits; ++z) v += part[(size_t)z * n + i];
+    out[i] = v;
+}
+
+// Input gradient of a convolution (the adjoint), masked by the ReLU of the
+// layer that produced the input: dX[m][c] = bf16([h[m][c] > 0] sum over
+// taps (ky, kx) and o of dY[n][oy][ox][o] W[o][ky][kx][c]), where
+// (oy, ox) s + (ky, kx) = (iy, ix) is an output pixel.  A GEMM whose rows are
+// input pixels, K = taps x out_c (8 consecutive o of one tap per load, zero
+// where the tap reaches no output pixel) and B = Wt [in_c][taps x out_c].
+__global__ __launch_bounds__(256) void k_conv_dx(const uint16_t *__restrict__ dy, const uint16_t *__restrict__ Wt,
+                                                 const uint16_t *__restrict__ h, ConvGeom g,
+                                                 uint16_t *__restrict__ dx)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int M = (g.rows / (g.oh * g.ow)) * g.ih * g.iw;   // input pixels
+    const int N = g.in_c, K = g.kw * g.kw * g.out_c;
+    const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int r = t >> 2, kk = (t & 3) * 8;
+    const int m = m0 + r;
+    int e = 0, iy = 0, ix = 0;
+    if (m < M) {
+        const int per = g.ih * g.iw;
+        e = m / per;
+        const int rem = m - e * per;
+        iy = rem / g.iw;
+        ix = rem - iy * g.iw;
+    }
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        {
+            const int k = k0 + kk;
+            uint16_t v[8];
+            bool ok = m < M && k < K;
+            size_t src = 0;
+            if (ok) {
+                const int tap = k / g.out_c, o = k - tap * g.out_c;
+                const int ky = tap / g.kw, kx = tap - ky * g.kw;
+                const int ny = iy - ky, nx = ix - kx;
+                ok = ny >= 0 && nx >= 0 && ny % g.stride == 0 && nx % g.stride == 0;
+                const int oy = ny / g.stride, ox = nx / g.stride;
+                ok = ok && oy < g.oh && ox < g.ow;
+                src = (((size_t)e * g.oh + (size_t)oy) * g.ow + (size_t)ox) * g.out_c + o;
+            }
+            if (ok) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(dy + src);
+                memcpy(v, &q, 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = 0;
+            }
+            memcpy(&As[r][kk], v, 16);
+        }
+        {
+            const int n = n0 + r, k = k0 + kk;
+            uint16_t v[8];
+            if (n < N && k + 8 <= K) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(Wt + (size_t)n * K + k);
+                memcpy(v, &q, 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = (n < N && k + j < K) ? Wt[(size_t)n * K + k + j] : 0;
+            }
+            memcpy(&Bs[r][kk], v, 16);
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + r16][kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + r16][kq]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mm = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (mm >= M || n >= N) continue;
+                const uint16_t hv = h[(size_t)mm * N + n];
+                const bool on = (hv & 0x8000u) == 0 && (hv & 0x7FFFu) != 0;
+                dx[(size_t)mm * N + n] = f2bf(on ? acc[i][j][q] : 0.f);
+            }
+}
+
+// Wt[c][tap * O + o] = W[o][tap][c] (the adjoint's B operand)
+__global__ void k_conv_wt(const uint16_t *__restrict__ W, int O, int taps, int C, uint16_t *__restrict__ Wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= O * taps * C) return;
+    const int o = i / (taps * C), rem = i - o * taps * C, tap = rem / C, c = rem - tap * C;
+    Wt[((size_t)c * taps + tap) * O + o] = W[i];
+}
+
+// The PPO loss of sample s (one wave): the heads from h4 and the joint angles,
+// logp of the taken action, the ratio to the behaviour policy's, the clipped
+// surrogate and the value error.  Writes per sample: gm [A] = dL/dmean,
+// gls [A] = dL/dlog_std (without the entropy term), gv = dL/dV, the loss terms
+// [3] (policy, value, 0), and d4 = bf16([h4 > 0] (gm W_a + gv w_v)) over the
+// 512 features.  L is the mean over S samples.
+__global__ __launch_bounds__(256) void k_ppo_heads(const uint16_t *__restrict__ h, const float *__restrict__ state,
+                                                   const float *__restrict__ aw, const float *__restrict__ ab,
+                                                   const float *__restrict__ vw, const float *__restrict__ vb,
+                                                   const float *__restrict__ log_std, int A, int S,
+                                                   const float *__restrict__ actions, const float *__restrict__ old_logp,
+                                                   const float *__restrict__ adv, const float *__restrict__ ret,
+                                                   float clip, float vcoef, float *__restrict__ gm,
+                                                   float *__restrict__ gls, float *__restrict__ gv,
+                                                   float *__restrict__ terms, uint16_t *__restrict__ d4)
+{
+    const int lane = threadIdx.x & 63;
+    const int e = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)threadIdx.x / 64);
+    if (e >= S) return;
+    constexpr int F = kPolicyFeat + kPolicyProprio;
+    constexpr int NF = (F + 63) / 64;
+    float f[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const int k = lane + 64 * i;
+        f[i] = k < kPolicyFeat ? bf2f(h[(size_t)e * kPolicyFeat + k])
+                               : (k < F ? state[(size_t)e * 10 + 3 + (k - kPolicyFeat)] : 0.0f);
+    }
+    float zs[kPolicyMaxAct];
+    float logp = 0.0f, V = 0.0f;
+    for (int a = 0; a <= A; ++a) {
+        const float *w = a < A ? aw + (size_t)a * F : vw;
+        float sum = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int k = lane + 64 * i;
+            if (k < F) sum += w[k] * f[i];
+        }
+        for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if (a < A) {
+            const float mean = sum + ab[a];
+            const float z = (actions[(size_t)e * A + a] - mean) / expf(log_std[a]);
+            zs[a] = z;
+            logp += -0.5f * z * z - log_std[a];
+        } else {
+            V = sum + vb[0];
+        }
+    }
+    logp -= 0.9189385332046727f * (float)A;
+    const float r = expf(logp - old_logp[e]);
+    const float Ad = adv[e];
+    const float rc = fminf(fmaxf(r, 1.0f - clip), 1.0f + clip);
+    const float s1 = r * Ad, s2 = rc * Ad;
+    const bool use1 = s1 <= s2;
+    const float invS = 1.0f / (float)S;
+    const float dlogp = use1 ? -Ad * r * invS : 0.0f;
+    const float dv = vcoef * 2.0f * (V - ret[e]) * invS;
+    float g_mean[kPolicyMaxAct];
+    for (int a = 0; a < A; ++a) {
+        g_mean[a] = dlogp * zs[a] / expf(log_std[a]);
+        if (lane == 0) {
+            gm[(size_t)e * A + a] = g_mean[a];
+            gls[(size_t)e * A + a] = dlogp * (zs[a] * zs[a] - 1.0f);
+        }
+    }
+    if (lane == 0) {
+        gv[e] = dv;
+        terms[(size_t)e * 3 + 0] = -(use1 ? s1 : s2);
+        terms[(size_t)e * 3 + 1] = (V - ret[e]) * (V - ret[e]);
+        terms[(size_t)e * 3 + 2] = r;
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const int k = lane + 64 * i;
+        if (k < kPolicyFeat) {
+            float df = dv * vw[k];
+            for (int a = 0; a < A; ++a) df += g_mean[a] * aw[(size_t)a * F + k];
+            d4[(size_t)e * kPolicyFeat + k] = f2bf(f[i] > 0.0f ? df : 0.0f);
+        }
+    }
+}
+
+// Gradients of the heads, summed over the S samples in sample order (one
+// thread per output): actor W [A][F] and b [A], critic w [F] and b, log_std
+// (minus the entropy coefficient); and the loss statistics [4] = mean policy
+// loss, mean value error, entropy, mean ratio.
+__global__ void k_ppo_head_grads(const uint16_t *__restrict__ h, const float *__restrict__ state,
+                                 const float *__restrict__ gm, const float *__restrict__ gls,
+                                 const float *__restrict__ gv, const float *__restrict__ terms,
+                                 const float *__restrict__ log_std, int A, int S, float ecoef,
+                                 float *__restrict__ g_aw, float *__restrict__ g_ab, float *__restrict__ g_vw,
+                                 float *__restrict__ g_vb, float *__restrict__ g_ls, float *__restrict__ stats)
+{
+    constexpr int F = kPolicyFeat + kPolicyProprio;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = (A + 1) * F;
+    if (i < nw) {
+        const int a = i / F, k = i - a * F;
+        float acc = 0.0f;
+        for (int e = 0; e < S; ++e) {
+            const float fk = k < kPolicyFeat ? bf2f(h[(size_t)e * kPolicyFeat + k])
+                                             : state[(size_t)e * 10 + 3 + (k - kPolicyFeat)];
+            acc += (a < A ? gm[(size_t)e * A + a] : gv[e]) * fk;
+        }
+        if (a < A) g_aw[(size_t)a * F + k] = acc;
+        else g_vw[k] = acc;
+    } else if (i < nw + A) {
+        const int a = i - nw;
+        float acc = 0.0f, accl = 0.0f;
+        for (int e = 0; e < S; ++e) {
+            acc += gm[(size_t)e * A + a];
+            accl += gls[(size_t)e * A + a];
+        }
+        g_ab[a] = acc;
+        g_ls[a] = accl - ecoef;
+    } else if (i == nw + A) {
+        float acc = 0.0f;
+        for (int e = 0; e < S; ++e) acc += gv[e];
+        g_vb[0] = acc;
+    } else if (i == nw + A + 1 && stats) {
+        float lp = 0.0f, lv = 0.0f, rr = 0.0f, ent = 0.0f;
+        for (int e = 0; e < S; ++e) {
+            lp += terms[(size_t)e * 3 + 0];
+            lv += terms[(size_t)e * 3 + 1];
+            rr += terms[(size_t)e * 3 + 2];
+        }
+        for (int a = 0; a < A; ++a) ent += log_std[a] + 1.4189385332046727f;
+        stats[0] = lp / (float)S;
+        stats[1] = lv / (float)S;
+        stats[2] = ent;
+        stats[3] = rr / (float)S;
+    }
+}
+
+// Column sums of a BF16 [rows][D] matrix in chunks of kColChunk rows: part
+// [chunk][D] (one thread per column; the chunks are summed in order after).
+constexpr int kColChunk = 4096;
+__global__ void k_colsum_chunks(const uint16_t *__restrict__ g, int rows, int D, float *__restrict__ part)
+{
+    const int c = threadIdx.x, chunk = blockIdx.x;
+    if (c >= D) return;
+    const int r0 = chunk * kColChunk, r1 = min(rows, r0 + kColChunk);
+    float acc = 0.0f;
+    for (int r = r0; r < r1; ++r) acc += bf2f(g[(size_t)r * D + c]);
+    part[(size_t)chunk * D + c] = acc;
+}
+
+// Generalised advantage estimation, one thread per env, backwards in time.
+__global__ void k_gae(const float *__restrict__ rew, const float *__restrict__ val, const uint8_t *__restrict__ done,
+                      const float *__restrict__ last, int T, int N, float gamma, float lam, float *__restrict__ adv,
+                      float *__restrict__ ret)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float nv = last[n], na = 0.0f;
+    for (int t = T - 1; t >= 0; --t) {
+        const size_t i = (size_t)t * N + n;
+        const float live = done[i] ? 0.0f : 1.0f;
+        const float delta = (rew[i] + gamma * nv * live) - val[i];
+        na = delta + gamma * lam * live * na;
+        adv[i] = na;
+        ret[i] = na + val[i];
+        nv = val[i];
+    }
+}
+
 }  // namespace
+
+hipError_t conv_dw(bool depth_input, const void *in, const uint16_t *dy, const ConvGeom &g, float *part,
+                   size_t part_floats, float *out, hipStream_t s)
+{
+    if (g.rows <= 0) return hipMemsetAsync(out, 0, sizeof(float) * g.out_c * g.k, s);
+    const size_t slab = (size_t)g.out_c * g.k;
+    int splits = (int)std::min<size_t>(part_floats / slab, (size_t)256);
+    splits = std::max(1, std::min(splits, (g.rows + 4095) / 4096));
+    int per = (g.rows + splits - 1) / splits;
+    per = (per + kBK - 1) / kBK * kBK;
+    splits = (g.rows + per - 1) / per;
+    const dim3 grid((g.k + kBN - 1) / kBN, splits);
+    if (depth_input)
+        hipLaunchKernelGGL(k_conv_dw<true>, grid, dim3(256), 0, s, in, dy, g, per, part);
+    else
+        hipLaunchKernelGGL(k_conv_dw<false>, grid, dim3(256), 0, s, in, dy, g, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)slab;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, splits, n, out);
+    return hipGetLastError();
+}
+
+hipError_t colsum(const uint16_t *g, int rows, int D, float *part, size_t part_floats, float *out, hipStream_t s)
+{
+    const int chunks = (rows + kColChunk - 1) / kColChunk;
+    if (rows <= 0) return hipMemsetAsync(out, 0, sizeof(float) * D, s);
+    if ((size_t)chunks * D > part_floats || D > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colsum_chunks, dim3(chunks), dim3((D + 63) / 64 * 64), 0, s, g, rows, D, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3((D + 255) / 256), dim3(256), 0, s, part, chunks, (int64_t)D, out);
+    return hipGetLastError();
+}
+
+hipError_t conv_dx(const uint16_t *dy, const uint16_t *W, uint16_t *Wt, const uint16_t *h, const ConvGeom &g,
+                   uint16_t *dx, hipStream_t s)
+{
+    const int taps = g.kw * g.kw;
+    const int nw = g.out_c * taps * g.in_c;
+    hipLaunchKernelGGL(k_conv_wt, dim3((nw + 255) / 256), dim3(256), 0, s, W, g.out_c, taps, g.in_c, Wt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int M = (g.rows / (g.oh * g.ow)) * g.ih * g.iw;
+    if (M <= 0) return hipSuccess;
+    const dim3 grid((M + kBM - 1) / kBM, (g.in_c + kBN - 1) / kBN);
+    hipLaunchKernelGGL(k_conv_dx, grid, dim3(256), 0, s, dy, Wt, h, g, dx);
+    return hipGetLastError();
+}
+
+hipError_t ppo_heads(const uint16_t *h, const float *state, const float *aw, const float *ab, const float *vw,
+                     const float *vb, const float *log_std, int A, int S, const float *actions, const float *old_logp,
+                     const float *adv, const float *ret, float clip, float vcoef, float *gm, float *gls, float *gv,
+                     float *terms, uint16_t *d4, hipStream_t s)
+{
+    if (S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ppo_heads, dim3((S + 3) / 4), dim3(256), 0, s, h, state, aw, ab, vw, vb, log_std, A, S,
+                       actions, old_logp, adv, ret, clip, vcoef, gm, gls, gv, terms, d4);
+    return hipGetLastError();
+}
+
+hipError_t ppo_head_grads(const uint16_t *h, const float *state, const float *gm, const float *gls, const float *gv,
+                          const float *terms, const float *log_std, int A, int S, float ecoef, float *g_aw,
+                          float *g_ab, float *g_vw, float *g_vb, float *g_ls, float *stats, hipStream_t s)
+{
+    const int n = (A + 1) * (kPolicyFeat + kPolicyProprio) + A + 2;
+    hipLaunchKernelGGL(k_ppo_head_grads, dim3((n + 255) / 256), dim3(256), 0, s, h, state, gm, gls, gv, terms, log_std,
+                       A, S, ecoef, g_aw, g_ab, g_vw, g_vb, g_ls, stats);
+    return hipGetLastError();
+}
+
+hipError_t gae(const float *rew, const float *val, const uint8_t *done, const float *last, int T, int N, float gamma,
+               float lam, float *adv, float *ret, hipStream_t s)
+{
+    if (N <= 0 || T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gae, dim3((N + 255) / 256), dim3(256), 0, s, rew, val, done, last, T, N, gamma, lam, adv, ret);
+    return hipGetLastError();
+}
 
 hipError_t conv_gemm(bool depth_input, const void *in, const uint16_t *W, const float *bias, const ConvGeom &g,
                      uint16_t *out, hipStream_t s)

@@ -129,6 +129,11 @@ def load_library():
         L.gal_policy_act.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gal_policy_activations.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_uint16), C.c_size_t]
+        L.gal_policy_ppo_gradients.argtypes = [C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_void_p,
+                                                                                  C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gal_policy_adam_step.argtypes = [C.c_void_p, C.c_float, C.c_void_p]
+        L.gal_gae.argtypes = [C.c_void_p] * 4 + [C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_void_p,
+                                                 C.c_void_p, C.c_void_p]
         L.gal_policy_destroy.argtypes = [C.c_void_p]
         L.gal_policy_destroy.restype = None
         L.gal_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -598,6 +603,22 @@ class Policy:
                                              _stream_handle(stream)))
         self._last = n
 
+    def ppo_gradients(self, depth, state, actions, old_logp, adv, ret, clip=0.2, value_coef=0.5,
+                      entropy_coef=0.01, grads=None, stats=None, samples=None, stream=None):
+        """One PPO gradient over the samples (kept for adam_step; copied to
+        `grads` when given); `stats` (4 floats): policy loss, value error,
+        entropy, mean ratio."""
+        S = int(state.shape[0]) if samples is None else int(samples)
+        hp = GalPpoParams(float(clip), float(value_coef), float(entropy_coef))
+        _check(load_library().gal_policy_ppo_gradients(self._h, depth.data_ptr(), state.data_ptr(),
+                                                       actions.data_ptr(), old_logp.data_ptr(), adv.data_ptr(),
+                                                       ret.data_ptr(), S, C.cast(C.pointer(hp), C.c_void_p),
+                                                       _ptr(grads), _ptr(stats), _stream_handle(stream)))
+        self._last = S
+
+    def adam_step(self, lr, stream=None):
+        _check(load_library().gal_policy_adam_step(self._h, float(lr), _stream_handle(stream)))
+
     SHAPES = {1: (31, 31, 32), 2: (14, 14, 64), 3: (12, 12, 32), 4: (512,)}
 
     def activations(self, layer: int) -> np.ndarray:
@@ -607,3 +628,15 @@ class Policy:
         _check(load_library().gal_policy_activations(self._h, int(layer),
                                                      out.ctypes.data_as(C.POINTER(C.c_uint16)), out.size))
         return out
+
+
+class GalPpoParams(C.Structure):
+    _fields_ = [("clip", C.c_float), ("value_coef", C.c_float), ("entropy_coef", C.c_float)]
+
+
+def gae(rewards, values, dones, last_value, gamma, lam, adv, ret, stream=None):
+    """Generalised advantage estimation over a rollout [T][N] on the device."""
+    T, N = int(rewards.shape[0]), int(rewards.shape[1])
+    _check(load_library().gal_gae(rewards.data_ptr(), values.data_ptr(), dones.data_ptr(), last_value.data_ptr(),
+                                  T, N, float(gamma), float(lam), adv.data_ptr(), ret.data_ptr(),
+                                  _stream_handle(stream)))
