@@ -32,7 +32,8 @@ def log(msg):
 
 # Tuning keys that change what the raster kernel reads and writes (the others
 # only change how the same pixels are rasterised, or other kernels).
-TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split")
+TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split", "bin")
+TUNING_DEFAULTS = {"bin": 0}   # settings that older records leave out
 # the instruction count also depends on how pixels are spread over lanes and
 # waves (the queue order changes neither bytes nor instructions)
 VALU_KEYS = TRAFFIC_KEYS + ("block", "lane_max", "small_max")
@@ -54,7 +55,8 @@ def counter_record(kernel_sources, record, tuning, field, keys=None):
     if rec.get("source_sha256") != h:
         return None
     for r in rec["records"]:
-        if field in r and all(r["tuning"].get(k) == tuning.get(k) for k in (keys or TRAFFIC_KEYS)):
+        if field in r and all(r["tuning"].get(k, TUNING_DEFAULTS.get(k)) == tuning.get(k, TUNING_DEFAULTS.get(k))
+                              for k in (keys or TRAFFIC_KEYS)):
             return r[field]
     return None
 

@@ -317,10 +317,16 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             radius <= 12.5 cm lies wholly inside a cell of one of them;
  *             a cell lists the objects whose footprint meets it), 0 = every
  *             object is tested; the contacts are the same either way
+ *  bin        1 = the triangles between lane_max and small_max pixels are
+ *             binned: each is listed, in LDS, under every 8x8 pixel tile of
+ *             the region it can cover, and the tiles are drawn one per wave
+ *             (lane = pixel) when the list buffer fills; 0 = they are drawn
+ *             by the wave that set them up.  The z-buffer and the bins must
+ *             fit one CU's 160 KB of LDS (with colour: region <= 64)
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
  * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0,
- * objgrid 1 with 16 or more objects per env (else 0).
+ * objgrid 1 with 16 or more objects per env (else 0), bin 0.
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -336,6 +342,7 @@ typedef struct gal_tuning {
     int32_t split;
     int32_t order;
     int32_t objgrid;
+    int32_t bin;
 } gal_tuning;
 
 /* Read / replace the launch configuration above (Section 3.1 batching
@@ -350,7 +357,8 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
  * fixes one batch size per GPU; here the split of the batch's work into
  * workgroups is searched per batch): times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
- * queue, robot lanes per env) on this batch with the given actions and
+ * queue, robot lanes per env, and the 8x8-tile binning wherever its LDS
+ * fits) on this batch with the given actions and
  * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
  * it with the other launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the
  * workgroups resident at once, each with an occlusion prologue of 128 and 256

@@ -390,6 +390,7 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->split = b->split;
     t->order = b->rast.order;
     t->objgrid = b->rp.objgrid;
+    t->bin = b->rast.bin;
     return GAL_OK;
 }
 
@@ -411,6 +412,16 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->split < 0 || t->split > b->N) return fail(GAL_EINVAL, "split must be in 0..num_envs");
     if (t->order != 0 && t->order != 1) return fail(GAL_EINVAL, "order must be 0 or 1");
     if (t->objgrid != 0 && t->objgrid != 1) return fail(GAL_EINVAL, "objgrid must be 0 or 1");
+    if (t->bin != 0 && t->bin != 1) return fail(GAL_EINVAL, "bin must be 0 or 1");
+    {
+        gal::RasterParams probe = b->rast;
+        probe.block = t->block;
+        probe.region = t->region;
+        probe.bin = t->bin;
+        if (!gal::raster_fits(probe, b->max_res, (b->flags & GAL_COLOR) != 0))
+            return fail(GAL_EINVAL, "block %d region %d%s: the z-buffer and bins exceed the 160 KB of LDS",
+                        t->block, t->region, (b->flags & GAL_COLOR) ? " with colour" : "");
+    }
     const bool rebuild = t->region != b->rast.region || t->split != b->split;
     b->rast.block = t->block;
     b->rast.region = t->region;
@@ -425,6 +436,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->split = t->split;
     b->rast.order = t->order;
     b->rp.objgrid = t->objgrid;
+    b->rast.bin = t->bin;
     b->tune_gen += 1;
     b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
     if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");
@@ -514,8 +526,39 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                                 t.graph = 0;
                                 t.split = 0;
                                 t.order = 0;
+                                t.bin = 0;
                                 cands.push_back(t);
                             }
+    // binned candidates (mid-sized triangles listed per 8x8 tile in LDS)
+    for (int block : {256, 512, 1024})
+        for (int region : regions)
+            for (int lane_max : {4, 8})
+                for (int small_max : {256})
+                    for (int persist : {0, 1}) {
+                        bool ok = true;
+                        for (int e = 0; e < b->N && ok; ++e)
+                            if (b->res_host[e] > region && b->res_host[e] % region) ok = false;
+                        gal::RasterParams probe = b->rast;
+                        probe.block = block;
+                        probe.region = region;
+                        probe.bin = 1;
+                        if (!ok || !gal::raster_fits(probe, b->max_res, (b->flags & GAL_COLOR) != 0)) continue;
+                        gal_tuning t = orig;
+                        t.block = block;
+                        t.region = region;
+                        t.lane_max = lane_max;
+                        t.small_max = small_max;
+                        t.occlusion = 1;
+                        t.refresh = 1;
+                        t.prologue = 128;
+                        t.persistent = persist;
+                        t.robot_lanes = 64;
+                        t.graph = 0;
+                        t.split = 0;
+                        t.order = 0;
+                        t.bin = 1;
+                        cands.push_back(t);
+                    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         b->rast.stats = stats_on;
@@ -544,8 +587,8 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
             have_ref = true;
         } else if (h != ref_hash) {
             return fail(GAL_ESTATE, "autotune: candidate (block %d region %d lane_max %d small_max %d "
-                        "occlusion %d persistent %d split %d) changed the output bits",
-                        t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent, t.split);
+                        "occlusion %d persistent %d split %d bin %d) changed the output bits",
+                        t.block, t.region, t.lane_max, t.small_max, t.occlusion, t.persistent, t.split, t.bin);
         }
         (void)hipEventRecord(e0, s);
         for (int k = 0; k < nsteps; ++k)

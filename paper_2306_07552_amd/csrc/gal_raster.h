@@ -63,6 +63,7 @@ struct RasterParams {
     int32_t prologue;  // clusters drawn before occlusion culling starts
     int32_t persistent;// 1 = persistent kernel draining the work queue
     int32_t order;     // 1 = the queue follows the last step's item times, longest first
+    int32_t bin;       // 1 = mid-sized triangles are binned per 8x8 tile in LDS and drawn tile by tile
     unsigned long long *stats; // optional work counters [8] (null = off)
     uint32_t *item_cost;        // [work] last time of each work item (wall-clock ticks)
     const uint32_t *item_order; // [work] queue position -> work item
@@ -71,6 +72,8 @@ struct RasterParams {
 hipError_t raster_prepare();   // raises the dynamic-LDS limit of the raster kernels
 // Workgroups of the persistent raster kernel that fit on the device at once.
 int raster_persistent_grid(const RasterParams &rp, int max_region, bool color);
+// Whether one workgroup's LDS (z-buffer, bins, shared state) fits a CU.
+bool raster_fits(const RasterParams &rp, int max_region, bool color);
 hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const float *camera,
                          const int32_t *env_res, const uint64_t *env_depth_off,
                          const uint32_t *work, int32_t num_work, int32_t max_region,

@@ -33,10 +33,13 @@
 // projection once per vertex), lane = triangle (gathers its vertices with
 // ds_bpermute); triangles whose pixel bbox is small are rasterised by their
 // own lane, mid-sized ones by the whole wave with the pixels spread over the
-// lanes, large ones one 8x8 tile (lane = pixel) at a time.  Every extra
-// rejection only removes triangles that cannot change a pixel of the region.
+// lanes (or, with binning, listed per 8x8 tile in LDS and drawn tile by tile,
+// lane = pixel), large ones one 8x8 tile (lane = pixel) at a time.  Every
+// extra rejection only removes triangles that cannot change a pixel of the
+// region.
 #include "gal_raster.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace gal {
@@ -218,14 +221,21 @@ __host__ __device__ constexpr int zpitch(int R) { return 8 * (((R >> 3) + 1) | 1
 // Z-buffer sinks in LDS: depth only (u32, 24-bit depth) or depth and colour
 // (u64 key = depth << 32 | triangle id: the smallest depth wins, ties go to
 // the smallest triangle id).
+// key_at / set_key / make: plain access for a wave that owns a pixel tile
+// while no other wave writes it (the binned pass).
 struct DepthSink {
+    typedef uint32_t Key;
     uint32_t *z;
     __device__ __forceinline__ void put(int p, uint32_t D, uint32_t) const { atomicMin(&z[p], D); }
     __device__ __forceinline__ uint32_t depth_at(int p) const { return z[p]; }
     __device__ __forceinline__ void clear(int p) const { z[p] = kFar; }
+    __device__ __forceinline__ Key key_at(int p) const { return z[p]; }
+    __device__ __forceinline__ void set_key(int p, Key k) const { z[p] = k; }
+    static __device__ __forceinline__ Key make(uint32_t D, uint32_t) { return D; }
 };
 
 struct ColorSink {
+    typedef unsigned long long Key;
     unsigned long long *k;
     __device__ __forceinline__ void put(int p, uint32_t D, uint32_t id) const
     {
@@ -235,6 +245,12 @@ struct ColorSink {
     __device__ __forceinline__ void clear(int p) const
     {
         k[p] = ((unsigned long long)kFar << 32) | 0xFFFFFFFFull;
+    }
+    __device__ __forceinline__ Key key_at(int p) const { return k[p]; }
+    __device__ __forceinline__ void set_key(int p, Key v) const { k[p] = v; }
+    static __device__ __forceinline__ Key make(uint32_t D, uint32_t id)
+    {
+        return ((unsigned long long)D << 32) | (unsigned long long)id;
     }
 };
 
@@ -668,6 +684,81 @@ __device__ __forceinline__ bool any_plane_front(const uint32_t *bits, uint32_t p
            plane_front(bits, p23 & 0xFFFFu) || plane_front(bits, p23 >> 16);
 }
 
+// 8x8-tile binning (tuning `bin`).  Mid-sized triangles are not drawn by the
+// wave that sets them up: their edge functions go to a record buffer in LDS
+// and the record's index to the list of every 8x8 tile of the region that can
+// hold one of their pixels.  When the buffer is nearly full, and at the end of
+// each occlusion round, the workgroup synchronises and every wave draws whole
+// tiles: lane = pixel, looping over the tile's list with the pixel's key in a
+// register (no other wave writes the tile meanwhile, so no atomics).  A
+// triangle that finds the buffer or one of its tiles' lists full is drawn by
+// the balanced pass instead; drawing a triangle twice changes nothing, the
+// z-buffer keeping a minimum.
+constexpr int kBinTris = 256;   // records per flush
+constexpr int kBinCap = 24;     // list entries per tile
+
+// A binned triangle: per edge k, E_k = C + A * px + B * py at the pixel
+// (px, py) relative to the region origin (the same integer as the edge
+// function at that pixel centre), covered iff E_k >= b_k (top-left rule).
+struct BinRec {
+    int4 e0, e1, e2;   // A, B, C, b
+    float4 q;          // q0, q1, q2, bits of the triangle id
+};
+
+struct Bins {
+    BinRec *rec;       // [kBinTris]
+    int *cnt;          // [tiles] list entries claimed (above kBinCap: overflowed)
+    uint16_t *list;    // [tiles][kBinCap] record indices
+    int *ntri;         // records claimed
+    int TW;            // tiles per region row
+};
+
+// Bytes of a region's bins in dynamic LDS (after the z-buffer).
+__host__ __device__ constexpr size_t bin_bytes(int R)
+{
+    return sizeof(BinRec) * kBinTris + (size_t)(R / 8) * (R / 8) * (4 + 2 * kBinCap) + 16;
+}
+
+// Whether the edge function can reach its threshold somewhere in tile
+// (tx, ty): its largest value over the tile's 64 pixel centres (it is linear).
+__device__ __forceinline__ bool tile_live(const int4 &e, int tx, int ty)
+{
+    const int px = 8 * tx + (e.x > 0 ? 7 : 0), py = 8 * ty + (e.y > 0 ? 7 : 0);
+    return e.z + mul24(e.x, px) + mul24(e.y, py) >= e.w;
+}
+
+// Draw the binned triangles: wave w takes tiles w, w + nwaves, ...
+template <class Sink>
+__device__ void flush_bins(const Bins &bn, int wave, int nwaves, int lane, int P, const Sink &zb)
+{
+    const int lx = lane & 7, ly = lane >> 3;
+    const int ntiles = bn.TW * bn.TW;
+    for (int t = wave; t < ntiles; t += nwaves) {
+        const int n = __builtin_amdgcn_readfirstlane(min(bn.cnt[t], kBinCap));
+        if (n == 0) continue;
+        const int ty = t / bn.TW, tx = t - ty * bn.TW;
+        const int px = 8 * tx + lx, py = 8 * ty + ly;
+        const int zi = py * P + px;
+        typename Sink::Key best = zb.key_at(zi);
+        const uint16_t *L = bn.list + t * kBinCap;
+        for (int j = 0; j < n; ++j) {
+            const int k = __builtin_amdgcn_readfirstlane((int)L[j]);
+            const BinRec r = bn.rec[k];
+            const int e0 = r.e0.z + mul24(r.e0.x, px) + mul24(r.e0.y, py);
+            const int e1 = r.e1.z + mul24(r.e1.x, px) + mul24(r.e1.y, py);
+            const int e2 = r.e2.z + mul24(r.e2.x, px) + mul24(r.e2.y, py);
+            if (e0 >= r.e0.w && e1 >= r.e1.w && e2 >= r.e2.w) {
+                const uint32_t D = frag_depth(e0, e1, e2, r.q.x, r.q.y, r.q.z);
+                if (D < kFar) {
+                    const typename Sink::Key key = Sink::make(D, __float_as_uint(r.q.w));
+                    best = key < best ? key : best;
+                }
+            }
+        }
+        zb.set_key(zi, best);
+    }
+}
+
 // Everything a wave needs to draw clusters of one (env, region) item.
 struct Ctx {
     Cam cam;
@@ -681,7 +772,55 @@ struct Ctx {
     int lane_max;
     BigRec *big;     // the workgroup's list of deferred large triangles
     int *nbig;
+    bool binning;    // mid-sized triangles go to the 8x8-tile bins
+    Bins bins;
 };
+
+// The record of one set-up triangle.
+__device__ __forceinline__ BinRec bin_record(const Ctx &c, const Setup &S, uint32_t id)
+{
+    const int ex0 = S.x2 - S.x1, ey0 = S.y2 - S.y1;
+    const int ex1 = S.x0 - S.x2, ey1 = S.y0 - S.y2;
+    const int ex2 = S.x1 - S.x0, ey2 = S.y1 - S.y0;
+    const int Px = 16 * c.rx0 + 8, Py = 16 * c.ry0 + 8;   // centre of the region's first pixel
+    BinRec r;
+    r.e0 = make_int4(-16 * ey0, 16 * ex0, mul24(ex0, Py - S.y1) - mul24(ey0, Px - S.x1), S.bias & 1);
+    r.e1 = make_int4(-16 * ey1, 16 * ex1, mul24(ex1, Py - S.y2) - mul24(ey1, Px - S.x2), (S.bias >> 1) & 1);
+    r.e2 = make_int4(-16 * ey2, 16 * ex2, mul24(ex2, Py - S.y0) - mul24(ey2, Px - S.x0), (S.bias >> 2) & 1);
+    r.q = make_float4(S.q0, S.q1, S.q2, __uint_as_float(id));
+    return r;
+}
+
+// Bin the wave's mid-sized triangles (lanes with `bal`): one record each,
+// then each lane lists its record under every tile of its bbox that can hold
+// one of its pixels.  Clears `bal` for the triangles binned whole; the others
+// (record buffer or a tile's list full) stay with the caller, which draws
+// them itself.  (Listing tile by tile over the union of the wave's ranges,
+// one atomic per tile and wave, measured slower: the unions are wide.)
+__device__ __forceinline__ void bin_wave(const Ctx &c, const Setup &S, uint32_t id, int lane, bool &bal)
+{
+    const uint64_t mm = __ballot(bal);
+    if (!mm) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(c.bins.ntri, __popcll(mm));
+    base = __builtin_amdgcn_readlane(base, 0);
+    const int slot = base + __popcll(mm & ((1ull << lane) - 1ull));
+    if (!bal || slot >= kBinTris) return;
+    const BinRec r = bin_record(c, S, id);
+    c.bins.rec[slot] = r;
+    const int tx0 = (S.px0 - c.rx0) >> 3, tx1 = (S.px1 - c.rx0) >> 3;
+    const int ty0 = (S.py0 - c.ry0) >> 3, ty1 = (S.py1 - c.ry0) >> 3;
+    bool full = false;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            if (!(tile_live(r.e0, tx, ty) && tile_live(r.e1, tx, ty) && tile_live(r.e2, tx, ty))) continue;
+            const int t = ty * c.bins.TW + tx;
+            const int pos = atomicAdd(&c.bins.cnt[t], 1);
+            if (pos < kBinCap) c.bins.list[t * kBinCap + pos] = (uint16_t)slot;
+            else full = true;
+        }
+    if (!full) bal = false;
+}
 
 // One cluster's per-lane inputs: lane l holds vertex l and triangle l.
 struct ClusterData {
@@ -859,7 +998,7 @@ __device__ __forceinline__ void stat_add(unsigned long long *stats, int k, int l
 }
 
 // Draw one cluster.
-template <class Sink>
+template <bool kBin, class Sink>
 __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const Sink &zb,
                              unsigned long long *stats)
 {
@@ -955,6 +1094,7 @@ __device__ void draw_cluster(const Ctx &c, const ClusterData &d, int lane, const
             const int tot = wave_incl_sum(npx, lane);
             stat_add(stats, kStatCandPixels, lane, (uint64_t)__builtin_amdgcn_readlane(tot, 63));
         }
+        if (kBin && c.binning) bin_wave(c, S, myid, lane, bal);
         if (__ballot(bal)) raster_balanced(S, myid, bal, lane, c.rx0, c.ry0, c.P, c.own, zb);
         bool spill = false;
         if (big) {
@@ -1034,7 +1174,7 @@ struct ItemShared {
 };
 
 // Render one (env, region) work item into the depth (and colour) output.
-template <int kBlock, bool kColor>
+template <int kBlock, bool kColor, bool kBin>
 __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterParams &rp,
                                             const float *__restrict__ camera,
                                             const int32_t *__restrict__ env_res,
@@ -1069,7 +1209,19 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     c.planefront = sh.planefront;
     c.small_max = rp.small_max;
     c.lane_max = rp.lane_max;
+    c.binning = false;   // objects and links are drawn directly
     const int R = c.R;
+    if (kBin) {
+        unsigned char *after = reinterpret_cast<unsigned char *>(zdyn) + (size_t)R * c.P * (kColor ? 8 : 4);
+        const int TW = R >> 3;
+        c.bins.rec = reinterpret_cast<BinRec *>(after);
+        c.bins.cnt = reinterpret_cast<int *>(after + sizeof(BinRec) * kBinTris);
+        c.bins.list = reinterpret_cast<uint16_t *>(c.bins.cnt + TW * TW);
+        c.bins.ntri = reinterpret_cast<int *>(c.bins.list + (size_t)TW * TW * kBinCap);
+        c.bins.TW = TW;
+        for (int i = threadIdx.x; i < TW * TW; i += kBlock) c.bins.cnt[i] = 0;
+        if (threadIdx.x == 0) *c.bins.ntri = 0;
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     Occl oc;
@@ -1152,7 +1304,7 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
         for (int cidx = wave; cidx < nc; cidx += kWaves) {
             ClusterData cd;
             object_cluster(m, env, cidx, lane, first_id, cd);
-            draw_cluster(c, cd, lane, zb, stats);
+            draw_cluster<kBin>(c, cd, lane, zb, stats);
         }
     }
     // ---- the robot's links (four links per cluster, on the last two waves)
@@ -1161,8 +1313,9 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
                                   (m.obj_frames ? 12u * (uint32_t)m.num_objects : 0u);
         ClusterData cd;
         link_cluster(m, env, kWaves - 1 - wave, lane, first_id, cd);
-        draw_cluster(c, cd, lane, zb, stats);
+        draw_cluster<kBin>(c, cd, lane, zb, stats);
     }
+    c.binning = kBin;
     // Clusters are processed in windows of up to kVisCap: the workgroup tests
     // a window against the region frustum and compacts the visible ones, in
     // mesh order, into an LDS list; waves then pull list entries one at a
@@ -1220,19 +1373,33 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
             idx = __builtin_amdgcn_readfirstlane(idx);
             ClusterData cd;
             if (idx < end) fetch_cluster(m, wbase + vis[idx], lane, cd);
-            while (idx < end) {
-                int nidx = 0;
-                if (lane == 0) nidx = atomicAdd(&next, 1);
-                nidx = __builtin_amdgcn_readfirstlane(nidx);
-                ClusterData nd;
-                if (nidx < end) fetch_cluster(m, wbase + vis[nidx], lane, nd);
-                draw_cluster(c, cd, lane, zb, stats);
-                ++drawn;
-                idx = nidx;
-                cd = nd;
+            // with bins: sub-rounds that end when the record buffer is nearly
+            // full; the cluster a wave has fetched waits for the next one
+            for (;;) {
+                while (idx < end) {
+                    int nidx = 0;
+                    if (lane == 0) nidx = atomicAdd(&next, 1);
+                    nidx = __builtin_amdgcn_readfirstlane(nidx);
+                    ClusterData nd;
+                    if (nidx < end) fetch_cluster(m, wbase + vis[nidx], lane, nd);
+                    draw_cluster<kBin>(c, cd, lane, zb, stats);
+                    ++drawn;
+                    idx = nidx;
+                    cd = nd;
+                    if (kBin && __builtin_amdgcn_readfirstlane(*(volatile int *)c.bins.ntri) > kBinTris - 64)
+                        break;
+                }
+                __syncthreads();
+                if (kBin) {
+                    flush_bins(c.bins, wave, kWaves, lane, c.P, zb);
+                    __syncthreads();
+                }
+                drain_big(sh.big, &sh.nbig, sh.big_gofs, wave, kWaves, lane, c.rx0, c.ry0, c.P, zb);
+                if (!kBin) break;
+                for (int i = threadIdx.x; i < c.bins.TW * c.bins.TW; i += kBlock) c.bins.cnt[i] = 0;
+                if (threadIdx.x == 0) *c.bins.ntri = 0;
+                if (!__syncthreads_or(idx < end)) break;
             }
-            __syncthreads();
-            drain_big(sh.big, &sh.nbig, sh.big_gofs, wave, kWaves, lane, c.rx0, c.ry0, c.P, zb);
             pos = end;
             if (pos >= V) break;
             refresh_bounds(zb, oc, R, wave, kWaves, lane);
@@ -1336,30 +1503,40 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
 }
 
 // One workgroup per work item.
-template <int kBlock, bool kColor>
-__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster(
+// Waves per SIMD the register allocation is sized for: 4 at 512 and 1024
+// threads (two workgroups' or one workgroup's waves per CU); with bins a
+// 512-thread workgroup's z-buffer and bins at the largest region leave LDS for
+// one workgroup per CU, so its waves may use twice the registers.
+template <int kBlock, bool kBin>
+constexpr int raster_waves_per_eu()
+{
+    return kBlock >= 1024 ? 4 : kBlock >= 512 ? (kBin ? 2 : 4) : 2;
+}
+
+template <int kBlock, bool kColor, bool kBin>
+__global__ __launch_bounds__(kBlock, (raster_waves_per_eu<kBlock, kBin>())) void k_raster(
     RenderMesh m, RasterParams rp, const float *__restrict__ camera,
     const int32_t *__restrict__ env_res, const uint64_t *__restrict__ env_depth_off,
     const uint32_t *__restrict__ work, int32_t num_work, uint32_t *__restrict__ queue,
     uint32_t *__restrict__ depth, uint8_t *__restrict__ rgb)
 {
-    extern __shared__ unsigned long long zdyn[];
+    extern __shared__ __attribute__((aligned(16))) unsigned long long zdyn[];
     __shared__ ItemShared<kBlock> sh;
-    raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[blockIdx.x], depth, rgb,
+    raster_item<kBlock, kColor, kBin>(m, rp, camera, env_res, env_depth_off, work[blockIdx.x], depth, rgb,
                                 zdyn, sh);
 }
 
 // Persistent: as many workgroups as fit on the chip drain the work queue
 // (items in longest-first order; the counter is reset by the robot kernel
 // that precedes this launch in the step).
-template <int kBlock, bool kColor>
-__global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_persistent(
+template <int kBlock, bool kColor, bool kBin>
+__global__ __launch_bounds__(kBlock, (raster_waves_per_eu<kBlock, kBin>())) void k_raster_persistent(
     RenderMesh m, RasterParams rp, const float *__restrict__ camera,
     const int32_t *__restrict__ env_res, const uint64_t *__restrict__ env_depth_off,
     const uint32_t *__restrict__ work, int32_t num_work, uint32_t *__restrict__ queue,
     uint32_t *__restrict__ depth, uint8_t *__restrict__ rgb)
 {
-    extern __shared__ unsigned long long zdyn[];
+    extern __shared__ __attribute__((aligned(16))) unsigned long long zdyn[];
     __shared__ ItemShared<kBlock> sh;
     for (;;) {
         if (threadIdx.x == 0) sh.queue_item = (int)atomicAdd(queue, 1u);
@@ -1374,7 +1551,7 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_pers
             if ((unsigned)idx >= (unsigned)num_work) idx = i;
         }
         const uint64_t t0 = wall_clock64();
-        raster_item<kBlock, kColor>(m, rp, camera, env_res, env_depth_off, work[idx], depth, rgb, zdyn,
+        raster_item<kBlock, kColor, kBin>(m, rp, camera, env_res, env_depth_off, work[idx], depth, rgb, zdyn,
                                     sh);
         // the item's time, which orders the next step's queue (raster_item
         // ends with a barrier, so every wave is done)
@@ -1385,7 +1562,7 @@ __global__ __launch_bounds__(kBlock, (kBlock >= 512 ? 4 : 2)) void k_raster_pers
     }
 }
 
-template <bool kColor, bool kPersist>
+template <bool kColor, bool kPersist, bool kBin>
 hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const float *camera,
                            const int32_t *env_res, const uint64_t *env_depth_off,
                            const uint32_t *work, int32_t num_work, uint32_t *queue,
@@ -1393,7 +1570,7 @@ hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const fl
 {
     const int g = kPersist ? grid : num_work;
 #define GAL_RASTER_LAUNCH(B)                                                                     \
-    hipLaunchKernelGGL((kPersist ? k_raster_persistent<B, kColor> : k_raster<B, kColor>), dim3(g), \
+    hipLaunchKernelGGL((kPersist ? k_raster_persistent<B, kColor, kBin> : k_raster<B, kColor, kBin>), dim3(g), \
                        dim3(B), lds, s, m, rp, camera, env_res, env_depth_off, work, num_work,     \
                        queue, depth, rgb)
     switch (rp.block) {
@@ -1405,16 +1582,36 @@ hipError_t launch_raster_t(const RenderMesh &m, const RasterParams &rp, const fl
     return hipGetLastError();
 }
 
-size_t lds_bytes(int region, bool color)
+size_t lds_bytes(int region, bool color, bool bin)
 {
-    return (size_t)region * zpitch(region) * (color ? 8 : 4);
+    return (size_t)region * zpitch(region) * (color ? 8 : 4) + (bin ? bin_bytes(region) : 0);
 }
 
+// LDS a workgroup of kernel f may use beside its static LDS (the device's
+// per-workgroup limit, 160 KB on gfx950, less the kernel's own static LDS).
 template <class K>
-hipError_t allow(K f, bool color)
+hipError_t lds_room(K f, size_t *room)
 {
-    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes(kMaxRegion, color));
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void *)f);
+    if (e != hipSuccess) return e;
+    int dev = 0, max_lds = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    *room = (size_t)max_lds > fa.sharedSizeBytes ? (size_t)max_lds - fa.sharedSizeBytes : 0;
+    return hipSuccess;
+}
+
+// The largest dynamic LDS any tuning asks of kernel f: the largest region's
+// z-buffer (and bins, for the binned kernels), within the room there is.
+template <class K>
+hipError_t allow(K f, bool color, bool bin)
+{
+    size_t room = 0;
+    hipError_t e = lds_room(f, &room);
+    if (e != hipSuccess) return e;
+    const size_t want = std::min(lds_bytes(kMaxRegion, color, bin), room);
+    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
 }
 
 }  // namespace
@@ -1423,23 +1620,51 @@ hipError_t raster_prepare()
 {
     hipError_t e = hipSuccess;
 #define GAL_ALLOW(B, C)                                                                  \
-    if ((e = allow(k_raster<B, C>, C)) != hipSuccess) return e;                          \
-    if ((e = allow(k_raster_persistent<B, C>, C)) != hipSuccess) return e;
+    if ((e = allow(k_raster<B, C, false>, C, false)) != hipSuccess) return e;            \
+    if ((e = allow(k_raster_persistent<B, C, false>, C, false)) != hipSuccess) return e; \
+    if ((e = allow(k_raster<B, C, true>, C, true)) != hipSuccess) return e;              \
+    if ((e = allow(k_raster_persistent<B, C, true>, C, true)) != hipSuccess) return e;
     GAL_ALLOW(256, false) GAL_ALLOW(512, false) GAL_ALLOW(1024, false)
     GAL_ALLOW(256, true) GAL_ALLOW(512, true) GAL_ALLOW(1024, true)
 #undef GAL_ALLOW
     return e;
 }
 
+bool raster_fits(const RasterParams &rp, int max_region, bool color)
+{
+    const int R = max_region < rp.region ? max_region : rp.region;
+    size_t room = 0, room2 = 0;
+    hipError_t e = hipSuccess;
+#define GAL_ROOM(B, C, BIN)                                                   \
+    e = lds_room(k_raster<B, C, BIN>, &room);                                 \
+    if (e == hipSuccess) e = lds_room(k_raster_persistent<B, C, BIN>, &room2)
+#define GAL_ROOM_B(B)                                                         \
+    if (color) {                                                              \
+        if (rp.bin) { GAL_ROOM(B, true, true); } else { GAL_ROOM(B, true, false); } \
+    } else {                                                                  \
+        if (rp.bin) { GAL_ROOM(B, false, true); } else { GAL_ROOM(B, false, false); } \
+    }
+    switch (rp.block) {
+    case 256: GAL_ROOM_B(256); break;
+    case 1024: GAL_ROOM_B(1024); break;
+    default: GAL_ROOM_B(512); break;
+    }
+#undef GAL_ROOM_B
+#undef GAL_ROOM
+    return e == hipSuccess && lds_bytes(R, color, rp.bin != 0) <= std::min(room, room2);
+}
+
 int raster_persistent_grid(const RasterParams &rp, int max_region, bool color)
 {
     const int R = max_region < rp.region ? max_region : rp.region;
-    const size_t lds = lds_bytes(R, color);
+    const size_t lds = lds_bytes(R, color, rp.bin != 0);
     int per_cu = 0;
     hipError_t e = hipSuccess;
 #define GAL_OCC(B)                                                                              \
-    e = color ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, true>, B, lds) \
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, false>, B, lds)
+    e = rp.bin ? (color ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, true, true>, B, lds) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, false, true>, B, lds)) \
+               : (color ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, true, false>, B, lds) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raster_persistent<B, false, false>, B, lds))
     switch (rp.block) {
     case 256: GAL_OCC(256); break;
     case 1024: GAL_OCC(1024); break;
@@ -1461,20 +1686,21 @@ hipError_t launch_raster(const RenderMesh &m, const RasterParams &rp, const floa
 {
     if (num_work <= 0) return hipSuccess;
     const int R = max_region < rp.region ? max_region : rp.region;
-    const size_t lds = lds_bytes(R, rgb != nullptr);
+    const size_t lds = lds_bytes(R, rgb != nullptr, rp.bin != 0);
     const bool persist = rp.persistent && queue && persistent_grid > 0;
+    const int grid = persist ? persistent_grid : 0;
+#define GAL_RASTER_SELECT(C, P)                                                                         \
+    return rp.bin ? launch_raster_t<C, P, true>(m, rp, camera, env_res, env_depth_off, work, num_work,   \
+                                                queue, depth, rgb, lds, grid, s)                          \
+                  : launch_raster_t<C, P, false>(m, rp, camera, env_res, env_depth_off, work, num_work,  \
+                                                 queue, depth, rgb, lds, grid, s)
     if (rgb) {
-        if (persist)
-            return launch_raster_t<true, true>(m, rp, camera, env_res, env_depth_off, work, num_work,
-                                               queue, depth, rgb, lds, persistent_grid, s);
-        return launch_raster_t<true, false>(m, rp, camera, env_res, env_depth_off, work, num_work,
-                                            queue, depth, rgb, lds, 0, s);
+        if (persist) GAL_RASTER_SELECT(true, true);
+        GAL_RASTER_SELECT(true, false);
     }
-    if (persist)
-        return launch_raster_t<false, true>(m, rp, camera, env_res, env_depth_off, work, num_work,
-                                            queue, depth, nullptr, lds, persistent_grid, s);
-    return launch_raster_t<false, false>(m, rp, camera, env_res, env_depth_off, work, num_work,
-                                         queue, depth, nullptr, lds, 0, s);
+    if (persist) GAL_RASTER_SELECT(false, true);
+    GAL_RASTER_SELECT(false, false);
+#undef GAL_RASTER_SELECT
 }
 
 }  // namespace gal

@@ -239,6 +239,17 @@ TUNINGS = [
     # queue ordered by the previous step's item times
     dict(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=128,
          persistent=1, robot_lanes=64, split=4, order=1),
+    # mid-sized triangles binned per 8x8 tile in LDS
+    dict(block=512, region=128, lane_max=4, small_max=256, refresh=1, occlusion=1, prologue=128,
+         persistent=1, robot_lanes=64, bin=1),
+    # everything but the per-lane ones binned: floors and walls over many
+    # tiles, full tile lists (the overflow path draws them directly)
+    dict(block=256, region=64, lane_max=0, small_max=65536, refresh=4, occlusion=1, prologue=8,
+         persistent=0, robot_lanes=64, bin=1),
+    dict(block=1024, region=128, lane_max=8, small_max=1024, refresh=1, occlusion=0, prologue=0,
+         persistent=1, robot_lanes=32, split=4, order=1, bin=1),
+    dict(block=512, region=32, lane_max=0, small_max=4096, refresh=2, occlusion=1, prologue=64,
+         persistent=1, robot_lanes=64, split=12, bin=1),
 ]
 
 
@@ -266,7 +277,9 @@ def test_tuning_invariance(torch_cuda, tuning):
     dict(block=256, region=64, lane_max=0, small_max=64, refresh=4, occlusion=1, prologue=8),
     dict(block=512, region=128, lane_max=8, small_max=256, refresh=1, occlusion=1, prologue=256,
          persistent=1, split=5, order=1),
-], ids=["r128", "r64-occl", "r128-persistent-split"])
+    dict(block=256, region=64, lane_max=0, small_max=1024, refresh=2, occlusion=1, prologue=8,
+         persistent=1, bin=1),
+], ids=["r128", "r64-occl", "r128-persistent-split", "r64-bin"])
 def test_color_parity(torch_cuda, tuning):
     """Flat colour: the winning triangle (smallest depth, then smallest id)
     and its seeded colour, mixed scene sizes and 64/128/256 resolutions."""
@@ -289,6 +302,23 @@ def test_color_parity(torch_cuda, tuning):
         b.step(torch.from_numpy(a).cuda(), out)
         torch.cuda.synchronize()
         compare_step(b, ob, out, ob.step(a), label=f"step {k}")
+
+
+def test_bin_lds_limit_rejected(torch_cuda):
+    """With colour, a 128-pixel region's 64-bit z-buffer and the bins do not
+    fit one CU's LDS: the tuning is refused and the batch keeps its own."""
+    print("case: bin LDS limit", flush=True)
+    from paper_2306_07552_amd import gal
+    cfg = sg.scaled_config(4, 2, tri_target=(2000.0, 4000.0))
+    scenes = sg.make_scene_set(cfg)
+    scenes.res[:] = [128, 128]
+    b = gal.Batch(sg.make_robot_for(cfg), scenes, sg.config_constants(cfg), color=True)
+    before = b.get_tuning()
+    with pytest.raises(gal.GalError, match="LDS"):
+        b.set_tuning(region=128, bin=1)
+    assert b.get_tuning() == before
+    b.set_tuning(region=64, bin=1)
+    assert b.get_tuning()["bin"] == 1
 
 
 def test_graph_replay_matches_eager(torch_cuda):
