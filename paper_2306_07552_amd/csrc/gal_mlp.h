@@ -24,6 +24,10 @@ enum { kGemmFwd = 0, kGemmDx, kGemmDw, kGemmNtF32, kGemmNnF32, kGemmTnF32 };
 // variant splits its reduction over the rows into the FP32 workspace ws
 // (ws_floats values; NULL = no split) and sums the splits in a fixed order.
 constexpr int kMaxDwSplits = 16;
+// Split-K partial products of A B^T (A [M][K], B [N][K], BF16): split z of
+// K (in 32-column steps) into part + z M N, FP32 [M][N]; no reduction.
+hipError_t mlp_gemm_parts(const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda, int ldb, int splits,
+                          float *part, hipStream_t s);
 hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda,
                     int ldb, const float *bias, const uint16_t *mask, int ldm, float *Cf,
                     uint16_t *Cb, int ldc, hipStream_t s, float *ws = nullptr, size_t ws_floats = 0);

@@ -41,6 +41,8 @@ struct gal_policy {
     float *w = nullptr;        // FP32 parameters
     uint16_t *wb = nullptr;    // BF16 copy (the convolutions' and the fc layer's weights are read from it)
     uint16_t *h[4] = {nullptr, nullptr, nullptr, nullptr};   // activations of conv1..3, fc
+    float *fc_ws = nullptr;    // split-K partial products of the fc layer
+    size_t fc_ws_floats = 0;
     int32_t last_envs = 0;
     // training (allocated on the first update)
     float *g = nullptr, *m = nullptr, *v = nullptr;          // gradient, Adam moments
@@ -120,6 +122,21 @@ int gal_policy_create(int32_t max_envs, int32_t act_dim, uint64_t seed, gal_poli
             delete p;
             return rc;
         }
+    {
+        // the fc layer's split-K workspace: the most any batch size up to max_envs needs
+        const int flat = p->side[3] * p->side[3] * kConv[2][0];
+        size_t need = 0;
+        for (int n = 1; n <= max_envs; n = n < 64 ? n + 1 : n + 64) {
+            const int m = std::min(n, (int)max_envs);
+            need = std::max(need, (size_t)gal::fc_splits(m, gal::kPolicyFeat, flat) * m * gal::kPolicyFeat);
+        }
+        need = std::max(need, (size_t)gal::fc_splits(max_envs, gal::kPolicyFeat, flat) * max_envs * gal::kPolicyFeat);
+        p->fc_ws_floats = need;
+        if ((rc = p->alloc(&p->fc_ws, need))) {
+            delete p;
+            return rc;
+        }
+    }
     // He-uniform weights of the encoder, small heads, zero biases, log_std -0.5
     std::vector<float> host(off, 0.0f);
     std::mt19937_64 rng(seed);
@@ -199,8 +216,8 @@ int encode(gal_policy *p, const uint32_t *depth_dev, int n, hipStream_t s)
         in = p->h[l];
     }
     const int flat = p->side[3] * p->side[3] * kConv[2][0];
-    POL_TRY(gal::mlp_gemm(gal::kGemmFwd, p->h[2], p->wb + p->off_w[3], n, gal::kPolicyFeat, flat, flat, flat,
-                          p->w + p->off_b[3], nullptr, 0, nullptr, p->h[3], gal::kPolicyFeat, s));
+    POL_TRY(gal::fc_forward(p->h[2], p->wb + p->off_w[3], p->w + p->off_b[3], n, gal::kPolicyFeat, flat, p->fc_ws,
+                            p->fc_ws_floats, p->h[3], s));
     return GAL_OK;
 }
 
@@ -273,7 +290,7 @@ int gal_policy_ppo_gradients(gal_policy *p, const uint32_t *depth_dev, const flo
                            hp->clip, hp->value_coef, p->gm, p->gls, p->gv, p->terms, p->d[3], s));
     POL_TRY(gal::ppo_head_grads(p->h[3], state_dev, p->gm, p->gls, p->gv, p->terms, p->w + p->off_ls, A, S,
                                 hp->entropy_coef, g + p->off_aw, g + p->off_ab, g + p->off_vw, g + p->off_vb,
-                                g + p->off_ls, stats_dev, s));
+                                g + p->off_ls, stats_dev, p->part, p->part_floats, s));
     // fully connected layer
     const int flat = p->side[3] * p->side[3] * kConv[2][0];
     POL_TRY(gal::mlp_gemm(gal::kGemmDw, p->d[3], p->h[2], gal::kPolicyFeat, flat, S, gal::kPolicyFeat, flat, nullptr,
@@ -285,8 +302,7 @@ int gal_policy_ppo_gradients(gal_policy *p, const uint32_t *depth_dev, const flo
     for (int l = 2; l >= 0; --l) {
         const gal::ConvGeom gg = geom(p, l, S);
         const void *in = l == 0 ? (const void *)depth_dev : (const void *)p->h[l - 1];
-        POL_TRY(gal::conv_dw(l == 0, in, p->d[l], gg, p->part, p->part_floats, g + p->off_w[l], s));
-        POL_TRY(gal::colsum(p->d[l], gg.rows, kConv[l][0], p->part, p->part_floats, g + p->off_b[l], s));
+        POL_TRY(gal::conv_dw(l == 0, in, p->d[l], gg, p->part, p->part_floats, g + p->off_w[l], g + p->off_b[l], s));
         if (l > 0)
             POL_TRY(gal::conv_dx(p->d[l], p->wb + p->off_w[l], p->wt, p->h[l - 1], gg, p->d[l - 1], s));
     }

@@ -317,6 +317,17 @@ hipError_t mlp_gemm(int variant, const uint16_t *A, const uint16_t *B, int M, in
     }
 }
 
+hipError_t mlp_gemm_parts(const uint16_t *A, const uint16_t *B, int M, int N, int K, int lda, int ldb, int splits,
+                          float *part, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (splits < 1 || !part) return hipErrorInvalidValue;
+    const dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM, splits);
+    hipLaunchKernelGGL((k_gemm<false, true, kEpiF32>), grid, dim3(256), 0, s, A, B, M, N, K, lda, ldb, nullptr,
+                       nullptr, 0, part, nullptr, N);
+    return hipGetLastError();
+}
+
 hipError_t mlp_head_fwd(const uint16_t *h, const uint16_t *w, const float *b, int rows, int D,
                         float *z, hipStream_t s)
 {

@@ -14,6 +14,7 @@
 // directly: 8 consecutive k are 8 consecutive pixels of one image row, each
 // scaled to D / (2^24 - 1) and rounded to BF16 as it is loaded.
 #include "gal_internal.h"
+#include "gal_mlp.h"
 #include "gal_policy.h"
 
 #include <algorithm>
@@ -44,28 +45,44 @@ __device__ __forceinline__ uint16_t depth_bf16(uint32_t D)
 
 // Y[m][n] = relu(sum_k A(m, k) W[n][k] + b[n]) in BF16, A gathered from the
 // layer input (DEPTH: the u32 depth images, one channel).  One workgroup (4
-// waves) per 64 x 64 tile, as the surrogate's GEMM.
-template <bool DEPTH>
+// waves, each 32 x 32 outputs) per TM x TN tile: 64 x 64 (waves 2 x 2), or
+// 128 x 32 for the layers with 32 output channels (waves stacked in M), so
+// that no matrix-core work is spent on columns that do not exist.
+template <int TN>
+struct ConvTile {
+    static constexpr int TM = TN == 64 ? 64 : 128;
+    static constexpr int kALoads = TM / 64;   // 16-byte A loads per thread and K-step
+    __device__ static int wm(int wave) { return TN == 64 ? (wave >> 1) * 32 : wave * 32; }
+    __device__ static int wn(int wave) { return TN == 64 ? (wave & 1) * 32 : 0; }
+};
+
+template <bool DEPTH, int TN>
 __global__ __launch_bounds__(256) void k_conv_gemm(const void *__restrict__ in, const uint16_t *__restrict__ W,
                                                    const float *__restrict__ bias, ConvGeom g,
                                                    uint16_t *__restrict__ out)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
+    using T = ConvTile<TN>;
+    constexpr int TM = T::TM;
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][kBK + kPad];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int M = g.rows, N = g.out_c, K = g.k;
-    const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;   // M tiles on x (up to 2^31 - 1)
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    // this thread's A row, decomposed once: env, output pixel
-    const int r = t >> 2, kk = (t & 3) * 8;
-    const int m = m0 + r;
-    const bool mrow = m < M;
-    size_t base = 0;
-    {
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;   // M tiles on x (up to 2^31 - 1)
+    const int wm = T::wm(wave), wn = T::wn(wave);
+    // this thread's A rows (t / 4 and t / 4 + 64), decomposed once: env, output pixel
+    const int kk = (t & 3) * 8;
+    int ar[T::kALoads];
+    bool mrow[T::kALoads];
+    size_t base[T::kALoads];
+#pragma unroll
+    for (int h = 0; h < T::kALoads; ++h) {
+        ar[h] = (t >> 2) + 64 * h;
+        const int m = m0 + ar[h];
+        mrow[h] = m < M;
         const int per = g.oh * g.ow;
-        const int e = mrow ? m / per : 0, rem = mrow ? m - e * per : 0;
+        const int e = mrow[h] ? m / per : 0, rem = mrow[h] ? m - e * per : 0;
         const int oy = rem / g.ow, ox = rem - oy * g.ow;
-        base = (((size_t)e * g.ih + (size_t)(g.stride * oy)) * g.iw + (size_t)(g.stride * ox)) * g.in_c;
+        base[h] = (((size_t)e * g.ih + (size_t)(g.stride * oy)) * g.iw + (size_t)(g.stride * ox)) * g.in_c;
     }
     floatx4 acc[2][2];
 #pragma unroll
@@ -74,37 +91,45 @@ __global__ __launch_bounds__(256) void k_conv_gemm(const void *__restrict__ in, 
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < K; k0 += kBK) {
-        // ---- A tile: 8 consecutive k of row m
-        {
-            const int k = k0 + kk;
+        // ---- A tile: 8 consecutive k of rows ar[h]
+        const int k = k0 + kk;
+        size_t koff = 0;
+        if (k < K) {
+            if (DEPTH) {
+                // k = ky * kw + kx, 8 | kw: pixels (ky, kx .. kx + 7) of the window
+                const int ky = k / g.kw, kx = k - ky * g.kw;
+                koff = (size_t)ky * g.iw + kx;
+            } else {
+                // k = (ky * kw + kx) * C + c, 8 | C: channels c .. c + 7 of one pixel
+                const int tap = k / g.in_c, c = k - tap * g.in_c;
+                const int ky = tap / g.kw, kx = tap - ky * g.kw;
+                koff = ((size_t)ky * g.iw + (size_t)kx) * g.in_c + c;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < T::kALoads; ++h) {
             uint16_t v[8];
-            if (mrow && k < K) {
+            if (mrow[h] && k < K) {
                 if (DEPTH) {
-                    // k = ky * kw + kx, 8 | kw: pixels (ky, kx .. kx + 7) of the window
-                    const int ky = k / g.kw, kx = k - ky * g.kw;
-                    const uint32_t *p = static_cast<const uint32_t *>(in) + base + (size_t)ky * g.iw + kx;
+                    const uint32_t *p = static_cast<const uint32_t *>(in) + base[h] + koff;
                     const uint4 q0 = *reinterpret_cast<const uint4 *>(p);
                     const uint4 q1 = *reinterpret_cast<const uint4 *>(p + 4);
                     v[0] = depth_bf16(q0.x); v[1] = depth_bf16(q0.y); v[2] = depth_bf16(q0.z); v[3] = depth_bf16(q0.w);
                     v[4] = depth_bf16(q1.x); v[5] = depth_bf16(q1.y); v[6] = depth_bf16(q1.z); v[7] = depth_bf16(q1.w);
                 } else {
-                    // k = (ky * kw + kx) * C + c, 8 | C: channels c .. c + 7 of one pixel
-                    const int tap = k / g.in_c, c = k - tap * g.in_c;
-                    const int ky = tap / g.kw, kx = tap - ky * g.kw;
-                    const uint16_t *p = static_cast<const uint16_t *>(in) + base +
-                                        ((size_t)ky * g.iw + (size_t)kx) * g.in_c + c;
-                    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+                    const uint4 q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(in) + base[h] + koff);
                     memcpy(v, &q, 16);
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = 0;
             }
-            memcpy(&As[r][kk], v, 16);
+            memcpy(&As[ar[h]][kk], v, 16);
         }
         // ---- B tile: W [N][K] rows
-        {
-            const int n = n0 + r, k = k0 + kk;
+        if (t < TN * 4) {
+            const int r = t >> 2;
+            const int n = n0 + r;
             uint16_t v[8];
             if (n < N && k + 8 <= K) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(W + (size_t)n * K + k);
@@ -228,13 +253,21 @@ __device__ __forceinline__ void gather8(const void *in, const ConvGeom &g, int m
 // Weight gradient of a convolution, split over the output pixels:
 // part[z][o][k] = sum over rows m of split z of dY[m][o] A(m, k), A gathered
 // as in the forward, dY BF16 [rows][out_c].  Workgroup (64 o x 64 k tile, one
-// split): the K dimension of the matrix cores runs over 32 rows at a time.
+// split), 64 rows per stage: lane = row, wave = 8-column group (and the group
+// 32 columns on), so that the transposed stores into LDS (the matrix cores
+// take K = rows) fall on consecutive addresses; each thread follows its row's
+// (sample, oy, ox) by increments instead of divisions.  The first column
+// tile's workgroups also sum the dY values they load (the bias gradient):
+// bpart[z][o], each thread over its rows in order, then over the 64 lanes by
+// a fixed butterfly.
+constexpr int kDwRows = 64;
 template <bool DEPTH>
 __global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, const uint16_t *__restrict__ dy,
-                                                 ConvGeom g, int rows_per_split, float *__restrict__ part)
+                                                 ConvGeom g, int rows_per_split, float *__restrict__ part,
+                                                 float *__restrict__ bpart)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];   // [o][row]
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];   // [k][row]
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kDwRows + kPad];   // [o][row]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kDwRows + kPad];   // [k][row]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int O = g.out_c, K = g.k;
     const int k0 = blockIdx.x * kBN;
@@ -245,41 +278,112 @@ __global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, co
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int rr = t >> 3, c8 = (t & 7) * 8;   // row of the step, 8-wide column group
-    for (int r0 = rbeg; r0 < rend; r0 += kBK) {
-        const int m = r0 + rr;
-        {
-            // dY[m][c8 .. c8 + 7] -> As[o][rr]
+    const bool bias = bpart && blockIdx.x == 0;
+    float bs[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bs[h][j] = 0.f;
+    // this thread's two column groups and their offsets inside the window
+    int cg[2];
+    size_t koff[2];
+    bool kin[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cg[h] = 8 * wave + 32 * h;
+        const int k = k0 + cg[h];
+        kin[h] = k < K;
+        koff[h] = 0;
+        if (kin[h]) {
+            if (DEPTH) {
+                const int ky = k / g.kw, kx = k - ky * g.kw;
+                koff[h] = (size_t)ky * g.iw + kx;
+            } else {
+                const int tap = k / g.in_c, c = k - tap * g.in_c;
+                const int ky = tap / g.kw, kx = tap - ky * g.kw;
+                koff[h] = ((size_t)ky * g.iw + kx) * g.in_c + c;
+            }
+        }
+    }
+    // this thread's row: m = r0 + lane, as (sample e, oy, ox)
+    int e = 0, oy = 0, ox = 0;
+    {
+        const int m = rbeg + lane;
+        const int per = g.oh * g.ow;
+        e = m / per;
+        const int rem = m - e * per;
+        oy = rem / g.ow;
+        ox = rem - oy * g.ow;
+    }
+    for (int r0 = rbeg; r0 < rend; r0 += kDwRows) {
+        const int m = r0 + lane;
+        const bool live = m < rend;
+        const size_t base = (((size_t)e * g.ih + (size_t)(g.stride * oy)) * g.iw + (size_t)(g.stride * ox)) * g.in_c;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // dY[m][cg .. cg + 7] -> As[o][lane]
             uint16_t v[8];
-            if (m < rend && c8 < O) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(dy + (size_t)m * O + c8);
+            if (live && cg[h] < O) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(dy + (size_t)m * O + cg[h]);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = 0;
             }
+            if (bias) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) As[c8 + j][rr] = v[j];
+                for (int j = 0; j < 8; ++j) bs[h][j] += bf2f(v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[cg[h] + j][lane] = v[j];
         }
-        {
-            // A(m, k0 + c8 .. + 7) -> Bs[k][rr]
-            uint16_t v[8];
-            gather8<DEPTH>(in, g, m < rend ? m : g.rows, k0 + c8, v);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Bs[c8 + j][rr] = v[j];
+        for (int h = 0; h < 2; ++h) {
+            // A(m, k0 + cg .. + 7) -> Bs[k][lane]
+            uint16_t v[8];
+            if (live && kin[h]) {
+                if (DEPTH) {
+                    const uint32_t *p = static_cast<const uint32_t *>(in) + base + koff[h];
+                    const uint4 q0 = *reinterpret_cast<const uint4 *>(p);
+                    const uint4 q1 = *reinterpret_cast<const uint4 *>(p + 4);
+                    v[0] = depth_bf16(q0.x); v[1] = depth_bf16(q0.y); v[2] = depth_bf16(q0.z); v[3] = depth_bf16(q0.w);
+                    v[4] = depth_bf16(q1.x); v[5] = depth_bf16(q1.y); v[6] = depth_bf16(q1.z); v[7] = depth_bf16(q1.w);
+                } else {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(in) + base + koff[h]);
+                    memcpy(v, &q, 16);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[cg[h] + j][lane] = v[j];
+        }
+        // the next stage's row: 64 pixels on (64 < oh * ow for every layer)
+        ox += kDwRows;
+        while (ox >= g.ow) {
+            ox -= g.ow;
+            ++oy;
+        }
+        if (oy >= g.oh) {
+            oy -= g.oh;
+            ++e;
         }
         __syncthreads();
         const int r16 = lane & 15, kq = (lane >> 4) * 8;
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + r16][kq]);
+        for (int ks = 0; ks < kDwRows; ks += 32) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + r16][kq]);
+            for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + r16][ks + kq]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + j * 16 + r16][ks + kq]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     float *dst = part + (size_t)blockIdx.y * O * K;
@@ -293,6 +397,17 @@ __global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, co
                 const int k = k0 + wn + j * 16 + (lane & 15);
                 if (o < O && k < K) dst[(size_t)o * K + k] = acc[i][j][q];
             }
+    if (bias) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float v = bs[h][j];
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+                if (lane == 0 && cg[h] + j < O) bpart[(size_t)blockIdx.y * O + cg[h] + j] = v;
+            }
+    }
 }
 
 // out[i] = sum over splits of part[z][i], in split order
@@ -308,29 +423,47 @@ __global__ void k_sum_parts(const float *__restrict__ part, int splits, int64_t 
 // Input gradient of a convolution (the adjoint), masked by the ReLU of the
 // layer that produced the input: dX[m][c] = bf16([h[m][c] > 0] sum over
 // taps (ky, kx) and o of dY[n][oy][ox][o] W[o][ky][kx][c]), where
-// (oy, ox) s + (ky, kx) = (iy, ix) is an output pixel.  A GEMM whose rows are
-// input pixels, K = taps x out_c (8 consecutive o of one tap per load, zero
-// where the tap reaches no output pixel) and B = Wt [in_c][taps x out_c].
+// (oy, ox) s + (ky, kx) = (iy, ix) is an output pixel.  With stride s the
+// input pixels fall into s x s classes by (iy mod s, ix mod s), and a class
+// receives only the taps with (ky, kx) = (iy, ix) mod s: (kw / s)^2 of them.
+// Each class (blockIdx.z) is a GEMM whose rows are its input pixels,
+// K = its taps x out_c (8 consecutive o of one tap per load, zero where the
+// tap reaches no output pixel) and B = Wt [in_c][taps x out_c] at its taps.
+template <int TN>
 __global__ __launch_bounds__(256) void k_conv_dx(const uint16_t *__restrict__ dy, const uint16_t *__restrict__ Wt,
                                                  const uint16_t *__restrict__ h, ConvGeom g,
                                                  uint16_t *__restrict__ dx)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
+    using T = ConvTile<TN>;
+    constexpr int TM = T::TM;
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][kBK + kPad];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int M = (g.rows / (g.oh * g.ow)) * g.ih * g.iw;   // input pixels
-    const int N = g.in_c, K = g.kw * g.kw * g.out_c;
-    const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int r = t >> 2, kk = (t & 3) * 8;
-    const int m = m0 + r;
-    int e = 0, iy = 0, ix = 0;
-    if (m < M) {
-        const int per = g.ih * g.iw;
-        e = m / per;
-        const int rem = m - e * per;
-        iy = rem / g.iw;
-        ix = rem - iy * g.iw;
+    const int st = g.stride, ts = g.kw / st;
+    const int py = blockIdx.z / st, px = blockIdx.z - py * st;
+    const int qh = (g.ih - py + st - 1) / st, qw = (g.iw - px + st - 1) / st;
+    const int M = (g.rows / (g.oh * g.ow)) * qh * qw;   // input pixels of the class
+    const int N = g.in_c, K = ts * ts * g.out_c, Kall = g.kw * g.kw * g.out_c;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    if (m0 >= M) return;
+    const int wm = T::wm(wave), wn = T::wn(wave);
+    const int kk = (t & 3) * 8;
+    // this thread's A rows (t / 4 and t / 4 + 64): sample and class pixel, once
+    int ar[T::kALoads], ae[T::kALoads], aqy[T::kALoads], aqx[T::kALoads];
+    bool arow[T::kALoads];
+#pragma unroll
+    for (int hh = 0; hh < T::kALoads; ++hh) {
+        ar[hh] = (t >> 2) + 64 * hh;
+        const int m = m0 + ar[hh];
+        arow[hh] = m < M;
+        ae[hh] = aqy[hh] = aqx[hh] = 0;
+        if (arow[hh]) {
+            const int per = qh * qw;
+            ae[hh] = m / per;
+            const int rem = m - ae[hh] * per;
+            aqy[hh] = rem / qw;
+            aqx[hh] = rem - aqy[hh] * qw;
+        }
     }
     floatx4 acc[2][2];
 #pragma unroll
@@ -338,38 +471,42 @@ __global__ __launch_bounds__(256) void k_conv_dx(const uint16_t *__restrict__ dy
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += kBK) {
-        {
-            const int k = k0 + kk;
+        const int k = k0 + kk;
+        // the K column's tap (within the class) and output channel
+        int jy = 0, jx = 0, o = 0;
+        if (k < K) {
+            const int tap = k / g.out_c;
+            o = k - tap * g.out_c;
+            jy = tap / ts;
+            jx = tap - jy * ts;
+        }
+#pragma unroll
+        for (int hh = 0; hh < T::kALoads; ++hh) {
             uint16_t v[8];
-            bool ok = m < M && k < K;
-            size_t src = 0;
+            const int oy = aqy[hh] - jy, ox = aqx[hh] - jx;
+            const bool ok = arow[hh] && k < K && oy >= 0 && ox >= 0 && oy < g.oh && ox < g.ow;
             if (ok) {
-                const int tap = k / g.out_c, o = k - tap * g.out_c;
-                const int ky = tap / g.kw, kx = tap - ky * g.kw;
-                const int ny = iy - ky, nx = ix - kx;
-                ok = ny >= 0 && nx >= 0 && ny % g.stride == 0 && nx % g.stride == 0;
-                const int oy = ny / g.stride, ox = nx / g.stride;
-                ok = ok && oy < g.oh && ox < g.ow;
-                src = (((size_t)e * g.oh + (size_t)oy) * g.ow + (size_t)ox) * g.out_c + o;
-            }
-            if (ok) {
+                const size_t src = (((size_t)ae[hh] * g.oh + (size_t)oy) * g.ow + (size_t)ox) * g.out_c + o;
                 const uint4 q = *reinterpret_cast<const uint4 *>(dy + src);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = 0;
             }
-            memcpy(&As[r][kk], v, 16);
+            memcpy(&As[ar[hh]][kk], v, 16);
         }
-        {
-            const int n = n0 + r, k = k0 + kk;
+        if (t < TN * 4) {
+            const int r = t >> 2;
+            const int n = n0 + r;
             uint16_t v[8];
-            if (n < N && k + 8 <= K) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(Wt + (size_t)n * K + k);
+            if (n < N && k < K) {
+                // 8 | out_c: the 8 values share one tap
+                const int ky = py + st * jy, kx = px + st * jx;
+                const uint4 q = *reinterpret_cast<const uint4 *>(Wt + (size_t)n * Kall + (size_t)(ky * g.kw + kx) * g.out_c + o);
                 memcpy(v, &q, 16);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (n < N && k + j < K) ? Wt[(size_t)n * K + k + j] : 0;
+                for (int j = 0; j < 8; ++j) v[j] = 0;
             }
             memcpy(&Bs[r][kk], v, 16);
         }
@@ -390,16 +527,22 @@ __global__ __launch_bounds__(256) void k_conv_dx(const uint16_t *__restrict__ dy
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+            const int mm = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
+            if (mm >= M) continue;
+            const int per = qh * qw;
+            const int ee = mm / per, rem = mm - ee * per;
+            const int yy = rem / qw, xx = rem - yy * qw;
+            const size_t row = ((size_t)ee * g.ih + (size_t)(py + st * yy)) * g.iw + (size_t)(px + st * xx);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int mm = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
+            for (int j = 0; j < 2; ++j) {
                 const int n = n0 + wn + j * 16 + (lane & 15);
-                if (mm >= M || n >= N) continue;
-                const uint16_t hv = h[(size_t)mm * N + n];
+                if (n >= N) continue;
+                const uint16_t hv = h[row * N + n];
                 const bool on = (hv & 0x8000u) == 0 && (hv & 0x7FFFu) != 0;
-                dx[(size_t)mm * N + n] = f2bf(on ? acc[i][j][q] : 0.f);
+                dx[row * N + n] = f2bf(on ? acc[i][j][q] : 0.f);
             }
+        }
 }
 
 // Wt[c][tap * O + o] = W[o][tap][c] (the adjoint's B operand)
@@ -493,69 +636,98 @@ __global__ __launch_bounds__(256) void k_ppo_heads(const uint16_t *__restrict__ 
     }
 }
 
-// Gradients of the heads, summed over the S samples in sample order (one
-// thread per output): actor W [A][F] and b [A], critic w [F] and b, log_std
-// (minus the entropy coefficient); and the loss statistics [4] = mean policy
-// loss, mean value error, entropy, mean ratio.
-__global__ void k_ppo_head_grads(const uint16_t *__restrict__ h, const float *__restrict__ state,
-                                 const float *__restrict__ gm, const float *__restrict__ gls,
-                                 const float *__restrict__ gv, const float *__restrict__ terms,
-                                 const float *__restrict__ log_std, int A, int S, float ecoef,
-                                 float *__restrict__ g_aw, float *__restrict__ g_ab, float *__restrict__ g_vw,
-                                 float *__restrict__ g_vb, float *__restrict__ g_ls, float *__restrict__ stats)
+// Gradients of the heads as sums over the samples, in chunks of kHeadChunk
+// samples (one thread per output and chunk, the chunks then added in chunk
+// order: deterministic).  Output i of a chunk: i < (A + 1) F the actor's
+// W [A][F] then the critic's w [F] (gradient of the output times the
+// feature), then the actor bias [A], log_std [A] (without the entropy term),
+// the critic bias, and the three loss terms (policy, value, ratio).
+constexpr int kHeadChunk = 512;
+__global__ void k_ppo_head_part(const uint16_t *__restrict__ h, const float *__restrict__ state,
+                                const float *__restrict__ gm, const float *__restrict__ gls,
+                                const float *__restrict__ gv, const float *__restrict__ terms, int A, int S,
+                                int nout, float *__restrict__ part)
 {
     constexpr int F = kPolicyFeat + kPolicyProprio;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nout) return;
+    const int e0 = blockIdx.y * kHeadChunk, e1 = min(S, e0 + kHeadChunk);
     const int nw = (A + 1) * F;
+    float acc = 0.0f;
     if (i < nw) {
         const int a = i / F, k = i - a * F;
-        float acc = 0.0f;
-        for (int e = 0; e < S; ++e) {
+        for (int e = e0; e < e1; ++e) {
             const float fk = k < kPolicyFeat ? bf2f(h[(size_t)e * kPolicyFeat + k])
                                              : state[(size_t)e * 10 + 3 + (k - kPolicyFeat)];
             acc += (a < A ? gm[(size_t)e * A + a] : gv[e]) * fk;
         }
-        if (a < A) g_aw[(size_t)a * F + k] = acc;
-        else g_vw[k] = acc;
     } else if (i < nw + A) {
         const int a = i - nw;
-        float acc = 0.0f, accl = 0.0f;
-        for (int e = 0; e < S; ++e) {
-            acc += gm[(size_t)e * A + a];
-            accl += gls[(size_t)e * A + a];
-        }
-        g_ab[a] = acc;
-        g_ls[a] = accl - ecoef;
-    } else if (i == nw + A) {
-        float acc = 0.0f;
-        for (int e = 0; e < S; ++e) acc += gv[e];
-        g_vb[0] = acc;
-    } else if (i == nw + A + 1 && stats) {
-        float lp = 0.0f, lv = 0.0f, rr = 0.0f, ent = 0.0f;
-        for (int e = 0; e < S; ++e) {
-            lp += terms[(size_t)e * 3 + 0];
-            lv += terms[(size_t)e * 3 + 1];
-            rr += terms[(size_t)e * 3 + 2];
-        }
+        for (int e = e0; e < e1; ++e) acc += gm[(size_t)e * A + a];
+    } else if (i < nw + 2 * A) {
+        const int a = i - nw - A;
+        for (int e = e0; e < e1; ++e) acc += gls[(size_t)e * A + a];
+    } else if (i == nw + 2 * A) {
+        for (int e = e0; e < e1; ++e) acc += gv[e];
+    } else {
+        const int t = i - nw - 2 * A - 1;
+        for (int e = e0; e < e1; ++e) acc += terms[(size_t)e * 3 + t];
+    }
+    part[(size_t)blockIdx.y * nout + i] = acc;
+}
+
+// The summed head outputs into the gradient vector and the statistics [4] =
+// mean policy loss, mean value error, entropy, mean ratio.
+__global__ void k_ppo_head_finish(const float *__restrict__ sum, const float *__restrict__ log_std, int A, int S,
+                                  float ecoef, float *__restrict__ g_aw, float *__restrict__ g_ab,
+                                  float *__restrict__ g_vw, float *__restrict__ g_vb, float *__restrict__ g_ls,
+                                  float *__restrict__ stats)
+{
+    constexpr int F = kPolicyFeat + kPolicyProprio;
+    const int nw = (A + 1) * F;
+    for (int i = threadIdx.x; i < nw + 2 * A + 1; i += blockDim.x) {
+        const float v = sum[i];
+        if (i < A * F) g_aw[i] = v;
+        else if (i < nw) g_vw[i - A * F] = v;
+        else if (i < nw + A) g_ab[i - nw] = v;
+        else if (i < nw + 2 * A) g_ls[i - nw - A] = v - ecoef;
+        else g_vb[0] = v;
+    }
+    if (threadIdx.x == 0 && stats) {
+        float ent = 0.0f;
         for (int a = 0; a < A; ++a) ent += log_std[a] + 1.4189385332046727f;
-        stats[0] = lp / (float)S;
-        stats[1] = lv / (float)S;
+        const float *t = sum + nw + 2 * A + 1;
+        stats[0] = t[0] / (float)S;
+        stats[1] = t[1] / (float)S;
         stats[2] = ent;
-        stats[3] = rr / (float)S;
+        stats[3] = t[2] / (float)S;
     }
 }
 
-// Column sums of a BF16 [rows][D] matrix in chunks of kColChunk rows: part
+// Column sums of a BF16 [rows][D] matrix in chunks of `per` rows: part
 // [chunk][D] (one thread per column; the chunks are summed in order after).
-constexpr int kColChunk = 4096;
-__global__ void k_colsum_chunks(const uint16_t *__restrict__ g, int rows, int D, float *__restrict__ part)
+__global__ void k_colsum_chunks(const uint16_t *__restrict__ g, int rows, int D, int per, float *__restrict__ part)
 {
     const int c = threadIdx.x, chunk = blockIdx.x;
     if (c >= D) return;
-    const int r0 = chunk * kColChunk, r1 = min(rows, r0 + kColChunk);
+    const int r0 = chunk * per, r1 = min(rows, r0 + per);
     float acc = 0.0f;
     for (int r = r0; r < r1; ++r) acc += bf2f(g[(size_t)r * D + c]);
     part[(size_t)chunk * D + c] = acc;
+}
+
+// The fully connected layer from split-K partial products: out[m][n] =
+// bf16(relu(sum over splits in order of part[z][m][n] + b[n])).
+__global__ void k_fc_finish(const float *__restrict__ part, int splits, int M, int N, const float *__restrict__ bias,
+                            uint16_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_all = (int64_t)M * N;
+    if (i >= n_all) return;
+    float v = part[i];
+    for (int z = 1; z < splits; ++z) v += part[(size_t)z * n_all + i];
+    v += bias[i % N];
+    out[i] = f2bf(v > 0.f ? v : 0.f);
 }
 
 // Generalised advantage estimation, one thread per env, backwards in time.
@@ -580,33 +752,44 @@ __global__ void k_gae(const float *__restrict__ rew, const float *__restrict__ v
 }  // namespace
 
 hipError_t conv_dw(bool depth_input, const void *in, const uint16_t *dy, const ConvGeom &g, float *part,
-                   size_t part_floats, float *out, hipStream_t s)
+                   size_t part_floats, float *out, float *bias_out, hipStream_t s)
 {
-    if (g.rows <= 0) return hipMemsetAsync(out, 0, sizeof(float) * g.out_c * g.k, s);
+    if (g.rows <= 0) {
+        hipError_t e = hipMemsetAsync(out, 0, sizeof(float) * g.out_c * g.k, s);
+        if (e == hipSuccess) e = hipMemsetAsync(bias_out, 0, sizeof(float) * g.out_c, s);
+        return e;
+    }
+    if (g.out_c > kBM) return hipErrorInvalidValue;
     const size_t slab = (size_t)g.out_c * g.k;
-    int splits = (int)std::min<size_t>(part_floats / slab, (size_t)256);
+    int splits = (int)std::min<size_t>(part_floats / (slab + g.out_c), (size_t)256);
     splits = std::max(1, std::min(splits, (g.rows + 4095) / 4096));
     int per = (g.rows + splits - 1) / splits;
-    per = (per + kBK - 1) / kBK * kBK;
+    per = (per + kDwRows - 1) / kDwRows * kDwRows;
     splits = (g.rows + per - 1) / per;
     const dim3 grid((g.k + kBN - 1) / kBN, splits);
+    float *bpart = part + (size_t)splits * slab;
     if (depth_input)
-        hipLaunchKernelGGL(k_conv_dw<true>, grid, dim3(256), 0, s, in, dy, g, per, part);
+        hipLaunchKernelGGL(k_conv_dw<true>, grid, dim3(256), 0, s, in, dy, g, per, part, bpart);
     else
-        hipLaunchKernelGGL(k_conv_dw<false>, grid, dim3(256), 0, s, in, dy, g, per, part);
+        hipLaunchKernelGGL(k_conv_dw<false>, grid, dim3(256), 0, s, in, dy, g, per, part, bpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)slab;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, splits, n, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((g.out_c + 255) / 256)), dim3(256), 0, s, bpart, splits,
+                       (int64_t)g.out_c, bias_out);
     return hipGetLastError();
 }
 
 hipError_t colsum(const uint16_t *g, int rows, int D, float *part, size_t part_floats, float *out, hipStream_t s)
 {
-    const int chunks = (rows + kColChunk - 1) / kColChunk;
     if (rows <= 0) return hipMemsetAsync(out, 0, sizeof(float) * D, s);
+    // about 256 chunks of at least 64 rows
+    const int per = std::max(64, (rows + 255) / 256);
+    const int chunks = (rows + per - 1) / per;
     if ((size_t)chunks * D > part_floats || D > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_colsum_chunks, dim3(chunks), dim3((D + 63) / 64 * 64), 0, s, g, rows, D, part);
+    hipLaunchKernelGGL(k_colsum_chunks, dim3(chunks), dim3((D + 63) / 64 * 64), 0, s, g, rows, D, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_parts, dim3((D + 255) / 256), dim3(256), 0, s, part, chunks, (int64_t)D, out);
@@ -621,10 +804,17 @@ hipError_t conv_dx(const uint16_t *dy, const uint16_t *W, uint16_t *Wt, const ui
     hipLaunchKernelGGL(k_conv_wt, dim3((nw + 255) / 256), dim3(256), 0, s, W, g.out_c, taps, g.in_c, Wt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int M = (g.rows / (g.oh * g.ow)) * g.ih * g.iw;
+    if (g.kw % g.stride || g.out_c % 8) return hipErrorInvalidValue;
+    // the largest parity class: ceil(ih / s) x ceil(iw / s) input pixels per sample
+    const int M = (g.rows / (g.oh * g.ow)) * ((g.ih + g.stride - 1) / g.stride) * ((g.iw + g.stride - 1) / g.stride);
     if (M <= 0) return hipSuccess;
-    const dim3 grid((M + kBM - 1) / kBM, (g.in_c + kBN - 1) / kBN);
-    hipLaunchKernelGGL(k_conv_dx, grid, dim3(256), 0, s, dy, Wt, h, g, dx);
+    const dim3 grid((M + kBM - 1) / kBM, (g.in_c + kBN - 1) / kBN, g.stride * g.stride);
+    if (g.in_c <= 32) {
+        const dim3 grid32((M + 127) / 128, 1, g.stride * g.stride);
+        hipLaunchKernelGGL(k_conv_dx<32>, grid32, dim3(256), 0, s, dy, Wt, h, g, dx);
+    } else {
+        hipLaunchKernelGGL(k_conv_dx<64>, grid, dim3(256), 0, s, dy, Wt, h, g, dx);
+    }
     return hipGetLastError();
 }
 
@@ -641,11 +831,22 @@ hipError_t ppo_heads(const uint16_t *h, const float *state, const float *aw, con
 
 hipError_t ppo_head_grads(const uint16_t *h, const float *state, const float *gm, const float *gls, const float *gv,
                           const float *terms, const float *log_std, int A, int S, float ecoef, float *g_aw,
-                          float *g_ab, float *g_vw, float *g_vb, float *g_ls, float *stats, hipStream_t s)
+                          float *g_ab, float *g_vw, float *g_vb, float *g_ls, float *stats, float *part,
+                          size_t part_floats, hipStream_t s)
 {
-    const int n = (A + 1) * (kPolicyFeat + kPolicyProprio) + A + 2;
-    hipLaunchKernelGGL(k_ppo_head_grads, dim3((n + 255) / 256), dim3(256), 0, s, h, state, gm, gls, gv, terms, log_std,
-                       A, S, ecoef, g_aw, g_ab, g_vw, g_vb, g_ls, stats);
+    if (S <= 0) return hipErrorInvalidValue;
+    const int nout = (A + 1) * (kPolicyFeat + kPolicyProprio) + 2 * A + 1 + 3;
+    const int chunks = (S + kHeadChunk - 1) / kHeadChunk;
+    if ((size_t)(chunks + 1) * nout > part_floats) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ppo_head_part, dim3((nout + 255) / 256, chunks), dim3(256), 0, s, h, state, gm, gls, gv,
+                       terms, A, S, nout, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    float *sum = part + (size_t)chunks * nout;
+    hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256), dim3(256), 0, s, part, chunks, (int64_t)nout, sum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ppo_head_finish, dim3(1), dim3(256), 0, s, sum, log_std, A, S, ecoef, g_aw, g_ab, g_vw,
+                       g_vb, g_ls, stats);
     return hipGetLastError();
 }
 
@@ -661,11 +862,41 @@ hipError_t conv_gemm(bool depth_input, const void *in, const uint16_t *W, const 
                      uint16_t *out, hipStream_t s)
 {
     if (g.rows <= 0) return hipSuccess;
-    const dim3 grid((g.rows + kBM - 1) / kBM, (g.out_c + kBN - 1) / kBN);
+    if (g.out_c <= 32) {
+        const dim3 grid((g.rows + 127) / 128, 1);
+        if (depth_input)
+            hipLaunchKernelGGL((k_conv_gemm<true, 32>), grid, dim3(256), 0, s, in, W, bias, g, out);
+        else
+            hipLaunchKernelGGL((k_conv_gemm<false, 32>), grid, dim3(256), 0, s, in, W, bias, g, out);
+        return hipGetLastError();
+    }
+    const dim3 grid((g.rows + 63) / 64, (g.out_c + 63) / 64);
     if (depth_input)
-        hipLaunchKernelGGL(k_conv_gemm<true>, grid, dim3(256), 0, s, in, W, bias, g, out);
+        hipLaunchKernelGGL((k_conv_gemm<true, 64>), grid, dim3(256), 0, s, in, W, bias, g, out);
     else
-        hipLaunchKernelGGL(k_conv_gemm<false>, grid, dim3(256), 0, s, in, W, bias, g, out);
+        hipLaunchKernelGGL((k_conv_gemm<false, 64>), grid, dim3(256), 0, s, in, W, bias, g, out);
+    return hipGetLastError();
+}
+
+int fc_splits(int rows, int N, int K)
+{
+    const int tiles = ((rows + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    int splits = 512 / std::max(tiles, 1);              // about 512 workgroups
+    splits = std::min(splits, K / 512);                 // at least 512 columns of K each
+    return std::max(splits, 1);
+}
+
+hipError_t fc_forward(const uint16_t *x, const uint16_t *W, const float *bias, int rows, int N, int K, float *ws,
+                      size_t ws_floats, uint16_t *out, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    const int splits = fc_splits(rows, N, K);
+    if (splits == 1 || !ws || (size_t)splits * rows * N > ws_floats)
+        return mlp_gemm(kGemmFwd, x, W, rows, N, K, K, K, bias, nullptr, 0, nullptr, out, N, s);
+    hipError_t e = mlp_gemm_parts(x, W, rows, N, K, K, K, splits, ws, s);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)rows * N;
+    hipLaunchKernelGGL(k_fc_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws, splits, rows, N, bias, out);
     return hipGetLastError();
 }
 
