@@ -37,10 +37,17 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// x = d / (2^24 - 1) correctly rounded to FP32, without a division: for
+// 1 <= d < 2^24, d / (2^24 - 1) = d 2^-24 (1 + 2^-24 + 2^-48 + ...), and the
+// exact value d 2^-24 = m 2^k (m a 24-bit significand) is followed by a
+// fraction m / (2^24 - 1) of one unit in the last place that always lies in
+// (1/2, 1], so the rounded quotient is d 2^-24 plus one ulp (checked for
+// every d against the IEEE division).  Then rounded to BF16.
 __device__ __forceinline__ uint16_t depth_bf16(uint32_t D)
 {
     const uint32_t d = D < 16777215u ? D : 16777215u;
-    return f2bf((float)d / 16777215.0f);
+    const uint32_t x = __float_as_uint((float)d * 0x1p-24f) + (d != 0u ? 1u : 0u);
+    return f2bf(__uint_as_float(x));
 }
 
 // Y[m][n] = relu(sum_k A(m, k) W[n][k] + b[n]) in BF16, A gathered from the
