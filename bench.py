@@ -30,13 +30,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Tuning keys that change what the raster kernel reads and writes (the others
-# only change how the same pixels are rasterised, or other kernels).
-TRAFFIC_KEYS = ("region", "occlusion", "prologue", "refresh", "persistent", "split", "bin")
+# Tuning keys a counter record must match: every raster setting that changes
+# what the kernel reads and writes or how its pixels are spread over lanes and
+# waves (the queue order changes neither bytes nor instructions).
+TRAFFIC_KEYS = ("block", "region", "lane_max", "small_max", "occlusion", "prologue", "refresh", "persistent",
+                "split", "bin")
 TUNING_DEFAULTS = {"bin": 0}   # settings that older records leave out
-# the instruction count also depends on how pixels are spread over lanes and
-# waves (the queue order changes neither bytes nor instructions)
-VALU_KEYS = TRAFFIC_KEYS + ("block", "lane_max", "small_max")
+VALU_KEYS = TRAFFIC_KEYS
 
 
 def counter_record(kernel_sources, record, tuning, field, keys=None):
