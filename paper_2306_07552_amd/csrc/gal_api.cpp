@@ -505,7 +505,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     for (int block : {256, 512, 1024})
         for (int region : regions)
             for (int lane_max : {4, 8, 16})
-                for (int small_max : {256, 1024, 4096})
+                for (int small_max : {256, 1024})
                     for (int occl : {0, 1})   // 1: one refresh after a 128-cluster prologue
                         for (int persist : {0, 1})
                             for (int rl : {32, 64}) {
