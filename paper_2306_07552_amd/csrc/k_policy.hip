@@ -322,49 +322,27 @@ __global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, co
         oy = rem / g.ow;
         ox = rem - oy * g.ow;
     }
-    for (int r0 = rbeg; r0 < rend; r0 += kDwRows) {
+    // Raw global data of one stage, loaded a stage ahead: the next stage's
+    // loads are in flight during this stage's MFMAs.
+    uint4 qy[2], qa[2][2];
+    auto fetch = [&](int r0) {
         const int m = r0 + lane;
         const bool live = m < rend;
         const size_t base = (((size_t)e * g.ih + (size_t)(g.stride * oy)) * g.iw + (size_t)(g.stride * ox)) * g.in_c;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            // dY[m][cg .. cg + 7] -> As[o][lane]
-            uint16_t v[8];
-            if (live && cg[h] < O) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(dy + (size_t)m * O + cg[h]);
-                memcpy(v, &q, 16);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = 0;
-            }
-            if (bias) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) bs[h][j] += bf2f(v[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) As[cg[h] + j][lane] = v[j];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // A(m, k0 + cg .. + 7) -> Bs[k][lane]
-            uint16_t v[8];
+            qy[h] = make_uint4(0u, 0u, 0u, 0u);
+            qa[h][0] = qa[h][1] = make_uint4(0u, 0u, 0u, 0u);
+            if (live && cg[h] < O) qy[h] = *reinterpret_cast<const uint4 *>(dy + (size_t)m * O + cg[h]);
             if (live && kin[h]) {
                 if (DEPTH) {
                     const uint32_t *p = static_cast<const uint32_t *>(in) + base + koff[h];
-                    const uint4 q0 = *reinterpret_cast<const uint4 *>(p);
-                    const uint4 q1 = *reinterpret_cast<const uint4 *>(p + 4);
-                    v[0] = depth_bf16(q0.x); v[1] = depth_bf16(q0.y); v[2] = depth_bf16(q0.z); v[3] = depth_bf16(q0.w);
-                    v[4] = depth_bf16(q1.x); v[5] = depth_bf16(q1.y); v[6] = depth_bf16(q1.z); v[7] = depth_bf16(q1.w);
+                    qa[h][0] = *reinterpret_cast<const uint4 *>(p);
+                    qa[h][1] = *reinterpret_cast<const uint4 *>(p + 4);
                 } else {
-                    const uint4 q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(in) + base + koff[h]);
-                    memcpy(v, &q, 16);
+                    qa[h][0] = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(in) + base + koff[h]);
                 }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = 0;
             }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) Bs[cg[h] + j][lane] = v[j];
         }
         // the next stage's row: 64 pixels on (64 < oh * ow for every layer)
         ox += kDwRows;
@@ -376,7 +354,37 @@ __global__ __launch_bounds__(256) void k_conv_dw(const void *__restrict__ in, co
             oy -= g.oh;
             ++e;
         }
+    };
+    if (rbeg < rend) fetch(rbeg);
+    for (int r0 = rbeg; r0 < rend; r0 += kDwRows) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // dY[m][cg .. cg + 7] -> As[o][lane]
+            uint16_t v[8];
+            memcpy(v, &qy[h], 16);
+            if (bias) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bs[h][j] += bf2f(v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[cg[h] + j][lane] = v[j];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // A(m, k0 + cg .. + 7) -> Bs[k][lane]
+            uint16_t v[8];
+            if (DEPTH) {
+                const uint4 q0 = qa[h][0], q1 = qa[h][1];
+                v[0] = depth_bf16(q0.x); v[1] = depth_bf16(q0.y); v[2] = depth_bf16(q0.z); v[3] = depth_bf16(q0.w);
+                v[4] = depth_bf16(q1.x); v[5] = depth_bf16(q1.y); v[6] = depth_bf16(q1.z); v[7] = depth_bf16(q1.w);
+            } else {
+                memcpy(v, &qa[h][0], 16);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[cg[h] + j][lane] = v[j];
+        }
         __syncthreads();
+        if (r0 + kDwRows < rend) fetch(r0 + kDwRows);
         const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
         for (int ks = 0; ks < kDwRows; ks += 32) {
