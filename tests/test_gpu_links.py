@@ -70,8 +70,8 @@ def test_links_parity(torch_cuda, color):
 
 def test_links_tunings_graph(torch_cuda):
     """Links under the persistent queue with split items, measured order and
-    graph replay, and under one workgroup per item with 64^2 regions: the same
-    bits as the oracle."""
+    graph replay, under one workgroup per item with 64^2 regions, and with the
+    8x8-tile binned raster: the same bits as the oracle."""
     torch = torch_cuda
     print("case: links tunings + graph", flush=True)
     cfg = sg.scaled_config(1, 12)
@@ -79,7 +79,9 @@ def test_links_tunings_graph(torch_cuda):
     out = b.alloc_outputs()
     act = torch.empty((12, 9), dtype=torch.float32, device="cuda")
     tunings = [dict(persistent=1, split=4, order=1, graph=1, region=128),
-               dict(persistent=0, split=0, order=0, graph=0, region=64, lane_max=0)]
+               dict(persistent=0, split=0, order=0, graph=0, region=64, lane_max=0),
+               # the 8x8-tile binned raster (links are drawn directly, the scene binned)
+               dict(persistent=1, split=0, order=1, graph=1, region=128, lane_max=4, bin=1)]
     k = 0
     for t in tunings:
         b.set_tuning(**t)

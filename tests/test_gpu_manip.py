@@ -118,7 +118,8 @@ def test_manip_scripted_grasp_carry_release(torch_cuda, color):
 def test_manip_state_roundtrip_and_graph(torch_cuda):
     """Mid-episode (objects held): the state round-trips through
     gal_get_state / gal_set_state, and the persistent queue replayed as a
-    graph gives the same bits as the oracle from there on."""
+    graph gives the same bits as the oracle from there on (the last ten steps
+    with the 8x8-tile binned raster)."""
     torch = torch_cuda
     print("case: manip state round trip + graph", flush=True)
     from oracle import oracle as O
@@ -147,6 +148,8 @@ def test_manip_state_roundtrip_and_graph(torch_cuda):
     b.set_tuning(persistent=1, order=1, graph=1)
     act = torch.empty((n, 11), dtype=torch.float32, device="cuda")
     for k in range(8, 30):
+        if k == 20:
+            b.set_tuning(bin=1)   # the 8x8-tile binned raster from here on
         a = fn(k)
         act.copy_(torch.from_numpy(a))
         b.step(act, out)

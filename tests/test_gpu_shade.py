@@ -32,15 +32,17 @@ def shade_pair(cfg, links=True):
     return b, ob
 
 
-@pytest.mark.parametrize("region", [128, 64])
-def test_shade_parity_scenes_and_links(torch_cuda, region):
+@pytest.mark.parametrize("region,bin_", [(128, 0), (64, 0), (64, 1)])
+def test_shade_parity_scenes_and_links(torch_cuda, region, bin_):
     """8 paper-scale scenes at 128x128 with links: lit, textured colour
-    bit-exact, with both checker shades and lit and unlit faces present."""
+    bit-exact, with both checker shades and lit and unlit faces present
+    (also with the 8x8-tile binned raster, which with colour fits LDS at
+    64^2 regions)."""
     torch = torch_cuda
-    print(f"case: shade parity region={region}", flush=True)
+    print(f"case: shade parity region={region} bin={bin_}", flush=True)
     cfg = sg.scaled_config(1, 8)
     b, ob = shade_pair(cfg)
-    b.set_tuning(region=region, persistent=1 if region == 128 else 0)
+    b.set_tuning(region=region, persistent=1 if region == 128 else 0, bin=bin_)
     out = b.alloc_outputs()
     for k in range(6):
         a = sg.actions(cfg, k) * 3.0
