@@ -1231,7 +1231,13 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     oc.BW = (R + 31) >> 5;
     oc.P = c.P;
 
-    for (int i = threadIdx.x; i < R * c.P; i += kBlock) zb.clear(i);
+    if constexpr (kColor) {
+        for (int i = threadIdx.x; i < R * c.P; i += kBlock) zb.clear(i);
+    } else {
+        // 16-byte stores (R P is a multiple of 4 words, the buffer 16-byte aligned)
+        uint4 *z4 = reinterpret_cast<uint4 *>(zdyn);
+        for (int i = threadIdx.x; i < (R * c.P) >> 2; i += kBlock) z4[i] = make_uint4(kFar, kFar, kFar, kFar);
+    }
     for (int i = threadIdx.x; i < oc.TW * oc.TW; i += kBlock) tilemax[i] = kFar;
     for (int i = threadIdx.x; i < oc.BW * oc.BW; i += kBlock) blockmax[i] = kFar;
 
@@ -1442,7 +1448,22 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     __syncthreads();
     const uint64_t doff = env_depth_off[env];
     uint32_t *dst = depth + doff;
-    for (int i = threadIdx.x; i < R * R; i += kBlock) {
+    if constexpr (!kColor) {
+        // depth only: four pixels of a row per thread, one 16-byte LDS read and
+        // one 16-byte store each (R, the pitch and res are multiples of 8, the
+        // region origin a multiple of R); a thread keeps its column
+        const int tw = R >> 2;
+        const int rows_per_pass = kBlock / tw;
+        const int x = ((int)threadIdx.x % tw) * 4;
+        const uint32_t *z = reinterpret_cast<const uint32_t *>(zdyn);
+        if ((int)threadIdx.x < rows_per_pass * tw) {
+            for (int y = (int)threadIdx.x / tw; y < R; y += rows_per_pass) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(z + y * c.P + x);
+                *reinterpret_cast<uint4 *>(dst + (size_t)(c.ry0 + y) * res + (c.rx0 + x)) = v;
+            }
+        }
+    }
+    for (int i = threadIdx.x; kColor && i < R * R; i += kBlock) {
         const int y = i / R, x = i - y * R;
         const size_t o = (size_t)(c.ry0 + y) * res + (c.rx0 + x);
         const int zi = y * c.P + x;
