@@ -650,13 +650,36 @@ template <class Sink>
 __device__ __forceinline__ void refresh_bounds(const Sink &zb, const Occl &oc, int R,
                                                int wave, int nwaves, int lane)
 {
-    const int lx = lane & 7, ly = lane >> 3;
-    for (int t = wave; t < oc.TW * oc.TW; t += nwaves) {
-        const int tx = t % oc.TW, ty = t / oc.TW;
-        const int px = tx * 8 + lx, py = ty * 8 + ly;
-        const int v = (px < R && py < R) ? (int)zb.depth_at(py * oc.P + px) : 0;
-        const int m = wave_max(v);
-        if (lane == 0) oc.tilemax[t] = (uint32_t)m;
+    if constexpr (std::is_same<Sink, DepthSink>::value) {
+        // four tiles per wave and pass: a row of 16 lanes per tile, each lane
+        // four pixels of one tile row (one 16-byte LDS read; R, the pitch and
+        // the tile origins are multiples of 8), the row maximum by DPP
+        constexpr int kMin = -2147483647 - 1;
+        const int q = lane >> 4, row = (lane >> 1) & 7, half = lane & 1;
+        const int ntile = oc.TW * oc.TW;
+        for (int t0 = wave * 4; t0 < ntile; t0 += nwaves * 4) {
+            const int t = t0 + q;
+            int v = 0;
+            if (t < ntile) {
+                const int tx = t % oc.TW, ty = t / oc.TW;
+                const uint4 w = *reinterpret_cast<const uint4 *>(zb.z + (8 * ty + row) * oc.P + 8 * tx + 4 * half);
+                v = (int)max(max(w.x, w.y), max(w.z, w.w));
+            }
+            v = max(v, dpp_shift<0x111>(v, kMin));
+            v = max(v, dpp_shift<0x112>(v, kMin));
+            v = max(v, dpp_shift<0x114>(v, kMin));
+            v = max(v, dpp_shift<0x118>(v, kMin));
+            if ((lane & 15) == 15 && t < ntile) oc.tilemax[t] = (uint32_t)v;
+        }
+    } else {
+        const int lx = lane & 7, ly = lane >> 3;
+        for (int t = wave; t < oc.TW * oc.TW; t += nwaves) {
+            const int tx = t % oc.TW, ty = t / oc.TW;
+            const int px = tx * 8 + lx, py = ty * 8 + ly;
+            const int v = (px < R && py < R) ? (int)zb.depth_at(py * oc.P + px) : 0;
+            const int m = wave_max(v);
+            if (lane == 0) oc.tilemax[t] = (uint32_t)m;
+        }
     }
     __syncthreads();
     for (int b = wave; b < oc.BW * oc.BW; b += nwaves) {
