@@ -1188,6 +1188,7 @@ struct ItemShared {
     uint16_t vis[kVisCap];
     int wave_cnt[kBlock / 64];
     int own[kBlock];   // 64 words per wave, balanced raster
+    RegionPlanes rplanes;   // the item's region frustum in world space
     uint32_t planefront[kMaxPlanes / 32];   // camera strictly in front of face plane p
     BigRec big[kBigCap];
     int big_gofs[kBigCap + 1];
@@ -1281,8 +1282,11 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     c.kr = ((float)(c.rx0 + R) - c.pj.hw) / c.pj.hw;
     c.kt = ((float)c.ry0 - c.pj.hw) / c.pj.hw;
     c.kb = ((float)(c.ry0 + R) - c.pj.hw) / c.pj.hw;
-    RegionPlanes P;
-    {
+    // the region's frustum planes, the same for every thread: kept in LDS (the
+    // compaction passes read them; registers are the persistent kernel's
+    // scarce resource)
+    RegionPlanes &P = sh.rplanes;
+    if (threadIdx.x == 0) {
         // camera-space plane  a*X + b*Y + c*Z + e >= 0  ->  world normal, offset
         const float pa[5][4] = {{0.f, 0.f, 1.f, -c.pj.near_m},
                                 {1.f, 0.f, -c.kl, 0.f},
