@@ -1187,6 +1187,7 @@ struct ItemShared {
     uint32_t blockmax[(kMaxRegion / 32) * (kMaxRegion / 32)];
     uint16_t vis[kVisCap];
     int wave_cnt[kBlock / 64];
+    int wave_cnt2[2][kBlock / 64];   // per wave, the two halves of a frustum compaction pass
     int own[kBlock];   // 64 words per wave, balanced raster
     RegionPlanes rplanes;   // the item's region frustum in world space
     uint32_t planefront[kMaxPlanes / 32];   // camera strictly in front of face plane p
@@ -1357,31 +1358,46 @@ __device__ __forceinline__ void raster_item(const RenderMesh &m, const RasterPar
     for (uint64_t wbase = c0; wbase < c1; wbase += kVisCap) {
         const int wn = (int)min((uint64_t)kVisCap, c1 - wbase);
         // ---- ordered compaction of the frustum-visible clusters
+        // (two clusters per thread and pass, k and k + kBlock: both records in
+        // flight together, one pair of barriers per 2 kBlock clusters)
         int vis_total = 0;
-        for (int off = 0; off < wn; off += kBlock) {
-            const int k = off + (int)threadIdx.x;
-            bool fr = false;
-            if (k < wn) {
-                const uint64_t ci = wbase + k;
-                const float4 w0 = m.clusters[ci * 3 + 0];
-                const float4 w1 = m.clusters[ci * 3 + 1];
-                const uint4 w2 = *reinterpret_cast<const uint4 *>(&m.clusters[ci * 3 + 2]);
-                fr = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z) &&
-                     any_plane_front(sh.planefront, w2.z, w2.w);
+        for (int off = 0; off < wn; off += 2 * kBlock) {
+            bool fr[2];
+            uint64_t bm[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = off + h * kBlock + (int)threadIdx.x;
+                fr[h] = false;
+                if (k < wn) {
+                    const uint64_t ci = wbase + k;
+                    const float4 w0 = m.clusters[ci * 3 + 0];
+                    const float4 w1 = m.clusters[ci * 3 + 1];
+                    const uint4 w2 = *reinterpret_cast<const uint4 *>(&m.clusters[ci * 3 + 2]);
+                    fr[h] = aabb_visible(P, w0.x, w0.y, w0.z, w1.x, w1.y, w1.z) &&
+                            any_plane_front(sh.planefront, w2.z, w2.w);
+                }
             }
-            const uint64_t bm = __ballot(fr);
-            if (lane == 0) wave_cnt[wave] = __popcll(bm);
-            __syncthreads();
-            int before = vis_total;
-            for (int w = 0; w < wave; ++w) before += wave_cnt[w];
-            int all = vis_total;
-            for (int w = 0; w < kWaves; ++w) all += wave_cnt[w];
-            if (fr) {
-                const int rank = __popcll(bm & ((1ull << lane) - 1ull));
-                vis[before + rank] = (uint16_t)k;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                bm[h] = __ballot(fr[h]);
+                if (lane == 0) sh.wave_cnt2[h][wave] = __popcll(bm[h]);
             }
             __syncthreads();
-            vis_total = all;
+            int before0 = vis_total, all0 = vis_total;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) before0 += sh.wave_cnt2[0][w];
+                all0 += sh.wave_cnt2[0][w];
+            }
+            int before1 = all0, all1 = all0;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) before1 += sh.wave_cnt2[1][w];
+                all1 += sh.wave_cnt2[1][w];
+            }
+            const uint64_t below = (1ull << lane) - 1ull;
+            if (fr[0]) vis[before0 + __popcll(bm[0] & below)] = (uint16_t)(off + (int)threadIdx.x);
+            if (fr[1]) vis[before1 + __popcll(bm[1] & below)] = (uint16_t)(off + kBlock + (int)threadIdx.x);
+            __syncthreads();
+            vis_total = all1;
         }
         if (stats) {
             if (threadIdx.x == 0) {
