@@ -323,10 +323,15 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             (lane = pixel) when the list buffer fills; 0 = they are drawn
  *             by the wave that set them up.  The z-buffer and the bins must
  *             fit one CU's 160 KB of LDS (with colour: region <= 64)
+ *  layer_cache 1 = each sphere's column-grid query starts at the layer where
+ *             its previous query found free space (Appendix G's layer
+ *             cache: a per (env, sphere) offset into the column's layer
+ *             list, kept on the device), 0 = at the column's first layer;
+ *             the contacts are the same either way.  Not with GAL_MANIP
  * A new batch starts with block 512, region 128 (or the resolution, if
  * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
  * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0,
- * objgrid 1 with 16 or more objects per env (else 0), bin 0.
+ * objgrid 1 with 16 or more objects per env (else 0), bin 0, layer_cache 0.
  */
 typedef struct gal_tuning {
     int32_t block;
@@ -343,6 +348,7 @@ typedef struct gal_tuning {
     int32_t order;
     int32_t objgrid;
     int32_t bin;
+    int32_t layer_cache;
 } gal_tuning;
 
 /* Read / replace the launch configuration above (Section 3.1 batching

@@ -243,6 +243,7 @@ struct gal_batch {
     float sur_thr_logit = 0.0f;
     uint32_t sur_audit = 16;
     uint8_t *d_flags = nullptr;             // [N] routing
+    uint8_t *d_layer_hint = nullptr;        // [N][S] column-layer cache (allocated when first enabled)
     unsigned long long *d_sur_stats = nullptr;
     uint8_t *d_occ = nullptr;               // occupancy lattice (built on first use)
     uint64_t *d_occ_off = nullptr;
@@ -391,6 +392,7 @@ int gal_get_tuning(const gal_batch *b, gal_tuning *t)
     t->order = b->rast.order;
     t->objgrid = b->rp.objgrid;
     t->bin = b->rast.bin;
+    t->layer_cache = b->sb.layer_hint != nullptr ? 1 : 0;
     return GAL_OK;
 }
 
@@ -413,6 +415,13 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     if (t->order != 0 && t->order != 1) return fail(GAL_EINVAL, "order must be 0 or 1");
     if (t->objgrid != 0 && t->objgrid != 1) return fail(GAL_EINVAL, "objgrid must be 0 or 1");
     if (t->bin != 0 && t->bin != 1) return fail(GAL_EINVAL, "bin must be 0 or 1");
+    if (t->layer_cache != 0 && t->layer_cache != 1) return fail(GAL_EINVAL, "layer_cache must be 0 or 1");
+    if (t->layer_cache && b->rp.manip) return fail(GAL_EINVAL, "the layer cache serves the plain robot step, not GAL_MANIP");
+    if (t->layer_cache && !b->d_layer_hint) {
+        int rc = b->mem.alloc(&b->d_layer_hint, (size_t)b->N * (size_t)b->S);
+        if (rc) return rc;
+        HIP_TRY(hipMemset(b->d_layer_hint, 0, (size_t)b->N * (size_t)b->S));
+    }
     {
         gal::RasterParams probe = b->rast;
         probe.block = t->block;
@@ -437,6 +446,7 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t)
     b->rast.order = t->order;
     b->rp.objgrid = t->objgrid;
     b->rast.bin = t->bin;
+    b->sb.layer_hint = t->layer_cache ? b->d_layer_hint : nullptr;
     b->tune_gen += 1;
     b->persist_grid = gal::raster_persistent_grid(b->rast, b->max_res, (b->flags & GAL_COLOR) != 0);
     if (b->persist_grid <= 0) return fail(GAL_EDEVICE, "occupancy query for the persistent raster kernel failed");

@@ -107,6 +107,10 @@ struct SimBuffers {
     // the resting objects' regular grids (null: every object is tested)
     const ObjGridMeta *objgrid_meta; // [N]
     unsigned long long *objgrid_mask;// per env 4 x ny x nx words
+    // column-layer cache (Appendix G; null = off): per (env, sphere) the
+    // offset, within its column's layer list, of the free layer the sphere's
+    // last grid query found; the next query starts there
+    uint8_t *layer_hint;             // [N][S]
 };
 
 // Step outputs (device, caller-owned).

@@ -49,14 +49,17 @@ __device__ __forceinline__ Frame pick(const Fk &fk, int link)
 
 // Column-grid test of one sphere centre, split into stages so that the
 // dependent loads of several spheres are in flight together: the column's
-// layer range, then its first two layers, then (rarely) the rest.  Contact
+// layer range, then two of its layers, then (rarely) the rest.  Contact
 // when the centre is outside the grid or inside no free layer [lo, hi]
-// (touching a layer bound counts as free).
+// (touching a layer bound counts as free).  The two layers loaded first are
+// the column's first two, or, with the layer cache, the one at the sphere's
+// cached offset and the next: which layers are read first changes no result.
 struct GridProbe {
     bool outside;
     uint32_t l0, l1;
+    uint32_t s0;   // first of the two layers loaded up front
     float z;
-    float2 a, b;   // layers l0 and l0 + 1 when present
+    float2 a, b;   // layers s0 and s0 + 1 when present
 };
 
 __device__ __forceinline__ void grid_probe_column(const SimBuffers &sb, const GridMeta &gm,
@@ -64,7 +67,7 @@ __device__ __forceinline__ void grid_probe_column(const SimBuffers &sb, const Gr
                                                   GridProbe &g)
 {
     g.z = z;
-    g.l0 = g.l1 = 0;
+    g.l0 = g.l1 = g.s0 = 0;
     const float fx = (x - gm.x0) * sb.inv_cell;
     const float fy = (y - gm.y0) * sb.inv_cell;
     g.outside = !(fx >= 0.0f && fx < (float)gm.nx) || !(fy >= 0.0f && fy < (float)gm.ny);
@@ -76,26 +79,48 @@ __device__ __forceinline__ void grid_probe_column(const SimBuffers &sb, const Gr
     g.l1 = off[1];
 }
 
-__device__ __forceinline__ void grid_probe_layers(const SimBuffers &sb, uint64_t layer_base, GridProbe &g)
+// hint: the layer cache's offset for this sphere (0 without the cache)
+__device__ __forceinline__ void grid_probe_layers(const SimBuffers &sb, uint64_t layer_base, GridProbe &g,
+                                                  uint32_t hint = 0)
 {
     const float2 *lay = sb.grid_layers + layer_base;
-    if (g.l0 < g.l1) g.a = lay[g.l0];
-    if (g.l0 + 1 < g.l1) g.b = lay[g.l0 + 1];
+    g.s0 = g.l0 + hint < g.l1 ? g.l0 + hint : g.l0;
+    if (g.s0 < g.l1) g.a = lay[g.s0];
+    if (g.s0 + 1 < g.l1) g.b = lay[g.s0 + 1];
+}
+
+// found: the index of the free layer holding the centre (l1 if none)
+__device__ __forceinline__ bool grid_probe_contact(const SimBuffers &sb, uint64_t layer_base,
+                                                   const GridProbe &g, uint32_t &found)
+{
+    found = g.l1;
+    if (g.outside) return true;
+    const float z = g.z;
+    if (g.s0 < g.l1 && g.a.x <= z && z <= g.a.y) {
+        found = g.s0;
+        return false;
+    }
+    if (g.s0 + 1 < g.l1 && g.b.x <= z && z <= g.b.y) {
+        found = g.s0 + 1;
+        return false;
+    }
+    const float2 *lay = sb.grid_layers + layer_base;
+    for (uint32_t l = g.l0; l < g.l1; ++l) {
+        if (l == g.s0 || l == g.s0 + 1) continue;
+        const float2 L = lay[l];
+        if (L.x <= z && z <= L.y) {
+            found = l;
+            return false;
+        }
+    }
+    return true;
 }
 
 __device__ __forceinline__ bool grid_probe_contact(const SimBuffers &sb, uint64_t layer_base,
                                                    const GridProbe &g)
 {
-    if (g.outside) return true;
-    const float z = g.z;
-    if (g.l0 < g.l1 && g.a.x <= z && z <= g.a.y) return false;
-    if (g.l0 + 1 < g.l1 && g.b.x <= z && z <= g.b.y) return false;
-    const float2 *lay = sb.grid_layers + layer_base;
-    for (uint32_t l = g.l0 + 2; l < g.l1; ++l) {
-        const float2 L = lay[l];
-        if (L.x <= z && z <= L.y) return false;
-    }
-    return true;
+    uint32_t found;
+    return grid_probe_contact(sb, layer_base, g, found);
 }
 
 __device__ __forceinline__ bool obb_contact(const float *o, float x, float y, float z, float r)
@@ -201,6 +226,8 @@ struct SphereSlots {
     Sphere sp[kSlots];
     bool live[kSlots];
     uint64_t off_base[kSlots], layer_base[kSlots];
+    int idx[kSlots];         // sphere index
+    uint32_t hint[kSlots];   // layer-cache offset (0 without the cache)
 };
 
 template <int kLanes>
@@ -212,6 +239,8 @@ __device__ __forceinline__ void load_slots(const RobotParams &rp, const SimBuffe
         const int s = base + k * kLanes + sub;
         sl.live[k] = false;
         sl.off_base[k] = sl.layer_base[k] = 0;
+        sl.idx[k] = s;
+        sl.hint[k] = 0;
         if (active && s < rp.num_spheres) {
             sl.sp[k] = sb.spheres[s];
             if (!(sl.sp[k].held_only && !held)) {
@@ -219,6 +248,7 @@ __device__ __forceinline__ void load_slots(const RobotParams &rp, const SimBuffe
                 const size_t gk = (size_t)env * rp.num_classes + sl.sp[k].cls;
                 sl.off_base[k] = sb.grid_off_base[gk];
                 sl.layer_base[k] = sb.grid_layer_base[gk];
+                if (sb.layer_hint) sl.hint[k] = sb.layer_hint[(size_t)env * rp.num_spheres + s];
             }
         }
     }
@@ -356,14 +386,24 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         }
 #pragma unroll
         for (int k = 0; k < kSlots; ++k)
-            if (sl.live[k] && grid) grid_probe_layers(sb, sl.layer_base[k], g[k]);
+            if (sl.live[k] && grid) grid_probe_layers(sb, sl.layer_base[k], g[k], sl.hint[k]);
         bool hit_static[kSlots], hit_object[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             hit_static[k] = false;
             hit_object[k] = false;
             if (sl.live[k]) {
-                if (grid) hit_static[k] = grid_probe_contact(sb, sl.layer_base[k], g[k]);
+                if (grid) {
+                    uint32_t found;
+                    hit_static[k] = grid_probe_contact(sb, sl.layer_base[k], g[k], found);
+                    // the layer cache: where this sphere's free layer was
+                    // found (kept when the centre is in no free layer)
+                    if (sb.layer_hint && found < g[k].l1) {
+                        const uint32_t off = found - g[k].l0;
+                        const uint32_t h = off < 255u ? off : 0u;
+                        if (h != sl.hint[k]) sb.layer_hint[(size_t)env * rp.num_spheres + sl.idx[k]] = (uint8_t)h;
+                    }
+                }
                 const float r = rp.class_radius[sl.sp[k].cls];
                 for (uint64_t m = cm[k]; m; m &= m - 1) {
                     const int o = __ffsll((unsigned long long)m) - 1;

@@ -65,7 +65,7 @@ class GalTuning(C.Structure):
                 ("refresh", C.c_int32), ("occlusion", C.c_int32), ("prologue", C.c_int32),
                 ("persistent", C.c_int32), ("robot_lanes", C.c_int32), ("graph", C.c_int32),
                 ("split", C.c_int32), ("order", C.c_int32), ("objgrid", C.c_int32),
-                ("bin", C.c_int32)]
+                ("bin", C.c_int32), ("layer_cache", C.c_int32)]
 
 
 class GalOutputs(C.Structure):
