@@ -176,6 +176,105 @@ __global__ __launch_bounds__(256) void k_conv_gemm(const void *__restrict__ in, 
             }
 }
 
+// The first convolution (8x8 stride 4 over the 128x128 depth image, one
+// input channel, at most 32 output channels) with its input staged in LDS:
+// one workgroup per (env, 4 output rows) converts the 20 image rows their
+// windows cover to BF16 once (the windows overlap: each pixel is in up to 4
+// of them) and then runs the same 16x16x32 MFMA tiles as k_conv_gemm, its A
+// fragments (8 consecutive pixels of one window row) read from LDS.  Output
+// rows m = (oy - oy0) * ow + ox of the block, 128 per workgroup (4 x 31
+// used).
+constexpr int kC1Rows = 4;                                  // output rows per workgroup
+constexpr int kC1InRows = (kC1Rows - 1) * 4 + 8;            // image rows they cover
+constexpr int kC1Pitch = kPolicyRes + 8;                    // LDS row pitch (BF16 values)
+__global__ __launch_bounds__(256) void k_conv1_depth(const uint32_t *__restrict__ depth,
+                                                     const uint16_t *__restrict__ W,
+                                                     const float *__restrict__ bias, ConvGeom g,
+                                                     uint16_t *__restrict__ out)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t img[kC1InRows][kC1Pitch];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[32][64 + kPad];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nblk = (g.oh + kC1Rows - 1) / kC1Rows;
+    const int env = blockIdx.x / nblk, oy0 = (blockIdx.x - env * nblk) * kC1Rows;
+    const int rows_out = min(kC1Rows, g.oh - oy0);
+    const int rows_in = (rows_out - 1) * 4 + 8;
+    // the image rows, four pixels per thread and pass (16-byte loads)
+    const uint32_t *src = depth + ((size_t)env * g.ih + (size_t)(4 * oy0)) * g.iw;
+    for (int i = t; i < rows_in * (kPolicyRes / 4); i += 256) {
+        const int r = i / (kPolicyRes / 4), c4 = (i - r * (kPolicyRes / 4)) * 4;
+        const uint4 q = *reinterpret_cast<const uint4 *>(src + (size_t)r * g.iw + c4);
+        img[r][c4 + 0] = depth_bf16(q.x);
+        img[r][c4 + 1] = depth_bf16(q.y);
+        img[r][c4 + 2] = depth_bf16(q.z);
+        img[r][c4 + 3] = depth_bf16(q.w);
+    }
+    // the weights W [out_c][64], 8 per thread
+    {
+        const int o = t >> 3, k8 = (t & 7) * 8;
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (o < g.out_c) q = *reinterpret_cast<const uint4 *>(W + (size_t)o * 64 + k8);
+        memcpy(&Bs[o][k8], &q, 16);
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    const int wm = wave * 32;
+    // this lane's two A rows: output pixel (oy0 + m / ow, m % ow), or none
+    int arow[2], acol[2];
+    bool alive[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int m = wm + 16 * i + r16;
+        alive[i] = m < rows_out * g.ow;
+        const int oy = alive[i] ? m / g.ow : 0;
+        arow[i] = 4 * oy;
+        acol[i] = 4 * (alive[i] ? m - oy * g.ow : 0);
+    }
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        // K = 32 ks + kq .. + 7: window row ky = 4 ks + kq / 8, pixels 0..7
+        const int ky = 4 * ks + (lane >> 4);
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            uint2 lo = make_uint2(0u, 0u), hi = make_uint2(0u, 0u);
+            if (alive[i]) {
+                const uint16_t *p = &img[arow[i] + ky][acol[i]];
+                lo = *reinterpret_cast<const uint2 *>(p);
+                hi = *reinterpret_cast<const uint2 *>(p + 4);
+            }
+            const uint4 q = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            memcpy(&a[i], &q, 16);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[16 * j + r16][32 * ks + kq]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    const size_t obase = ((size_t)env * g.oh + (size_t)oy0) * g.ow;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mm = wm + i * 16 + (lane >> 4) * 4 + q;
+                const int n = j * 16 + (lane & 15);
+                if (mm >= rows_out * g.ow || n >= g.out_c) continue;
+                float v = acc[i][j][q] + bias[n];
+                v = v > 0.f ? v : 0.f;
+                out[(obase + (size_t)mm) * g.out_c + n] = f2bf(v);
+            }
+}
+
 // The heads of env e (one wave): f = [h (BF16 features), q (joint angles)];
 // mean_a = b_a + sum_k W_a[k] f_k, value = b_v + sum_k w_v[k] f_k (FP32,
 // lane-strided partial sums combined by a fixed butterfly); the action
@@ -877,6 +976,13 @@ hipError_t conv_gemm(bool depth_input, const void *in, const uint16_t *W, const 
                      uint16_t *out, hipStream_t s)
 {
     if (g.rows <= 0) return hipSuccess;
+    if (depth_input && g.ih == kPolicyRes && g.iw == kPolicyRes && g.kw == 8 && g.stride == 4 && g.in_c == 1 &&
+        g.k == 64 && g.out_c <= 32 && kC1Rows * g.ow <= 128 && (g.oh - 1) * 4 + 8 <= g.ih) {
+        const int envs = g.rows / (g.oh * g.ow);
+        const dim3 grid((unsigned)(envs * ((g.oh + kC1Rows - 1) / kC1Rows)));
+        hipLaunchKernelGGL(k_conv1_depth, grid, dim3(256), 0, s, static_cast<const uint32_t *>(in), W, bias, g, out);
+        return hipGetLastError();
+    }
     if (g.out_c <= 32) {
         const dim3 grid((g.rows + 127) / 128, 1);
         if (depth_input)
