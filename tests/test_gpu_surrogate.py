@@ -64,27 +64,13 @@ def small_batch(n=16):
     return cfg, scenes, robot, sg.config_constants(cfg)
 
 
-def lattice_cell(offs, lay, nx, i, j, k) -> bool:
-    """Occupancy of grid column (i, j) in layer k: blocked when at one of
-    four heights inside the layer (none below 0.125 m) it has no free layer
-    of the largest sphere class."""
-    f32 = np.float32
-    c = j * nx + i
-    lo_hi = lay[offs[c]:offs[c + 1]]
-    for m in range(4):
-        z = max(f32(f32(k) * f32(0.25)) + f32(f32(0.0625) * f32(m + 1)), f32(0.125))
-        if not np.any((lo_hi[:, 0] <= z) & (z <= lo_hi[:, 1])):
-            return True
-    return False
-
-
 def test_features_match_cpu(torch_cuda):
-    """Scalars and the occupancy patch, recomputed on the CPU from the
-    oracle's column grid (class 0) and its sincos, are bit-identical."""
+    """Scalars, arm pose and occupancy patch equal the oracle's definition
+    of the surrogate's input (oracle/oracle_features.py, on the oracle's own
+    column grid, FK and sincos), bit for bit."""
     torch = torch_cuda
     print("case: features", flush=True)
     from oracle import oracle as O
-    from oracle.oracle_mlp import bf16_round_f32
     from paper_2306_07552_amd import gal
     cfg, scenes, robot, consts = small_batch(6)
     b = gal.Batch(robot, scenes, consts)
@@ -102,55 +88,12 @@ def test_features_match_cpu(torch_cuda):
     X = x.cpu().numpy().view(np.uint16)
     st, _ = b.get_state()
     ob = O.OracleBatch(robot, scenes, consts)
-    f32 = np.float32
-    lim = [f32(v) for v in cfg.act_lim]
-    pi_f, two_pi_f = f32(np.pi), f32(2 * np.pi)
+    from oracle import oracle_features as OF
     blocked_total = 0
     for e in range(6):
-        san = np.clip(np.nan_to_num(a[e], nan=0.0).astype(np.float32),
-                      -np.array([lim[0], lim[1]] + [lim[2]] * 7, np.float32),
-                      np.array([lim[0], lim[1]] + [lim[2]] * 7, np.float32))
-        q = np.clip((st[e, 3:10] + san[2:9]).astype(np.float32), robot.qlim[:, 0], robot.qlim[:, 1])
-        x0, y0 = (f32(v) for v in scenes.grid_origin[e])
-        nx, ny = (int(v) for v in scenes.grid_dims[e])
-        cell = f32(sg.CELL)
-        sc = np.concatenate([q, san[2:9] / lim[2], [san[0] / lim[0], san[1] / lim[1]],
-                             [(st[e, 0] - x0) / (f32(nx) * cell), (st[e, 1] - y0) / (f32(ny) * cell),
-                              st[e, 2] * f32(0.31830988618), f32(scenes.held[e] != 0)]]).astype(np.float32)
-        want = np.zeros(2112, np.uint16)
-        want[:20] = (bf16_round_f32(sc).view(np.uint32) >> 16).astype(np.uint16)
-        # frames of the candidate arm pose with the base at the origin (the oracle's FK)
-        fr = O.fk(robot, np.concatenate([np.zeros(3, np.float32), q]).astype(np.float32)).reshape(8, 3, 4)
-        arm = np.concatenate([fr[1:, :, 3].reshape(-1), fr[7, :, 2]]).astype(np.float32)
-        want[20:44] = (bf16_round_f32(arm).view(np.uint32) >> 16).astype(np.uint16)
-        yaw = f32(st[e, 2] + san[1])
-        if yaw > pi_f:
-            yaw = f32(yaw - two_pi_f)
-        elif yaw < -pi_f:
-            yaw = f32(yaw + two_pi_f)
-        sy, cy = (f32(v[0]) for v in O.sincos(np.array([yaw], np.float32)))
-        bx, by = f32(st[e, 0] + f32(san[0] * cy)), f32(st[e, 1] + f32(san[0] * sy))
-        offs, lay = ob.grid(e, len(consts["radius_classes"]) - 1)
-        cache = {}
-        hx = f32(f32(0.05) * f32(abs(cy) + abs(sy)))
-        for pa in range(16):
-            for pb in range(16):
-                px, py = f32(f32(pa) - f32(7.5)) * f32(0.1), f32(f32(pb) - f32(7.5)) * f32(0.1)
-                wx = f32(bx + f32(f32(cy * px) - f32(sy * py)))
-                wy = f32(by + f32(f32(sy * px) + f32(cy * py)))
-                i0, i1 = (np.floor(f32(f32(f32(wx + d) - x0) / cell)) for d in (-hx, hx))
-                j0, j1 = (np.floor(f32(f32(f32(wy + d) - y0) / cell)) for d in (-hx, hx))
-                inside = i0 >= 0 and j0 >= 0 and i1 < nx and j1 < ny
-                assert not inside or (i1 - i0 < 4 and j1 - j0 < 4)
-                for k in range(8):
-                    blocked = not inside
-                    if inside:
-                        for j in range(int(j0), int(j1) + 1):
-                            for i in range(int(i0), int(i1) + 1):
-                                if (i, j, k) not in cache:
-                                    cache[(i, j, k)] = lattice_cell(offs, lay, nx, i, j, k)
-                                blocked = blocked or cache[(i, j, k)]
-                    want[64 + (pa * 16 + pb) * 8 + k] = 0x3F80 if blocked else 0
+        grid = ob.grid(e, len(consts["radius_classes"]) - 1)
+        want = OF.features(robot, cfg.act_lim, grid, scenes.grid_origin[e], scenes.grid_dims[e], sg.CELL,
+                           st[e], a[e], scenes.held[e])
         assert np.array_equal(X[e], want), f"env {e}: {np.flatnonzero(X[e] != want)[:10]}"
         blocked_total += int((want[64:] != 0).sum())
     assert 0 < blocked_total < 6 * 2048, "the patches are all free or all blocked"
