@@ -329,7 +329,7 @@ int gal_step(gal_batch *b, const float *actions_dev, const gal_outputs *out, voi
  *             list, kept on the device), 0 = at the column's first layer;
  *             the contacts are the same either way.  Not with GAL_MANIP
  * A new batch starts with block 512, region 128 (or the resolution, if
- * smaller), lane_max 4, small_max 256, occlusion 1 with refresh 1 and
+ * smaller), lane_max 8, small_max 1024, occlusion 1 with refresh 1 and
  * prologue 128, persistent 0, robot_lanes 64, graph 0, split 0, order 0,
  * objgrid 1 with 16 or more objects per env (else 0), bin 0, layer_cache 0.
  */

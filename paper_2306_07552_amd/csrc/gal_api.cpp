@@ -1109,8 +1109,8 @@ int gal_create_batch(const gal_config *cfg, const gal_robot *robot, const gal_sc
         const float invf = 1.0f / cfg->far_m;
         b->rast.kd = 16777215.0f / (b->rast.invn - invf);
         b->rast.region = gal::kMaxRegion;
-        b->rast.lane_max = 4;
-        b->rast.small_max = 256;
+        b->rast.lane_max = 8;
+        b->rast.small_max = 1024;
         b->rast.block = 512;
         b->rast.refresh = 1;
         b->rast.occlusion = 1;
