@@ -74,7 +74,9 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, co
             }
             memcpy(&As[r][kk], v, 16);
         } else {
-            const int kk = t >> 3, mm = (t & 7) * 8;
+            // lane = K row, so that the transposed LDS stores of a wave fall
+            // on consecutive addresses (32 K rows x 8 column groups)
+            const int kk = t & 31, mm = (t >> 5) * 8;
             const int k = k0 + kk, m = m0 + mm;
             uint16_t v[8];
             if (k < kend && m + 8 <= M && ((((size_t)k * lda + m) & 7) == 0)) {
