@@ -1185,7 +1185,9 @@ int ensure_occupancy(gal_batch *b, hipStream_t s)
         maxc = std::max(maxc, ox * oy);
     }
     int rc;
-    if ((rc = b->mem.alloc(&b->d_occ, tot)) || (rc = b->mem.alloc(&b->d_occ_off, (size_t)b->N)) ||
+    // 8 bytes of slack: the feature kernels read each lattice row as the two
+    // aligned words around its first byte
+    if ((rc = b->mem.alloc(&b->d_occ, tot + 8)) || (rc = b->mem.alloc(&b->d_occ_off, (size_t)b->N)) ||
         (rc = b->mem.alloc(&b->d_occ_dims, 2 * (size_t)b->N)))
         return rc;
     HIP_TRY(hipMemcpy(b->d_occ_off, off.data(), sizeof(uint64_t) * b->N, hipMemcpyHostToDevice));

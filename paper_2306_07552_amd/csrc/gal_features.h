@@ -122,28 +122,34 @@ __device__ __forceinline__ bool patch_box(const CandBase &cb, float x0, float y0
 }
 
 // Occupancy bits (bit k = layer k blocked) of a patch column: the OR of the
-// lattice bytes of its box, all 0xFF outside the grid.  A fixed 4 x 4 block
-// of loads (indices clamped into the lattice; box 0..0 when outside) issued
-// without a branch, so that the loads of several columns can be in flight
-// together; the columns past the box are masked out.
+// lattice bytes of its box, all 0xFF outside the grid.  Each of the box's
+// (at most 4) rows is read as the 4 bytes from column i0 on, cut out of the
+// two aligned words that hold them; the bytes past column i1 are masked out.
+// The loads are a fixed 4 x 2 block (row indices clamped into the lattice,
+// box 0..0 when outside) issued without a branch, so that the loads of
+// several columns can be in flight together.  The lattice's allocation has 8
+// bytes of slack past its end for the second word of its last bytes.
 __device__ __forceinline__ uint32_t patch_or(const uint8_t *occ, int ox, int oy, bool inside, int i0,
                                              int i1, int j0, int j1)
 {
-    uint32_t v[4][4];
+    uint32_t lo[4], hi[4], sh[4];
+#pragma unroll
+    for (int dj = 0; dj < 4; ++dj) {
+        const int j = min(j0 + dj, oy - 1);
+        const uintptr_t a = (uintptr_t)(occ + (size_t)j * ox + i0);
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+        lo[dj] = w[0];
+        hi[dj] = w[1];
+        sh[dj] = (uint32_t)(a & 3);
+    }
+    const uint32_t keep = i1 - i0 >= 3 ? 0xFFFFFFFFu : (1u << (8 * (i1 - i0 + 1))) - 1u;
+    uint32_t acc = 0;
 #pragma unroll
     for (int dj = 0; dj < 4; ++dj)
-#pragma unroll
-        for (int di = 0; di < 4; ++di) {
-            const int i = min(i0 + di, ox - 1), j = min(j0 + dj, oy - 1);
-            v[dj][di] = occ[(size_t)j * ox + i];
-        }
-    uint32_t bits = 0;
-#pragma unroll
-    for (int dj = 0; dj < 4; ++dj)
-#pragma unroll
-        for (int di = 0; di < 4; ++di)
-            if (i0 + di <= i1 && j0 + dj <= j1) bits |= v[dj][di];
-    return inside ? bits : 0xFFu;
+        if (j0 + dj <= j1) acc |= __builtin_amdgcn_alignbyte(hi[dj], lo[dj], sh[dj]) & keep;
+    acc |= acc >> 16;
+    acc |= acc >> 8;
+    return inside ? (acc & 0xFFu) : 0xFFu;
 }
 
 __device__ __forceinline__ uint32_t patch_bits(const OccGrid &og, const GridMeta &gm, int env,

@@ -62,17 +62,19 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 __device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
 
 
-// Layers 2..4, the head and the routing of the tile's 32 rows, from the first
-// hidden layer in H[0]; f2, f3, f4 hold this wave's fragments of the three
-// layers, all loaded before the first of them runs (a chain of per-layer loads
-// waits on memory three times over).
+// Layers 2..4, the head and the routing of R rows (16 or 32) from row0 on,
+// from the first hidden layer in H[0]; f2, f3, f4 hold this wave's fragments
+// of the three layers, all loaded before the first of them runs (a chain of
+// per-layer loads waits on memory three times over).
+template <int R>
 __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
-                                            uint16_t (*H)[kR][kHPitch], float *zs,
+                                            uint16_t (*H)[R][kHPitch], float *zs,
                                             const bf16x8 (&f2)[kMlpHidden / 32][2],
                                             const bf16x8 (&f3)[kMlpHidden / 32][2],
                                             const bf16x8 (&f4)[kMlpHidden / 32][2])
 {
-    constexpr int D = kMlpHidden;
+    constexpr int D = kMlpHidden, M = R / 16;
+    static_assert(R % 16 == 0 && R % kWaves == 0 && R <= 64, "whole MFMA row tiles");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     float bias[3][2];
@@ -84,15 +86,15 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
 #pragma unroll
     for (int k = 0; k < D / 64; ++k) hw[k] = p.t.w[3][lane + 64 * k];
     auto layer = [&](const bf16x8(&f)[D / 32][2], const float(&bl)[2], int cur) {
-        floatx4 ac[2][2];
+        floatx4 ac[M][2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < M; ++m)
 #pragma unroll
             for (int j = 0; j < 2; ++j) ac[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int st = 0; st < D / 32; ++st)
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < M; ++m) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&H[cur][16 * m + r16][32 * st + kq]);
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
@@ -102,7 +104,7 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
         for (int j = 0; j < 2; ++j) {
             const int n = kColsW * wave + 16 * j + r16;
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < M; ++m)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     H[cur ^ 1][16 * m + 4 * (lane >> 4) + i][n] = to_bf16(relu(ac[m][j][i] + bl[j]));
@@ -114,8 +116,8 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
     layer(f4, bias[2], 0);
     // head (summed in the training head's order): wave w takes rows 4w .. 4w + 3
 #pragma unroll
-    for (int rr = 0; rr < kR / kWaves; ++rr) {
-        const int r = (kR / kWaves) * wave + rr;
+    for (int rr = 0; rr < R / kWaves; ++rr) {
+        const int r = (R / kWaves) * wave + rr;
         float h = 0.f;
 #pragma unroll
         for (int k = 0; k < D / 64; ++k) h += bf16_to_f(H[1][r][lane + 64 * k]) * bf16_to_f(hw[k]);
@@ -125,7 +127,7 @@ __device__ __forceinline__ void tail_layers(const SurInferArgs &p, int row0,
     __syncthreads();
     if (wave == 0) {
         const int e = row0 + lane;
-        const bool live = lane < kR && e < p.rows;
+        const bool live = lane < R && e < p.rows;
         int flag = 0;
         if (live) {
             if (p.z) p.z[e] = zs[lane];
@@ -226,21 +228,37 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
                 w[st][j] = st < ns ? *reinterpret_cast<const bf16x8 *>(p.t.w0 + frag_offset(s0, ns, wave, st, j, lane))
                                    : bf16x8{};
     };
+    // per row: the candidate base pose and the lattice placement, once.  The
+    // row's loads are issued before the weight fragments: loads complete in
+    // order, and behind the fragments they would wait for all of them.
+    const bool rlive = FEAT && tid < kR && row0 + tid < p.rows;
+    float rst[3] = {0.f, 0.f, 0.f}, ract[2] = {0.f, 0.f}, rx0 = 0.f, ry0 = 0.f;
+    int rox = 1, roy = 1;
+    uint64_t roff = 0;
+    if (rlive) {
+        const int e = row0 + tid;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rst[k] = p.sb.state[(size_t)e * 10 + k];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) ract[k] = p.actions[(size_t)e * 9 + k];
+        rx0 = p.sb.grid_meta[e].x0;
+        ry0 = p.sb.grid_meta[e].y0;
+        rox = p.og.occ_dims[2 * e];
+        roy = p.og.occ_dims[2 * e + 1];
+        roff = p.og.occ_off[e];
+    }
     load_chunk(cbeg);
     if (FEAT) {
-        // per row: the candidate base pose and the lattice placement, once
         if (tid < kR) {
             RowInfo ri{};
-            const int e = row0 + tid;
-            ri.live = e < p.rows;
-            if (ri.live) {
-                ri.cb = cand_base(p.rp, p.sb.state + (size_t)e * 10, p.actions + (size_t)e * 9);
-                const GridMeta gm = p.sb.grid_meta[e];
-                ri.x0 = gm.x0;
-                ri.y0 = gm.y0;
-                ri.ox = p.og.occ_dims[2 * e];
-                ri.oy = p.og.occ_dims[2 * e + 1];
-                ri.occ_off = p.og.occ_off[e];
+            ri.live = rlive;
+            if (rlive) {
+                ri.cb = cand_base(p.rp, rst, ract);
+                ri.x0 = rx0;
+                ri.y0 = ry0;
+                ri.ox = rox;
+                ri.oy = roy;
+                ri.occ_off = roff;
             }
             rows[tid] = ri;
         }
@@ -370,68 +388,81 @@ __global__ __launch_bounds__(kThreads) void k_sur_l1(SurInferArgs p)
             for (int i = 0; i < 4; ++i) H[0][16 * m + 4 * (lane >> 4) + i][n] = to_bf16(relu(acc[m][j][i] + bn));
     }
     __syncthreads();
-    tail_layers(p, row0, H, zs, f2, f3, f4);
+    tail_layers<kR>(p, row0, H, zs, f2, f3, f4);
 }
 
-// Second launch with several splits: one workgroup per tile adds the tile's
-// partial sums in split order (bias, ReLU, BF16) and runs the hidden layers.
+// Second launch with several splits: a workgroup per half tile (16 rows)
+// adds the partial sums of its rows in split order (bias, ReLU, BF16) and
+// runs the hidden layers.  The partial sums (up to 8 x 16 KB) go straight
+// from memory into LDS (global_load_lds), so the registers hold the three
+// hidden layers' weights, and all of it is requested at once: the workgroup
+// waits on memory one time.
+constexpr int kTR = 16;                     // rows per tail workgroup
+constexpr int kMaxSplits = 8;
+
 __global__ __launch_bounds__(kThreads) void k_sur_tail(SurInferArgs p)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kR * kHPitch];
-    __shared__ float zs[kR];
-    uint16_t(*H)[kR][kHPitch] = reinterpret_cast<uint16_t(*)[kR][kHPitch]>(lds);
+    __shared__ __attribute__((aligned(16))) float part[kMaxSplits][kTR][kMlpHidden];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kTR * kHPitch];
+    __shared__ float zs[kTR];
+    uint16_t(*H)[kTR][kHPitch] = reinterpret_cast<uint16_t(*)[kTR][kHPitch]>(lds);
     const int S = p.splits;
-    const int tile = blockIdx.x, row0 = tile * kR;
-    // thread: 4 adjacent columns of rows r, r + 8, r + 16, r + 24; every
-    // split's partial sums of two of them in flight at once (the splits are
-    // added in split order afterwards)
-    constexpr int kMaxSplits = 8;
-    const int c = (threadIdx.x % (kMlpHidden / 4)) * 4, r0 = threadIdx.x / (kMlpHidden / 4);
-    constexpr int kRowStep = kThreads / (kMlpHidden / 4);   // 8
-    const float *tp = p.part + (size_t)tile * S * kR * kMlpHidden;
-    auto load_rows = [&](int h, float4 (&v)[2][kMaxSplits]) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float *q = tp + (size_t)(r0 + kRowStep * (h + k)) * kMlpHidden + c;
-#pragma unroll
-            for (int sp = 0; sp < kMaxSplits; ++sp)
-                v[k][sp] = sp < S ? *reinterpret_cast<const float4 *>(q + (size_t)sp * kR * kMlpHidden)
-                                  : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    };
-    auto store_rows = [&](int h, const float4 (&v)[2][kMaxSplits]) {
-        const float4 bb = *reinterpret_cast<const float4 *>(p.t.b0 + c);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            float4 a = v[k][0];
-#pragma unroll
-            for (int sp = 1; sp < kMaxSplits; ++sp)
-                if (sp < S) {
-                    a.x += v[k][sp].x;
-                    a.y += v[k][sp].y;
-                    a.z += v[k][sp].z;
-                    a.w += v[k][sp].w;
-                }
-            const int r = r0 + kRowStep * (h + k);
-            H[0][r][c + 0] = to_bf16(relu(a.x + bb.x));
-            H[0][r][c + 1] = to_bf16(relu(a.y + bb.y));
-            H[0][r][c + 2] = to_bf16(relu(a.z + bb.z));
-            H[0][r][c + 3] = to_bf16(relu(a.w + bb.w));
-        }
-    };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the first launch sends tile t to XCD t mod 8 when the tile count is a
+    // multiple of 8; keep both halves of tile t there too
+    const int tiles_all = gridDim.x / 2;
+    int tile, half;
+    if (tiles_all % 8 == 0) {
+        tile = (blockIdx.x & 7) + 8 * (blockIdx.x >> 4);
+        half = (blockIdx.x >> 3) & 1;
+    } else {
+        tile = blockIdx.x >> 1;
+        half = blockIdx.x & 1;
+    }
+    const int row0 = tile * kR + kTR * half;
+    // one wave-wide copy = one row of one split (256 floats, 16 bytes a lane)
+    const float *tp = p.part + (size_t)tile * S * kR * kMlpHidden + (size_t)kTR * half * kMlpHidden;
+    for (int i = wave; i < S * kTR; i += kWaves) {
+        const int sp = i / kTR, r = i - sp * kTR;
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(tp + (size_t)sp * kR * kMlpHidden + (size_t)r * kMlpHidden + 4 * lane),
+            (__attribute__((address_space(3))) void *)&part[sp][r][0], 16, 0, 0);
+    }
     bf16x8 f2[kMlpHidden / 32][2], f3[kMlpHidden / 32][2], f4[kMlpHidden / 32][2];
     load_layer(p.t.w[0], f2);
-    {
-        float4 v[2][kMaxSplits];
-        load_rows(0, v);
-        load_layer(p.t.w[1], f3);
-        store_rows(0, v);
-        load_rows(2, v);
-        store_rows(2, v);
-    }
+    load_layer(p.t.w[1], f3);
     load_layer(p.t.w[2], f4);
     __syncthreads();
-    tail_layers(p, row0, H, zs, f2, f3, f4);
+    {
+        // thread: 8 adjacent columns of one row
+        const int r = tid >> 5, c = (tid & 31) * 8;
+        float a[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float4 v = *reinterpret_cast<const float4 *>(&part[0][r][c + 4 * h]);
+            a[4 * h + 0] = v.x;
+            a[4 * h + 1] = v.y;
+            a[4 * h + 2] = v.z;
+            a[4 * h + 3] = v.w;
+        }
+        for (int sp = 1; sp < S; ++sp)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 v = *reinterpret_cast<const float4 *>(&part[sp][r][c + 4 * h]);
+                a[4 * h + 0] += v.x;
+                a[4 * h + 1] += v.y;
+                a[4 * h + 2] += v.z;
+                a[4 * h + 3] += v.w;
+            }
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            w[k] = (uint32_t)to_bf16(relu(a[2 * k] + p.t.b0[c + 2 * k])) |
+                   ((uint32_t)to_bf16(relu(a[2 * k + 1] + p.t.b0[c + 2 * k + 1])) << 16);
+        *reinterpret_cast<uint4 *>(&H[0][r][c]) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+    tail_layers<kTR>(p, row0, H, zs, f2, f3, f4);
 }
 
 // One thread per 8 consecutive K values of one output column of one layer:
@@ -518,7 +549,7 @@ hipError_t sur_infer(const SurInferArgs &args, hipStream_t s)
         hipLaunchKernelGGL(k_sur_l1<1>, grid, dim3(kThreads), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.splits == 1) return e;
-    hipLaunchKernelGGL(k_sur_tail, dim3((unsigned)tiles), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL(k_sur_tail, dim3((unsigned)(2 * tiles)), dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
 
