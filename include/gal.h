@@ -363,13 +363,14 @@ int gal_set_tuning(gal_batch *b, const gal_tuning *t);
  * fixes one batch size per GPU; here the split of the batch's work into
  * workgroups is searched per batch): times the candidate launch configurations (raster workgroup
  * size, region, small-triangle thresholds, occlusion culling, persistent
- * queue, robot lanes per env, and the 8x8-tile binning wherever its LDS
- * fits) on this batch with the given actions and
+ * queue, and the 8x8-tile binning wherever its LDS fits) on this batch with
+ * the given actions and
  * outputs (`steps` timed steps each, HIP events); then, on the fastest and on
  * it with the other launch mode, `split` at 0, 1/16, 1/8, 1/4 and 1/2 of the
  * workgroups resident at once, each with an occlusion prologue of 128 and 256
  * clusters and, with the queue, both item orders (3 x `steps` each, two
- * interleaved rounds).  It
+ * interleaved rounds); last, the robot step's 32 or 64 lanes per env on the
+ * winner (3 x `steps` each, three interleaved rounds).  It
  * checks that every candidate produces the same depth bits from the same
  * state, keeps the fastest (also written to *best, with its time per step in
  * *best_ms) and restores the simulation state it started from.  The outputs'

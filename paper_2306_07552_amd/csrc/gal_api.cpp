@@ -518,7 +518,7 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                 for (int small_max : {256, 1024})
                     for (int occl : {0, 1})   // 1: one refresh after a 128-cluster prologue
                         for (int persist : {0, 1})
-                            for (int rl : {32, 64}) {
+                            for (int rl : {64}) {
                                 bool ok = true;
                                 for (int e = 0; e < b->N && ok; ++e)
                                     if (b->res_host[e] > region && b->res_host[e] % region) ok = false;
@@ -654,6 +654,27 @@ int gal_autotune(gal_batch *b, const float *actions_dev, const gal_outputs *out,
                 if (t2[i] < t2[k]) k = i;
             best_c = c2[k];
             best_t = t2[k];
+        }
+    }
+    // Third stage: the robot step's lanes per env (32 or 64) on the winner,
+    // in three interleaved rounds of 3 x `steps`; their difference of a few
+    // microseconds per step is smaller than the spread between raster
+    // candidates, so the first stage does not vary them.
+    if (result == GAL_OK) {
+        gal_tuning c3[2] = {best_c, best_c};
+        c3[0].robot_lanes = 64;
+        c3[1].robot_lanes = 32;
+        double t3[2] = {1e30, 1e30};
+        for (int round = 0; round < 3 && result == GAL_OK; ++round)
+            for (int i = 0; i < 2; ++i) {
+                best_t = 1e30;
+                if ((result = evaluate(c3[i], 3 * steps))) break;
+                t3[i] = std::min(t3[i], best_t);
+            }
+        if (result == GAL_OK) {
+            const int k = t3[1] < t3[0] ? 1 : 0;
+            best_c = c3[k];
+            best_t = t3[k];
         }
     }
     (void)hipEventDestroy(e0);

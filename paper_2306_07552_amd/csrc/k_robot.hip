@@ -318,6 +318,18 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
     const int half = kLanes == 32 ? (lane >> 5) : 0;
     int env = (int)blockIdx.x * kEnvsPerBlock + (int)threadIdx.x / kLanes;
     if (kLanes == 64) env = __builtin_amdgcn_readfirstlane(env);
+    // The object records of the workgroup's envs, staged in LDS once: every
+    // sphere may test all of them, and read from global memory each test of
+    // the chain would wait on a load of its own.
+    __shared__ float4 obj_lds[kEnvsPerBlock * kMaxObjects * 2];
+    const int env0 = (int)blockIdx.x * kEnvsPerBlock;
+    {
+        const int ne = min(kEnvsPerBlock, sb.num_envs - env0);
+        const int n4 = ne * rp.num_objects * 2;
+        const float4 *src = reinterpret_cast<const float4 *>(sb.objects + (size_t)env0 * rp.num_objects * 8);
+        for (int i = (int)threadIdx.x; i < n4; i += 256) obj_lds[i] = src[i];
+        __syncthreads();
+    }
     if (kLanes == 64 && env >= sb.num_envs) return;
     // with two envs per wave, a half-wave past the end still joins the ballots
     const bool active = env < sb.num_envs;
@@ -361,7 +373,7 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
     Fk fk;
     forward_kinematics(rp, cand, fk);
     const GridMeta gm = sb.grid_meta[env];
-    const float *objs = sb.objects + (size_t)env * rp.num_objects * 8;
+    const float *objs = reinterpret_cast<const float *>(obj_lds) + (active ? env - env0 : 0) * rp.num_objects * 8;
     // surrogate routing: 1 = static check skipped (no contact assumed),
     // 2 = skipped but audited (exact check runs; a contact is a mismatch)
     const int route = sb.skip_flags ? sb.skip_flags[env] : 0;
@@ -388,10 +400,38 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
         for (int k = 0; k < kSlots; ++k)
             if (sl.live[k] && grid) grid_probe_layers(sb, sl.layer_base[k], g[k], sl.hint[k]);
         bool hit_static[kSlots], hit_object[kSlots];
+        // object boxes: one pass over the candidates of every slot of the
+        // env's lanes (the OR of their masks), each record read from LDS once
+        // for all of its tests; the tests are pure, so testing a lane's
+        // candidates past its first contact changes nothing
+        {
+            uint64_t m[kSlots], u = 0ull;
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                hit_object[k] = false;
+                m[k] = sl.live[k] ? cm[k] : 0ull;
+                u |= m[k];
+            }
+            uint32_t ulo = (uint32_t)u, uhi = (uint32_t)(u >> 32);
+#pragma unroll
+            for (int d = kLanes / 2; d >= 1; d >>= 1) {
+                ulo |= (uint32_t)__shfl_xor((int)ulo, d, 64);
+                uhi |= (uint32_t)__shfl_xor((int)uhi, d, 64);
+            }
+            float r[kSlots];
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) r[k] = sl.live[k] ? rp.class_radius[sl.sp[k].cls] : 0.0f;
+            for (u = ((uint64_t)uhi << 32) | ulo; u; u &= u - 1) {
+                const int o = __ffsll((unsigned long long)u) - 1;
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k)
+                    if ((m[k] >> o) & 1ull)
+                        hit_object[k] = hit_object[k] | obb_contact(objs + 8 * o, cx[k], cy[k], cz[k], r[k]);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             hit_static[k] = false;
-            hit_object[k] = false;
             if (sl.live[k]) {
                 if (grid) {
                     uint32_t found;
@@ -402,14 +442,6 @@ __global__ __launch_bounds__(256) void k_robot_step(RobotParams rp, SimBuffers s
                         const uint32_t off = found - g[k].l0;
                         const uint32_t h = off < 255u ? off : 0u;
                         if (h != sl.hint[k]) sb.layer_hint[(size_t)env * rp.num_spheres + sl.idx[k]] = (uint8_t)h;
-                    }
-                }
-                const float r = rp.class_radius[sl.sp[k].cls];
-                for (uint64_t m = cm[k]; m; m &= m - 1) {
-                    const int o = __ffsll((unsigned long long)m) - 1;
-                    if (obb_contact(objs + 8 * o, cx[k], cy[k], cz[k], r)) {
-                        hit_object[k] = true;
-                        break;
                     }
                 }
             }
