@@ -310,33 +310,37 @@ def test_adam_matches_oracle(torch_cuda):
             assert np.count_nonzero(wd != w0) > 0.9 * wd.size * (np.count_nonzero(g) / g.size)
 
 
-def test_forward_65536_rows(torch_cuda):
-    """Inference at the surrogate's query-batch size (65,536 rows of real
-    features from 64 scenes under 1024 action draws): 256 sampled rows and
-    the last row element by element against the FP64 oracle within the
-    derived per-row bound; the throughput is printed."""
+@pytest.mark.parametrize("R", [3000, 5000, 65536])
+def test_forward_large_batches(torch_cuda, R):
+    """Inference on large batches of real features from 64 scenes under
+    random action draws: 3000 rows (4 first-layer splits, a ragged last
+    tile), 5000 rows (2 splits, ragged) and the surrogate's query-batch size
+    of 65,536 rows (one split, no second launch).  256 sampled rows and the
+    last row element by element against the FP64 oracle within the derived
+    per-row bound; the throughput is printed."""
     torch = torch_cuda
-    print("case: mlp forward, 65536 rows", flush=True)
+    print(f"case: mlp forward, {R} rows", flush=True)
     from paper_2306_07552_amd import gal
     cfg = sg.scaled_config(1, 64)
     scenes = sg.make_scene_set(cfg)
     robot = sg.make_robot_for(cfg)
     b = gal.Batch(robot, scenes, sg.config_constants(cfg))
-    R = 65536
-    X = torch.empty((R, 2112), dtype=torch.int16, device="cuda")
+    Xall = torch.empty(((R + 63) // 64 * 64, 2112), dtype=torch.int16, device="cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     lim = torch.tensor([0.1, 0.1] + [0.05] * 7, device="cuda")
     out = {k: v for k, v in b.alloc_outputs().items() if k != "depth"}
-    for k in range(R // 64):
+    for k in range(Xall.shape[0] // 64):
         a = ((torch.rand((64, 9), generator=g, device="cuda") * 2 - 1) * lim).contiguous()
-        b.features(a, X[64 * k:64 * (k + 1)])
+        b.features(a, Xall[64 * k:64 * (k + 1)])
         if k % 8 == 0:
             b.step(a, out)                    # move the robots now and then
+    X = Xall[:R]
     mlp = gal.Mlp(max_rows=R, seed=5)
-    yt = torch.from_numpy((np.random.default_rng(1).uniform(size=4096) < 0.3).astype(np.float32)).cuda()
+    nt = min(R, 4096)
+    yt = torch.from_numpy((np.random.default_rng(1).uniform(size=nt) < 0.3).astype(np.float32)).cuda()
     for _ in range(3):
-        mlp.train_step(X[:4096], yt, 4.0, 1e-3)
+        mlp.train_step(X[:nt], yt, 4.0, 1e-3)
     z = torch.full((R,), np.nan, dtype=torch.float32, device="cuda")
     mlp.forward(X, z)
     torch.cuda.synchronize()
@@ -348,7 +352,7 @@ def test_forward_65536_rows(torch_cuda):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / 5
     flop = 2.0 * (2112 * 256 + 3 * 256 * 256 + 256) * R
-    print(f"forward 65536 rows: {ms * 1e3:.1f} us, {flop / ms / 1e9:.1f} TFLOP/s", flush=True)
+    print(f"forward {R} rows: {ms * 1e3:.1f} us, {flop / ms / 1e9:.1f} TFLOP/s", flush=True)
     zg_all = z.cpu().numpy()
     assert np.isfinite(zg_all).all()
     rows = np.sort(np.concatenate([np.random.default_rng(11).choice(R - 1, 256, replace=False),
@@ -356,7 +360,7 @@ def test_forward_65536_rows(torch_cuda):
     w = mlp.get_weights()
     x64 = bits_to_f64(X[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint16))
     zo = oracle_net(w).forward(x64, round_bf16=True)
-    check_logits_elementwise(zg_all[rows].astype(np.float64), zo, w, x64, "65536-row forward")
+    check_logits_elementwise(zg_all[rows].astype(np.float64), zo, w, x64, f"{R}-row forward")
 
 
 def test_training_reduces_loss(torch_cuda):
