@@ -230,7 +230,7 @@ struct gal_batch {
     uint64_t *d_depth_off = nullptr;
     uint32_t *d_work = nullptr;
     uint32_t *d_item_cost = nullptr;        // last step's time per work item
-    uint64_t *d_item_order = nullptr;       // queue position -> item index << 32 | work word
+    uint32_t *d_item_order = nullptr;       // queue position -> work item
     int32_t num_work = 0;
     int32_t max_res = 0;
     int64_t n_clusters = 0, n_cverts = 0, n_tris = 0;
@@ -353,17 +353,16 @@ int build_work(gal_batch *b)
     }
     b->num_work = (int32_t)work.size();
     // until items have been timed: the static order (costs decreasing along it)
-    std::vector<uint32_t> cost(work.size());
-    std::vector<uint64_t> ord(work.size());
+    std::vector<uint32_t> cost(work.size()), ord(work.size());
     for (size_t i = 0; i < work.size(); ++i) {
         cost[i] = (uint32_t)(work.size() - i);
-        ord[i] = ((uint64_t)i << 32) | work[i];
+        ord[i] = (uint32_t)i;
     }
     hipError_t e = hipMemcpy(b->d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_item_cost, cost.data(), sizeof(uint32_t) * cost.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(b->d_item_order, ord.data(), sizeof(uint64_t) * ord.size(), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->d_item_order, ord.data(), sizeof(uint32_t) * ord.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(GAL_EDEVICE, "hipMemcpy(work) failed: %s", hipGetErrorString(e));
     b->rast.item_cost = b->d_item_cost;
     b->rast.item_order = b->d_item_order;
@@ -1264,7 +1263,7 @@ int enqueue_step(gal_batch *b, const float *actions_dev, const gal_outputs *out,
     // by an extra workgroup of the robot launch
     const bool order_items =
         out->depth && b->rast.persistent && b->rast.order && b->num_work <= gal::kOrderCap;
-    const gal::ItemOrder ord{b->d_item_cost, order_items ? b->num_work : 0, b->d_item_order, b->d_work};
+    const gal::ItemOrder ord{b->d_item_cost, order_items ? b->num_work : 0, b->d_item_order};
     HIP_TRY(gal::launch_robot_step(b->rp, sb, actions_dev, so, b->d_queue, b->robot_lanes, ord, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (out->depth)

@@ -11,8 +11,7 @@ namespace gal {
 struct ItemOrder {
     const uint32_t *cost;   // [n] last step's time per work item
     int32_t n;              // items to order (0: no ordering in this launch)
-    uint64_t *order;        // [n] out: queue position -> item index << 32 | its work word
-    const uint32_t *work;   // [n] the work words
+    uint32_t *order;        // [n] out: queue position -> work item
 };
 
 hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const float *actions,

@@ -66,7 +66,7 @@ struct RasterParams {
     int32_t bin;       // 1 = mid-sized triangles are binned per 8x8 tile in LDS and drawn tile by tile
     unsigned long long *stats; // optional work counters [8] (null = off)
     uint32_t *item_cost;        // [work] last time of each work item (wall-clock ticks)
-    const uint64_t *item_order; // [work] queue position -> item index << 32 | its work word
+    const uint32_t *item_order; // [work] queue position -> work item
 };
 
 hipError_t raster_prepare();   // raises the dynamic-LDS limit of the raster kernels

@@ -1610,20 +1610,13 @@ __global__ __launch_bounds__(kBlock, (raster_waves_per_eu<kBlock, kBin>())) void
         if (i >= num_work) break;
         // the queue position's work item (static order: the position itself)
         int idx = i;
-        uint32_t item;
         if (rp.order && rp.item_order) {
-            const uint64_t ow = rp.item_order[i];
-            idx = (int)(ow >> 32);
-            item = (uint32_t)ow;
-            if ((unsigned)idx >= (unsigned)num_work) {
-                idx = i;
-                item = work[i];
-            }
-        } else {
-            item = work[idx];
+            idx = (int)rp.item_order[i];
+            if ((unsigned)idx >= (unsigned)num_work) idx = i;
         }
         const uint64_t t0 = wall_clock64();
-        raster_item<kBlock, kColor, kBin>(m, rp, camera, env_res, env_depth_off, item, depth, rgb, zdyn, sh);
+        raster_item<kBlock, kColor, kBin>(m, rp, camera, env_res, env_depth_off, work[idx], depth, rgb, zdyn,
+                                    sh);
         // the item's time, which orders the next step's queue (raster_item
         // ends with a barrier, so every wave is done)
         if (threadIdx.x == 0 && rp.item_cost) {

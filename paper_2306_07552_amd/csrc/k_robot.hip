@@ -292,10 +292,7 @@ __device__ void order_items_block(const ItemOrder &ord)
         count[4 * t + 3] = ex + a + b + d;
     }
     __syncthreads();
-    // each position holds the item's index and its work word, so that the
-    // raster reads one word per item rather than two in a chain
-    for (int i = t; i < n; i += 256)
-        ord.order[atomicAdd(&count[bucket(ord.cost[i])], 1u)] = ((uint64_t)i << 32) | ord.work[i];
+    for (int i = t; i < n; i += 256) ord.order[atomicAdd(&count[bucket(ord.cost[i])], 1u)] = (uint32_t)i;
 }
 
 // kLanes lanes per environment: 64 (one env per wave, spheres lane + 64k) or
@@ -1079,7 +1076,7 @@ hipError_t launch_robot_step(const RobotParams &rp, const SimBuffers &sb, const 
                              const StepOutputs &out, uint32_t *queue_reset, int lanes_per_env,
                              const ItemOrder &ord, hipStream_t s)
 {
-    if (ord.n < 0 || ord.n > kOrderCap || (ord.n > 0 && (!ord.cost || !ord.order || !ord.work)))
+    if (ord.n < 0 || ord.n > kOrderCap || (ord.n > 0 && (!ord.cost || !ord.order)))
         return hipErrorInvalidValue;
     const int extra = ord.n > 0 ? 1 : 0;
     if (rp.manip) {
